@@ -1,0 +1,111 @@
+"""Pins of the oracle's P1 assembly (eq. (1)) against closed forms and invariants."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import assemble as asm
+
+
+def test_complex_symmetric_not_hermitian():
+    # eq. (1) with impedance BC gives a complex symmetric, non-Hermitian matrix
+    n, k = 9, 7.0
+    A = asm.assemble(k, [1.0], n)
+    assert abs(A - A.T).max() == 0.0
+    assert abs(A - A.conj().T).max() > 0.1
+    # the imaginary part lives on boundary rows only (the impedance term)
+    im = abs(A.imag).sum(axis=1).A.ravel().reshape(n, n)
+    assert np.all(im[1:-1, 1:-1] == 0.0)
+    assert np.all(im[0, :] > 0) and np.all(im[-1, :] > 0)
+    assert np.all(im[:, 0] > 0) and np.all(im[:, -1] > 0)
+
+
+def test_constant_mode_sums():
+    # K 1 = 0; 1' M 1 = area = 1; 1' M_Gamma 1 = perimeter = 4  =>  1' A 1 = -k^2 - 4 i k
+    n, k = 13, 3.5
+    K, Mk2, Mg = asm.operator_parts(k, [1.0], n)
+    one = np.ones(n * n)
+    assert np.abs(K @ one).max() < 1e-12
+    assert one @ Mk2 @ one == pytest.approx(k * k, rel=1e-13)
+    assert one @ Mg @ one == pytest.approx(4 * k, rel=1e-13)
+    A = asm.assemble(k, [1.0], n)
+    assert one @ A @ one == pytest.approx(-k * k - 4j * k, rel=1e-13)
+
+
+def test_interior_rows_match_textbook_stencils():
+    # P1 on right isosceles triangles: stiffness = 5-point Laplacian, mass = 7-point
+    n = 11
+    h = 1.0 / (n - 1)
+    K, M, _ = asm.operator_parts(1.0, [1.0], n)
+    i, j = 5, 4
+    p = asm.node_id(n, i, j)
+    rowK = dict(zip(K[p].indices, K[p].data))
+    expect = {p: 4.0, p - 1: -1.0, p + 1: -1.0, p - n: -1.0, p + n: -1.0}
+    assert set(k for k, v in rowK.items() if abs(v) > 1e-14) == set(expect)
+    for q, v in expect.items():
+        assert rowK[q] == pytest.approx(v, abs=1e-13)
+    rowM = dict(zip(M[p].indices, M[p].data))
+    nb = [p - 1, p + 1, p - n, p + n, p + n + 1, p - n - 1]   # "/" diagonal neighbours
+    assert set(k for k, v in rowM.items() if abs(v) > 0) == set(nb + [p])
+    assert rowM[p] == pytest.approx(h * h / 2, rel=1e-13)
+    for q in nb:
+        assert rowM[q] == pytest.approx(h * h / 12, rel=1e-13)
+
+
+def _exact_layer(y_frac, L):
+    return min(int(y_frac * L), L - 1)
+
+
+def test_layer_classification_exact():
+    # centroid heights (3j+1)h/3 and (3j+2)h/3, edge heights jh and (j+1/2)h,
+    # classified with exact rational arithmetic
+    n, L = 11, 3
+    for P in range(0, 6 * (n - 1) + 1):
+        y = Fraction(P, 6 * (n - 1))
+        assert asm.layer_of(P, n, L) == _exact_layer(y, L)
+
+
+def test_layered_medium_weighted_sums():
+    # layers aligned with grid lines: 1' M_{k^2} 1 = (1/L) sum k_l^2,
+    # 1' M_Gamma 1 = 2 (1/L) sum k_l + k_0 + k_{L-1}
+    n, L = 17, 4
+    c = np.array([1.0, 2.0, 1.5, 3.0])
+    omega = 9.0
+    kl = omega / c
+    _, Mk2, Mg = asm.operator_parts(omega, c, n)
+    one = np.ones(n * n)
+    assert one @ Mk2 @ one == pytest.approx((kl ** 2).sum() / L, rel=1e-13)
+    assert one @ Mg @ one == pytest.approx(2 * kl.sum() / L + kl[0] + kl[-1], rel=1e-13)
+
+
+def test_source_load_integrates_constant():
+    n = 9
+    b = asm.source_load(n, np.ones(n * n))
+    assert b.sum() == pytest.approx(-1.0, rel=1e-13)
+
+
+def _plane_wave_error(n, k):
+    d = np.array([np.cos(np.pi / 6), np.sin(np.pi / 6)])
+    u = lambda x, y: np.exp(1j * k * (d[0] * x + d[1] * y))
+    g = lambda x, y, nx, ny: 1j * k * (d[0] * nx + d[1] * ny - 1.0) * u(x, y)
+    A = asm.assemble(k, [1.0], n)
+    b = asm.impedance_load(n, g)
+    uh = spla.spsolve(A.tocsc(), b)
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    e = uh - u(X, Y).ravel()
+    M = asm.mass_matrix(n)
+    return np.sqrt(abs(np.vdot(e, M @ e)))
+
+
+@pytest.mark.slow
+def test_plane_wave_converges_second_order():
+    # u = exp(i k d.x) solves eq. (1a) with f = 0 and du/dn - i k u = i k (d.n - 1) u
+    k = 10.0
+    ns = [33, 65, 129, 257]
+    errs = [_plane_wave_error(n, k) for n in ns]
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert orders[-1] > 1.9 and orders[-1] < 2.1, orders
+    assert all(o > 1.7 for o in orders), orders
