@@ -1,0 +1,219 @@
+/*
+ * hh.h -- C ABI of the MI355X multipreconditioned sweeping Helmholtz solver.
+ *
+ * Solves the impedance Helmholtz problem of Bootland & Rees (arXiv 2408.11929),
+ * eq. (1):  Delta u + k^2 u = f in (0,1)^2,  du/dn - i k u = 0 on the boundary,
+ * k = omega / c, discretised with continuous P1 triangles, by selective
+ * multipreconditioned GMRES (Sec. 3) whose preconditioners are directional
+ * double sweeps over overlapping strips with zeroth-order Robin transmission
+ * (Sec. 2, eqs. (2)-(4)); the x sweep is "LRL", the y sweep "BTB" (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: n x n nodes at (i h, j h), h = 1/(n-1); node index p = j*n + i.
+ *   - Complex numbers are interleaved (re, im) pairs: hh_c128 is two doubles,
+ *     layout-compatible with C99 double _Complex and numpy/torch complex128.
+ *   - "device pointer" means memory allocated on the current HIP device
+ *     (hipMalloc or any allocator over it); "host pointer" means ordinary
+ *     CPU memory.  Arrays are only read or written during the call unless an
+ *     entry point says otherwise; the library keeps no reference to them.
+ *   - Every call returns an int status: HH_OK (0), HH_PENDING (1), or a
+ *     negative error code.  hh_last_error() returns a message for the last
+ *     failing call of the calling thread.  On error, output arrays may be
+ *     partially written; handles stay valid.
+ *   - All work runs on the library's own HIP streams (default priority) and
+ *     every call is synchronous with respect to the host unless it says
+ *     otherwise.  One problem handle must not be used from two threads at
+ *     once; different handles may.
+ */
+#ifndef HH_H
+#define HH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HH_OK 0
+#define HH_PENDING 1
+#define HH_EINVAL (-1)     /* invalid argument or state                      */
+#define HH_ENOMEM (-2)     /* device memory allocation failed                */
+#define HH_ESINGULAR (-3)  /* zero pivot in a strip factorisation            */
+#define HH_ENOCONV (-4)    /* MPGMRES hit maxit before reaching the tolerance */
+#define HH_EDEVICE (-5)    /* HIP runtime error                              */
+#define HH_EBUDGET (-6)    /* request can never fit the server's HBM budget  */
+
+#define HH_DIR_X 1u        /* LRL: strips in x, swept left to right and back  */
+#define HH_DIR_Y 2u        /* BTB: strips in y, swept bottom to top and back  */
+
+#define HH_FP64 0          /* strip factors and sweeps in complex128          */
+#define HH_FP32 1          /* strip factors and sweeps in complex64           */
+
+typedef struct {
+  double re, im;
+} hh_c128;
+
+typedef struct hh_problem hh_problem;
+
+/* Per right-hand-side result of hh_mpgmres. */
+typedef struct {
+  int iterations;        /* outer MPGMRES iterations (each applies all t sweeps) */
+  int converged;         /* 1 if the least-squares residual reached tol           */
+  double res_est;        /* least-squares residual estimate, relative to ||b||    */
+  double res_true;       /* ||b - A x||_2 / ||b||_2 recomputed in FP64             */
+  int basis_size;        /* number of orthonormal basis vectors built              */
+  int deflated;          /* Z columns whose A z added no new basis direction       */
+} hh_stats;
+
+/* ---- assembly: eq. (1) ------------------------------------------------------
+ * Builds the P1 operator A = K - M_{k^2} - i M_{Gamma,k} of eq. (1) on the
+ * n x n grid and keeps it on the device (four upper diagonals of the complex
+ * symmetric matrix, complex128).  The wave speed c is piecewise constant on
+ * nlayers equal horizontal layers (layer 0 at the bottom); the wave number of a
+ * triangle is omega / c at its centroid, that of a boundary edge omega / c at
+ * its midpoint, with the layer of a height y = P / (6(n-1)) computed in exact
+ * integer arithmetic as min(floor(P nlayers / (6(n-1))), nlayers - 1).
+ *   omega      angular frequency (> 0, finite); with c = 1, k = omega
+ *   nlayers    >= 1;  c_layers: host pointer, nlayers positive finite speeds
+ *   n          nodes per side, 3 <= n <= 8193
+ *   out        receives a new problem handle (free with hh_free)
+ * Errors: HH_EINVAL for bad arguments, HH_ENOMEM, HH_EDEVICE. */
+int hh_assemble(double omega, int nlayers, const double* c_layers, int n, hh_problem** out);
+
+/* Right-hand side of eq. (1) for nodal sources: b = -M f (P1 mass matrix M),
+ * impedance data g = 0.  f and b are device pointers to nvec x n*n hh_c128
+ * (vector v at offset v*n*n); f and b must not overlap. */
+int hh_load_vector(hh_problem* pb, int nvec, const hh_c128* f, hh_c128* b);
+
+/* ---- strip factorisation: Sec. 2 (Fig. 1) and Sec. 4 setup -----------------
+ * Decomposes the square into nstrips overlapping strips per selected
+ * direction (one extra mesh line per internal boundary, overlap 2h) and
+ * factors every strip matrix (P1 operator of the strip with the impedance
+ * operator of eq. (4) on its artificial sides) by band LU with partial
+ * pivoting, all strips of all directions in one launch.  Replaces any
+ * previous factorisation of the handle.
+ *   dirs       HH_DIR_X, HH_DIR_Y or both; with both, the preconditioner order
+ *              is M_1 = LRL, M_2 = BTB (the ordered combination of Sec. 4)
+ *   nstrips    N >= 1 with (n-1) % N == 0 and (n-1)/N >= 2 when N > 1
+ *   precision  HH_FP64 or HH_FP32 (factors, transmission data and sweeps)
+ * Errors: HH_EINVAL, HH_ENOMEM, HH_ESINGULAR (exactly zero pivot; the message
+ * names the strip), HH_EDEVICE. */
+int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision);
+
+/* ---- preconditioner application: eqs. (2)-(4) -------------------------------
+ * z = M_dir^{-1} r for nvec vectors: forward sweep over strips 1..N, backward
+ * sweep over N-1..1, 2N-1 strip solves, overlap values from the most recent
+ * solve.  r, z: device pointers, nvec x n*n hh_c128 (non-overlapping).  With
+ * HH_FP32 factors, r is rounded to complex64 and z holds the complex64 result
+ * exactly.  dir is HH_DIR_X or HH_DIR_Y (must have been factored). */
+int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_c128* z);
+
+/* One strip solve x = A_s^{-1} rhs with the stored factors (strip s is
+ * 1-based, vectors in the strip's local order q = long*w + short, where w is
+ * the strip width in mesh lines).  rhs, x: device pointers of
+ * n*w hh_c128 each.  Test hook for the factorisation. */
+int hh_strip_solve(hh_problem* pb, unsigned dir, int s, const hh_c128* rhs, hh_c128* x);
+
+/* Geometry of strip s (1-based): first node line a, width w (node lines),
+ * band half-width kl. Host pointers; any may be NULL. */
+int hh_strip_info(const hh_problem* pb, unsigned dir, int s, int* a, int* w, int* kl);
+
+/* ---- operator products ------------------------------------------------------
+ * y = A x for nvec vectors (device pointers, nvec x n*n, non-overlapping). */
+int hh_spmv(hh_problem* pb, int nvec, const hh_c128* x, hh_c128* y);
+
+/* Copies the assembled operator to host memory: diag is 4 x n*n hh_c128 with
+ * rows A[p][p], A[p][p+1], A[p][p+n], A[p][p+n+1] (zero where the neighbour
+ * does not exist); the lower part follows from A = A^T. */
+int hh_get_operator(const hh_problem* pb, hh_c128* diag);
+
+/* ---- selective MPGMRES: Sec. 3 with the selection rule of Sec. 4 -----------
+ * Solves A x = b for nrhs independent right-hand sides that share the
+ * factored sweeps (one MPGMRES per RHS, batched on the device).  x0 = 0, no
+ * restart; iteration k applies every factored sweep once (the t = 2 cross
+ * rule: LRL is applied to the basis vector that came from BTB's column and
+ * vice versa; t = 1 is right-preconditioned GMRES).  The new block is
+ * orthogonalised by two passes of block classical Gram-Schmidt and a
+ * reorthogonalised modified Gram-Schmidt inside the block; the small least
+ * squares problem is solved on the host in FP64.  Stops when the
+ * least-squares residual is <= tol ||b||_2.  SpMV, Gram-Schmidt, least
+ * squares and the final residual check are FP64 whatever the strip precision.
+ *   b, x       device pointers, nrhs x n*n hh_c128 (x is overwritten)
+ *   tol        > 0;  maxit >= 1
+ *   stats      host pointer to nrhs hh_stats (may be NULL)
+ * Returns HH_ENOCONV (x and stats still filled) if any RHS did not converge. */
+int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit,
+               hh_c128* x, hh_stats* stats);
+
+/* Releases the handle and all its device memory.  NULL is accepted. */
+int hh_free(hh_problem* pb);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hh_last_error(void);
+
+/* ---- timing of the library's kernels ------------------------------------------
+ * When enabled, every launch of the named kernel family is bracketed by HIP
+ * events on the stream it runs on; hh_timing_get returns the number of
+ * launches, their summed duration (ms) and the summed algorithmic bytes they
+ * were charged (see the kernel's documentation) since the last reset.
+ * Families: "sweep", "spmv", "factor", "orth", "assemble".
+ * Timing adds an event query per launch; leave it off outside measurements. */
+int hh_timing_enable(int on);
+int hh_timing_reset(void);
+int hh_timing_get(const char* family, long long* launches, double* total_ms, double* bytes);
+
+/* ---- serving: continuous batching of solve requests ---------------------------
+ * A server owns a scheduler thread that admits requests in arrival order
+ * when their device footprint (operator, strip factors, Krylov workspace for
+ * maxit iterations) fits the HBM budget, assembles and factors them, and
+ * advances every admitted solve by one MPGMRES iteration per tick with
+ * batched launches that mix requests of different sizes.  Results do not
+ * depend on what else is in flight. */
+typedef struct hh_server hh_server;
+
+typedef struct {
+  int n;                    /* nodes per side                                 */
+  double omega;             /* angular frequency                              */
+  int nlayers;              /* layer count                                    */
+  const double* c_layers;   /* host pointer, copied at submit                 */
+  int nsrc;                 /* right-hand sides in this request               */
+  const hh_c128* f;         /* device pointer, nsrc x n*n nodal sources; read
+                               until the request completes                   */
+  hh_c128* x;               /* device pointer, nsrc x n*n solutions; written
+                               before hh_poll reports completion             */
+  int nstrips;              /* strips per direction                           */
+  unsigned dirs;            /* HH_DIR_X | HH_DIR_Y                             */
+  int precision;            /* HH_FP64 or HH_FP32                             */
+  double tol;
+  int maxit;
+} hh_request;
+
+typedef struct {
+  int status;               /* HH_OK, HH_ENOCONV, or another error code       */
+  int iterations_max;       /* largest iteration count over the request's RHS */
+  double res_true_max;      /* largest FP64 relative residual over its RHS    */
+  double t_submit;          /* seconds on the server clock                    */
+  double t_admit;
+  double t_done;
+} hh_result;
+
+/* hbm_budget: bytes of device memory the server may hold for requests;
+ * max_active: cap on concurrently admitted requests (>= 1). */
+int hh_server_create(size_t hbm_budget, int max_active, hh_server** out);
+/* Thread-safe; never waits for the GPU.  HH_EBUDGET if the request alone
+ * exceeds the budget, HH_EINVAL for invalid fields. */
+int hh_submit(hh_server* srv, const hh_request* req, uint64_t* ticket);
+/* HH_PENDING while the request is queued or running; otherwise fills res and
+ * returns HH_OK (the ticket is then retired). */
+int hh_poll(hh_server* srv, uint64_t ticket, hh_result* res);
+/* Seconds on the server clock (the clock of hh_result's time stamps). */
+double hh_server_clock(const hh_server* srv);
+/* Waits for all requests, stops the scheduler, frees the server. */
+int hh_server_destroy(hh_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H */

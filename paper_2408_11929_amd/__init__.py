@@ -1,0 +1,203 @@
+"""MI355X-native multipreconditioned sweeping solver for 2D Helmholtz problems.
+
+Python binding of the C ABI in ``include/hh.h`` (Bootland & Rees, arXiv
+2408.11929: selective MPGMRES over directional double-sweep preconditioners
+for the impedance Helmholtz problem, discretised with P1 triangles).  The
+functions carry the C names; vectors are torch tensors on the GPU
+(complex128, contiguous) whose device pointers are handed to the library.
+Nothing here computes: it marshals arguments and raises on error codes.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (HH_DIR_X, HH_DIR_Y, HH_EBUDGET, HH_EDEVICE, HH_EINVAL, HH_ENOCONV,
+                   HH_ENOMEM, HH_ESINGULAR, HH_FP32, HH_FP64, HH_OK, HH_PENDING, HHError)
+
+_L = None
+
+
+def lib():
+    """The loaded libhh.so (raises ImportError if it has not been built)."""
+    global _L
+    if _L is None:
+        _L = _lib.load()
+    return _L
+
+
+def _check(rc, allowed=(HH_OK,)):
+    if rc not in allowed:
+        raise HHError(rc, lib().hh_last_error().decode(errors="replace"))
+    return rc
+
+
+def _dev(t, what="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a torch tensor on the GPU")
+    if t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError(f"{what} must be contiguous complex128")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _empty_like_vecs(nvec, nn, device):
+    import torch
+    return torch.empty((nvec, nn), dtype=torch.complex128, device=device)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+class Problem:
+    """Handle of an assembled problem (``hh_problem``)."""
+
+    def __init__(self, omega, c_layers, n):
+        c = np.ascontiguousarray(np.asarray(c_layers, dtype=np.float64).ravel())
+        h = ctypes.c_void_p()
+        _check(lib().hh_assemble(float(omega), len(c),
+                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n),
+                                 ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.omega = float(omega)
+        self.c_layers = c
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("problem has been freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib().hh_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- assembly
+    def load_vector(self, f, b=None):
+        nvec = f.shape[0] if f.dim() == 2 else 1
+        if b is None:
+            b = _empty_like_vecs(nvec, self.n * self.n, f.device).reshape(f.shape)
+        _sync()
+        _check(lib().hh_load_vector(self.handle, nvec, _dev(f, "f"), _dev(b, "b")))
+        return b
+
+    def get_operator(self):
+        out = np.zeros((4, self.n * self.n), dtype=np.complex128)
+        _check(lib().hh_get_operator(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    # -- strips
+    def factor_sweeps(self, dirs=HH_DIR_X | HH_DIR_Y, nstrips=4, precision=HH_FP64):
+        _check(lib().hh_factor_sweeps(self.handle, int(dirs), int(nstrips), int(precision)))
+        self.dirs, self.nstrips, self.precision = int(dirs), int(nstrips), int(precision)
+
+    def strip_info(self, direction, s):
+        a, w, kl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().hh_strip_info(self.handle, int(direction), int(s), ctypes.byref(a),
+                                   ctypes.byref(w), ctypes.byref(kl)))
+        return a.value, w.value, kl.value
+
+    def strip_solve(self, direction, s, rhs, x=None):
+        if x is None:
+            x = rhs.new_empty(rhs.shape)
+        _sync()
+        _check(lib().hh_strip_solve(self.handle, int(direction), int(s), _dev(rhs, "rhs"),
+                                    _dev(x, "x")))
+        return x
+
+    def sweep_apply(self, direction, r, z=None):
+        nvec = r.shape[0] if r.dim() == 2 else 1
+        if z is None:
+            z = r.new_empty(r.shape)
+        _sync()
+        _check(lib().hh_sweep_apply(self.handle, int(direction), nvec, _dev(r, "r"), _dev(z, "z")))
+        return z
+
+    # -- operator and solver
+    def spmv(self, x, y=None):
+        nvec = x.shape[0] if x.dim() == 2 else 1
+        if y is None:
+            y = x.new_empty(x.shape)
+        _sync()
+        _check(lib().hh_spmv(self.handle, nvec, _dev(x, "x"), _dev(y, "y")))
+        return y
+
+    def mpgmres(self, b, tol=1e-6, maxit=200, x=None):
+        """Returns (x, stats, rc) with stats a list of dicts, rc HH_OK or HH_ENOCONV."""
+        nrhs = b.shape[0] if b.dim() == 2 else 1
+        if x is None:
+            x = b.new_empty(b.shape)
+        st = (_lib.hh_stats * nrhs)()
+        _sync()
+        rc = _check(lib().hh_mpgmres(self.handle, nrhs, _dev(b, "b"), float(tol), int(maxit),
+                                     _dev(x, "x"), st), allowed=(HH_OK, HH_ENOCONV))
+        stats = [{k: getattr(s, k) for k, _ in _lib.hh_stats._fields_} for s in st]
+        return x, stats, rc
+
+
+# C-named entry points
+def hh_assemble(omega, c_layers, n):
+    return Problem(omega, c_layers, n)
+
+
+def hh_load_vector(pb, f, b=None):
+    return pb.load_vector(f, b)
+
+
+def hh_factor_sweeps(pb, dirs, nstrips, precision):
+    return pb.factor_sweeps(dirs, nstrips, precision)
+
+
+def hh_sweep_apply(pb, direction, r, z=None):
+    return pb.sweep_apply(direction, r, z)
+
+
+def hh_strip_solve(pb, direction, s, rhs, x=None):
+    return pb.strip_solve(direction, s, rhs, x)
+
+
+def hh_strip_info(pb, direction, s):
+    return pb.strip_info(direction, s)
+
+
+def hh_spmv(pb, x, y=None):
+    return pb.spmv(x, y)
+
+
+def hh_get_operator(pb):
+    return pb.get_operator()
+
+
+def hh_mpgmres(pb, b, tol=1e-6, maxit=200, x=None):
+    return pb.mpgmres(b, tol, maxit, x)
+
+
+def hh_free(pb):
+    pb.free()
+
+
+def hh_timing_enable(on=True):
+    _check(lib().hh_timing_enable(1 if on else 0))
+
+
+def hh_timing_reset():
+    _check(lib().hh_timing_reset())
+
+
+def hh_timing_get(family):
+    n, ms, by = ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().hh_timing_get(family.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return {"launches": n.value, "ms": ms.value, "bytes": by.value}
+
+
+from .serving import Server, hh_server_create  # noqa: E402,F401

@@ -1,0 +1,640 @@
+// Batched selective MPGMRES (Sec. 3) with the Sec. 4 selection rule.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+namespace hh {
+
+// ------------------------------------------------------------ least squares
+void LeastSquares::init(double beta) {
+  R_.clear();
+  piv_.clear();
+  rots_.clear();
+  g_.assign(1, zd(beta, 0.0));
+  rank_ = 0;
+}
+
+void LeastSquares::add_rows(int count) { g_.resize(g_.size() + count, zd(0.0, 0.0)); }
+
+void LeastSquares::add_column(std::vector<zd> h) {
+  h.resize(g_.size(), zd(0.0, 0.0));
+  double nrm = 0;
+  for (auto& v : h) nrm += std::norm(v);
+  nrm = std::sqrt(nrm);
+  for (const Rot& r : rots_) {
+    zd a = h[r.i], b = h[r.k];
+    h[r.i] = r.c * a + r.s * b;
+    h[r.k] = -std::conj(r.s) * a + r.c * b;
+  }
+  const int pr = rank_;
+  for (int row = pr + 1; row < (int)h.size(); ++row) {
+    zd a = h[pr], b = h[row];
+    if (b == zd(0.0, 0.0)) continue;
+    Rot r;
+    r.i = pr;
+    r.k = row;
+    double aa = std::abs(a), bb = std::abs(b);
+    double rho = std::hypot(aa, bb);
+    if (aa == 0.0) {
+      r.c = 0.0;
+      r.s = zd(1.0, 0.0);
+    } else {
+      r.c = aa / rho;
+      r.s = (a / aa) * std::conj(b) / rho;
+    }
+    h[pr] = r.c * a + r.s * b;
+    h[row] = zd(0.0, 0.0);
+    zd ga = g_[pr], gb = g_[row];
+    g_[pr] = r.c * ga + r.s * gb;
+    g_[row] = -std::conj(r.s) * ga + r.c * gb;
+    rots_.push_back(r);
+  }
+  if (pr < (int)h.size() && std::abs(h[pr]) > 1e-14 * nrm && nrm > 0) {
+    piv_.push_back(pr);
+    ++rank_;
+  } else {
+    piv_.push_back(-1);
+  }
+  R_.push_back(std::move(h));
+}
+
+double LeastSquares::residual() const {
+  double s = 0;
+  for (int i = rank_; i < (int)g_.size(); ++i) s += std::norm(g_[i]);
+  return std::sqrt(s);
+}
+
+std::vector<zd> LeastSquares::solve() const {
+  const int nc = (int)R_.size();
+  std::vector<zd> y(nc, zd(0.0, 0.0));
+  for (int j = nc - 1; j >= 0; --j) {
+    const int pr = piv_[j];
+    if (pr < 0) continue;
+    zd acc = g_[pr];
+    for (int jj = j + 1; jj < nc; ++jj)
+      if (piv_[jj] >= 0) acc -= R_[jj][pr] * y[jj];
+    y[j] = acc / R_[j][pr];
+  }
+  return y;
+}
+
+// ------------------------------------------------------------ layout
+HdLayout::HdLayout(int m, int t) {
+  size_t o = 0;
+  g1 = o;
+  o += (size_t)(m + t) * t;
+  g2 = o;
+  o += (size_t)m * t;
+  r1 = o;
+  o += (size_t)t * t;
+  r2 = o;
+  o += (size_t)t * t;
+  rd = o;
+  o += t;
+  nr = o;
+  o += t;
+  total = o;
+}
+
+namespace {
+size_t esz_of(int prec) { return prec == HH_FP64 ? sizeof(c128) : sizeof(c64); }
+int nblk_for(long long len) {
+  long long b = (len + 4095) / 4096;
+  return (int)std::max(1LL, std::min(b, 256LL));
+}
+}  // namespace
+
+Engine::Engine(hipStream_t st) : st_(st) {}
+Engine::~Engine() {
+  if (task_dev_) dev_free(task_dev_);
+}
+
+template <class TT>
+TT* Engine::stage(const std::vector<TT>& v, size_t& off) {
+  size_t bytes = (v.size() * sizeof(TT) + 255) & ~size_t(255);
+  if (task_host_.size() < off + bytes) task_host_.resize((off + bytes) * 2);
+  std::memcpy(task_host_.data() + off, v.data(), v.size() * sizeof(TT));
+  TT* d = reinterpret_cast<TT*>(off);  // resolved in upload()
+  off += bytes;
+  return d;
+}
+
+// Copies the staged host descriptors to the device in one transfer.
+void Engine::upload() {
+  if (task_host_.size() < staged_) task_host_.resize(staged_);
+  if (staged_ > task_cap_) {
+    HH_HIP(hipStreamSynchronize(st_));
+    if (task_dev_) dev_free(task_dev_);
+    task_cap_ = staged_ * 2;
+    task_dev_ = dev_alloc(task_cap_);
+  }
+  if (staged_) HH_HIP(hipMemcpyAsync(task_dev_, task_host_.data(), staged_, hipMemcpyHostToDevice, st_));
+}
+
+#define DEV(ptr) reinterpret_cast<std::remove_reference_t<decltype(ptr)>>((char*)task_dev_ + (size_t)(ptr))
+
+size_t Engine::footprint(const hh_problem* pb, int t, int prec, int maxit) {
+  const long long len = (long long)pb->n * pb->n;
+  const int cols = 1 + (maxit + 1) * t;
+  size_t b = (size_t)len * cols * sizeof(c128);                  // V
+  b += (size_t)len * (size_t)maxit * t * esz_of(prec);           // Z
+  HdLayout L(cols, t);
+  b += L.total * sizeof(c128);
+  b += (size_t)nblk_for(len) * (cols + t) * t * sizeof(c128);    // partial sums
+  b += (size_t)t * (pb->fs.max_ns + (size_t)pb->fs.N * pb->n) * esz_of(prec);
+  b += (size_t)cols * t * sizeof(c128);
+  return b;
+}
+
+void Engine::release(Solve* s) {
+  dev_free(s->V);
+  dev_free(s->Z);
+  dev_free(s->Hd);
+  dev_free(s->part);
+  dev_free(s->flags);
+  dev_free(s->rho);
+  dev_free(s->g1);
+  dev_free(s->ydev);
+  s->V = nullptr;
+  s->Z = nullptr;
+  s->Hd = nullptr;
+  s->part = nullptr;
+  s->flags = nullptr;
+  s->rho = s->g1 = nullptr;
+  s->ydev = nullptr;
+}
+
+// Grows V, Z and the coefficient scratch so that the next iteration fits.
+void Engine::ensure_capacity(Solve* s) {
+  const int t = s->t;
+  const size_t es = esz_of(s->prec);
+  const int need_v = s->m + t, need_z = (s->k + 1) * t;
+  if (need_v > s->vcap || need_z > s->zcap) {
+    int it_cap = std::max(16, 2 * (s->k + 1));
+    it_cap = std::min(it_cap, s->maxit);
+    it_cap = std::max(it_cap, s->k + 1);
+    int vcap = 1 + it_cap * t, zcap = it_cap * t;
+    c128* V = (c128*)dev_alloc((size_t)s->len * vcap * sizeof(c128));
+    void* Z = dev_alloc((size_t)s->len * zcap * es);
+    if (s->V) {
+      HH_HIP(hipMemcpyAsync(V, s->V, (size_t)s->len * s->m * sizeof(c128), hipMemcpyDeviceToDevice, st_));
+      HH_HIP(hipMemcpyAsync(Z, s->Z, (size_t)s->len * s->k * t * es, hipMemcpyDeviceToDevice, st_));
+      HH_HIP(hipStreamSynchronize(st_));
+      dev_free(s->V);
+      dev_free(s->Z);
+    }
+    s->V = V;
+    s->Z = Z;
+    s->vcap = vcap;
+    s->zcap = zcap;
+  }
+  if (s->m + t > s->hcap || !s->Hd) {
+    if (s->Hd) dev_free(s->Hd);
+    if (s->part) dev_free(s->part);
+    if (s->ydev) dev_free(s->ydev);
+    s->hcap = s->vcap;
+    HdLayout L(s->hcap, t);
+    s->Hd = (c128*)dev_alloc(L.total * sizeof(c128));
+    s->part_elems = (size_t)nblk_for(s->len) * (s->hcap + t) * t;
+    s->part = (c128*)dev_alloc(s->part_elems * sizeof(c128));
+    s->ydev = (c128*)dev_alloc((size_t)s->zcap * sizeof(c128) + 256);
+  }
+}
+
+// ------------------------------------------------------------ begin
+void Engine::begin(std::vector<Solve*>& solves) {
+  std::vector<Solve*> live;
+  for (Solve* s : solves) {
+    s->k = 0;
+    s->m = 1;
+    s->done = s->converged = s->breakdown = false;
+    s->deflated = 0;
+    const FactorSet& fs = s->pb->fs;
+    s->t = fs.nd;
+    s->prec = fs.precision;
+    const size_t es = esz_of(s->prec);
+    ensure_capacity(s);
+    if (!s->flags) s->flags = (int*)dev_alloc(4 * sizeof(int));
+    if (!s->rho) s->rho = dev_alloc((size_t)s->t * fs.max_ns * es + 256);
+    if (!s->g1) s->g1 = dev_alloc((size_t)s->t * fs.N * s->pb->n * es + 256);
+    HH_HIP(hipMemcpyAsync(s->V, s->b, (size_t)s->len * sizeof(c128), hipMemcpyDeviceToDevice, st_));
+    live.push_back(s);
+  }
+  if (live.empty()) return;
+  // beta^2 = b^H b into NR slot 0, then v1 = b / beta
+  staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
+  std::vector<GramTask> gt;
+  std::vector<NormTask> nt;
+  long long maxlen = 0;
+  int maxblk = 1;
+  for (Solve* s : live) {
+    HdLayout L(s->hcap, s->t);
+    GramTask g{};
+    g.X = s->V;
+    g.Y = s->V;
+    g.out = s->Hd + L.nr;
+    g.part = s->part;
+    g.len = s->len;
+    g.ldx = g.ldy = s->len;
+    g.ldo = 1;
+    g.px = 1;
+    g.ty = 1;
+    g.nblk = nblk_for(s->len);
+    g.accumulate = 0;
+    gt.push_back(g);
+    NormTask q{};
+    q.y = s->V;
+    q.nrm2 = s->Hd + L.nr;
+    q.ref2 = s->Hd + L.nr;
+    q.rdiag = s->Hd + L.rd;
+    q.flag = s->flags;
+    q.len = s->len;
+    q.tol = 0.0;
+    nt.push_back(q);
+    maxlen = std::max(maxlen, s->len);
+    maxblk = std::max(maxblk, g.nblk);
+  }
+  GramTask* dg = stage(gt, staged_);
+  NormTask* dn = stage(nt, staged_);
+  upload();
+  launch_gram(DEV(dg), (int)gt.size(), maxblk, 1, 1, st_);
+  launch_normalize(DEV(dn), (int)nt.size(), maxlen, st_);
+  for (Solve* s : live) {
+    HdLayout L(s->hcap, s->t);
+    zd v;
+    HH_HIP(hipMemcpyAsync(&v, s->Hd + L.rd, sizeof(zd), hipMemcpyDeviceToHost, st_));
+    HH_HIP(hipStreamSynchronize(st_));
+    s->beta = v.real();
+  }
+  for (Solve* s : live) {
+    s->ls.init(s->beta);
+    for (int i = 0; i < s->t; ++i) s->inputs[i] = 0;
+    s->res_est = 1.0;
+    if (s->beta == 0.0) {
+      s->done = true;
+      s->converged = true;
+      s->res_est = 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------ step
+void Engine::step(std::vector<Solve*>& solves) {
+  std::vector<Solve*> live;
+  for (Solve* s : solves)
+    if (!s->done) live.push_back(s);
+  if (live.empty()) return;
+  for (Solve* s : live) ensure_capacity(s);
+  staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
+
+  // 1. sweeps: every preconditioner of every solve; grouped by precision and band class
+  struct Group {
+    std::vector<SweepTask> tasks;
+    int klmax = 0;
+  };
+  Group grp[2][2];  // [precision][wide band]
+  for (Solve* s : live) {
+    const FactorSet& fs = s->pb->fs;
+    const size_t es = esz_of(s->prec);
+    for (int i = 0; i < s->t; ++i) {
+      SweepTask tk{};
+      tk.strips = fs.d_strips + (size_t)i * fs.N;
+      tk.band = fs.band;
+      tk.piv = fs.piv;
+      tk.tr = fs.tr;
+      tk.r = s->V + (size_t)s->inputs[i] * s->len;
+      tk.z = (char*)s->Z + ((size_t)s->k * s->t + i) * s->len * es;
+      tk.rho = (char*)s->rho + (size_t)i * fs.max_ns * es;
+      tk.g1 = (char*)s->g1 + (size_t)i * fs.N * s->pb->n * es;
+      tk.n = s->pb->n;
+      tk.N = fs.N;
+      const int wide = 2 * fs.max_kl + 1 > 64 ? 1 : 0;
+      Group& G = grp[s->prec == HH_FP64 ? 0 : 1][wide];
+      G.tasks.push_back(tk);
+      G.klmax = std::max(G.klmax, fs.max_kl);
+    }
+  }
+  SweepTask* dsw[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) dsw[a][b] = grp[a][b].tasks.empty() ? nullptr : stage(grp[a][b].tasks, staged_);
+
+  // 2. SpMV: W = A Z_k into the basis slots m..m+t-1
+  std::vector<SpmvTask> sp[2];
+  long long maxlen = 0;
+  for (Solve* s : live) {
+    SpmvTask tk{};
+    tk.A = s->pb->d_A;
+    tk.x = (char*)s->Z + (size_t)s->k * s->t * s->len * esz_of(s->prec);
+    tk.y = s->V + (size_t)s->m * s->len;
+    tk.n = s->pb->n;
+    tk.nvec = s->t;
+    sp[s->prec == HH_FP64 ? 0 : 1].push_back(tk);
+    maxlen = std::max(maxlen, s->len);
+  }
+  SpmvTask* dsp[2];
+  for (int a = 0; a < 2; ++a) dsp[a] = sp[a].empty() ? nullptr : stage(sp[a], staged_);
+
+  // 3-6. two passes of block CGS against the basis
+  std::vector<GramTask> g1, g2;
+  std::vector<UpdTask> u1, u2;
+  int maxblk = 1, maxpx = 1, maxt = 1;
+  for (Solve* s : live) {
+    HdLayout L(s->hcap, s->t);
+    const int m = s->m, t = s->t;
+    c128* W = s->V + (size_t)m * s->len;
+    GramTask g{};
+    g.X = s->V;
+    g.Y = W;
+    g.out = s->Hd + L.g1;
+    g.part = s->part;
+    g.len = s->len;
+    g.ldx = g.ldy = s->len;
+    g.ldo = m + t;
+    g.px = m + t;
+    g.ty = t;
+    g.nblk = nblk_for(s->len);
+    g.accumulate = 0;
+    g1.push_back(g);
+    g.px = m;
+    g.ldo = m;
+    g.out = s->Hd + L.g2;
+    g2.push_back(g);
+    UpdTask u{};
+    u.X = s->V;
+    u.Y = W;
+    u.C = s->Hd + L.g1;
+    u.len = s->len;
+    u.ldx = u.ldy = s->len;
+    u.ldc = m + t;
+    u.px = m;
+    u.ty = t;
+    u1.push_back(u);
+    u.C = s->Hd + L.g2;
+    u.ldc = m;
+    u2.push_back(u);
+    maxblk = std::max(maxblk, g.nblk);
+    maxpx = std::max(maxpx, m + t);
+    maxt = std::max(maxt, t);
+  }
+  GramTask* dg1 = stage(g1, staged_);
+  UpdTask* du1 = stage(u1, staged_);
+  GramTask* dg2 = stage(g2, staged_);
+  UpdTask* du2 = stage(u2, staged_);
+
+  // 7. modified Gram-Schmidt inside the block, two passes, then normalisation
+  std::vector<std::vector<GramTask>> mg(4 * 3);
+  std::vector<std::vector<UpdTask>> mu(4 * 2);
+  std::vector<std::vector<NormTask>> mn(4);
+  for (Solve* s : live) {
+    HdLayout L(s->hcap, s->t);
+    const int m = s->m, t = s->t;
+    c128* W = s->V + (size_t)m * s->len;
+    for (int c = 0; c < t; ++c) {
+      c128* wc = W + (size_t)c * s->len;
+      for (int pass = 0; pass < 2 && c > 0; ++pass) {
+        GramTask g{};
+        g.X = W;
+        g.Y = wc;
+        g.out = s->Hd + (pass == 0 ? L.r1 : L.r2) + (size_t)c * t;
+        g.part = s->part;
+        g.len = s->len;
+        g.ldx = g.ldy = s->len;
+        g.ldo = t;
+        g.px = c;
+        g.ty = 1;
+        g.nblk = nblk_for(s->len);
+        mg[c * 3 + pass].push_back(g);
+        UpdTask u{};
+        u.X = W;
+        u.Y = wc;
+        u.C = g.out;
+        u.len = s->len;
+        u.ldx = u.ldy = s->len;
+        u.ldc = t;
+        u.px = c;
+        u.ty = 1;
+        mu[c * 2 + pass].push_back(u);
+      }
+      GramTask g{};
+      g.X = wc;
+      g.Y = wc;
+      g.out = s->Hd + L.nr + c;
+      g.part = s->part;
+      g.len = s->len;
+      g.ldx = g.ldy = s->len;
+      g.ldo = 1;
+      g.px = 1;
+      g.ty = 1;
+      g.nblk = nblk_for(s->len);
+      mg[c * 3 + 2].push_back(g);
+      NormTask q{};
+      q.y = wc;
+      q.nrm2 = s->Hd + L.nr + c;
+      q.ref2 = s->Hd + L.g1 + (size_t)(m + c) + (size_t)c * (m + t);  // ||A z_c||^2
+      q.rdiag = s->Hd + L.rd + c;
+      q.flag = s->flags + c;
+      q.len = s->len;
+      q.tol = 1e-12;
+      mn[c].push_back(q);
+    }
+  }
+  std::vector<GramTask*> dmg(mg.size(), nullptr);
+  std::vector<UpdTask*> dmu(mu.size(), nullptr);
+  std::vector<NormTask*> dmn(mn.size(), nullptr);
+  for (size_t i = 0; i < mg.size(); ++i)
+    if (!mg[i].empty()) dmg[i] = stage(mg[i], staged_);
+  for (size_t i = 0; i < mu.size(); ++i)
+    if (!mu[i].empty()) dmu[i] = stage(mu[i], staged_);
+  for (size_t i = 0; i < mn.size(); ++i)
+    if (!mn[i].empty()) dmn[i] = stage(mn[i], staged_);
+  upload();
+
+  // ---- launches
+  {
+    // algorithmic bytes: each (problem, direction) factor read once per strip
+    // solve of the launch, plus FP64 input and sweep-precision output per task
+    double bytes = 0;
+    std::vector<const hh_problem*> seen;
+    for (Solve* s : live) {
+      const FactorSet& fs = s->pb->fs;
+      const size_t es = esz_of(s->prec);
+      const bool first = std::find(seen.begin(), seen.end(), s->pb) == seen.end();
+      if (first) seen.push_back(s->pb);
+      for (int i = 0; i < s->t; ++i)
+        for (int q = 0; q < fs.N; ++q) {
+          const StripDesc& sd = fs.strips[(size_t)i * fs.N + q];
+          const double solves = q == fs.N - 1 ? 1.0 : 2.0;
+          if (first) bytes += solves * (double)sd.ns * sd.ldab * es;
+          bytes += solves * (double)sd.ns * (sizeof(c128) + es);
+        }
+    }
+    TimedRegion tr(FAM_SWEEP, st_, bytes);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        if (dsw[a][b])
+          launch_sweep(DEV(dsw[a][b]), (int)grp[a][b].tasks.size(), a == 0 ? HH_FP64 : HH_FP32,
+                       grp[a][b].klmax, st_);
+  }
+  {
+    double bytes = 0;
+    for (Solve* s : live) bytes += (double)s->len * (64.0 + s->t * (esz_of(s->prec) + 16.0));
+    TimedRegion tr(FAM_SPMV, st_, bytes);
+    for (int a = 0; a < 2; ++a)
+      if (dsp[a]) launch_spmv(DEV(dsp[a]), (int)sp[a].size(), maxlen, a == 0 ? HH_FP64 : HH_FP32, st_);
+  }
+  {
+    double bytes = 0;
+    for (Solve* s : live) bytes += (double)s->len * 16.0 * (4.0 * s->m + 8.0 * s->t);
+    TimedRegion tr(FAM_ORTH, st_, bytes);
+    const int n = (int)live.size();
+    launch_gram(DEV(dg1), n, maxblk, maxpx, maxt, st_);
+    launch_block_update(DEV(du1), n, maxlen, maxt, st_);
+    launch_gram(DEV(dg2), n, maxblk, maxpx, maxt, st_);
+    launch_block_update(DEV(du2), n, maxlen, maxt, st_);
+    for (int c = 0; c < 4; ++c) {
+      for (int pass = 0; pass < 2; ++pass) {
+        if (dmg[c * 3 + pass]) {
+          launch_gram(DEV(dmg[c * 3 + pass]), (int)mg[c * 3 + pass].size(), maxblk, c, 1, st_);
+          launch_block_update(DEV(dmu[c * 2 + pass]), (int)mu[c * 2 + pass].size(), maxlen, 1, st_);
+        }
+      }
+      if (dmg[c * 3 + 2]) {
+        launch_gram(DEV(dmg[c * 3 + 2]), (int)mg[c * 3 + 2].size(), maxblk, 1, 1, st_);
+        launch_normalize(DEV(dmn[c]), (int)mn[c].size(), maxlen, st_);
+      }
+    }
+  }
+
+  // ---- coefficients to the host, least squares, selection
+  std::vector<std::vector<int>> flags(live.size());
+  for (size_t q = 0; q < live.size(); ++q) {
+    Solve* s = live[q];
+    HdLayout L(s->hcap, s->t);
+    s->hbuf.resize(L.total);
+    HH_HIP(hipMemcpyAsync(s->hbuf.data(), s->Hd, L.total * sizeof(c128), hipMemcpyDeviceToHost, st_));
+    flags[q].resize(s->t);
+    HH_HIP(hipMemcpyAsync(flags[q].data(), s->flags, s->t * sizeof(int), hipMemcpyDeviceToHost, st_));
+  }
+  HH_HIP(hipStreamSynchronize(st_));
+  for (size_t q = 0; q < live.size(); ++q) {
+    Solve* s = live[q];
+    HdLayout L(s->hcap, s->t);
+    const int m = s->m, t = s->t;
+    const zd* H = s->hbuf.data();
+    s->ls.add_rows(t);
+    for (int c = 0; c < t; ++c) {
+      std::vector<zd> col(m + t, zd(0.0, 0.0));
+      for (int i = 0; i < m; ++i) col[i] = H[L.g1 + i + (size_t)c * (m + t)] + H[L.g2 + i + (size_t)c * m];
+      for (int i = 0; i < c; ++i) col[m + i] = H[L.r1 + i + (size_t)c * t] + H[L.r2 + i + (size_t)c * t];
+      col[m + c] = H[L.rd + c];
+      s->ls.add_column(col);
+    }
+    std::vector<int> kept;
+    for (int c = 0; c < t; ++c) {
+      if (flags[q][c]) ++s->deflated;
+      else kept.push_back(m + c);
+    }
+    s->k += 1;
+    s->m += t;
+    s->res_est = s->ls.residual() / s->beta;
+    if (s->res_est <= s->tol) {
+      s->done = true;
+      s->converged = true;
+    } else if (kept.empty()) {
+      s->done = true;
+      s->breakdown = true;
+    } else if (s->k >= s->maxit) {
+      s->done = true;
+    } else if (t == 2 && kept.size() == 2) {
+      s->inputs[0] = kept[1];  // LRL gets the vector from BTB's column (Sec. 4)
+      s->inputs[1] = kept[0];
+    } else {
+      for (int i = 0; i < t; ++i) s->inputs[i] = kept[0];
+    }
+  }
+}
+
+// ------------------------------------------------------------ finish
+void Engine::finish(std::vector<Solve*>& solves) {
+  std::vector<Solve*> fin;
+  for (Solve* s : solves)
+    if (s->done) fin.push_back(s);
+  if (fin.empty()) return;
+  staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
+  std::vector<CombTask> ct[2];
+  std::vector<SpmvTask> sp;
+  std::vector<ResTask> rt;
+  std::vector<GramTask> gt;
+  long long maxlen = 0;
+  int maxblk = 1;
+  for (Solve* s : fin) {
+    std::vector<zd> y = s->ls.solve();
+    const int nc = (int)y.size();
+    if (nc > 0)
+      HH_HIP(hipMemcpyAsync(s->ydev, y.data(), nc * sizeof(zd), hipMemcpyHostToDevice, st_));
+    HH_HIP(hipStreamSynchronize(st_));
+    CombTask c{};
+    c.Z = s->Z;
+    c.y = s->ydev;
+    c.x = s->x;
+    c.len = s->len;
+    c.ncols = nc;
+    ct[s->prec == HH_FP64 ? 0 : 1].push_back(c);
+    // residual scratch: basis slot m (free after the last iteration) when capacity allows
+    c128* r = s->V + (size_t)std::min(s->m, s->vcap - 1) * s->len;
+    SpmvTask tk{};
+    tk.A = s->pb->d_A;
+    tk.x = s->x;
+    tk.y = r;
+    tk.n = s->pb->n;
+    tk.nvec = 1;
+    sp.push_back(tk);
+    ResTask rs{};
+    rs.b = s->b;
+    rs.r = r;
+    rs.len = s->len;
+    rt.push_back(rs);
+    HdLayout L(s->hcap, s->t);
+    GramTask g{};
+    g.X = r;
+    g.Y = r;
+    g.out = s->Hd + L.nr;
+    g.part = s->part;
+    g.len = s->len;
+    g.ldx = g.ldy = s->len;
+    g.ldo = 1;
+    g.px = 1;
+    g.ty = 1;
+    g.nblk = nblk_for(s->len);
+    gt.push_back(g);
+    maxlen = std::max(maxlen, s->len);
+    maxblk = std::max(maxblk, g.nblk);
+  }
+  CombTask* dct[2];
+  for (int a = 0; a < 2; ++a) dct[a] = ct[a].empty() ? nullptr : stage(ct[a], staged_);
+  SpmvTask* dsp = stage(sp, staged_);
+  ResTask* drt = stage(rt, staged_);
+  GramTask* dgt = stage(gt, staged_);
+  upload();
+  for (int a = 0; a < 2; ++a)
+    if (dct[a]) launch_combine(DEV(dct[a]), (int)ct[a].size(), maxlen, a == 0 ? HH_FP64 : HH_FP32, st_);
+  launch_spmv(DEV(dsp), (int)sp.size(), maxlen, HH_FP64, st_);
+  launch_residual(DEV(drt), (int)rt.size(), maxlen, st_);
+  launch_gram(DEV(dgt), (int)gt.size(), maxblk, 1, 1, st_);
+  std::vector<zd> nr(fin.size());
+  for (size_t q = 0; q < fin.size(); ++q) {
+    Solve* s = fin[q];
+    HdLayout L(s->hcap, s->t);
+    HH_HIP(hipMemcpyAsync(&nr[q], s->Hd + L.nr, sizeof(zd), hipMemcpyDeviceToHost, st_));
+  }
+  HH_HIP(hipStreamSynchronize(st_));
+  for (size_t q = 0; q < fin.size(); ++q) {
+    Solve* s = fin[q];
+    s->res_true = s->beta > 0 ? std::sqrt(std::max(0.0, nr[q].real())) / s->beta : 0.0;
+  }
+}
+
+}  // namespace hh

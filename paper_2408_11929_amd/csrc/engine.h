@@ -1,0 +1,116 @@
+// Batched selective MPGMRES engine (Sec. 3, selection rule of Sec. 4).
+//
+// A Solve is one right-hand side of one problem.  The engine advances any set
+// of solves (of one or several problems) by one outer iteration with batched
+// launches: the sweeps of every preconditioner of every solve in one launch,
+// one SpMV launch, and the block Gram-Schmidt kernels over all bases at once.
+// The only host synchronisation per iteration is the copy of the new
+// Hessenberg block columns to the host, where the small least-squares problem
+// is updated with Givens rotations in FP64.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+#include "hh_internal.h"
+#include "krylov.h"
+
+namespace hh {
+
+using zd = std::complex<double>;
+
+// Incremental QR (Givens) of the block Hessenberg matrix Hbar: rows are basis
+// vectors, columns are preconditioned vectors.  Columns found dependent (zero
+// pivot after rotation) get a zero coefficient.
+class LeastSquares {
+ public:
+  void init(double beta);
+  void add_rows(int count);
+  void add_column(std::vector<zd> h);  // h.size() == rows()
+  int rows() const { return (int)g_.size(); }
+  int cols() const { return (int)R_.size(); }
+  double residual() const;
+  std::vector<zd> solve() const;
+
+ private:
+  struct Rot {
+    int i, k;
+    double c;
+    zd s;
+  };
+  std::vector<std::vector<zd>> R_;
+  std::vector<int> piv_;
+  std::vector<Rot> rots_;
+  std::vector<zd> g_;
+  int rank_ = 0;
+};
+
+struct Solve {
+  hh_problem* pb = nullptr;
+  const c128* b = nullptr;  // device
+  c128* x = nullptr;        // device
+  long long len = 0;
+  int t = 0;
+  int prec = HH_FP64;
+  double tol = 1e-6;
+  int maxit = 200;
+  // state
+  double beta = 0;
+  int k = 0;        // completed iterations
+  int m = 0;        // basis columns in use (1 + k t)
+  int vcap = 0, zcap = 0;
+  c128* V = nullptr;
+  void* Z = nullptr;
+  c128* Hd = nullptr;     // device scratch for one iteration's coefficients
+  int hcap = 0;           // basis capacity Hd was sized for
+  c128* part = nullptr;   // partial sums
+  size_t part_elems = 0;
+  int* flags = nullptr;   // t deflation flags
+  void* rho = nullptr;    // sweep scratch, t chains
+  void* g1 = nullptr;
+  c128* ydev = nullptr;
+  int inputs[4] = {0, 0, 0, 0};
+  LeastSquares ls;
+  bool done = false, converged = false, breakdown = false;
+  int deflated = 0;
+  double res_est = 0, res_true = 0;
+  std::vector<zd> hbuf;   // host copy of Hd
+};
+
+// Layout of Solve::Hd for an iteration with basis size m and block width t:
+//   G1 : (m+t) x t, ld m+t   (X^H W against [V, W] before any update)
+//   G2 : m x t, ld m          (second CGS pass)
+//   R1 : t x t, R2 : t x t    (in-block MGS, two passes)
+//   RD : t                    (norms after in-block orthogonalisation)
+//   NR : t                    (squared norms before normalisation)
+struct HdLayout {
+  size_t g1, g2, r1, r2, rd, nr, total;
+  HdLayout(int m, int t);
+};
+
+class Engine {
+ public:
+  explicit Engine(hipStream_t st);
+  ~Engine();
+  // Prepares solves (allocates, beta = ||b||, v1 = b / beta).
+  void begin(std::vector<Solve*>& solves);
+  // One outer iteration for every solve that is not done.
+  void step(std::vector<Solve*>& solves);
+  // x = Z y and the FP64 residual for solves that are done but not finalised.
+  void finish(std::vector<Solve*>& solves);
+  static void release(Solve* s);
+  static size_t footprint(const hh_problem* pb, int t, int prec, int maxit);
+
+ private:
+  hipStream_t st_;
+  void* task_dev_ = nullptr;
+  size_t task_cap_ = 0;
+  std::vector<unsigned char> task_host_;
+  template <class TT>
+  TT* stage(const std::vector<TT>& v, size_t& off);
+  void upload();
+  void ensure_capacity(Solve* s);
+  size_t staged_ = 0;
+};
+
+}  // namespace hh

@@ -1,0 +1,185 @@
+// Batched band LU with partial pivoting of every strip matrix (Sec. 2: the
+// sweep is a block LU forward/backward substitution; Sec. 4 solves each
+// strip problem directly).  One workgroup per strip, all strips of all
+// directions in one launch.
+//
+// Storage (per strip, column-major, ldab = 3 kl + 1, kv = 2 kl): on entry,
+// A_s(i, j) sits at column j, position kv + i - j (general band storage with
+// kl rows of fill space on top).  The elimination keeps the active
+// (kl+1) x (kv+1) window in LDS as a circular buffer, so each column step
+// touches HBM only to retire one row of U and one column of L and to bring
+// in the one row of A that enters the window.
+//
+// Pivot rule: largest |Re| + |Im| in the column, first index on ties.
+//
+// After the elimination a second pass rewrites every column into the form the
+// sweep kernels read: position kv holds 1/U(j,j), positions 0..kv-1 hold
+// U(i,j)/U(j,j) (columns of U scaled by the inverse pivot), positions
+// kv+1..kv+kl the multipliers of L.
+#include "hh_internal.h"
+
+namespace hh {
+
+namespace {
+
+constexpr int LU_THREADS = 256;
+constexpr int LU_EPT = 32;  // per-thread element budget: kl*2kl <= 256*32 -> kl <= 63
+
+template <class T>
+__device__ __forceinline__ void wave_argmax(T& v, int& idx) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    T v2 = __shfl_xor(v, off, 64);
+    int i2 = __shfl_xor(idx, off, 64);
+    if (v2 > v || (v2 == v && i2 < idx)) {
+      v = v2;
+      idx = i2;
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restrict__ strips,
+                                                        cx<T>* __restrict__ band,
+                                                        int* __restrict__ pivbuf, int* err) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
+  const StripDesc sd = strips[blockIdx.x];
+  const int kl = sd.kl, kv = 2 * kl, R = kl + 1, C = kv + 1, ldab = sd.ldab, ns = sd.ns;
+  cx<T>* ab = band + sd.band_off;
+  int* piv = pivbuf + sd.piv_off;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const cx<T> zero = mk((T)0, (T)0);
+
+  // window at j = 0: logical (r, c) = physical (r, c)
+  for (int e = tid; e < R * C; e += LU_THREADS) {
+    int r = e / C, c = e - r * C;
+    cx<T> v = zero;
+    if (r < ns && c < ns && r - c <= kl && c - r <= kl) v = ab[(long long)c * ldab + kv + r - c];
+    W[r * C + c] = v;
+  }
+  // entering row for the first steps: row j+kl+1, absolute columns j+1..j+1+kv
+  auto fetch_row = [&](int j) -> cx<T> {
+    int i = j + kl + 1, cabs = j + 1 + tid;
+    if (tid < C && i < ns && cabs < ns) return ab[(long long)cabs * ldab + kv + i - cabs];
+    return zero;
+  };
+  cx<T> nr[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) nr[u] = fetch_row(u);
+  __syncthreads();
+
+  const int nel = kl * kv;
+  // element list of this thread: e = tid + k*LU_THREADS -> (r, c) = (1 + e / kv, 1 + e % kv)
+  const int dr = LU_THREADS / kv, dc = LU_THREADS % kv;
+  const int r_first = 1 + tid / kv, c_first = 1 + tid % kv;
+  for (int j0 = 0; j0 < ns; j0 += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u;
+      if (j >= ns) break;
+      const int r0 = j % R, c0 = j % C;
+      auto prow = [&](int r) { int x = r0 + r; return x >= R ? x - R : x; };
+      auto pcol = [&](int c) { int x = c0 + c; return x >= C ? x - C : x; };
+      // ---- read phase: pivot search (every wave redundantly) and operands
+      const int rmax = min(kl, ns - 1 - j);
+      T v = (T)-1;
+      int idx = 64;
+      if (lane <= rmax) {
+        v = cabs1(W[prow(lane) * C + c0]);
+        idx = lane;
+      }
+      wave_argmax(v, idx);
+      const int rp = idx;
+      const int prp = prow(rp);
+      const cx<T> pv = W[prp * C + c0];
+      const bool singular = (pv.re == (T)0 && pv.im == (T)0);
+      const cx<T> ipv = singular ? zero : cinv(pv);
+      if (singular && tid == 0) atomicCAS(err, 0, (int)blockIdx.x + 1);
+      if (tid == 0) piv[j] = j + rp;
+      // retire row j of U (pivot row) and column j of L
+      for (int c = tid; c < C; c += LU_THREADS)
+        if (j + c < ns) ab[(long long)(j + c) * ldab + kv - c] = W[prp * C + pcol(c)];
+      for (int r = 1 + tid; r <= rmax; r += LU_THREADS) {
+        int src = (r == rp) ? 0 : r;
+        ab[(long long)j * ldab + kv + r] = W[prow(src) * C + c0] * ipv;
+      }
+      cx<T> nv[LU_EPT];
+      {
+        int r = r_first, c = c_first;
+#pragma unroll
+        for (int k = 0; k < LU_EPT; ++k) {
+          if (tid + k * LU_THREADS < nel) {
+            const int psrc = prow(r == rp ? 0 : r), pc = pcol(c);
+            cx<T> lr = W[psrc * C + c0] * ipv;
+            nv[k] = cfms(W[psrc * C + pc], lr, W[prp * C + pc]);
+          }
+          r += dr;
+          c += dc;
+          if (c > kv) { c -= kv; r += 1; }
+        }
+      }
+      __syncthreads();
+      // ---- write phase: updated window, entering row, fill column
+      {
+        int r = r_first, c = c_first;
+#pragma unroll
+        for (int k = 0; k < LU_EPT; ++k) {
+          if (tid + k * LU_THREADS < nel) W[prow(r) * C + pcol(c)] = nv[k];
+          r += dr;
+          c += dc;
+          if (c > kv) { c -= kv; r += 1; }
+        }
+      }
+      if (tid < C) W[r0 * C + pcol(1 + tid < C ? 1 + tid : 1 + tid - C)] = nr[u];
+      for (int r = tid; r < kl; r += LU_THREADS) W[prow(1 + r) * C + c0] = zero;
+      nr[u] = fetch_row(j + 4);
+      __syncthreads();
+    }
+  }
+}
+
+// Scale U's columns by the inverse pivot and store the inverse on the diagonal.
+template <class T>
+__global__ void k_band_finalize(const StripDesc* __restrict__ strips, cx<T>* __restrict__ band) {
+  const StripDesc sd = strips[blockIdx.y];
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= sd.ns) return;
+  const int kv = 2 * sd.kl;
+  cx<T>* col = band + sd.band_off + (long long)j * sd.ldab;
+  cx<T> d = col[kv];
+  cx<T> rd = (d.re == (T)0 && d.im == (T)0) ? mk((T)0, (T)0) : cinv(d);
+  for (int p = 0; p < kv; ++p) col[p] = col[p] * rd;
+  col[kv] = rd;
+}
+
+}  // namespace
+
+void launch_band_lu(const hh_problem* pb, hipStream_t st) {
+  const FactorSet& fs = pb->fs;
+  int nstr = (int)fs.strips.size();
+  size_t esz = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
+  size_t lds = (size_t)(fs.max_kl + 1) * (2 * fs.max_kl + 1) * esz;
+  double bytes = 0;
+  for (auto& s : fs.strips) bytes += 2.0 * (double)s.ns * s.ldab * esz;
+  TimedRegion tr(FAM_FACTOR, st, bytes);
+  if (fs.precision == HH_FP64) {
+    HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_band_lu<double>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
+                       (c128*)fs.band, fs.piv, fs.d_err);
+    HH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_band_finalize<double>, dim3((fs.max_ns + 255) / 256, nstr), dim3(256), 0,
+                       st, fs.d_strips, (c128*)fs.band);
+  } else {
+    HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_band_lu<float>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
+                       (c64*)fs.band, fs.piv, fs.d_err);
+    HH_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_band_finalize<float>, dim3((fs.max_ns + 255) / 256, nstr), dim3(256), 0,
+                       st, fs.d_strips, (c64*)fs.band);
+  }
+  HH_HIP(hipGetLastError());
+}
+
+}  // namespace hh

@@ -1,0 +1,204 @@
+// Internal declarations shared by the HIP kernels, the MPGMRES engine and the
+// C ABI.  Nothing here is part of the public interface (include/hh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hh.h"
+
+namespace hh {
+
+// ---------------------------------------------------------------- complex
+template <class T>
+struct cx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) {
+  cx<T> z;
+  z.re = r;
+  z.im = i;
+  return z;
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return mk(a.re + b.re, a.im + b.im);
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return mk(a.re - b.re, a.im - b.im);
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) {
+  return mk(a.re * s, a.im * s);
+}
+// a - b * c
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cfms(cx<T> a, cx<T> b, cx<T> c) {
+  return mk(a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re);
+}
+// conj(a) * b
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cdotc(cx<T> a, cx<T> b) {
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cinv(cx<T> a) {
+  // 1/a with scaling to avoid overflow in |a|^2
+  T s = fabs(a.re) > fabs(a.im) ? fabs(a.re) : fabs(a.im);
+  if (s == T(0)) return mk(T(0), T(0));
+  T ar = a.re / s, ai = a.im / s;
+  T d = (ar * ar + ai * ai) * s;
+  return mk(ar / d, -ai / d);
+}
+template <class T>
+__host__ __device__ __forceinline__ T cabs1(cx<T> a) {
+  return fabs(a.re) + fabs(a.im);
+}
+template <class To, class Ti>
+__host__ __device__ __forceinline__ cx<To> ccast(cx<Ti> a) {
+  return mk((To)a.re, (To)a.im);
+}
+
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+#define HH_HIP(call)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::hh::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call, hipGetErrorString(e_)); \
+      throw ::hh::DeviceError();                                                   \
+    }                                                                              \
+  } while (0)
+
+struct DeviceError {};
+struct ArgError {};
+struct MemError {};
+
+// ---------------------------------------------------------------- geometry
+// One strip of one sweep direction (0 = x / LRL, 1 = y / BTB).
+struct StripDesc {
+  int dir;        // 0 x, 1 y
+  int s;          // 0-based position in the sweep
+  int a;          // first node line across the strip
+  int w;          // width in node lines
+  int ns;         // unknowns n*w, local order q = long*w + short
+  int kl;         // band half-width w + 1 (ku = kl)
+  int ldab;       // band column stride 3*kl + 1
+  int has1;       // interface Gamma_{s,1} (short index 0) present
+  int has2;       // interface Gamma_{s,2} (short index w-1) present
+  int pad;
+  long long band_off;  // complex elements into the factor buffer
+  long long piv_off;   // ints into the pivot buffer
+  long long tr1_off;   // complex elements into the transmission buffer (n*7), or -1
+  long long tr2_off;
+};
+
+// Strip factors of every strip of every factored direction.
+struct FactorSet {
+  int N = 0;
+  unsigned dirs = 0;
+  int precision = -1;       // HH_FP64 / HH_FP32, -1 = not factored
+  int nd = 0;               // number of directions
+  int dir_id[2] = {-1, -1}; // direction (0/1) of preconditioner slot 0/1
+  std::vector<StripDesc> strips;  // dir-major: strips[d*N + s]
+  StripDesc* d_strips = nullptr;  // device copy
+  void* band = nullptr;            // complex<precision> elements
+  int* piv = nullptr;
+  void* tr = nullptr;              // transmission stencils, complex<precision>
+  int* d_err = nullptr;            // [0] = 1 + strip index of first zero pivot, [1] = column
+  size_t band_elems = 0, piv_elems = 0, tr_elems = 0;
+  int max_ns = 0, max_kl = 0;
+  size_t bytes() const;
+};
+
+}  // namespace hh
+
+struct hh_problem {
+  int n = 0;
+  double omega = 0;
+  std::vector<double> c;
+  double* d_c = nullptr;           // layer speeds on the device
+  hh::c128* d_A = nullptr;         // 4 * n*n upper diagonals
+  hh::FactorSet fs;
+  hipStream_t st[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int device = 0;
+  size_t bytes() const;
+};
+
+namespace hh {
+
+// ---------------------------------------------------------------- timing
+struct TimingFamily {
+  long long launches = 0;
+  double ms = 0;
+  double bytes = 0;
+};
+bool timing_on();
+// Records (start, stop) events around a launch; resolved lazily.
+struct TimedRegion {
+  int fam;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double bytes;
+  TimedRegion(int family, hipStream_t s, double b);
+  ~TimedRegion();
+};
+enum { FAM_SWEEP = 0, FAM_SPMV, FAM_FACTOR, FAM_ORTH, FAM_ASSEMBLE, FAM_COUNT };
+void timing_flush();
+
+// ---------------------------------------------------------------- memory
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+// ---------------------------------------------------------------- kernels
+// assemble.hip
+void launch_assemble(int n, double omega, int nlayers, const double* d_c, c128* d_A,
+                     hipStream_t st);
+void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st);
+void launch_pack_strips(const hh_problem* pb, hipStream_t st);
+
+// factor.hip
+void launch_band_lu(const hh_problem* pb, hipStream_t st);
+
+// sweep.hip
+struct SweepTask {
+  const StripDesc* strips;  // N descriptors of one direction (device)
+  const void* band;
+  const int* piv;
+  const void* tr;
+  const c128* r;            // FP64 input, n*n
+  void* z;                  // output in sweep precision, n*n
+  void* rho;                // scratch, >= max ns elements of sweep precision
+  void* g1;                 // scratch, N*n elements of sweep precision
+  int n;
+  int N;
+  int pad[2];
+};
+// All tasks share the precision and have kl <= klmax.
+void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int klmax,
+                  hipStream_t st);
+// Single strip solve (test hook): rhs/x in FP64, strip-local order.
+void launch_strip_solve(const hh_problem* pb, int strip_index, const c128* rhs, c128* x,
+                        void* scratch, hipStream_t st);
+
+// krylov.hip: see krylov.h
+
+}  // namespace hh

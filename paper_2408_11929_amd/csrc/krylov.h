@@ -1,0 +1,87 @@
+// Task descriptors and launchers of the batched FP64 Krylov kernels.
+#pragma once
+
+#include "hh_internal.h"
+
+namespace hh {
+
+// y = A x for nvec vectors of one problem.
+struct SpmvTask {
+  const c128* A;   // 4 n*n upper diagonals
+  const void* x;   // nvec vectors, stride n*n (complex of the launch's xprec)
+  c128* y;         // nvec vectors, stride n*n
+  int n;
+  int nvec;
+};
+
+// out (px x ty, column stride ldo) (=|+=) X^H Y, X: px columns, Y: ty columns.
+struct GramTask {
+  const c128* X;
+  const c128* Y;
+  c128* out;
+  c128* part;      // >= nblk * px * ty scratch
+  long long len;
+  long long ldx, ldy;
+  int ldo;
+  int px;
+  int ty;
+  int nblk;
+  int accumulate;
+};
+
+// Y[:, c] -= X C[:, c].
+struct UpdTask {
+  const c128* X;
+  c128* Y;
+  const c128* C;
+  long long len;
+  long long ldx, ldy;
+  int ldc;
+  int px;
+  int ty;
+};
+
+// y /= ||y|| unless ||y|| <= tol * ref (then y = 0 and *flag = 1).
+struct NormTask {
+  c128* y;
+  const c128* nrm2;  // .re = ||y||^2
+  const c128* ref2;  // .re = reference norm squared
+  c128* rdiag;       // receives ||y|| (0 if deflated)
+  int* flag;
+  long long len;
+  double tol;
+};
+
+// x = Z y.
+struct CombTask {
+  const void* Z;
+  const c128* y;
+  c128* x;
+  long long len;
+  int ncols;
+};
+
+// r = b - r.
+struct ResTask {
+  const c128* b;
+  c128* r;
+  long long len;
+};
+
+void launch_spmv(const SpmvTask* d_tasks, int ntasks, long long max_rows, int xprec,
+                 hipStream_t st);
+void launch_gram(const GramTask* d_tasks, int ntasks, int max_nblk, int max_px, int max_ty,
+                 hipStream_t st);
+void launch_block_update(const UpdTask* d_tasks, int ntasks, long long max_len, int max_ty,
+                         hipStream_t st);
+void launch_normalize(const NormTask* d_tasks, int ntasks, long long max_len, hipStream_t st);
+void launch_combine(const CombTask* d_tasks, int ntasks, long long max_len, int zprec,
+                    hipStream_t st);
+void launch_residual(const ResTask* d_tasks, int ntasks, long long max_len, hipStream_t st);
+
+}  // namespace hh
+
+namespace hh {
+// b = (complex128) a, elementwise.
+void launch_widen(const c64* a, c128* b, long long n, hipStream_t st);
+}  // namespace hh

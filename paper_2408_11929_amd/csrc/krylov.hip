@@ -1,0 +1,264 @@
+// FP64 kernels of the MPGMRES outer loop (Sec. 3): the sparse product with
+// the P1 operator, block classical Gram-Schmidt (tall-skinny Gram products
+// and rank-t updates), normalisation with deflation, the solution update
+// x = Z y and the residual.  Every kernel takes an array of task descriptors
+// so that one launch serves a whole batch of independent solves, possibly of
+// different sizes.  All reductions are two-stage and deterministic.
+#include "hh_internal.h"
+#include "krylov.h"
+
+namespace hh {
+
+namespace {
+
+template <class T>
+__device__ __forceinline__ c128 ld_c128(const void* base, long long idx) {
+  const cx<T> v = ((const cx<T>*)base)[idx];
+  return mk((double)v.re, (double)v.im);
+}
+
+// y = A x with A complex symmetric, stored as its upper diagonals
+// d0 = A[p][p], d1 = A[p][p+1], dn = A[p][p+n], dn1 = A[p][p+n+1].
+template <class T>
+__global__ __launch_bounds__(256) void k_spmv(const SpmvTask* __restrict__ tasks) {
+  const SpmvTask tk = tasks[blockIdx.y];
+  const int n = tk.n;
+  const long long nn = (long long)n * n;
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= nn) return;
+  const c128* A = tk.A;
+  const c128 a0 = A[p], a1 = A[nn + p], an = A[2 * nn + p], an1 = A[3 * nn + p];
+  const c128 zero = mk(0.0, 0.0);
+  const c128 b1 = p >= 1 ? A[nn + p - 1] : zero;
+  const c128 bn = p >= n ? A[2 * nn + p - n] : zero;
+  const c128 bn1 = p >= n + 1 ? A[3 * nn + p - n - 1] : zero;
+  for (int v = 0; v < tk.nvec; ++v) {
+    const long long o = v * nn;
+    c128 acc = a0 * ld_c128<T>(tk.x, o + p);
+    if (p + 1 < nn) acc = acc + a1 * ld_c128<T>(tk.x, o + p + 1);
+    if (p + n < nn) acc = acc + an * ld_c128<T>(tk.x, o + p + n);
+    if (p + n + 1 < nn) acc = acc + an1 * ld_c128<T>(tk.x, o + p + n + 1);
+    if (p >= 1) acc = acc + b1 * ld_c128<T>(tk.x, o + p - 1);
+    if (p >= n) acc = acc + bn * ld_c128<T>(tk.x, o + p - n);
+    if (p >= n + 1) acc = acc + bn1 * ld_c128<T>(tk.x, o + p - n - 1);
+    tk.y[o + p] = acc;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Partial sums of X^H Y over one block of rows and one chunk of CH columns of X.
+// grid = (row blocks, column chunks, tasks); part[(blk * px + i) * ty + c].
+template <int CH, int TY>
+__global__ __launch_bounds__(256) void k_gram_partial(const GramTask* __restrict__ tasks) {
+  const GramTask tk = tasks[blockIdx.z];
+  const int blk = blockIdx.x, i0 = blockIdx.y * CH;
+  if (blk >= tk.nblk || i0 >= tk.px) return;
+  const long long rows_per = (tk.len + tk.nblk - 1) / tk.nblk;
+  const long long r0 = blk * rows_per;
+  const long long r1 = min((long long)tk.len, r0 + rows_per);
+  double acc_re[CH][TY], acc_im[CH][TY];
+#pragma unroll
+  for (int a = 0; a < CH; ++a)
+#pragma unroll
+    for (int c = 0; c < TY; ++c) acc_re[a][c] = acc_im[a][c] = 0.0;
+  const int ni = min(CH, tk.px - i0);
+  for (long long p = r0 + threadIdx.x; p < r1; p += 256) {
+    c128 y[TY];
+#pragma unroll
+    for (int c = 0; c < TY; ++c) y[c] = c < tk.ty ? tk.Y[c * (long long)tk.ldy + p] : mk(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < CH; ++a) {
+      if (a < ni) {
+        const c128 x = tk.X[(i0 + a) * (long long)tk.ldx + p];
+#pragma unroll
+        for (int c = 0; c < TY; ++c) {
+          const c128 d = cdotc(x, y[c]);
+          acc_re[a][c] += d.re;
+          acc_im[a][c] += d.im;
+        }
+      }
+    }
+  }
+  __shared__ double red[4][CH * TY * 2];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+  for (int a = 0; a < CH; ++a)
+#pragma unroll
+    for (int c = 0; c < TY; ++c) {
+      double sr = wave_sum(acc_re[a][c]);
+      double si = wave_sum(acc_im[a][c]);
+      if (ln == 0) {
+        red[wv][(a * TY + c) * 2] = sr;
+        red[wv][(a * TY + c) * 2 + 1] = si;
+      }
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ni * tk.ty; e += 256) {
+    const int a = e / tk.ty, c = e - a * tk.ty;
+    const int k = (a * TY + c) * 2;
+    double sr = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    double si = red[0][k + 1] + red[1][k + 1] + red[2][k + 1] + red[3][k + 1];
+    tk.part[((long long)blk * tk.px + i0 + a) * tk.ty + c] = mk(sr, si);
+  }
+}
+
+// out[i + c*ldo] (=|+=) sum over blocks of part; grid = (ceil(px*ty/256), tasks)
+__global__ __launch_bounds__(256) void k_gram_reduce(const GramTask* __restrict__ tasks) {
+  const GramTask tk = tasks[blockIdx.y];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= tk.px * tk.ty) return;
+  const int i = e / tk.ty, c = e - i * tk.ty;
+  c128 s = mk(0.0, 0.0);
+  for (int b = 0; b < tk.nblk; ++b) s = s + tk.part[((long long)b * tk.px + i) * tk.ty + c];
+  c128* o = tk.out + i + (long long)c * tk.ldo;
+  *o = tk.accumulate ? *o + s : s;
+}
+
+// Y[:, c] -= X C[:, c]; C (px x ty, column stride ldc) on the device.
+template <int TY>
+__global__ __launch_bounds__(256) void k_block_update(const UpdTask* __restrict__ tasks) {
+  const UpdTask tk = tasks[blockIdx.y];
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= tk.len) return;
+  c128 y[TY];
+#pragma unroll
+  for (int c = 0; c < TY; ++c) y[c] = c < tk.ty ? tk.Y[c * (long long)tk.ldy + p] : mk(0.0, 0.0);
+  for (int i = 0; i < tk.px; ++i) {
+    const c128 x = tk.X[i * (long long)tk.ldx + p];
+#pragma unroll
+    for (int c = 0; c < TY; ++c)
+      if (c < tk.ty) y[c] = cfms(y[c], x, tk.C[i + (long long)c * tk.ldc]);
+  }
+#pragma unroll
+  for (int c = 0; c < TY; ++c)
+    if (c < tk.ty) tk.Y[c * (long long)tk.ldy + p] = y[c];
+}
+
+// Normalise y by the norm whose square is nrm2->re; deflate (zero y, flag) when
+// the norm is at most tol times sqrt(ref2->re).  grid = (row blocks, tasks).
+__global__ __launch_bounds__(256) void k_normalize(const NormTask* __restrict__ tasks) {
+  const NormTask tk = tasks[blockIdx.y];
+  const double nrm = sqrt(fmax(tk.nrm2->re, 0.0));
+  const double ref = sqrt(fmax(tk.ref2->re, 0.0));
+  const bool defl = !(nrm > tk.tol * ref) || nrm == 0.0;
+  const double s = defl ? 0.0 : 1.0 / nrm;
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *tk.rdiag = mk(defl ? 0.0 : nrm, 0.0);
+    *tk.flag = defl ? 1 : 0;
+  }
+  if (p < tk.len) tk.y[p] = cscale(tk.y[p], s);
+}
+
+// x = Z y (plus x0 if add); Z columns contiguous with stride len.
+template <class T>
+__global__ __launch_bounds__(256) void k_combine(const CombTask* __restrict__ tasks) {
+  const CombTask tk = tasks[blockIdx.y];
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= tk.len) return;
+  c128 acc = mk(0.0, 0.0);
+  for (int j = 0; j < tk.ncols; ++j) acc = acc + ld_c128<T>(tk.Z, j * (long long)tk.len + p) * tk.y[j];
+  tk.x[p] = acc;
+}
+
+// r = b - Ab (elementwise), in place on ab.
+__global__ __launch_bounds__(256) void k_residual(const ResTask* __restrict__ tasks) {
+  const ResTask tk = tasks[blockIdx.y];
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= tk.len) return;
+  tk.r[p] = tk.b[p] - tk.r[p];
+}
+
+}  // namespace
+
+void launch_spmv(const SpmvTask* d_tasks, int ntasks, long long max_rows, int xprec,
+                 hipStream_t st) {
+  if (ntasks <= 0) return;
+  dim3 grid((unsigned)((max_rows + 255) / 256), (unsigned)ntasks);
+  if (xprec == HH_FP64)
+    hipLaunchKernelGGL(k_spmv<double>, grid, dim3(256), 0, st, d_tasks);
+  else
+    hipLaunchKernelGGL(k_spmv<float>, grid, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_gram(const GramTask* d_tasks, int ntasks, int max_nblk, int max_px, int max_ty,
+                 hipStream_t st) {
+  if (ntasks <= 0) return;
+  if (max_ty <= 1) {
+    dim3 grid((unsigned)max_nblk, (unsigned)((max_px + 15) / 16), (unsigned)ntasks);
+    hipLaunchKernelGGL((k_gram_partial<16, 1>), grid, dim3(256), 0, st, d_tasks);
+  } else if (max_ty <= 2) {
+    dim3 grid((unsigned)max_nblk, (unsigned)((max_px + 7) / 8), (unsigned)ntasks);
+    hipLaunchKernelGGL((k_gram_partial<8, 2>), grid, dim3(256), 0, st, d_tasks);
+  } else if (max_ty <= 4) {
+    dim3 grid((unsigned)max_nblk, (unsigned)((max_px + 3) / 4), (unsigned)ntasks);
+    hipLaunchKernelGGL((k_gram_partial<4, 4>), grid, dim3(256), 0, st, d_tasks);
+  } else {
+    set_error("block width %d exceeds 4", max_ty);
+    throw ArgError();
+  }
+  HH_HIP(hipGetLastError());
+  dim3 g2((unsigned)((max_px * max_ty + 255) / 256), (unsigned)ntasks);
+  hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_block_update(const UpdTask* d_tasks, int ntasks, long long max_len, int max_ty,
+                         hipStream_t st) {
+  if (ntasks <= 0) return;
+  dim3 grid((unsigned)((max_len + 255) / 256), (unsigned)ntasks);
+  if (max_ty <= 1)
+    hipLaunchKernelGGL(k_block_update<1>, grid, dim3(256), 0, st, d_tasks);
+  else if (max_ty <= 2)
+    hipLaunchKernelGGL(k_block_update<2>, grid, dim3(256), 0, st, d_tasks);
+  else
+    hipLaunchKernelGGL(k_block_update<4>, grid, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_normalize(const NormTask* d_tasks, int ntasks, long long max_len, hipStream_t st) {
+  if (ntasks <= 0) return;
+  dim3 grid((unsigned)((max_len + 255) / 256), (unsigned)ntasks);
+  hipLaunchKernelGGL(k_normalize, grid, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_combine(const CombTask* d_tasks, int ntasks, long long max_len, int zprec,
+                    hipStream_t st) {
+  if (ntasks <= 0) return;
+  dim3 grid((unsigned)((max_len + 255) / 256), (unsigned)ntasks);
+  if (zprec == HH_FP64)
+    hipLaunchKernelGGL(k_combine<double>, grid, dim3(256), 0, st, d_tasks);
+  else
+    hipLaunchKernelGGL(k_combine<float>, grid, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_residual(const ResTask* d_tasks, int ntasks, long long max_len, hipStream_t st) {
+  if (ntasks <= 0) return;
+  dim3 grid((unsigned)((max_len + 255) / 256), (unsigned)ntasks);
+  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+}  // namespace hh
+
+namespace hh {
+namespace {
+__global__ void k_widen(const c64* __restrict__ a, c128* __restrict__ b, long long n) {
+  long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p < n) b[p] = mk((double)a[p].re, (double)a[p].im);
+}
+}  // namespace
+
+void launch_widen(const c64* a, c128* b, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+  HH_HIP(hipGetLastError());
+}
+}  // namespace hh

@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: FP64 kernels agree with the oracle to 1e-12 relative (assembly
+and SpMV to 1e-13: they differ only in summation order); complex64 strips
+agree with the FP64 oracle to 1e-5 relative (the acceptance bar for the
+complex64 sweep); MPGMRES runs are compared by iteration count (exact),
+solution (relative 1e-8 for FP64, both runs converged to a tighter
+tolerance) and the FP64-recomputed residual.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import assemble as oasm
+from oracle import direct as odr
+from oracle import mpgmres as omp
+from oracle import strips as ost
+from oracle import sweep as osw
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+hh = pytest.importorskip("paper_2408_11929_amd")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def rand(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+CASES = [
+    # (n, N, omega, c)  -- several tiles, ragged widths, layered media
+    (33, 4, 18.0, [1.0, 2.0, 1.5]),
+    (41, 5, 25.0, [1.0]),
+    (64, 9, 30.0, [2.2, 1.1, 1.7, 2.9, 1.3]),
+]
+
+
+def _upper_diagonals(A, n):
+    nn = n * n
+    out = np.zeros((4, nn), dtype=np.complex128)
+    Ad = A.todok() if hasattr(A, "todok") else A
+    coo = A.tocoo()
+    for r, c, v in zip(coo.row, coo.col, coo.data):
+        d = c - r
+        k = {0: 0, 1: 1, n: 2, n + 1: 3}.get(d)
+        if k is not None:
+            out[k, r] += v
+    del Ad
+    return out
+
+
+@pytest.mark.parametrize("n,N,omega,c", CASES)
+def test_assembly_matches_oracle(n, N, omega, c):
+    pb = hh.Problem(omega, c, n)
+    got = pb.get_operator()
+    A = oasm.assemble(omega, c, n)
+    ref = _upper_diagonals(A, n)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the lower triangle is the transpose (complex symmetric)
+    assert abs(A - A.T).max() == 0
+    pb.free()
+
+
+@pytest.mark.parametrize("n,N,omega,c", CASES[:2])
+def test_load_vector_and_spmv(n, N, omega, c):
+    pb = hh.Problem(omega, c, n)
+    f = np.stack([wl.gaussian_field(n, 0.3, 0.7, 0.05), rand(n * n, 1)])
+    b = host(pb.load_vector(dev(f)))
+    for v in range(2):
+        assert rel(b[v], oasm.source_load(n, f[v])) < 1e-13
+    x = rand((3, n * n), 2)
+    y = host(pb.spmv(dev(x)))
+    A = oasm.assemble(omega, c, n)
+    for v in range(3):
+        assert rel(y[v], A @ x[v]) < 1e-13
+    pb.free()
+
+
+@pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
+@pytest.mark.parametrize("n,N,omega,c", CASES)
+def test_strip_solves_match_lapack(n, N, omega, c, prec):
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+    tol = 1e-12 if prec == hh.HH_FP64 else 1e-5
+    worst = 0.0
+    for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
+        for s in range(1, N + 1):
+            a, w, kl = pb.strip_info(d, s)
+            a_ref, b_ref = ost.strip_lines(n, N, s)
+            assert (a, w, kl) == (a_ref, b_ref - a_ref + 1, ost.band_width(n, N, s))
+            As = ost.strip_matrix(omega, c, n, N, dname, s)
+            rhs = rand(As.shape[0], 10 * s + d)
+            x = host(pb.strip_solve(d, s, dev(rhs)))
+            xr = osw.StripSolver(As, kl).solve(rhs)
+            worst = max(worst, rel(x, xr))
+    assert worst < tol, worst
+    pb.free()
+
+
+@pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
+@pytest.mark.parametrize("n,N,omega,c", CASES)
+def test_sweeps_match_oracle(n, N, omega, c, prec):
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+    A = oasm.assemble(omega, c, n)
+    r = rand((2, n * n), 5)
+    tol = 1e-12 if prec == hh.HH_FP64 else 1e-5
+    for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
+        z = host(pb.sweep_apply(d, dev(r)))
+        S = osw.DoubleSweep(omega, c, n, N, dname, A=A)
+        for v in range(2):
+            assert rel(z[v], S.apply(r[v])) < tol
+    pb.free()
+
+
+def test_sweep_single_strip_is_exact_solve():
+    n, omega, c = 31, 12.0, [1.0, 2.0]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, 1, hh.HH_FP64)
+    A = oasm.assemble(omega, c, n)
+    r = rand(n * n, 3)
+    for d in (hh.HH_DIR_X, hh.HH_DIR_Y):
+        z = host(pb.sweep_apply(d, dev(r.reshape(1, -1))))[0]
+        assert rel(A @ z, r) < 1e-12
+    pb.free()
+
+
+def _oracle_solve(n, N, omega, c, b, tol, t=2):
+    A = oasm.assemble(omega, c, n)
+    precs = [osw.DoubleSweep(omega, c, n, N, ost.X, A=A).apply]
+    if t == 2:
+        precs.append(osw.DoubleSweep(omega, c, n, N, ost.Y, A=A).apply)
+    return A, omp.mpgmres(A, precs, b, tol=tol)
+
+
+@pytest.mark.parametrize("n,N,omega,c", CASES)
+def test_mpgmres_fp64_matches_oracle(n, N, omega, c):
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP64)
+    f = wl.gaussian_field(n, 0.45, 0.55, 0.05)
+    b = oasm.source_load(n, f)
+    x, st, rc = pb.mpgmres(dev(b.reshape(1, -1)), tol=1e-10, maxit=100)
+    A, ref = _oracle_solve(n, N, omega, c, b, 1e-10)
+    assert rc == hh.HH_OK and st[0]["converged"] == 1
+    assert st[0]["iterations"] == ref.iterations
+    assert rel(host(x)[0], ref.x) < 1e-8
+    assert st[0]["res_true"] < 1e-10
+    assert abs(st[0]["res_est"] - ref.res_hist[-1]) < 1e-3 * ref.res_hist[-1] + 1e-14
+    pb.free()
+
+
+def test_mpgmres_one_direction_is_gmres():
+    n, N, omega, c = 33, 4, 18.0, [1.0, 2.0, 1.5]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X, N, hh.HH_FP64)
+    b = oasm.source_load(n, wl.gaussian_field(n, 0.5, 0.5, 0.05))
+    x, st, rc = pb.mpgmres(dev(b.reshape(1, -1)), tol=1e-9, maxit=100)
+    A = oasm.assemble(omega, c, n)
+    SX = osw.DoubleSweep(omega, c, n, N, ost.X, A=A)
+    xr, its, _ = omp.gmres_right(A, SX.apply, b, tol=1e-9, maxit=100)
+    assert st[0]["iterations"] == its
+    assert rel(host(x)[0], xr) < 1e-7
+    pb.free()
+
+
+def test_mpgmres_single_strip_converges_in_one_iteration():
+    n, omega, c = 31, 12.0, [1.0, 2.0]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, 1, hh.HH_FP64)
+    b = rand(n * n, 8)
+    x, st, rc = pb.mpgmres(dev(b.reshape(1, -1)), tol=1e-10, maxit=10)
+    assert rc == hh.HH_OK and st[0]["iterations"] == 1
+    assert st[0]["res_true"] < 1e-11
+    assert st[0]["deflated"] >= 1
+    pb.free()
+
+
+def test_batched_rhs_equal_to_single():
+    n, N, omega, c = 41, 5, 25.0, [1.0, 1.7]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP32)
+    pos = wl.source_positions(11, 4)
+    f = np.stack([wl.gaussian_field(n, x0, y0, 0.03) for x0, y0 in pos])
+    b = pb.load_vector(dev(f))
+    xb, stb, _ = pb.mpgmres(b, tol=1e-8, maxit=100)
+    for v in range(4):
+        xs, sts, _ = pb.mpgmres(b[v:v + 1].contiguous(), tol=1e-8, maxit=100)
+        assert sts[0]["iterations"] == stb[v]["iterations"]
+        assert rel(host(xs)[0], host(xb)[v]) <= 1e-14
+    pb.free()
+
+
+def test_zero_rhs_and_maxit():
+    n, N, omega, c = 33, 4, 18.0, [1.0]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP64)
+    z = torch.zeros((1, n * n), dtype=torch.complex128, device="cuda")
+    x, st, rc = pb.mpgmres(z, tol=1e-6, maxit=5)
+    assert rc == hh.HH_OK and st[0]["iterations"] == 0 and torch.all(x == 0)
+    b = dev(rand((1, n * n), 4))
+    x, st, rc = pb.mpgmres(b, tol=1e-14, maxit=1)
+    assert rc == hh.HH_ENOCONV and st[0]["iterations"] == 1 and st[0]["converged"] == 0
+    pb.free()
+
+
+def test_invalid_factorisation_arguments():
+    pb = hh.Problem(10.0, [1.0], 33)
+    with pytest.raises(hh.HHError):
+        pb.factor_sweeps(3, 5, hh.HH_FP64)        # 32 not divisible by 5
+    with pytest.raises(hh.HHError):
+        pb.factor_sweeps(3, 32, hh.HH_FP64)       # one interval per strip
+    with pytest.raises(hh.HHError):
+        pb.factor_sweeps(4, 4, hh.HH_FP64)        # unknown direction bits
+    with pytest.raises(hh.HHError):
+        pb.mpgmres(torch.zeros((1, 33 * 33), dtype=torch.complex128, device="cuda"))  # not factored
+    pb.free()
