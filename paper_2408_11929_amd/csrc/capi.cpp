@@ -47,6 +47,7 @@ int guard(F&& f) {
 
 void free_factors(FactorSet& fs) {
   dev_free(fs.band);
+  dev_free(fs.img);
   dev_free(fs.piv);
   dev_free(fs.tr);
   dev_free(fs.d_strips);
@@ -65,6 +66,139 @@ int dir_slot(const hh_problem* pb, unsigned dir) {
 
 }  // namespace
 
+namespace hh {
+
+void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
+  REQUIRE(dirs >= 1 && dirs <= 3, "dirs must be HH_DIR_X, HH_DIR_Y or both");
+  REQUIRE(precision == HH_FP64 || precision == HH_FP32, "precision must be HH_FP64 or HH_FP32");
+  const int n = pb->n, N = nstrips;
+  REQUIRE(N >= 1 && (n - 1) % N == 0, "(n-1) = %d is not divisible by nstrips = %d", n - 1, N);
+  const int m = (n - 1) / N;
+  REQUIRE(N == 1 || m >= 2, "each strip needs at least 2 intervals (nstrips <= (n-1)/2)");
+  free_factors(pb->fs);
+  FactorSet& fs = pb->fs;
+  fs.N = N;
+  fs.dirs = dirs;
+  fs.precision = precision;
+  if (dirs & HH_DIR_X) fs.dir_id[fs.nd++] = 0;
+  if (dirs & HH_DIR_Y) fs.dir_id[fs.nd++] = 1;
+  long long band = 0, img = 0, piv = 0, tr = 0;
+  int kl_max = 0;
+  for (int s = 0; s < N; ++s) {
+    const int a = std::max(0, s * m - 1), b = std::min(n - 1, (s + 1) * m + 1);
+    kl_max = std::max(kl_max, b - a + 2);
+  }
+  REQUIRE(kl_max <= 63, "strip band half-width %d exceeds 63 (strips too wide)", kl_max);
+  const int S = 2 * kl_max + 1 <= 64 ? 1 : 2;
+  for (int i = 0; i < fs.nd; ++i) {
+    for (int s = 0; s < N; ++s) {
+      StripDesc sd{};
+      sd.dir = fs.dir_id[i];
+      sd.s = s;
+      sd.a = std::max(0, s * m - 1);
+      const int b = std::min(n - 1, (s + 1) * m + 1);
+      sd.w = b - sd.a + 1;
+      sd.ns = n * sd.w;
+      sd.kl = sd.w + 1;
+      sd.ldab = 3 * sd.kl + 1;
+      sd.has1 = s > 0;
+      sd.has2 = s < N - 1;
+      sd.S = S;
+      const long long NP = sd.ns + HH_PAD;
+      sd.band_off = band;
+      band += (long long)sd.ns * sd.ldab;
+      sd.img_off = img;
+      img += NP * (64LL * (1 + S) + 1);
+      sd.piv_off = piv;
+      piv += NP;
+      sd.tr1_off = sd.has1 ? tr : -1;
+      if (sd.has1) tr += 7LL * n;
+      sd.tr2_off = sd.has2 ? tr : -1;
+      if (sd.has2) tr += 7LL * n;
+      fs.max_ns = std::max(fs.max_ns, sd.ns);
+      fs.max_kl = std::max(fs.max_kl, sd.kl);
+      fs.strips.push_back(sd);
+    }
+  }
+  const size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
+  fs.band_elems = band;
+  fs.img_elems = img;
+  fs.piv_elems = piv;
+  fs.tr_elems = std::max(tr, 1LL);
+  fs.band = dev_alloc(fs.band_elems * es);
+  fs.img = dev_alloc(fs.img_elems * es);
+  fs.piv = (int*)dev_alloc(fs.piv_elems * sizeof(int));
+  fs.tr = dev_alloc(fs.tr_elems * es);
+  fs.d_strips = (StripDesc*)dev_alloc(fs.strips.size() * sizeof(StripDesc));
+  fs.d_err = (int*)dev_alloc(2 * sizeof(int));
+  fs.h_err = {0, 0};
+}
+
+// Queues the strip packing, the batched LU and the image build on st; the
+// zero-pivot flag is copied back asynchronously (read by factor_finish).
+void factor_launch(hh_problem* pb, hipStream_t st) {
+  FactorSet& fs = pb->fs;
+  HH_HIP(hipMemcpyAsync(fs.d_strips, fs.strips.data(), fs.strips.size() * sizeof(StripDesc),
+                        hipMemcpyHostToDevice, st));
+  HH_HIP(hipMemsetAsync(fs.d_err, 0, 2 * sizeof(int), st));
+  launch_pack_strips(pb, st);
+  launch_band_lu(pb, st);
+  HH_HIP(hipMemcpyAsync(fs.h_err.data(), fs.d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+}
+
+// After the factorisation stream has completed: releases the LU work buffer
+// and reports a zero pivot.
+int factor_finish(hh_problem* pb) {
+  FactorSet& fs = pb->fs;
+  dev_free(fs.band);
+  fs.band = nullptr;
+  if (fs.h_err[0]) {
+    const StripDesc& sd = fs.strips[fs.h_err[0] - 1];
+    set_error("zero pivot in the LU of strip %d of direction %c", sd.s + 1, sd.dir == 0 ? 'x' : 'y');
+    return HH_ESINGULAR;
+  }
+  return HH_OK;
+}
+
+// New problem handle with the operator assembled asynchronously on its stream.
+hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n) {
+  REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
+  REQUIRE(n >= 3 && n <= 8193, "n must be in [3, 8193]");
+  REQUIRE(nlayers >= 1 && c_layers != nullptr, "need at least one layer speed");
+  for (int l = 0; l < nlayers; ++l)
+    REQUIRE(std::isfinite(c_layers[l]) && c_layers[l] > 0, "layer speed %d is not positive", l);
+  std::unique_ptr<hh_problem> pb(new hh_problem());
+  pb->n = n;
+  pb->omega = omega;
+  pb->c.assign(c_layers, c_layers + nlayers);
+  HH_HIP(hipGetDevice(&pb->device));
+  HH_HIP(hipStreamCreate(&pb->st[0]));
+  HH_HIP(hipStreamCreate(&pb->st[1]));
+  pb->d_c = (double*)dev_alloc(nlayers * sizeof(double));
+  pb->d_A = (c128*)dev_alloc((size_t)4 * n * n * sizeof(c128));
+  HH_HIP(hipMemcpyAsync(pb->d_c, pb->c.data(), nlayers * sizeof(double), hipMemcpyHostToDevice,
+                        pb->st[0]));
+  {
+    TimedRegion tr(FAM_ASSEMBLE, pb->st[0], (double)n * n * 64.0);
+    launch_assemble(n, omega, nlayers, pb->d_c, pb->d_A, pb->st[0]);
+  }
+  return pb.release();
+}
+
+void problem_destroy(hh_problem* pb) {
+  if (!pb) return;
+  (void)hipStreamSynchronize(pb->st[0]);
+  (void)hipStreamSynchronize(pb->st[1]);
+  free_factors(pb->fs);
+  dev_free(pb->d_A);
+  dev_free(pb->d_c);
+  (void)hipStreamDestroy(pb->st[0]);
+  (void)hipStreamDestroy(pb->st[1]);
+  delete pb;
+}
+
+}  // namespace hh
+
 extern "C" {
 
 const char* hh_last_error(void) { return last_error(); }
@@ -73,27 +207,14 @@ int hh_assemble(double omega, int nlayers, const double* c_layers, int n, hh_pro
   return guard([&]() {
     REQUIRE(out != nullptr, "out is NULL");
     *out = nullptr;
-    REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
-    REQUIRE(n >= 3 && n <= 8193, "n must be in [3, 8193]");
-    REQUIRE(nlayers >= 1 && c_layers != nullptr, "need at least one layer speed");
-    for (int l = 0; l < nlayers; ++l)
-      REQUIRE(std::isfinite(c_layers[l]) && c_layers[l] > 0, "layer speed %d is not positive", l);
-    std::unique_ptr<hh_problem> pb(new hh_problem());
-    pb->n = n;
-    pb->omega = omega;
-    pb->c.assign(c_layers, c_layers + nlayers);
-    HH_HIP(hipGetDevice(&pb->device));
-    HH_HIP(hipStreamCreate(&pb->st[0]));
-    HH_HIP(hipStreamCreate(&pb->st[1]));
-    pb->d_c = (double*)dev_alloc(nlayers * sizeof(double));
-    pb->d_A = (c128*)dev_alloc((size_t)4 * n * n * sizeof(c128));
-    HH_HIP(hipMemcpyAsync(pb->d_c, c_layers, nlayers * sizeof(double), hipMemcpyHostToDevice, pb->st[0]));
-    {
-      TimedRegion tr(FAM_ASSEMBLE, pb->st[0], (double)n * n * 64.0);
-      launch_assemble(n, omega, nlayers, pb->d_c, pb->d_A, pb->st[0]);
+    hh_problem* pb = problem_create(omega, nlayers, c_layers, n);
+    hipError_t e = hipStreamSynchronize(pb->st[0]);
+    if (e != hipSuccess) {
+      problem_destroy(pb);
+      set_error("assembly failed: %s", hipGetErrorString(e));
+      return HH_EDEVICE;
     }
-    HH_HIP(hipStreamSynchronize(pb->st[0]));
-    *out = pb.release();
+    *out = pb;
     return HH_OK;
   });
 }
@@ -110,71 +231,10 @@ int hh_load_vector(hh_problem* pb, int nvec, const hh_c128* f, hh_c128* b) {
 int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
   return guard([&]() {
     REQUIRE(pb != nullptr, "problem is NULL");
-    REQUIRE(dirs >= 1 && dirs <= 3, "dirs must be HH_DIR_X, HH_DIR_Y or both");
-    REQUIRE(precision == HH_FP64 || precision == HH_FP32, "precision must be HH_FP64 or HH_FP32");
-    const int n = pb->n, N = nstrips;
-    REQUIRE(N >= 1 && (n - 1) % N == 0, "(n-1) = %d is not divisible by nstrips = %d", n - 1, N);
-    const int m = (n - 1) / N;
-    REQUIRE(N == 1 || m >= 2, "each strip needs at least 2 intervals (nstrips <= (n-1)/2)");
-    free_factors(pb->fs);
-    FactorSet& fs = pb->fs;
-    fs.N = N;
-    fs.dirs = dirs;
-    fs.precision = precision;
-    if (dirs & HH_DIR_X) fs.dir_id[fs.nd++] = 0;
-    if (dirs & HH_DIR_Y) fs.dir_id[fs.nd++] = 1;
-    long long band = 0, piv = 0, tr = 0;
-    for (int i = 0; i < fs.nd; ++i) {
-      for (int s = 0; s < N; ++s) {
-        StripDesc sd{};
-        sd.dir = fs.dir_id[i];
-        sd.s = s;
-        sd.a = std::max(0, s * m - 1);
-        const int b = std::min(n - 1, (s + 1) * m + 1);
-        sd.w = b - sd.a + 1;
-        sd.ns = n * sd.w;
-        sd.kl = sd.w + 1;
-        sd.ldab = 3 * sd.kl + 1;
-        sd.has1 = s > 0;
-        sd.has2 = s < N - 1;
-        REQUIRE(sd.kl <= 63, "strip band half-width %d exceeds 63 (strips too wide)", sd.kl);
-        sd.band_off = band;
-        band += (long long)sd.ns * sd.ldab;
-        sd.piv_off = piv;
-        piv += sd.ns;
-        sd.tr1_off = sd.has1 ? tr : -1;
-        if (sd.has1) tr += 7LL * n;
-        sd.tr2_off = sd.has2 ? tr : -1;
-        if (sd.has2) tr += 7LL * n;
-        fs.max_ns = std::max(fs.max_ns, sd.ns);
-        fs.max_kl = std::max(fs.max_kl, sd.kl);
-        fs.strips.push_back(sd);
-      }
-    }
-    const size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
-    fs.band_elems = band;
-    fs.piv_elems = piv;
-    fs.tr_elems = std::max(tr, 1LL);
-    fs.band = dev_alloc(fs.band_elems * es);
-    fs.piv = (int*)dev_alloc(fs.piv_elems * sizeof(int));
-    fs.tr = dev_alloc(fs.tr_elems * es);
-    fs.d_strips = (StripDesc*)dev_alloc(fs.strips.size() * sizeof(StripDesc));
-    fs.d_err = (int*)dev_alloc(2 * sizeof(int));
-    hipStream_t st = pb->st[0];
-    HH_HIP(hipMemcpyAsync(fs.d_strips, fs.strips.data(), fs.strips.size() * sizeof(StripDesc),
-                          hipMemcpyHostToDevice, st));
-    HH_HIP(hipMemsetAsync(fs.d_err, 0, 2 * sizeof(int), st));
-    launch_pack_strips(pb, st);
-    launch_band_lu(pb, st);
-    int err[2] = {0, 0};
-    HH_HIP(hipMemcpyAsync(err, fs.d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HH_HIP(hipStreamSynchronize(st));
-    if (err[0]) {
-      const StripDesc& sd = fs.strips[err[0] - 1];
-      set_error("zero pivot in the LU of strip %d of direction %c", sd.s + 1, sd.dir == 0 ? 'x' : 'y');
-      return HH_ESINGULAR;
-    }
-    return HH_OK;
+    factor_setup(pb, dirs, nstrips, precision);
+    factor_launch(pb, pb->st[0]);
+    HH_HIP(hipStreamSynchronize(pb->st[0]));
+    return factor_finish(pb);
   });
 }
 
@@ -217,23 +277,39 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
     void* rho = dev_alloc((size_t)nvec * fs.max_ns * es);
     void* g1 = dev_alloc((size_t)nvec * fs.N * pb->n * es);
     void* zs = fs.precision == HH_FP64 ? (void*)z : dev_alloc((size_t)nvec * len * es);
-    std::vector<SweepTask> tasks(nvec);
-    for (int v = 0; v < nvec; ++v) {
-      SweepTask& tk = tasks[v];
-      tk.strips = fs.d_strips + (size_t)i * fs.N;
-      tk.band = fs.band;
+    // one right-hand side per workgroup (a two-chain workgroup would take an
+    // odd chain's partner on scratch buffers)
+    const int C = 1;
+    const int ntask = (nvec + C - 1) / C;
+    const int nchain = ntask * C;
+    void* rho2 = nchain > nvec ? dev_alloc((size_t)fs.max_ns * es) : nullptr;
+    void* g12 = nchain > nvec ? dev_alloc((size_t)fs.N * pb->n * es) : nullptr;
+    void* z2 = nchain > nvec ? dev_alloc((size_t)len * es) : nullptr;
+    std::vector<SweepTask> tasks(ntask);
+    for (int v = 0; v < nchain; ++v) {
+      SweepTask& tk = tasks[v / C];
+      SweepChain& ch = tk.ch[v % C];
+      const int src = std::min(v, nvec - 1);
+      ch.strips = fs.d_strips + (size_t)i * fs.N;
+      ch.r = (const c128*)r + src * len;
+      if (v < nvec) {
+        ch.z = (char*)zs + v * len * es;
+        ch.rho = (char*)rho + (size_t)v * fs.max_ns * es;
+        ch.g1 = (char*)g1 + (size_t)v * fs.N * pb->n * es;
+      } else {
+        ch.z = z2;
+        ch.rho = rho2;
+        ch.g1 = g12;
+      }
+      tk.img = fs.img;
       tk.piv = fs.piv;
       tk.tr = fs.tr;
-      tk.r = (const c128*)r + v * len;
-      tk.z = (char*)zs + v * len * es;
-      tk.rho = (char*)rho + (size_t)v * fs.max_ns * es;
-      tk.g1 = (char*)g1 + (size_t)v * fs.N * pb->n * es;
       tk.n = pb->n;
       tk.N = fs.N;
     }
-    SweepTask* d_tasks = (SweepTask*)dev_alloc(nvec * sizeof(SweepTask));
+    SweepTask* d_tasks = (SweepTask*)dev_alloc(ntask * sizeof(SweepTask));
     hipStream_t st = pb->st[0];
-    HH_HIP(hipMemcpyAsync(d_tasks, tasks.data(), nvec * sizeof(SweepTask), hipMemcpyHostToDevice, st));
+    HH_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntask * sizeof(SweepTask), hipMemcpyHostToDevice, st));
     {
       double bytes = 0;
       for (int q = 0; q < fs.N; ++q) {
@@ -242,13 +318,16 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
         bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
       }
       TimedRegion tr(FAM_SWEEP, st, bytes);
-      launch_sweep(d_tasks, nvec, fs.precision, fs.max_kl, st);
+      launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].S, C, st);
     }
     if (fs.precision != HH_FP64) launch_widen((const c64*)zs, (c128*)z, nvec * len, st);
     HH_HIP(hipStreamSynchronize(st));
     dev_free(d_tasks);
     dev_free(rho);
     dev_free(g1);
+    dev_free(rho2);
+    dev_free(g12);
+    dev_free(z2);
     if (zs != (void*)z) dev_free(zs);
     return HH_OK;
   });
@@ -343,14 +422,7 @@ int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit
 int hh_free(hh_problem* pb) {
   if (!pb) return HH_OK;
   return guard([&]() {
-    (void)hipStreamSynchronize(pb->st[0]);
-    (void)hipStreamSynchronize(pb->st[1]);
-    free_factors(pb->fs);
-    dev_free(pb->d_A);
-    dev_free(pb->d_c);
-    (void)hipStreamDestroy(pb->st[0]);
-    (void)hipStreamDestroy(pb->st[1]);
-    delete pb;
+    problem_destroy(pb);
     return HH_OK;
   });
 }

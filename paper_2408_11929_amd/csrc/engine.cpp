@@ -210,7 +210,7 @@ void Engine::begin(std::vector<Solve*>& solves) {
   for (Solve* s : solves) {
     s->k = 0;
     s->m = 1;
-    s->done = s->converged = s->breakdown = false;
+    s->done = s->converged = s->breakdown = s->finalized = false;
     s->deflated = 0;
     const FactorSet& fs = s->pb->fs;
     s->t = fs.nd;
@@ -290,36 +290,86 @@ void Engine::step(std::vector<Solve*>& solves) {
   for (Solve* s : live) ensure_capacity(s);
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
 
-  // 1. sweeps: every preconditioner of every solve; grouped by precision and band class
-  struct Group {
-    std::vector<SweepTask> tasks;
-    int klmax = 0;
+  // 1. sweeps: every preconditioner of every solve.  Chains of the same
+  // problem are paired into two-chain workgroups (same strip sizes); an odd
+  // chain out gets a partner on scratch buffers.  Launch kinds are keyed by
+  // (precision, lane slots S, chains per task C).
+  struct Chain {
+    Solve* s;
+    int i;
   };
-  Group grp[2][2];  // [precision][wide band]
+  std::vector<std::pair<const hh_problem*, std::vector<Chain>>> by_problem;
   for (Solve* s : live) {
-    const FactorSet& fs = s->pb->fs;
-    const size_t es = esz_of(s->prec);
-    for (int i = 0; i < s->t; ++i) {
+    auto it = std::find_if(by_problem.begin(), by_problem.end(),
+                           [&](const auto& e) { return e.first == s->pb; });
+    if (it == by_problem.end()) {
+      by_problem.push_back({s->pb, {}});
+      it = by_problem.end() - 1;
+    }
+    for (int i = 0; i < s->t; ++i) it->second.push_back({s, i});
+  }
+  struct Kind {
+    std::vector<SweepTask> tasks;
+    int prec, S, C;
+  };
+  std::vector<Kind> kinds;
+  auto kind_of = [&](int prec, int S, int C) -> Kind& {
+    for (auto& k : kinds)
+      if (k.prec == prec && k.S == S && k.C == C) return k;
+    kinds.push_back({{}, prec, S, C});
+    return kinds.back();
+  };
+  size_t total_chains = 0;
+  for (auto& bp : by_problem) total_chains += bp.second.size();
+  std::vector<void*> dummies;
+  for (auto& bp : by_problem) {
+    const hh_problem* pb = bp.first;
+    const FactorSet& fs = pb->fs;
+    const size_t es = esz_of(fs.precision);
+    // One chain per wave: interleaving two chains in one wave serialises on
+    // the lane-select register and is slower than two independent waves.
+    const int C = 1;
+    (void)total_chains;
+    Kind& K = kind_of(fs.precision, fs.strips[0].S, C);
+    auto chain_of = [&](const Chain& ch) {
+      SweepChain c{};
+      Solve* s = ch.s;
+      c.strips = fs.d_strips + (size_t)ch.i * fs.N;
+      c.r = s->V + (size_t)s->inputs[ch.i] * s->len;
+      c.z = (char*)s->Z + ((size_t)s->k * s->t + ch.i) * s->len * es;
+      c.rho = (char*)s->rho + (size_t)ch.i * fs.max_ns * es;
+      c.g1 = (char*)s->g1 + (size_t)ch.i * fs.N * pb->n * es;
+      return c;
+    };
+    const auto& chs = bp.second;
+    for (size_t q = 0; q < chs.size(); q += C) {
       SweepTask tk{};
-      tk.strips = fs.d_strips + (size_t)i * fs.N;
-      tk.band = fs.band;
+      tk.img = fs.img;
       tk.piv = fs.piv;
       tk.tr = fs.tr;
-      tk.r = s->V + (size_t)s->inputs[i] * s->len;
-      tk.z = (char*)s->Z + ((size_t)s->k * s->t + i) * s->len * es;
-      tk.rho = (char*)s->rho + (size_t)i * fs.max_ns * es;
-      tk.g1 = (char*)s->g1 + (size_t)i * fs.N * s->pb->n * es;
-      tk.n = s->pb->n;
+      tk.n = pb->n;
       tk.N = fs.N;
-      const int wide = 2 * fs.max_kl + 1 > 64 ? 1 : 0;
-      Group& G = grp[s->prec == HH_FP64 ? 0 : 1][wide];
-      G.tasks.push_back(tk);
-      G.klmax = std::max(G.klmax, fs.max_kl);
+      tk.ch[0] = chain_of(chs[q]);
+      if (C == 2) {
+        if (q + 1 < chs.size()) {
+          tk.ch[1] = chain_of(chs[q + 1]);
+        } else {  // partner on scratch: same input, discarded output
+          SweepChain d = tk.ch[0];
+          const long long len = (long long)pb->n * pb->n;
+          d.z = dev_alloc((size_t)len * es);
+          d.rho = dev_alloc((size_t)fs.max_ns * es);
+          d.g1 = dev_alloc((size_t)fs.N * pb->n * es);
+          dummies.push_back(d.z);
+          dummies.push_back(d.rho);
+          dummies.push_back(d.g1);
+          tk.ch[1] = d;
+        }
+      }
+      K.tasks.push_back(tk);
     }
   }
-  SweepTask* dsw[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) dsw[a][b] = grp[a][b].tasks.empty() ? nullptr : stage(grp[a][b].tasks, staged_);
+  std::vector<SweepTask*> dsw(kinds.size());
+  for (size_t q = 0; q < kinds.size(); ++q) dsw[q] = stage(kinds[q].tasks, staged_);
 
   // 2. SpMV: W = A Z_k into the basis slots m..m+t-1
   std::vector<SpmvTask> sp[2];
@@ -472,11 +522,9 @@ void Engine::step(std::vector<Solve*>& solves) {
         }
     }
     TimedRegion tr(FAM_SWEEP, st_, bytes);
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b)
-        if (dsw[a][b])
-          launch_sweep(DEV(dsw[a][b]), (int)grp[a][b].tasks.size(), a == 0 ? HH_FP64 : HH_FP32,
-                       grp[a][b].klmax, st_);
+    for (size_t q = 0; q < kinds.size(); ++q)
+      launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].S, kinds[q].C,
+                   st_);
   }
   {
     double bytes = 0;
@@ -519,6 +567,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     HH_HIP(hipMemcpyAsync(flags[q].data(), s->flags, s->t * sizeof(int), hipMemcpyDeviceToHost, st_));
   }
   HH_HIP(hipStreamSynchronize(st_));
+  for (void* d : dummies) dev_free(d);
   for (size_t q = 0; q < live.size(); ++q) {
     Solve* s = live[q];
     HdLayout L(s->hcap, s->t);
@@ -561,7 +610,7 @@ void Engine::step(std::vector<Solve*>& solves) {
 void Engine::finish(std::vector<Solve*>& solves) {
   std::vector<Solve*> fin;
   for (Solve* s : solves)
-    if (s->done) fin.push_back(s);
+    if (s->done && !s->finalized) fin.push_back(s);
   if (fin.empty()) return;
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
   std::vector<CombTask> ct[2];
@@ -634,6 +683,7 @@ void Engine::finish(std::vector<Solve*>& solves) {
   for (size_t q = 0; q < fin.size(); ++q) {
     Solve* s = fin[q];
     s->res_true = s->beta > 0 ? std::sqrt(std::max(0.0, nr[q].real())) / s->beta : 0.0;
+    s->finalized = true;
   }
 }
 

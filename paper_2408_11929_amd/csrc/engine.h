@@ -71,7 +71,7 @@ struct Solve {
   c128* ydev = nullptr;
   int inputs[4] = {0, 0, 0, 0};
   LeastSquares ls;
-  bool done = false, converged = false, breakdown = false;
+  bool done = false, converged = false, breakdown = false, finalized = false;
   int deflated = 0;
   double res_est = 0, res_true = 0;
   std::vector<zd> hbuf;   // host copy of Hd

@@ -12,10 +12,15 @@
 //
 // Pivot rule: largest |Re| + |Im| in the column, first index on ties.
 //
-// After the elimination a second pass rewrites every column into the form the
-// sweep kernels read: position kv holds 1/U(j,j), positions 0..kv-1 hold
-// U(i,j)/U(j,j) (columns of U scaled by the inverse pivot), positions
-// kv+1..kv+kl the multipliers of L.
+// After the elimination a second pass writes the "solve image" the sweep
+// kernels stream through, one 64-lane row per substitution step so that a step
+// is one coalesced load (NP = ns + HH_PAD steps, zero rows past the end):
+//   Lm[j][l]       multiplier L(j+c, j), c = (l - j) mod 64, if 1 <= c <= kl
+//   Um[J][k][l]    U(j-c, j) / U(j, j) for column j = ns-1-J,
+//                  c = 64 k + ((l - J) mod 64), if 1 <= c <= 2 kl   (k < S)
+//   rd[J]          1 / U(j, j)
+// Lane l then always holds the coefficient of the window element it owns.
+// The pivot list is padded with identity interchanges.
 #include "hh_internal.h"
 
 namespace hh {
@@ -138,18 +143,38 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restr
   }
 }
 
-// Scale U's columns by the inverse pivot and store the inverse on the diagonal.
+// Solve image of every strip (layout above).  grid = (NP*64 / 256, strips).
 template <class T>
-__global__ void k_band_finalize(const StripDesc* __restrict__ strips, cx<T>* __restrict__ band) {
+__global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>* __restrict__ band,
+                              cx<T>* __restrict__ img, int* __restrict__ pivbuf) {
   const StripDesc sd = strips[blockIdx.y];
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= sd.ns) return;
-  const int kv = 2 * sd.kl;
-  cx<T>* col = band + sd.band_off + (long long)j * sd.ldab;
-  cx<T> d = col[kv];
-  cx<T> rd = (d.re == (T)0 && d.im == (T)0) ? mk((T)0, (T)0) : cinv(d);
-  for (int p = 0; p < kv; ++p) col[p] = col[p] * rd;
-  col[kv] = rd;
+  const int ns = sd.ns, NP = ns + HH_PAD, kl = sd.kl, kv = 2 * kl, S = sd.S, ldab = sd.ldab;
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)NP * 64) return;
+  const int j = (int)(e >> 6), l = (int)(e & 63);
+  const cx<T> zero = mk((T)0, (T)0);
+  const cx<T>* ab = band + sd.band_off;
+  cx<T>* Lm = img + sd.img_off;
+  cx<T>* Um = Lm + (long long)NP * 64;
+  cx<T>* rdg = Um + (long long)NP * 64 * S;
+  int c = (l - (j & 63)) & 63;
+  Lm[e] = (j < ns && c >= 1 && c <= kl && j + c < ns) ? ab[(long long)j * ldab + kv + c] : zero;
+  const int col = ns - 1 - j;  // step J = j of the back substitution
+  cx<T> rd = zero;
+  if (j < ns) {
+    const cx<T> d = ab[(long long)col * ldab + kv];
+    rd = (d.re == (T)0 && d.im == (T)0) ? zero : cinv(d);
+  }
+  for (int k = 0; k < S; ++k) {
+    c = 64 * k + ((l - (j & 63)) & 63);
+    cx<T> v = zero;
+    if (j < ns && c >= 1 && c <= kv && j + c < ns) v = ab[(long long)col * ldab + kv - c] * rd;
+    Um[((long long)j * S + k) * 64 + l] = v;
+  }
+  if (l == 0) {
+    rdg[j] = rd;
+    if (j >= ns) pivbuf[sd.piv_off + j] = j;
+  }
 }
 
 }  // namespace
@@ -168,16 +193,16 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
     hipLaunchKernelGGL(k_band_lu<double>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
                        (c128*)fs.band, fs.piv, fs.d_err);
     HH_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_band_finalize<double>, dim3((fs.max_ns + 255) / 256, nstr), dim3(256), 0,
-                       st, fs.d_strips, (c128*)fs.band);
+    hipLaunchKernelGGL(k_build_image<double>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
+                       dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv);
   } else {
     HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_band_lu<float>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
                        (c64*)fs.band, fs.piv, fs.d_err);
     HH_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_band_finalize<float>, dim3((fs.max_ns + 255) / 256, nstr), dim3(256), 0,
-                       st, fs.d_strips, (c64*)fs.band);
+    hipLaunchKernelGGL(k_build_image<float>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
+                       dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv);
   }
   HH_HIP(hipGetLastError());
 }

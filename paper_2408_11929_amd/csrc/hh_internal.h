@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <array>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -103,12 +104,17 @@ struct StripDesc {
   int ldab;       // band column stride 3*kl + 1
   int has1;       // interface Gamma_{s,1} (short index 0) present
   int has2;       // interface Gamma_{s,2} (short index w-1) present
-  int pad;
-  long long band_off;  // complex elements into the factor buffer
-  long long piv_off;   // ints into the pivot buffer
+  int S;          // lane slots of the back-substitution window (2 kl + 1 <= 64 S)
+  long long band_off;  // complex elements into the LU work buffer (factorisation only)
+  long long img_off;   // complex elements into the solve image (see factor.hip)
+  long long piv_off;   // ints into the pivot buffer (ns + HH_PAD entries)
   long long tr1_off;   // complex elements into the transmission buffer (n*7), or -1
   long long tr2_off;
 };
+
+// Zero steps appended to every strip's solve image and pivot list, so that the
+// substitution loops may run and prefetch past the end without bounds checks.
+constexpr int HH_PAD = 64;
 
 // Strip factors of every strip of every factored direction.
 struct FactorSet {
@@ -119,11 +125,13 @@ struct FactorSet {
   int dir_id[2] = {-1, -1}; // direction (0/1) of preconditioner slot 0/1
   std::vector<StripDesc> strips;  // dir-major: strips[d*N + s]
   StripDesc* d_strips = nullptr;  // device copy
-  void* band = nullptr;            // complex<precision> elements
+  void* band = nullptr;            // LU work buffer, freed after the image is built
+  void* img = nullptr;             // solve image, complex<precision> elements
   int* piv = nullptr;
   void* tr = nullptr;              // transmission stencils, complex<precision>
   int* d_err = nullptr;            // [0] = 1 + strip index of first zero pivot, [1] = column
-  size_t band_elems = 0, piv_elems = 0, tr_elems = 0;
+  std::array<int, 2> h_err{{0, 0}};  // host copy, valid once the factor stream completed
+  size_t band_elems = 0, img_elems = 0, piv_elems = 0, tr_elems = 0;
   int max_ns = 0, max_kl = 0;
   size_t bytes() const;
 };
@@ -164,9 +172,19 @@ struct TimedRegion {
 enum { FAM_SWEEP = 0, FAM_SPMV, FAM_FACTOR, FAM_ORTH, FAM_ASSEMBLE, FAM_COUNT };
 void timing_flush();
 
+// ---------------------------------------------------------------- problems
+// Internal halves of hh_assemble / hh_factor_sweeps / hh_free (capi.cpp),
+// also driven asynchronously by the serving loop.
+void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision);
+void factor_launch(hh_problem* pb, hipStream_t st);
+int factor_finish(hh_problem* pb);
+hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n);
+void problem_destroy(hh_problem* pb);
+
 // ---------------------------------------------------------------- memory
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+size_t dev_live_bytes();
 
 // ---------------------------------------------------------------- kernels
 // assemble.hip
@@ -179,21 +197,26 @@ void launch_pack_strips(const hh_problem* pb, hipStream_t st);
 void launch_band_lu(const hh_problem* pb, hipStream_t st);
 
 // sweep.hip
-struct SweepTask {
-  const StripDesc* strips;  // N descriptors of one direction (device)
-  const void* band;
-  const int* piv;
-  const void* tr;
+// One preconditioner application (one direction, one right-hand side).
+struct SweepChain {
+  const StripDesc* strips;  // N descriptors of the direction (device)
   const c128* r;            // FP64 input, n*n
   void* z;                  // output in sweep precision, n*n
   void* rho;                // scratch, >= max ns elements of sweep precision
   void* g1;                 // scratch, N*n elements of sweep precision
+};
+// Up to two chains that run interleaved in one wave; both must walk strips of
+// identical sizes (the same problem and strip count).
+struct SweepTask {
+  SweepChain ch[2];
+  const void* img;
+  const int* piv;
+  const void* tr;
   int n;
   int N;
-  int pad[2];
 };
-// All tasks share the precision and have kl <= klmax.
-void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int klmax,
+// All tasks share the precision and the slot count S.  C = chains per task.
+void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int S, int C,
                   hipStream_t st);
 // Single strip solve (test hook): rhs/x in FP64, strip-local order.
 void launch_strip_solve(const hh_problem* pb, int strip_index, const c128* rhs, c128* x,

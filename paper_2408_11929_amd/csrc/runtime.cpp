@@ -152,7 +152,7 @@ TimingFamily timing_get(int fam) {
 // ------------------------------------------------------------ sizes
 size_t FactorSet::bytes() const {
   size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
-  return band_elems * es + piv_elems * sizeof(int) + tr_elems * es +
+  return band_elems * es + img_elems * es + piv_elems * sizeof(int) + tr_elems * es +
          strips.size() * sizeof(StripDesc) + 2 * sizeof(int);
 }
 

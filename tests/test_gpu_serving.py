@@ -1,0 +1,106 @@
+"""Serving loop (continuous batching) through the C ABI: each result is the same
+alone and in the mix, admission respects the HBM budget, and a request that
+fails to converge does not disturb the others."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+hh = pytest.importorskip("paper_2408_11929_amd")
+
+MIX = [
+    # n, N, omega, layers, nsrc, precision
+    (33, 4, 15.0, [1.0, 2.0], 2, hh.HH_FP64),
+    (41, 5, 22.0, [1.4, 1.1, 2.5], 1, hh.HH_FP32),
+    (65, 8, 30.0, [1.0, 1.8, 2.6, 1.2], 3, hh.HH_FP32),
+    (49, 6, 18.0, [2.0], 2, hh.HH_FP64),
+]
+
+
+def sources(n, nsrc, seed):
+    pos = wl.source_positions(seed, nsrc)
+    f = np.stack([wl.gaussian_field(n, x0, y0, 0.04) for x0, y0 in pos])
+    return torch.from_numpy(f).to("cuda")
+
+
+def alone(n, N, omega, c, f, prec, tol, maxit):
+    pb = hh.Problem(omega, c, n)
+    b = pb.load_vector(f)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+    x, st, rc = pb.mpgmres(b, tol=tol, maxit=maxit)
+    pb.free()
+    return x.cpu().numpy(), st, rc
+
+
+def wait_all(srv, tickets, timeout=60.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < timeout, "serving loop made no progress"
+        time.sleep(0.002)
+    return out
+
+
+def test_results_identical_alone_and_in_the_mix():
+    srv = hh.Server(hbm_budget=8 << 30, max_active=8)
+    tickets, xs, refs = [], [], []
+    for k, (n, N, omega, c, nsrc, prec) in enumerate(MIX):
+        f = sources(n, nsrc, 20 + k)
+        x = torch.empty_like(f)
+        tickets.append(srv.submit(n, omega, c, f, x, nstrips=N, precision=prec, tol=1e-8, maxit=100))
+        xs.append(x)
+        refs.append(alone(n, N, omega, c, f, prec, 1e-8, 100))
+    res = wait_all(srv, tickets)
+    for t, x, (xr, st, rc) in zip(tickets, xs, refs):
+        r = res[t]
+        assert r["status"] == hh.HH_OK
+        assert r["iterations_max"] == max(s["iterations"] for s in st)
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        got = x.cpu().numpy()
+        assert np.array_equal(got, xr), np.abs(got - xr).max()
+    srv.destroy()
+
+
+def test_admission_limits_and_oversized_request_is_refused():
+    n, N, omega, c = 33, 4, 15.0, [1.0]
+    f = sources(n, 1, 3)
+    x1, x2 = torch.empty_like(f), torch.empty_like(f)
+    srv = hh.Server(hbm_budget=64 << 20, max_active=1)  # one request at a time
+    t1 = srv.submit(n, omega, c, f, x1, nstrips=N, precision=hh.HH_FP32, tol=1e-8, maxit=50)
+    t2 = srv.submit(n, omega, c, f, x2, nstrips=N, precision=hh.HH_FP32, tol=1e-8, maxit=50)
+    res = wait_all(srv, [t1, t2])
+    assert res[t1]["status"] == hh.HH_OK and res[t2]["status"] == hh.HH_OK
+    assert res[t2]["t_admit"] >= res[t1]["t_done"]
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    big = sources(321, 4, 4)
+    xb = torch.empty_like(big)
+    with pytest.raises(hh.HHError) as e:
+        srv.submit(321, 100.0, c, big, xb, nstrips=16, precision=hh.HH_FP64, tol=1e-6, maxit=50)
+    assert e.value.code == hh.HH_EBUDGET
+    srv.destroy()
+
+
+def test_failing_request_does_not_disturb_others():
+    srv = hh.Server(hbm_budget=8 << 30, max_active=8)
+    n, N, omega, c = 41, 5, 22.0, [1.0, 2.0]
+    f = sources(n, 2, 7)
+    good, bad = torch.empty_like(f), torch.empty_like(f)
+    tg = srv.submit(n, omega, c, f, good, nstrips=N, precision=hh.HH_FP32, tol=1e-8, maxit=100)
+    tb = srv.submit(n, omega, c, f, bad, nstrips=N, precision=hh.HH_FP32, tol=1e-14, maxit=2)
+    res = wait_all(srv, [tg, tb])
+    assert res[tb]["status"] == hh.HH_ENOCONV
+    assert res[tg]["status"] == hh.HH_OK
+    xr, st, rc = alone(n, N, omega, c, f, hh.HH_FP32, 1e-8, 100)
+    assert np.array_equal(good.cpu().numpy(), xr)
+    with pytest.raises(hh.HHError):
+        srv.submit(40, omega, c, f, good, nstrips=N)  # (n-1) not divisible by N
+    srv.destroy()
