@@ -78,6 +78,62 @@ def traffic_record(kernel_src):
         return None
 
 
+def serving_run(hh, torch, count=24, rate=8.0, max_active=16, budget_gb=96):
+    """Poisson arrivals of mixed requests (n in {161, 321, 641}, 4-12 layers,
+    1-16 sources, complex64 strips, 10 points per wavelength) through the
+    continuous-batching server; latency = completion - submission."""
+    import workloads as wl
+    reqs = wl.serving_stream(count=count, seed=4)
+    arrivals = wl.poisson_arrivals(5, rate, count)
+    fs = [torch.from_numpy(r.f()).to("cuda") for r in reqs]
+    xs = [torch.empty_like(f) for f in fs]
+    torch.cuda.synchronize()
+    srv = hh.Server(hbm_budget=int(budget_gb) << 30, max_active=max_active)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, f, x, ta in zip(reqs, fs, xs, arrivals):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.0005)
+        tickets.append(srv.submit(r.n, r.omega, r.c_layers, f, x, nstrips=r.nstrips,
+                                  precision=hh.HH_FP32, tol=r.tol, maxit=r.maxit))
+    done = {}
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                res = srv.poll(t)
+                if res is not None:
+                    done[t] = res
+        time.sleep(0.001)
+    makespan = time.perf_counter() - t0
+    srv.destroy()
+    lat = [done[t]["t_done"] - done[t]["t_submit"] for t in tickets]
+    rhs = sum(r.nsrc for r in reqs)
+    return {"requests": count, "rhs": rhs, "arrival_rate_per_s": rate, "max_active": max_active,
+            "sizes": sorted({r.n for r in reqs}), "makespan_s": makespan,
+            "solves_per_s": rhs / makespan, "requests_per_s": count / makespan,
+            "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
+            "all_ok": all(done[t]["status"] == hh.HH_OK for t in tickets),
+            "res_true_max": max(done[t]["res_true_max"] for t in tickets)}
+
+
+def kernel_probe(hh, torch):
+    """Short run for hardware-counter passes: one 512 MiB device copy (the
+    calibration kernel: 512 MiB read, 512 MiB written) and one complex64 solve
+    of the benchmark workload (its sweep launches are the measured kernel)."""
+    import workloads as wl
+    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    cfg = wl.layered_321()
+    f_dev = torch.from_numpy(cfg.f()).to("cuda")
+    st, rc = one_solve(hh, torch, cfg, f_dev, hh.HH_FP32)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "iterations": st[0]["iterations"]}))
+
+
 def cpu_baseline(cfg, budget_s=20.0):
     """The oracle (FP64, NumPy/SciPy) on this host's cores: whole solves of the
     same workload until about budget_s seconds of CPU work have been spent."""
@@ -86,6 +142,11 @@ def cpu_baseline(cfg, budget_s=20.0):
     from oracle import mpgmres as omp
     from oracle import strips as ost
     from oracle import sweep as osw
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)   # one core: the count reported below
+    except Exception:
+        limiter = None
     times = []
     t_start = time.perf_counter()
     while True:
@@ -98,13 +159,9 @@ def cpu_baseline(cfg, budget_s=20.0):
         times.append(time.perf_counter() - t0)
         if time.perf_counter() - t_start > budget_s or len(times) >= 5:
             break
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    cores = len(os.sched_getaffinity(0))
-    return {"value": len(times) / sum(times), "unit": "solves/s", "cores": min(cores, threads),
+    if limiter is not None:
+        limiter.unregister()
+    return {"value": len(times) / sum(times), "unit": "solves/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{len(times)} whole solves (assembly, strip LU, MPGMRES) of the benchmark "
                       f"workload, FP64 NumPy/SciPy, {res.iterations} iterations each",
@@ -118,6 +175,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-source batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only the short run used for hardware-counter passes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path "
@@ -129,6 +189,10 @@ def main():
 
     import paper_2408_11929_amd as hh
     import workloads as wl
+
+    if args.kernel_probe:
+        kernel_probe(hh, torch)
+        return
 
     cfg = wl.layered_321()
     f_dev = torch.from_numpy(cfg.f()).to("cuda")
@@ -172,6 +236,8 @@ def main():
                    "res_true_max": max(s["res_true"] for s in stb),
                    "all_converged": all(s["converged"] for s in stb)}
 
+    serving = None if args.no_serve else serving_run(hh, torch)
+
     value = args.steps / wall32
     achieved = sweep["bytes"] / 1e9 / (sweep["ms"] / 1e3) if sweep["ms"] > 0 else 0.0
     traffic = traffic_record(os.path.join(ROOT, "paper_2408_11929_amd", "csrc", "sweep.hip"))
@@ -199,6 +265,7 @@ def main():
                        "iterations": st64[0]["iterations"], "res_true": st64[0]["res_true"]},
         "speedup_vs_plain_fp64": (args.steps / wall32) / (args.steps / wall64),
         "batched": batched,
+        "serving": serving,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in
                                (("sweep", sweep), ("spmv", spmv), ("factor", factor),
                                 ("orth", orth))},
