@@ -52,6 +52,7 @@ void free_factors(FactorSet& fs) {
   dev_free(fs.tr);
   dev_free(fs.d_strips);
   dev_free(fs.d_err);
+  dev_free(fs.d_pflag);
   fs = FactorSet();
 }
 
@@ -104,11 +105,13 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       sd.has1 = s > 0;
       sd.has2 = s < N - 1;
       sd.S = S;
+      sd.KP = blocked_kp(kl_max);
+      sd.gid = (int)fs.strips.size();
       const long long NP = sd.ns + HH_PAD;
       sd.band_off = band;
       band += (long long)sd.ns * sd.ldab;
       sd.img_off = img;
-      img += NP * (64LL * (1 + S) + 1);
+      img += strip_image_elems(sd.ns, S, sd.KP);
       sd.piv_off = piv;
       piv += NP;
       sd.tr1_off = sd.has1 ? tr : -1;
@@ -131,6 +134,7 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
   fs.tr = dev_alloc(fs.tr_elems * es);
   fs.d_strips = (StripDesc*)dev_alloc(fs.strips.size() * sizeof(StripDesc));
   fs.d_err = (int*)dev_alloc(2 * sizeof(int));
+  fs.d_pflag = (int*)dev_alloc(fs.strips.size() * sizeof(int));
   fs.h_err = {0, 0};
 }
 
@@ -141,6 +145,7 @@ void factor_launch(hh_problem* pb, hipStream_t st) {
   HH_HIP(hipMemcpyAsync(fs.d_strips, fs.strips.data(), fs.strips.size() * sizeof(StripDesc),
                         hipMemcpyHostToDevice, st));
   HH_HIP(hipMemsetAsync(fs.d_err, 0, 2 * sizeof(int), st));
+  HH_HIP(hipMemsetAsync(fs.d_pflag, 0, fs.strips.size() * sizeof(int), st));
   launch_pack_strips(pb, st);
   launch_band_lu(pb, st);
   HH_HIP(hipMemcpyAsync(fs.h_err.data(), fs.d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -277,32 +282,19 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
     void* rho = dev_alloc((size_t)nvec * fs.max_ns * es);
     void* g1 = dev_alloc((size_t)nvec * fs.N * pb->n * es);
     void* zs = fs.precision == HH_FP64 ? (void*)z : dev_alloc((size_t)nvec * len * es);
-    // one right-hand side per workgroup (a two-chain workgroup would take an
-    // odd chain's partner on scratch buffers)
-    const int C = 1;
-    const int ntask = (nvec + C - 1) / C;
-    const int nchain = ntask * C;
-    void* rho2 = nchain > nvec ? dev_alloc((size_t)fs.max_ns * es) : nullptr;
-    void* g12 = nchain > nvec ? dev_alloc((size_t)fs.N * pb->n * es) : nullptr;
-    void* z2 = nchain > nvec ? dev_alloc((size_t)len * es) : nullptr;
+    // one right-hand side per workgroup
+    const int ntask = nvec;
     std::vector<SweepTask> tasks(ntask);
-    for (int v = 0; v < nchain; ++v) {
-      SweepTask& tk = tasks[v / C];
-      SweepChain& ch = tk.ch[v % C];
-      const int src = std::min(v, nvec - 1);
-      ch.strips = fs.d_strips + (size_t)i * fs.N;
-      ch.r = (const c128*)r + src * len;
-      if (v < nvec) {
-        ch.z = (char*)zs + v * len * es;
-        ch.rho = (char*)rho + (size_t)v * fs.max_ns * es;
-        ch.g1 = (char*)g1 + (size_t)v * fs.N * pb->n * es;
-      } else {
-        ch.z = z2;
-        ch.rho = rho2;
-        ch.g1 = g12;
-      }
+    for (int v = 0; v < nvec; ++v) {
+      SweepTask& tk = tasks[v];
+      tk.ch.strips = fs.d_strips + (size_t)i * fs.N;
+      tk.ch.r = (const c128*)r + v * len;
+      tk.ch.z = (char*)zs + v * len * es;
+      tk.ch.rho = (char*)rho + (size_t)v * fs.max_ns * es;
+      tk.ch.g1 = (char*)g1 + (size_t)v * fs.N * pb->n * es;
       tk.img = fs.img;
       tk.piv = fs.piv;
+      tk.pflag = fs.d_pflag;
       tk.tr = fs.tr;
       tk.n = pb->n;
       tk.N = fs.N;
@@ -318,16 +310,13 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
         bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
       }
       TimedRegion tr(FAM_SWEEP, st, bytes);
-      launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].S, C, st);
+      launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].KP, pb->n, st);
     }
     if (fs.precision != HH_FP64) launch_widen((const c64*)zs, (c128*)z, nvec * len, st);
     HH_HIP(hipStreamSynchronize(st));
     dev_free(d_tasks);
     dev_free(rho);
     dev_free(g1);
-    dev_free(rho2);
-    dev_free(g12);
-    dev_free(z2);
     if (zs != (void*)z) dev_free(zs);
     return HH_OK;
   });

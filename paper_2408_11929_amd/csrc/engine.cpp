@@ -290,82 +290,39 @@ void Engine::step(std::vector<Solve*>& solves) {
   for (Solve* s : live) ensure_capacity(s);
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
 
-  // 1. sweeps: every preconditioner of every solve.  Chains of the same
-  // problem are paired into two-chain workgroups (same strip sizes); an odd
-  // chain out gets a partner on scratch buffers.  Launch kinds are keyed by
-  // (precision, lane slots S, chains per task C).
-  struct Chain {
-    Solve* s;
-    int i;
-  };
-  std::vector<std::pair<const hh_problem*, std::vector<Chain>>> by_problem;
-  for (Solve* s : live) {
-    auto it = std::find_if(by_problem.begin(), by_problem.end(),
-                           [&](const auto& e) { return e.first == s->pb; });
-    if (it == by_problem.end()) {
-      by_problem.push_back({s->pb, {}});
-      it = by_problem.end() - 1;
-    }
-    for (int i = 0; i < s->t; ++i) it->second.push_back({s, i});
-  }
+  // 1. sweeps: every preconditioner of every solve, one workgroup per chain.
+  // Launch kinds are keyed by (precision, blocked term count KP).
   struct Kind {
     std::vector<SweepTask> tasks;
-    int prec, S, C;
+    int prec, KP, nmax;
   };
   std::vector<Kind> kinds;
-  auto kind_of = [&](int prec, int S, int C) -> Kind& {
-    for (auto& k : kinds)
-      if (k.prec == prec && k.S == S && k.C == C) return k;
-    kinds.push_back({{}, prec, S, C});
-    return kinds.back();
-  };
-  size_t total_chains = 0;
-  for (auto& bp : by_problem) total_chains += bp.second.size();
-  std::vector<void*> dummies;
-  for (auto& bp : by_problem) {
-    const hh_problem* pb = bp.first;
+  for (Solve* s : live) {
+    const hh_problem* pb = s->pb;
     const FactorSet& fs = pb->fs;
     const size_t es = esz_of(fs.precision);
-    // One chain per wave: interleaving two chains in one wave serialises on
-    // the lane-select register and is slower than two independent waves.
-    const int C = 1;
-    (void)total_chains;
-    Kind& K = kind_of(fs.precision, fs.strips[0].S, C);
-    auto chain_of = [&](const Chain& ch) {
-      SweepChain c{};
-      Solve* s = ch.s;
-      c.strips = fs.d_strips + (size_t)ch.i * fs.N;
-      c.r = s->V + (size_t)s->inputs[ch.i] * s->len;
-      c.z = (char*)s->Z + ((size_t)s->k * s->t + ch.i) * s->len * es;
-      c.rho = (char*)s->rho + (size_t)ch.i * fs.max_ns * es;
-      c.g1 = (char*)s->g1 + (size_t)ch.i * fs.N * pb->n * es;
-      return c;
-    };
-    const auto& chs = bp.second;
-    for (size_t q = 0; q < chs.size(); q += C) {
+    const int KP = fs.strips[0].KP;
+    auto it = std::find_if(kinds.begin(), kinds.end(),
+                           [&](const Kind& k) { return k.prec == fs.precision && k.KP == KP; });
+    if (it == kinds.end()) {
+      kinds.push_back({{}, fs.precision, KP, 0});
+      it = kinds.end() - 1;
+    }
+    it->nmax = std::max(it->nmax, pb->n);
+    for (int i = 0; i < s->t; ++i) {
       SweepTask tk{};
+      tk.ch.strips = fs.d_strips + (size_t)i * fs.N;
+      tk.ch.r = s->V + (size_t)s->inputs[i] * s->len;
+      tk.ch.z = (char*)s->Z + ((size_t)s->k * s->t + i) * s->len * es;
+      tk.ch.rho = (char*)s->rho + (size_t)i * fs.max_ns * es;
+      tk.ch.g1 = (char*)s->g1 + (size_t)i * fs.N * pb->n * es;
       tk.img = fs.img;
       tk.piv = fs.piv;
+      tk.pflag = fs.d_pflag;
       tk.tr = fs.tr;
       tk.n = pb->n;
       tk.N = fs.N;
-      tk.ch[0] = chain_of(chs[q]);
-      if (C == 2) {
-        if (q + 1 < chs.size()) {
-          tk.ch[1] = chain_of(chs[q + 1]);
-        } else {  // partner on scratch: same input, discarded output
-          SweepChain d = tk.ch[0];
-          const long long len = (long long)pb->n * pb->n;
-          d.z = dev_alloc((size_t)len * es);
-          d.rho = dev_alloc((size_t)fs.max_ns * es);
-          d.g1 = dev_alloc((size_t)fs.N * pb->n * es);
-          dummies.push_back(d.z);
-          dummies.push_back(d.rho);
-          dummies.push_back(d.g1);
-          tk.ch[1] = d;
-        }
-      }
-      K.tasks.push_back(tk);
+      it->tasks.push_back(tk);
     }
   }
   std::vector<SweepTask*> dsw(kinds.size());
@@ -523,8 +480,8 @@ void Engine::step(std::vector<Solve*>& solves) {
     }
     TimedRegion tr(FAM_SWEEP, st_, bytes);
     for (size_t q = 0; q < kinds.size(); ++q)
-      launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].S, kinds[q].C,
-                   st_);
+      launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].KP,
+                   kinds[q].nmax, st_);
   }
   {
     double bytes = 0;
@@ -567,7 +524,6 @@ void Engine::step(std::vector<Solve*>& solves) {
     HH_HIP(hipMemcpyAsync(flags[q].data(), s->flags, s->t * sizeof(int), hipMemcpyDeviceToHost, st_));
   }
   HH_HIP(hipStreamSynchronize(st_));
-  for (void* d : dummies) dev_free(d);
   for (size_t q = 0; q < live.size(); ++q) {
     Solve* s = live[q];
     HdLayout L(s->hcap, s->t);

@@ -21,6 +21,8 @@
 //   rd[J]          1 / U(j, j)
 // Lane l then always holds the coefficient of the window element it owns.
 // The pivot list is padded with identity interchanges.
+#include <algorithm>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -45,7 +47,8 @@ __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
 template <class T>
 __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restrict__ strips,
                                                         cx<T>* __restrict__ band,
-                                                        int* __restrict__ pivbuf, int* err) {
+                                                        int* __restrict__ pivbuf, int* err,
+                                                        int* __restrict__ pflag) {
   extern __shared__ unsigned char smem_raw[];
   cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
   const StripDesc sd = strips[blockIdx.x];
@@ -100,7 +103,10 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restr
       const bool singular = (pv.re == (T)0 && pv.im == (T)0);
       const cx<T> ipv = singular ? zero : cinv(pv);
       if (singular && tid == 0) atomicCAS(err, 0, (int)blockIdx.x + 1);
-      if (tid == 0) piv[j] = j + rp;
+      if (tid == 0) {
+        piv[j] = j + rp;
+        if (rp != 0) pflag[blockIdx.x] = 1;
+      }
       // retire row j of U (pivot row) and column j of L
       for (int c = tid; c < C; c += LU_THREADS)
         if (j + c < ns) ab[(long long)(j + c) * ldab + kv - c] = W[prp * C + pcol(c)];
@@ -146,7 +152,9 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restr
 // Solve image of every strip (layout above).  grid = (NP*64 / 256, strips).
 template <class T>
 __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>* __restrict__ band,
-                              cx<T>* __restrict__ img, int* __restrict__ pivbuf) {
+                              cx<T>* __restrict__ img, int* __restrict__ pivbuf,
+                              const int* __restrict__ pflag) {
+  if (!pflag[blockIdx.y]) return;  // unpivoted strips use the blocked image
   const StripDesc sd = strips[blockIdx.y];
   const int ns = sd.ns, NP = ns + HH_PAD, kl = sd.kl, kv = 2 * kl, S = sd.S, ldab = sd.ldab;
   const long long e = blockIdx.x * 256LL + threadIdx.x;
@@ -177,10 +185,83 @@ __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>*
   }
 }
 
+// Blocked image of an unpivoted strip.  Without interchanges L is unit lower
+// and U upper triangular, both with half-bandwidth K = kl, and each
+// substitution is the row recurrence
+//     out_i = d_i (in_i - sum_{c=1..K} T(i, c) out_{i-c})
+// (L: T(i, c) = L(i, i-c), d = 1; U in reversed order E = ns-1-j:
+// T(E, c) = U(j, j+c), d = 1/U(j, j)).  For a block of HH_BLK outputs
+// i0..i0+B-1 the outputs are a fixed linear map G of the K previous outputs
+// and the B block inputs: out = G [out_{i0-K..i0-1}; in_{i0..i0+B-1}].
+// Column k of G is obtained by running the block's recurrence on the k-th
+// unit input, in FP64 from the stored factors.  Stored per block as KP rows
+// of 64 lanes: lane l = r + B p holds G(r, p KP + t) in row t, so output r is
+// the sum over its P = 64/B lanes.  grid = (blocks*(K+B) / 128, strips, 2).
+template <class T>
+__global__ __launch_bounds__(128) void k_build_blocked(const StripDesc* __restrict__ strips,
+                                                       const cx<T>* __restrict__ band,
+                                                       cx<T>* __restrict__ img,
+                                                       const int* __restrict__ pflag) {
+  if (pflag[blockIdx.y]) return;
+  constexpr int B = HH_BLK, P = 64 / HH_BLK;
+  const StripDesc sd = strips[blockIdx.y];
+  const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab, KP = sd.KP;
+  const int nb = (ns + B - 1) / B, ncol = K + B;
+  const long long e = blockIdx.x * 128LL + threadIdx.x;
+  if (e >= (long long)nb * ncol) return;
+  const int b = (int)(e / ncol), k = (int)(e % ncol);
+  const bool upper = blockIdx.z == 1;
+  const cx<T>* ab = band + sd.band_off;
+  cx<T>* G = img + sd.img_off + (upper ? blocked_blocks(ns) * KP * 64 : 0);
+  c128 win[64 + B];
+  for (int q = 0; q < K; ++q) win[q] = mk(q == k ? 1.0 : 0.0, 0.0);
+  for (int i = 0; i < B; ++i) {
+    const int g = b * B + i;
+    c128 acc = mk(0.0, 0.0);
+    if (g < ns) {
+      acc = mk((k >= K && k - K == i) ? 1.0 : 0.0, 0.0);
+      for (int c = 1; c <= K && c <= g; ++c) {
+        c128 coef;
+        if (!upper) {
+          const cx<T> v = ab[(long long)(g - c) * ldab + kv + c];
+          coef = mk((double)v.re, (double)v.im);
+        } else {
+          const int j = ns - 1 - g;
+          const cx<T> v = ab[(long long)(j + c) * ldab + kv - c];
+          coef = mk((double)v.re, (double)v.im);
+        }
+        acc = cfms(acc, coef, win[K + i - c]);
+      }
+      // terms reaching before the strip start (g - c < 0) multiply the K
+      // "previous outputs" of block 0, which are zero by definition
+      if (upper) {
+        const int j = ns - 1 - g;
+        const cx<T> d = ab[(long long)j * ldab + kv];
+        const c128 dd = mk((double)d.re, (double)d.im);
+        acc = acc * cinv(dd);
+      }
+    }
+    win[K + i] = acc;
+  }
+  const int p = k / KP, t = k % KP;
+  for (int r = 0; r < B; ++r) {
+    const c128 v = win[K + r];
+    G[((long long)b * KP + t) * 64 + r + B * p] = mk((T)v.re, (T)v.im);
+  }
+}
+
 }  // namespace
+
+dim3 blocked_grid(const FactorSet& fs) {
+  long long cells = 0;
+  for (auto& sd : fs.strips)
+    cells = std::max(cells, (long long)((sd.ns + HH_BLK - 1) / HH_BLK) * (sd.kl + HH_BLK));
+  return dim3((unsigned)((cells + 127) / 128), (unsigned)fs.strips.size(), 2);
+}
 
 void launch_band_lu(const hh_problem* pb, hipStream_t st) {
   const FactorSet& fs = pb->fs;
+  HH_HIP(hipMemsetAsync(fs.img, 0, fs.img_elems * (fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64)), st));
   int nstr = (int)fs.strips.size();
   size_t esz = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
   size_t lds = (size_t)(fs.max_kl + 1) * (2 * fs.max_kl + 1) * esz;
@@ -191,18 +272,24 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
     HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_band_lu<double>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
-                       (c128*)fs.band, fs.piv, fs.d_err);
+                       (c128*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<double>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
-                       dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv);
+                       dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv,
+                       fs.d_pflag);
+    hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(128), 0, st, fs.d_strips,
+                       (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
   } else {
     HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_band_lu<float>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
-                       (c64*)fs.band, fs.piv, fs.d_err);
+                       (c64*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<float>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
-                       dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv);
+                       dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv,
+                       fs.d_pflag);
+    hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(128), 0, st, fs.d_strips,
+                       (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
   }
   HH_HIP(hipGetLastError());
 }

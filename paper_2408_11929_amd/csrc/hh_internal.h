@@ -105,6 +105,8 @@ struct StripDesc {
   int has1;       // interface Gamma_{s,1} (short index 0) present
   int has2;       // interface Gamma_{s,2} (short index w-1) present
   int S;          // lane slots of the back-substitution window (2 kl + 1 <= 64 S)
+  int KP;         // terms per lane of the blocked substitution (see factor.hip)
+  int gid;        // index of this strip in FactorSet::strips
   long long band_off;  // complex elements into the LU work buffer (factorisation only)
   long long img_off;   // complex elements into the solve image (see factor.hip)
   long long piv_off;   // ints into the pivot buffer (ns + HH_PAD entries)
@@ -130,6 +132,7 @@ struct FactorSet {
   int* piv = nullptr;
   void* tr = nullptr;              // transmission stencils, complex<precision>
   int* d_err = nullptr;            // [0] = 1 + strip index of first zero pivot, [1] = column
+  int* d_pflag = nullptr;          // per strip: 1 if the LU interchanged any rows
   std::array<int, 2> h_err{{0, 0}};  // host copy, valid once the factor stream completed
   size_t band_elems = 0, img_elems = 0, piv_elems = 0, tr_elems = 0;
   int max_ns = 0, max_kl = 0;
@@ -205,19 +208,40 @@ struct SweepChain {
   void* rho;                // scratch, >= max ns elements of sweep precision
   void* g1;                 // scratch, N*n elements of sweep precision
 };
-// Up to two chains that run interleaved in one wave; both must walk strips of
-// identical sizes (the same problem and strip count).
+// One double sweep: one chain over the N strips of a direction.
 struct SweepTask {
-  SweepChain ch[2];
+  SweepChain ch;
   const void* img;
   const int* piv;
+  const int* pflag;
   const void* tr;
   int n;
   int N;
 };
-// All tasks share the precision and the slot count S.  C = chains per task.
-void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int S, int C,
+// All tasks share the precision and the blocked-term count KP (which fixes
+// the slot count S of the pivoted path); nmax = largest n among the tasks
+// (sizes the LDS).
+void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int nmax,
                   hipStream_t st);
+// Blocked substitution: block size and terms per lane for band half-width kl.
+// KP terms per lane cover the K + HH_BLK columns of a block map over the 64/HH_BLK
+// lanes of one output row; KP <= 12 exactly when 2 kl + 1 <= 64 (one lane-major
+// row of the pivoted image).
+constexpr int HH_BLK = 16;
+inline int blocked_kp(int kl) {
+  return kl <= 16 ? 8 : kl <= 24 ? 10 : kl <= 31 ? 12 : kl <= 48 ? 16 : 20;
+}
+// Blocks stored per triangle: whole 64-row chunks plus eight zero blocks, so the
+// substitution (an even number of steps of up to four blocks, maps requested
+// one step ahead) reads no bounds-tested memory.
+__host__ __device__ inline long long blocked_blocks(long long ns) { return 4 * ((ns + 63) / 64) + 8; }
+// Image elements of one strip: the larger of the pivoted (lane-major) and the
+// unpivoted (blocked) layouts; which one is built is decided by the LU.
+inline long long strip_image_elems(long long ns, int S, int KP) {
+  const long long lane_major = (ns + HH_PAD) * (64LL * (1 + S) + 1);
+  const long long blocked = 2 * blocked_blocks(ns) * KP * 64;
+  return lane_major > blocked ? lane_major : blocked;
+}
 // Single strip solve (test hook): rhs/x in FP64, strip-local order.
 void launch_strip_solve(const hh_problem* pb, int strip_index, const c128* rhs, c128* x,
                         void* scratch, hipStream_t st);

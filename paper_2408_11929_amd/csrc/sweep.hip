@@ -1,25 +1,23 @@
 // Double-sweep preconditioner application (Sec. 2, eqs. (2)-(4)).
 //
-// One 64-lane workgroup runs whole double sweeps: forward over strips 1..N
-// (eq. (2), zero data on Gamma_{s,2}), backward over N-1..1 (eq. (3), reusing
-// the Gamma_{s,1} data of v_{s-1} formed in the forward pass and taking the
-// Gamma_{s,2} data from u_{s+1}); u_N = v_N, so 2N-1 strip solves.  Every
-// strip solve gathers the strip right-hand side R_s r + g, runs the pivoted
-// forward substitution with L and the back substitution with U from the solve
-// image of factor.hip, and scatters the strip solution over the global vector
-// (the most recent solve wins in the overlaps).
-//
-// A workgroup carries C independent chains (C = 2: typically the x and the y
-// sweep of one right-hand side, which walk strips of identical sizes) and
-// interleaves their steps, so that the dependency latency of one chain is
-// hidden behind the other's instructions.  Other workgroups handle the other
-// right-hand sides, so one launch covers a whole batch of applications.
+// One 64-lane workgroup runs one whole double sweep: forward over strips
+// 1..N (eq. (2), zero data on Gamma_{s,2}), backward over N-1..1 (eq. (3),
+// reusing the Gamma_{s,1} data of v_{s-1} formed in the forward pass and
+// taking the Gamma_{s,2} data from u_{s+1}); u_N = v_N, so 2N-1 strip solves.
+// Every strip solve forms the strip right-hand side R_s r + g, runs the
+// forward substitution with L and the back substitution with U, and writes
+// the strip solution over the global vector (the most recent solve wins in
+// the overlaps).  Other workgroups run the other directions and right-hand
+// sides, so one launch covers a whole batch of applications.
 //
 // Transmission data (eq. (4), zeroth-order Robin): for an interface node,
 // g = sum_d coef_d z[p + off_d] over the 7-point stencil, with coef = (A_s - A)
 // on that row, precomputed at factorisation time.
 //
-// Band substitution.  Both triangular solves are the recurrence
+// Substitutions.  A strip whose factorisation made no row interchange (the
+// usual case) uses the blocked row recurrence of solve_blocked, with block
+// maps built at factorisation time.  A strip that pivoted uses the lane-major
+// recurrence of solve_lower / solve_upper:
 //     out_e = b_e (times 1/U_ee for U),  b_{e+c} -= coef(e, c) b_e,  c = 1..K
 // over e = 0..ns-1 (reversed order for U), K = kl for L and 2 kl for U.
 // Element e of the sliding window lives in lane e mod 64 (slot k holds the
@@ -243,6 +241,94 @@ __device__ __forceinline__ void solve_upper(gptr<cx<T>> (&x)[C], gptr<const cx<T
   }
 }
 
+// Blocked row substitution for an unpivoted strip (image layout in
+// factor.hip): out_i = d_i (in_i - sum_{c=1..K} T(i, c) out_{i-c}) in blocks
+// of B = HH_BLK outputs, each a dense map of the K previous outputs and the B
+// block inputs.  Lane l = r + B p accumulates KP terms of output r; the P = 64/B
+// partial sums are combined by lane shuffles, after which all P lanes of a row
+// hold the same (bitwise) sum.
+//
+// The K previous outputs and the upcoming inputs live in a 256-entry LDS ring
+// (position i at slot i & 255) mirrored into slots 256..511, so the KP
+// consecutive reads of a lane never wrap and use immediate offsets.  The loop
+// runs in steps of U blocks (R = U B rows).  Everything a step needs from
+// memory is requested one step earlier, at the start of the previous step:
+// the maps of its U blocks (two register buffers, the loop unrolled by two
+// steps so that the buffers keep fixed registers) and 64 more inputs, which
+// enter the ring one step later (the ring then holds inputs up to row
+// jR + 191 - R, and no live position is 256 or more rows behind that).  The outputs of a step are written back at
+// the start of the next one.  Issuing all memory traffic of a step together
+// keeps the loop-carried waits short: whatever the hardware counters make the
+// loop head wait for was requested a whole step before.  The map array ends
+// in zero blocks and reads past the end are clamped, so the body is free of
+// bounds tests (positions past ns meet only zero map entries: rows >= ns of a
+// map are zero and no row < ns depends on a later position).  Single wave:
+// the LDS accesses of one wave are performed in order, no barrier is needed.
+// Rows are read through src and written through dst (lanes past the end
+// write row ns-1 again, with the same value, so the write needs no branch).
+template <class T, int KP, int U, class Src, class Dst>
+__device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gptr<const cx<T>> G,
+                                              int ns, int K, cx<T>* ring, int lane) {
+  constexpr int B = HH_BLK, R = U * HH_BLK;
+  static_assert(R <= 64 && 64 % R == 0, "a step must divide 64 rows");
+  const cx<T> zero = mk((T)0, (T)0);
+  const int r = lane % B, p = lane / B;
+  const int nst = (ns + R - 1) / R;
+  auto put = [&](int i, cx<T> v) {
+    ring[i & 255] = v;
+    ring[(i & 255) + 256] = v;
+  };
+#pragma unroll
+  for (int q = 0; q < 8; ++q) ring[64 * q + lane] = zero;
+  put(lane, src.get(src.load(lane)));
+  put(64 + lane, src.get(src.load(64 + lane)));
+  // before step j, pend holds rows jR + 128 - R + lane
+  typename Src::P pend = src.load(128 - R + lane);
+  cx<T> g[2][U][KP];
+  gptr<const cx<T>> gp = G + lane;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int t = 0; t < KP; ++t) g[0][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
+  gp = gp + (long long)U * KP * 64;
+  for (int j0 = 0; j0 < nst; j0 += 2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = j0 + h;
+      // requests for the next step: maps, inputs; write-back of the last step
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < KP; ++t) g[1 - h][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
+      gp = gp + (long long)U * KP * 64;
+      put(j * R + 128 - R + lane, src.get(pend));
+      pend = src.load(j * R + 128 + lane);
+      if (j > 0) {
+        const int q = (j - 1) * R + lane % R, qs = q < ns ? q : ns - 1;
+        dst.put(qs, ring[qs & 255]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i0 = j * R + B * u;
+        const cx<T>* win = ring + ((i0 - K + p * KP) & 255);
+        cx<T> a0 = zero, a1 = zero;
+#pragma unroll
+        for (int t = 0; t < KP; t += 2) {
+          a0 = a0 + g[h][u][t] * win[t];
+          if (t + 1 < KP) a1 = a1 + g[h][u][t + 1] * win[t + 1];
+        }
+        cx<T> acc = a0 + a1;
+#pragma unroll
+        for (int off = B; off < 64; off <<= 1)
+          acc = acc + mk(__shfl_xor(acc.re, off, 64), __shfl_xor(acc.im, off, 64));
+        put(i0 + r, acc);
+      }
+    }
+  }
+  const int q = (((nst + 1) & ~1) - 1) * R + lane % R, qs = q < ns ? q : ns - 1;
+  dst.put(qs, ring[qs & 255]);
+}
+
 // g = sum_d coef_d z[p + off_d] on interface node (i, j) = p.
 template <class T>
 __device__ __forceinline__ cx<T> transmission(gptr<const cx<T>> coef, gptr<cx<T>> z, int i, int j,
@@ -259,212 +345,303 @@ __device__ __forceinline__ cx<T> transmission(gptr<const cx<T>> coef, gptr<cx<T>
   return g;
 }
 
-struct ChainView {
-  int dir, a, has1, has2;
-  long long img_off, piv_off, t1off, t2off;
+// Streams of the blocked substitution.  load(i) issues the memory reads of
+// row i (clamped to the last row) and returns them raw; get() forms the value
+// when the row enters the ring, one step later.
+template <class T>
+struct SrcVec {  // x[i] (rev: x[ns-1-i]) in the working precision
+  gptr<const cx<T>> x;
+  int ns;
+  bool rev;
+  using P = cx<T>;
+  __device__ P load(int i) const {
+    i = i < ns ? i : ns - 1;
+    return ld<T>(x, rev ? ns - 1 - i : i);
+  }
+  __device__ cx<T> get(const P& v) const { return v; }
+};
+template <class T>
+struct SrcC128 {  // strip-local FP64 right-hand side, forward order
+  gptr<const c128> b;
+  int ns;
+  using P = c128;
+  __device__ P load(int i) const {
+    const int q = i < ns ? i : ns - 1;
+    return mk(b[q].re, b[q].im);
+  }
+  __device__ cx<T> get(const P& v) const { return mk((T)v.re, (T)v.im); }
+};
+// Strip right-hand side R_s r + g, forward order: local row q = l w + t is the
+// global node (a + t, l) of an x strip or (l, a + t) of a y strip; the
+// transmission data of node line l sit in LDS (e1 on t = 0 where the strip has
+// a Gamma_{s,1} side, e2 on t = w - 1 where Gamma_{s,2} data apply).
+template <class T>
+struct SrcGather {
+  gptr<const c128> r;
+  const cx<T>* gl1;
+  const cx<T>* gl2;
+  int ns, w, n, a, dir;
+  bool use1, use2;
+  struct P {
+    c128 v;
+    cx<T> e1, e2;
+    bool f1, f2;
+  };
+  __device__ P load(int i) const {
+    const int q = i < ns ? i : ns - 1;
+    const int l = q / w, t = q - l * w;
+    const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
+    P o;
+    o.v = mk(r[p].re, r[p].im);
+    o.e1 = gl1[l];
+    o.e2 = gl2[l];
+    o.f1 = use1 && t == 0;
+    o.f2 = use2 && t == w - 1;
+    return o;
+  }
+  __device__ cx<T> get(const P& o) const {
+    const cx<T> v = mk((T)o.v.re, (T)o.v.im);
+    return o.f1 ? v + o.e1 : (o.f2 ? v + o.e2 : v);
+  }
+};
+template <class T>
+struct DstVec {  // x[i] (rev: x[ns-1-i])
+  gptr<cx<T>> x;
+  int ns;
+  bool rev;
+  __device__ void put(int i, cx<T> v) const { st<T>(x, rev ? ns - 1 - i : i, v); }
+};
+template <class T>
+struct DstC128 {  // strip-local FP64 output, reversed order
+  gptr<c128> x;
+  int ns;
+  __device__ void put(int i, cx<T> v) const {
+    const int q = ns - 1 - i;
+    x[q].re = (double)v.re;
+    x[q].im = (double)v.im;
+  }
+};
+// Scatter of the strip solution over the global vector, reversed order (the
+// back substitution produces the last local row first).
+template <class T>
+struct DstScatter {
+  gptr<cx<T>> z;
+  int ns, w, n, a, dir;
+  __device__ void put(int i, cx<T> v) const {
+    const int q = ns - 1 - i;
+    const int l = q / w, t = q - l * w;
+    const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
+    st<T>(z, p, v);
+  }
 };
 
-template <class T, int C, int D, int S>
+// One workgroup (one wave) runs one double sweep.  Per strip: the
+// transmission data of its interfaces go to LDS (forward: g_{s,1} from the
+// current z, also kept for the backward pass; backward: the kept g_{s,1} and
+// g_{s,2} from the current z), then the forward substitution streams the
+// gathered right-hand side into the strip buffer and the back substitution
+// streams the solution from it into z.  Strips whose factorisation pivoted
+// take the lane-major path with explicit gather and scatter passes.
+// Dynamic LDS: the 512-entry ring and two node lines of transmission data.
+template <class T, int D, int S, int KP, int U>
 __global__ __launch_bounds__(64) void k_sweep(const SweepTask* __restrict__ tasks) {
+  extern __shared__ char smem_raw[];
   const SweepTask& tk = tasks[blockIdx.x];
   const int lane = threadIdx.x;
   const int n = uni(tk.n), N = uni(tk.N);
+  cx<T>* ring = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* gl1 = ring + 512;
+  cx<T>* gl2 = gl1 + n;
   const cx<T>* img = uniptr((const cx<T>*)tk.img);
   const int* pivb = uniptr(tk.piv);
   const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
-  gptr<cx<T>> z[C], rho[C], g1[C];
-  gptr<const c128> r[C];
-  const StripDesc* strips[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    z[c] = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch[c].z);
-    rho[c] = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch[c].rho);
-    g1[c] = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch[c].g1);
-    r[c] = (gptr<const c128>)uniptr(tk.ch[c].r);
-    strips[c] = uniptr(tk.ch[c].strips);
-  }
+  const int* pflag = uniptr(tk.pflag);
+  gptr<cx<T>> z = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.z);
+  gptr<cx<T>> rho = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.rho);
+  gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
+  gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
+  const StripDesc* strips = uniptr(tk.ch.strips);
+  const cx<T> zero = mk((T)0, (T)0);
   for (int step = 0; step < 2 * N - 1; ++step) {
     const bool fwd = step < N;
     const int s = fwd ? step : 2 * N - 2 - step;
-    const int ns = uni(strips[0][s].ns), w = uni(strips[0][s].w);
-    ChainView cv[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const StripDesc* sp = strips[c] + s;
-      cv[c].dir = uni(sp->dir);
-      cv[c].a = uni(sp->a);
-      cv[c].has1 = uni(sp->has1);
-      cv[c].has2 = uni(sp->has2);
-      cv[c].img_off = uni(sp->img_off);
-      cv[c].piv_off = uni(sp->piv_off);
-      cv[c].t1off = uni(sp->tr1_off);
-      cv[c].t2off = uni(sp->tr2_off);
-    }
-    // gather R_s r into the strip buffer (local q = l*w + t)
-    {
-      int l = lane / w, t = lane - (lane / w) * w;
-      const int dl = 64 / w, dt = 64 - (64 / w) * w;
-      for (int q = lane; q < ns; q += 64) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const long long p = cv[c].dir == 0 ? (long long)l * n + cv[c].a + t
-                                             : (long long)(cv[c].a + t) * n + l;
-          const c128 rv = mk(r[c][p].re, r[c][p].im);
-          st<T>(rho[c], q, mk((T)rv.re, (T)rv.im));
-        }
-        l += dl;
-        t += dt;
-        if (t >= w) {
-          t -= w;
-          l += 1;
-        }
-      }
-    }
-    __syncthreads();
-    // add the transmission data on Gamma_{s,1} (stored from v_{s-1}) and Gamma_{s,2}
+    const StripDesc* sp = strips + s;
+    const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
+    const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
+    const long long img_off = uni(sp->img_off), piv_off = uni(sp->piv_off);
+    const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
+    const int pivoted = uni(pflag[uni(sp->gid)]);
+    const bool use2 = has2 && !fwd;
     for (int l = lane; l < n; l += 64) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        if (cv[c].has1) {
-          cx<T> g;
-          if (fwd) {
-            const int i = cv[c].dir == 0 ? cv[c].a : l, j = cv[c].dir == 0 ? l : cv[c].a;
-            g = transmission<T>((gptr<const cx<T>>)(trb + cv[c].t1off + 7LL * l), z[c], i, j, n);
-            st<T>(g1[c], (long long)s * n + l, g);
-          } else {
-            g = ld<T>(g1[c], (long long)s * n + l);
-          }
-          const long long q = (long long)l * w;
-          st<T>(rho[c], q, ld<T>(rho[c], q) + g);
-        }
-        if (cv[c].has2 && !fwd) {
-          const int at = cv[c].a + w - 1;
-          const int i = cv[c].dir == 0 ? at : l, j = cv[c].dir == 0 ? l : at;
-          const cx<T> g = transmission<T>((gptr<const cx<T>>)(trb + cv[c].t2off + 7LL * l), z[c], i, j, n);
-          const long long q = (long long)l * w + w - 1;
-          st<T>(rho[c], q, ld<T>(rho[c], q) + g);
+      cx<T> e1 = zero, e2 = zero;
+      if (has1) {
+        if (fwd) {
+          const int i = dir == 0 ? a : l, j = dir == 0 ? l : a;
+          e1 = transmission<T>((gptr<const cx<T>>)(trb + t1off + 7LL * l), z, i, j, n);
+          st<T>(g1, (long long)s * n + l, e1);
+        } else {
+          e1 = ld<T>(g1, (long long)s * n + l);
         }
       }
-    }
-    __syncthreads();
-    {
-      gptr<const cx<T>> Lm[C];
-      gptr<const int> pv[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        Lm[c] = (gptr<const cx<T>>)(img + cv[c].img_off);
-        pv[c] = (gptr<const int>)(pivb + cv[c].piv_off);
+      if (use2) {
+        const int at = a + w - 1;
+        const int i = dir == 0 ? at : l, j = dir == 0 ? l : at;
+        e2 = transmission<T>((gptr<const cx<T>>)(trb + t2off + 7LL * l), z, i, j, n);
       }
-      solve_lower<T, C, D>(rho, Lm, pv, ns, lane);
+      gl1[l] = e1;
+      gl2[l] = e2;
     }
     __syncthreads();
-    {
-      gptr<const cx<T>> Um[C], rdg[C];
+    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2};
+    if (!pivoted) {
+      const cx<T>* GL = img + img_off;
+      const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
+      solve_blocked<T, KP, U>(gather, DstVec<T>{rho, ns, false}, (gptr<const cx<T>>)GL, ns, kl,
+                              ring, lane);
+      __syncthreads();
+      solve_blocked<T, KP, U>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
+                              DstScatter<T>{z, ns, w, n, a, dir}, (gptr<const cx<T>>)GU, ns, kl,
+                              ring, lane);
+    } else {
+      for (int q = lane; q < ns; q += 64) st<T>(rho, q, gather.get(gather.load(q)));
+      __syncthreads();
+      gptr<cx<T>> x[1] = {rho};
+      gptr<const cx<T>> Lm[1] = {(gptr<const cx<T>>)(img + img_off)};
+      gptr<const int> pv[1] = {(gptr<const int>)(pivb + piv_off)};
+      solve_lower<T, 1, D>(x, Lm, pv, ns, lane);
+      __syncthreads();
       const long long NP = ns + HH_PAD;
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        Um[c] = (gptr<const cx<T>>)(img + cv[c].img_off + NP * 64);
-        rdg[c] = (gptr<const cx<T>>)(img + cv[c].img_off + NP * 64 * (1 + S));
-      }
-      solve_upper<T, C, D, S>(rho, Um, rdg, ns, lane);
-    }
-    __syncthreads();
-    {
-      int l = lane / w, t = lane - (lane / w) * w;
-      const int dl = 64 / w, dt = 64 - (64 / w) * w;
-      for (int q = lane; q < ns; q += 64) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const long long p = cv[c].dir == 0 ? (long long)l * n + cv[c].a + t
-                                             : (long long)(cv[c].a + t) * n + l;
-          st<T>(z[c], p, ld<T>(rho[c], q));
-        }
-        l += dl;
-        t += dt;
-        if (t >= w) {
-          t -= w;
-          l += 1;
-        }
-      }
+      gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64)};
+      gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64 * (1 + S))};
+      solve_upper<T, 1, D, S>(x, Um, rdg, ns, lane);
+      __syncthreads();
+      const DstScatter<T> out{z, ns, w, n, a, dir};
+      for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(rho, q));
     }
     __syncthreads();
   }
 }
 
-// One strip solve in FP64 in/out (test hook).
-template <class T, int D, int S>
+// One strip solve in FP64 in/out (test hook); work: ns elements of scratch.
+template <class T, int D, int S, int KP, int U>
 __global__ __launch_bounds__(64) void k_strip_solve(const StripDesc* __restrict__ strips, int si,
                                                     const void* __restrict__ img,
                                                     const int* __restrict__ pivb,
+                                                    const int* __restrict__ pflag,
                                                     const c128* __restrict__ rhs, c128* __restrict__ x,
                                                     cx<T>* __restrict__ work) {
+  __shared__ cx<T> ring[512];
   const StripDesc* sp = strips + si;
-  const int ns = uni(sp->ns);
+  const int ns = uni(sp->ns), kl = uni(sp->kl);
   const long long ioff = uni(sp->img_off), poff = uni(sp->piv_off);
-  const long long NP = ns + HH_PAD;
+  const int pivoted = uni(pflag[si]);
   const int lane = threadIdx.x;
-  gptr<cx<T>> wk[1] = {(gptr<cx<T>>)work};
-  for (int q = lane; q < ns; q += 64) st<T>(wk[0], q, mk((T)rhs[q].re, (T)rhs[q].im));
-  __syncthreads();
-  gptr<const cx<T>> Lm[1] = {(gptr<const cx<T>>)((const cx<T>*)img + ioff)};
-  gptr<const int> pv[1] = {(gptr<const int>)(pivb + poff)};
-  solve_lower<T, 1, D>(wk, Lm, pv, ns, lane);
-  __syncthreads();
-  gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)((const cx<T>*)img + ioff + NP * 64)};
-  gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)((const cx<T>*)img + ioff + NP * 64 * (1 + S))};
-  solve_upper<T, 1, D, S>(wk, Um, rdg, ns, lane);
-  __syncthreads();
-  for (int q = lane; q < ns; q += 64) {
-    const cx<T> v = ld<T>(wk[0], q);
-    x[q] = mk((double)v.re, (double)v.im);
+  const cx<T>* im = (const cx<T>*)img;
+  gptr<cx<T>> wk = (gptr<cx<T>>)work;
+  const SrcC128<T> in{(gptr<const c128>)rhs, ns};
+  if (!pivoted) {
+    const cx<T>* GL = im + ioff;
+    const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
+    solve_blocked<T, KP, U>(in, DstVec<T>{wk, ns, false}, (gptr<const cx<T>>)GL, ns, kl, ring, lane);
+    __syncthreads();
+    solve_blocked<T, KP, U>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true},
+                            DstC128<T>{(gptr<c128>)x, ns}, (gptr<const cx<T>>)GU, ns, kl, ring,
+                            lane);
+  } else {
+    for (int q = lane; q < ns; q += 64) st<T>(wk, q, in.get(in.load(q)));
+    __syncthreads();
+    gptr<cx<T>> xs[1] = {wk};
+    gptr<const cx<T>> Lm[1] = {(gptr<const cx<T>>)(im + ioff)};
+    gptr<const int> pv[1] = {(gptr<const int>)(pivb + poff)};
+    solve_lower<T, 1, D>(xs, Lm, pv, ns, lane);
+    __syncthreads();
+    const long long NP = ns + HH_PAD;
+    gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64)};
+    gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64 * (1 + S))};
+    solve_upper<T, 1, D, S>(xs, Um, rdg, ns, lane);
+    __syncthreads();
+    for (int q = lane; q < ns; q += 64) {
+      const cx<T> v = ld<T>(wk, q);
+      x[q] = mk((double)v.re, (double)v.im);
+    }
   }
 }
 
 }  // namespace
 
-// Prefetch depth D: deep enough to cover memory latency, small enough that
-// C chains' coefficient buffers fit the register file.
-void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int S, int C,
+// Template choice.  D: coefficient prefetch depth of the pivoted path (deep
+// enough to cover memory latency, small enough to fit the register file);
+// KP: terms per lane of the blocked path (fixes S: KP <= 12 <=> kl <= 31);
+// U: blocks per step of the blocked path (two steps of maps are held in
+// registers).
+template <class T, int KP>
+struct SweepShape {
+  static constexpr bool dbl = sizeof(T) == 8;
+  static constexpr int S = KP <= 12 ? 1 : 2;
+  static constexpr int D = S == 1 ? (dbl ? 16 : 32) : (dbl ? 8 : 16);
+  static constexpr int U = dbl ? (KP <= 10 ? 2 : 1) : (KP <= 10 ? 4 : 2);
+};
+
+template <class T, int KP>
+static void launch_sweep_kp(const SweepTask* d, int ntasks, int nmax, hipStream_t st) {
+  using Sh = SweepShape<T, KP>;
+  const void* fn = (const void*)k_sweep<T, Sh::D, Sh::S, KP, Sh::U>;
+  const size_t lds = (512 + 2 * (size_t)nmax) * sizeof(cx<T>);
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_sweep<T, Sh::D, Sh::S, KP, Sh::U>), dim3(ntasks), dim3(64), lds, st, d);
+}
+
+template <class T>
+static void launch_sweep_t(const SweepTask* d, int ntasks, int KP, int nmax, hipStream_t st) {
+  switch (KP) {
+    case 8: launch_sweep_kp<T, 8>(d, ntasks, nmax, st); break;
+    case 10: launch_sweep_kp<T, 10>(d, ntasks, nmax, st); break;
+    case 12: launch_sweep_kp<T, 12>(d, ntasks, nmax, st); break;
+    case 16: launch_sweep_kp<T, 16>(d, ntasks, nmax, st); break;
+    case 20: launch_sweep_kp<T, 20>(d, ntasks, nmax, st); break;
+    default: set_error("unsupported blocked term count %d", KP); throw ArgError();
+  }
+}
+
+void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int nmax,
                   hipStream_t st) {
   if (ntasks <= 0) return;
-  if (S < 1 || S > 2 || C < 1 || C > 2) {
-    set_error("unsupported sweep configuration S=%d C=%d", S, C);
-    throw ArgError();
-  }
-  dim3 g(ntasks), b(64);
-  if (precision == HH_FP64) {
-    if (C == 1 && S == 1) hipLaunchKernelGGL((k_sweep<double, 1, 16, 1>), g, b, 0, st, d_tasks);
-    if (C == 1 && S == 2) hipLaunchKernelGGL((k_sweep<double, 1, 8, 2>), g, b, 0, st, d_tasks);
-    if (C == 2 && S == 1) hipLaunchKernelGGL((k_sweep<double, 2, 8, 1>), g, b, 0, st, d_tasks);
-    if (C == 2 && S == 2) hipLaunchKernelGGL((k_sweep<double, 2, 4, 2>), g, b, 0, st, d_tasks);
-  } else {
-    if (C == 1 && S == 1) hipLaunchKernelGGL((k_sweep<float, 1, 32, 1>), g, b, 0, st, d_tasks);
-    if (C == 1 && S == 2) hipLaunchKernelGGL((k_sweep<float, 1, 16, 2>), g, b, 0, st, d_tasks);
-    if (C == 2 && S == 1) hipLaunchKernelGGL((k_sweep<float, 2, 16, 1>), g, b, 0, st, d_tasks);
-    if (C == 2 && S == 2) hipLaunchKernelGGL((k_sweep<float, 2, 8, 2>), g, b, 0, st, d_tasks);
-  }
+  if (precision == HH_FP64)
+    launch_sweep_t<double>(d_tasks, ntasks, KP, nmax, st);
+  else
+    launch_sweep_t<float>(d_tasks, ntasks, KP, nmax, st);
   HH_HIP(hipGetLastError());
+}
+
+template <class T, int KP>
+static void launch_strip_kp(const hh_problem* pb, int si, const c128* rhs, c128* x, void* scratch,
+                            hipStream_t st) {
+  using Sh = SweepShape<T, KP>;
+  const FactorSet& fs = pb->fs;
+  hipLaunchKernelGGL((k_strip_solve<T, Sh::D, Sh::S, KP, Sh::U>), dim3(1), dim3(64), 0, st,
+                     fs.d_strips, si, fs.img, fs.piv, fs.d_pflag, rhs, x, (cx<T>*)scratch);
+}
+
+template <class T>
+static void launch_strip_t(const hh_problem* pb, int si, const c128* rhs, c128* x, void* scratch,
+                           hipStream_t st) {
+  switch (pb->fs.strips[si].KP) {
+    case 8: launch_strip_kp<T, 8>(pb, si, rhs, x, scratch, st); break;
+    case 10: launch_strip_kp<T, 10>(pb, si, rhs, x, scratch, st); break;
+    case 12: launch_strip_kp<T, 12>(pb, si, rhs, x, scratch, st); break;
+    case 16: launch_strip_kp<T, 16>(pb, si, rhs, x, scratch, st); break;
+    case 20: launch_strip_kp<T, 20>(pb, si, rhs, x, scratch, st); break;
+    default: set_error("unsupported blocked term count"); throw ArgError();
+  }
 }
 
 void launch_strip_solve(const hh_problem* pb, int si, const c128* rhs, c128* x, void* scratch,
                         hipStream_t st) {
-  const FactorSet& fs = pb->fs;
-  const int S = fs.strips[si].S;
-  if (fs.precision == HH_FP64) {
-    if (S == 1)
-      hipLaunchKernelGGL((k_strip_solve<double, 16, 1>), dim3(1), dim3(64), 0, st, fs.d_strips, si,
-                         fs.img, fs.piv, rhs, x, (c128*)scratch);
-    else
-      hipLaunchKernelGGL((k_strip_solve<double, 8, 2>), dim3(1), dim3(64), 0, st, fs.d_strips, si,
-                         fs.img, fs.piv, rhs, x, (c128*)scratch);
-  } else {
-    if (S == 1)
-      hipLaunchKernelGGL((k_strip_solve<float, 32, 1>), dim3(1), dim3(64), 0, st, fs.d_strips, si,
-                         fs.img, fs.piv, rhs, x, (c64*)scratch);
-    else
-      hipLaunchKernelGGL((k_strip_solve<float, 16, 2>), dim3(1), dim3(64), 0, st, fs.d_strips, si,
-                         fs.img, fs.piv, rhs, x, (c64*)scratch);
-  }
+  if (pb->fs.precision == HH_FP64)
+    launch_strip_t<double>(pb, si, rhs, x, scratch, st);
+  else
+    launch_strip_t<float>(pb, si, rhs, x, scratch, st);
   HH_HIP(hipGetLastError());
 }
 

@@ -3,7 +3,9 @@
 Tolerances: FP64 kernels agree with the oracle to 1e-12 relative (assembly
 and SpMV to 1e-13: they differ only in summation order); complex64 strips
 agree with the FP64 oracle to 1e-5 relative (the acceptance bar for the
-complex64 sweep); MPGMRES runs are compared by iteration count (exact),
+complex64 sweep), or, on strips conditioned so that a complex64 LAPACK band
+solve itself misses that bar (cond_1 above ~2e3), to three times that solve's
+own error; MPGMRES runs are compared by iteration count (exact),
 solution (relative 1e-8 for FP64, both runs converged to a tighter
 tolerance) and the FP64-recomputed residual.
 """
@@ -45,6 +47,17 @@ CASES = [
     (33, 4, 18.0, [1.0, 2.0, 1.5]),
     (41, 5, 25.0, [1.0]),
     (64, 9, 30.0, [2.2, 1.1, 1.7, 2.9, 1.3]),
+]
+# wide strips: band half-widths 35 and 51 take the 16- and 20-term blocked maps
+WIDE = [
+    (65, 2, 40.0, [1.0, 1.6]),
+    (97, 2, 50.0, [1.3, 0.9, 2.0]),
+]
+# under-resolved meshes whose strip factorisations pivot: every strip of the
+# first, only the x strips of the second (the y strips take the blocked path)
+PIVOTING = [
+    (33, 4, 100.0, [1.0]),
+    (33, 2, 80.0, [1.0, 0.5]),
 ]
 
 
@@ -90,7 +103,7 @@ def test_load_vector_and_spmv(n, N, omega, c):
 
 
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
-@pytest.mark.parametrize("n,N,omega,c", CASES)
+@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + PIVOTING)
 def test_strip_solves_match_lapack(n, N, omega, c, prec):
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
@@ -105,13 +118,17 @@ def test_strip_solves_match_lapack(n, N, omega, c, prec):
             rhs = rand(As.shape[0], 10 * s + d)
             x = host(pb.strip_solve(d, s, dev(rhs)))
             xr = osw.StripSolver(As, kl).solve(rhs)
-            worst = max(worst, rel(x, xr))
-    assert worst < tol, worst
+            bar = tol
+            if prec == hh.HH_FP32:
+                x32 = osw.StripSolver(As, kl, np.complex64).solve(rhs)
+                bar = max(tol, 3 * rel(x32, xr))
+            worst = max(worst, rel(x, xr) / bar)
+    assert worst < 1, worst
     pb.free()
 
 
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
-@pytest.mark.parametrize("n,N,omega,c", CASES)
+@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + PIVOTING)
 def test_sweeps_match_oracle(n, N, omega, c, prec):
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
@@ -121,8 +138,11 @@ def test_sweeps_match_oracle(n, N, omega, c, prec):
     for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
         z = host(pb.sweep_apply(d, dev(r)))
         S = osw.DoubleSweep(omega, c, n, N, dname, A=A)
+        S32 = osw.DoubleSweep(omega, c, n, N, dname, A=A, precision="fp32") if prec == hh.HH_FP32 else None
         for v in range(2):
-            assert rel(z[v], S.apply(r[v])) < tol
+            zr = S.apply(r[v])
+            bar = tol if S32 is None else max(tol, 3 * rel(S32.apply(r[v]), zr))
+            assert rel(z[v], zr) < bar
     pb.free()
 
 
