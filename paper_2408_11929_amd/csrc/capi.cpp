@@ -91,6 +91,7 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
   }
   REQUIRE(kl_max <= 63, "strip band half-width %d exceeds 63 (strips too wide)", kl_max);
   const int S = 2 * kl_max + 1 <= 64 ? 1 : 2;
+  const int P = sweep_segments(kl_max, n, precision == HH_FP64 ? sizeof(c128) : sizeof(c64));
   for (int i = 0; i < fs.nd; ++i) {
     for (int s = 0; s < N; ++s) {
       StripDesc sd{};
@@ -110,8 +111,11 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       const long long NP = sd.ns + HH_PAD;
       sd.band_off = band;
       band += (long long)sd.ns * sd.ldab;
+      sd.segs = P;
+      sd.seg = segment_rows(sd.ns, P);
       sd.img_off = img;
-      img += strip_image_elems(sd.ns, S, sd.KP);
+      sd.t_off = img + 2 * blocked_blocks(sd.ns) * sd.KP * 64;
+      img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P);
       sd.piv_off = piv;
       piv += NP;
       sd.tr1_off = sd.has1 ? tr : -1;
@@ -149,6 +153,9 @@ void factor_launch(hh_problem* pb, hipStream_t st) {
   launch_pack_strips(pb, st);
   launch_band_lu(pb, st);
   HH_HIP(hipMemcpyAsync(fs.h_err.data(), fs.d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  fs.h_pflag.assign(fs.strips.size(), 0);
+  HH_HIP(hipMemcpyAsync(fs.h_pflag.data(), fs.d_pflag, fs.strips.size() * sizeof(int),
+                        hipMemcpyDeviceToHost, st));
 }
 
 // After the factorisation stream has completed: releases the LU work buffer
@@ -157,6 +164,7 @@ int factor_finish(hh_problem* pb) {
   FactorSet& fs = pb->fs;
   dev_free(fs.band);
   fs.band = nullptr;
+  fs.any_pivot = std::any_of(fs.h_pflag.begin(), fs.h_pflag.end(), [](int f) { return f != 0; });
   if (fs.h_err[0]) {
     const StripDesc& sd = fs.strips[fs.h_err[0] - 1];
     set_error("zero pivot in the LU of strip %d of direction %c", sd.s + 1, sd.dir == 0 ? 'x' : 'y');
@@ -310,7 +318,8 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
         bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
       }
       TimedRegion tr(FAM_SWEEP, st, bytes);
-      launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].KP, pb->n, st);
+      launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].KP, fs.strips[0].segs, fs.max_kl,
+                   pb->n, fs.any_pivot, st);
     }
     if (fs.precision != HH_FP64) launch_widen((const c64*)zs, (c128*)z, nvec * len, st);
     HH_HIP(hipStreamSynchronize(st));

@@ -291,23 +291,27 @@ void Engine::step(std::vector<Solve*>& solves) {
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
 
   // 1. sweeps: every preconditioner of every solve, one workgroup per chain.
-  // Launch kinds are keyed by (precision, blocked term count KP).
+  // Launch kinds are keyed by (precision, blocked term count KP, segments P,
+  // presence of pivoted strips).
   struct Kind {
     std::vector<SweepTask> tasks;
-    int prec, KP, nmax;
+    int prec, KP, P, kmax, nmax;
+    bool piv;
   };
   std::vector<Kind> kinds;
   for (Solve* s : live) {
     const hh_problem* pb = s->pb;
     const FactorSet& fs = pb->fs;
     const size_t es = esz_of(fs.precision);
-    const int KP = fs.strips[0].KP;
-    auto it = std::find_if(kinds.begin(), kinds.end(),
-                           [&](const Kind& k) { return k.prec == fs.precision && k.KP == KP; });
+    const int KP = fs.strips[0].KP, P = fs.strips[0].segs;
+    auto it = std::find_if(kinds.begin(), kinds.end(), [&](const Kind& k) {
+      return k.prec == fs.precision && k.KP == KP && k.P == P && k.piv == fs.any_pivot;
+    });
     if (it == kinds.end()) {
-      kinds.push_back({{}, fs.precision, KP, 0});
+      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot});
       it = kinds.end() - 1;
     }
+    it->kmax = std::max(it->kmax, fs.max_kl);
     it->nmax = std::max(it->nmax, pb->n);
     for (int i = 0; i < s->t; ++i) {
       SweepTask tk{};
@@ -481,7 +485,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     TimedRegion tr(FAM_SWEEP, st_, bytes);
     for (size_t q = 0; q < kinds.size(); ++q)
       launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].KP,
-                   kinds[q].nmax, st_);
+                   kinds[q].P, kinds[q].kmax, kinds[q].nmax, kinds[q].piv, st_);
   }
   {
     double bytes = 0;

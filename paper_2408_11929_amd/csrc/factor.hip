@@ -195,15 +195,20 @@ __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>*
 // and the B block inputs: out = G [out_{i0-K..i0-1}; in_{i0..i0+B-1}].
 // Column k of G is obtained by running the block's recurrence on the k-th
 // unit input, in FP64 from the stored factors.  Stored per block as KP rows
-// of 64 lanes: lane l = r + B p holds G(r, p KP + t) in row t, so output r is
-// the sum over its P = 64/B lanes.  grid = (blocks*(K+B) / 128, strips, 2).
+// of 64 lanes; lane l = r + 16 p holds coefficients of output r, and the four
+// lanes of a row split the columns so that each holds four of the previous
+// block's outputs (row t = 0..3: out_{i0-16+4p+t}), four block inputs
+// (t = 4..7: in_{i0+4p+t-4}) and KO = KP - 8 of the older outputs
+// (t = 8..: out_{i0-K+p KO+t-8}, zero where that lies at or past i0-16).
+// grid = (blocks*(K+B) / 128, strips, 2).
 template <class T>
 __global__ __launch_bounds__(128) void k_build_blocked(const StripDesc* __restrict__ strips,
                                                        const cx<T>* __restrict__ band,
                                                        cx<T>* __restrict__ img,
                                                        const int* __restrict__ pflag) {
   if (pflag[blockIdx.y]) return;
-  constexpr int B = HH_BLK, P = 64 / HH_BLK;
+  constexpr int B = HH_BLK;
+  static_assert(HH_BLK == 16, "the column split assumes four lane groups of 16 rows");
   const StripDesc sd = strips[blockIdx.y];
   const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab, KP = sd.KP;
   const int nb = (ns + B - 1) / B, ncol = K + B;
@@ -243,10 +248,71 @@ __global__ __launch_bounds__(128) void k_build_blocked(const StripDesc* __restri
     }
     win[K + i] = acc;
   }
-  const int p = k / KP, t = k % KP;
+  // lane group p and row t of column k (see above)
+  const int KO = KP - 8;
+  int p, t;
+  if (k >= K) {  // block input k - K
+    p = (k - K) / 4;
+    t = 4 + (k - K) % 4;
+  } else if (k >= K - B) {  // output of the previous block, i0 - K + k = i0 - 16 + j
+    const int j = k - (K - B);
+    p = j / 4;
+    t = j % 4;
+  } else {  // older output
+    p = k / KO;
+    t = 8 + k % KO;
+  }
   for (int r = 0; r < B; ++r) {
     const c128 v = win[K + r];
     G[((long long)b * KP + t) * 64 + r + B * p] = mk((T)v.re, (T)v.im);
+  }
+}
+
+// Segment transfer maps of an unpivoted strip.  The substitutions split a
+// strip's rows into segments of sd.seg rows that are solved in parallel from a
+// zero state; the true state of segment s+1 (the K outputs before it) is then
+// the zero-state tail of segment s plus T_s times the state of segment s,
+// where column c' of T_s is the tail of the recurrence over segment s started
+// from the unit state e_c' with zero inputs.  Stored for s = 1..nseg-2 as
+// T[((s-1) K + c') K + c] = tail row c, in the order in which the sweep
+// kernel stages them.  One thread per (segment, c'); FP64 recurrence from the
+// stored factors (same conventions as the blocked maps).  grid = (cells / 64,
+// strips, 2).
+template <class T>
+__global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restrict__ strips,
+                                                       const cx<T>* __restrict__ band,
+                                                       cx<T>* __restrict__ img,
+                                                       const int* __restrict__ pflag) {
+  if (pflag[blockIdx.y]) return;
+  const StripDesc sd = strips[blockIdx.y];
+  const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab, seg = sd.seg;
+  const int nseg = (ns + seg - 1) / seg;
+  const long long e = blockIdx.x * 64LL + threadIdx.x;
+  if (e >= (long long)std::max(nseg - 2, 0) * K) return;
+  const int s = 1 + (int)(e / K), cp = (int)(e % K);
+  const bool upper = blockIdx.z == 1;
+  const cx<T>* ab = band + sd.band_off;
+  cx<T>* Tm = img + sd.t_off + (upper ? (long long)(nseg - 2) * K * K : 0);
+  c128 win[64];  // out_i at win[i & 63]
+  const int s0 = s * seg, s1 = s0 + seg;
+  for (int q = 0; q < K; ++q) win[(s0 - K + q) & 63] = mk(q == cp ? 1.0 : 0.0, 0.0);
+  for (int i = s0; i < s1; ++i) {
+    c128 acc = mk(0.0, 0.0);
+    const int j = ns - 1 - i;
+    for (int c = 1; c <= K; ++c) {
+      const cx<T> v = upper ? ab[(long long)(j + c) * ldab + kv - c]
+                            : ab[(long long)(i - c) * ldab + kv + c];
+      acc = cfms(acc, mk((double)v.re, (double)v.im), win[(i - c) & 63]);
+    }
+    if (upper) {
+      const cx<T> d = ab[(long long)j * ldab + kv];
+      acc = acc * cinv(mk((double)d.re, (double)d.im));
+    }
+    win[i & 63] = acc;
+    if (i >= s1 - K) {
+      const int c = i - (s1 - K);
+      Tm[((long long)(s - 1) * K + cp) * K + c] = mk((T)acc.re, (T)acc.im);
+    }
   }
 }
 
@@ -257,6 +323,15 @@ dim3 blocked_grid(const FactorSet& fs) {
   for (auto& sd : fs.strips)
     cells = std::max(cells, (long long)((sd.ns + HH_BLK - 1) / HH_BLK) * (sd.kl + HH_BLK));
   return dim3((unsigned)((cells + 127) / 128), (unsigned)fs.strips.size(), 2);
+}
+
+static dim3 transfer_grid(const FactorSet& fs) {
+  long long cells = 1;
+  for (auto& sd : fs.strips) {
+    const int nseg = (sd.ns + sd.seg - 1) / sd.seg;
+    cells = std::max(cells, (long long)std::max(nseg - 2, 0) * sd.kl);
+  }
+  return dim3((unsigned)((cells + 63) / 64), (unsigned)fs.strips.size(), 2);
 }
 
 void launch_band_lu(const hh_problem* pb, hipStream_t st) {
@@ -279,6 +354,8 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(128), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
+    hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
+                       (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
   } else {
     HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<float>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -289,6 +366,8 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv,
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(128), 0, st, fs.d_strips,
+                       (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
+    hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
   }
   HH_HIP(hipGetLastError());

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <array>
 #include <mutex>
 #include <string>
@@ -48,6 +49,13 @@ __host__ __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) {
 template <class T>
 __host__ __device__ __forceinline__ cx<T> cfms(cx<T> a, cx<T> b, cx<T> c) {
   return mk(a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re);
+}
+// a + b * c as four fused multiply-adds
+__host__ __device__ __forceinline__ float fmac_(float x, float y, float z) { return __builtin_fmaf(x, y, z); }
+__host__ __device__ __forceinline__ double fmac_(double x, double y, double z) { return __builtin_fma(x, y, z); }
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
+  return mk(fmac_(-b.im, c.im, fmac_(b.re, c.re, a.re)), fmac_(b.im, c.re, fmac_(b.re, c.im, a.im)));
 }
 // conj(a) * b
 template <class T>
@@ -112,6 +120,9 @@ struct StripDesc {
   long long piv_off;   // ints into the pivot buffer (ns + HH_PAD entries)
   long long tr1_off;   // complex elements into the transmission buffer (n*7), or -1
   long long tr2_off;
+  int segs;            // segments of the parallel substitution (waves of a sweep workgroup)
+  int seg;             // rows per segment (a multiple of 64); the last may be shorter
+  long long t_off;     // complex elements into the solve image: segment transfer maps
 };
 
 // Zero steps appended to every strip's solve image and pivot list, so that the
@@ -134,6 +145,8 @@ struct FactorSet {
   int* d_err = nullptr;            // [0] = 1 + strip index of first zero pivot, [1] = column
   int* d_pflag = nullptr;          // per strip: 1 if the LU interchanged any rows
   std::array<int, 2> h_err{{0, 0}};  // host copy, valid once the factor stream completed
+  std::vector<int> h_pflag;           // host copy of d_pflag, likewise
+  bool any_pivot = false;             // some strip pivoted (set by factor_finish)
   size_t band_elems = 0, img_elems = 0, piv_elems = 0, tr_elems = 0;
   int max_ns = 0, max_kl = 0;
   size_t bytes() const;
@@ -218,11 +231,13 @@ struct SweepTask {
   int n;
   int N;
 };
-// All tasks share the precision and the blocked-term count KP (which fixes
-// the slot count S of the pivoted path); nmax = largest n among the tasks
-// (sizes the LDS).
-void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int nmax,
-                  hipStream_t st);
+// All tasks share the precision, the blocked-term count KP (which fixes the
+// slot count S of the pivoted path) and the segment count P (waves per
+// workgroup); kmax and nmax = largest band half-width and n among the tasks
+// (they size the LDS); pivots: some strip of some task pivoted (selects the
+// kernel that carries the pivoted path).
+void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
+                  int nmax, bool pivots, hipStream_t st);
 // Blocked substitution: block size and terms per lane for band half-width kl.
 // KP terms per lane cover the K + HH_BLK columns of a block map over the 64/HH_BLK
 // lanes of one output row; KP <= 12 exactly when 2 kl + 1 <= 64 (one lane-major
@@ -231,15 +246,37 @@ constexpr int HH_BLK = 16;
 inline int blocked_kp(int kl) {
   return kl <= 16 ? 8 : kl <= 24 ? 10 : kl <= 31 ? 12 : kl <= 48 ? 16 : 20;
 }
-// Blocks stored per triangle: whole 64-row chunks plus eight zero blocks, so the
-// substitution (an even number of steps of up to four blocks, maps requested
-// one step ahead) reads no bounds-tested memory.
-__host__ __device__ inline long long blocked_blocks(long long ns) { return 4 * ((ns + 63) / 64) + 8; }
+// Blocks stored per triangle: whole 64-row chunks plus sixteen zero blocks, so
+// the substitution (steps of up to four blocks, rounded up to a multiple of
+// three, maps requested up to two steps ahead) reads no bounds-tested memory.
+__host__ __device__ inline long long blocked_blocks(long long ns) { return 4 * ((ns + 63) / 64) + 16; }
+// Rows per segment when a strip's substitutions are split over P waves.
+__host__ __device__ inline int segment_rows(int ns, int P) {
+  const int per = (ns + P - 1) / P;
+  return (per + 63) / 64 * 64;
+}
+// LDS of a sweep workgroup of P waves (complex elements): per-wave rings
+// (phase 1 and 3) sharing space with the staged transfer maps (phase 2), the
+// segment tails and states, and two node lines of transmission data.
+inline long long sweep_lds_elems(int P, int K, int n) {
+  const long long work = std::max(640LL * P, (long long)std::max(P - 2, 0) * K * K);
+  return work + 2LL * 64 * P + 2LL * n;
+}
+// Segments of the parallel substitution: the most (up to 8) whose workgroup
+// fits the LDS.
+inline int sweep_segments(int K, int n, size_t esz) {
+  for (int P : {8, 6, 4, 3, 2})
+    if (sweep_lds_elems(P, K, n) * (long long)esz <= 150 * 1024) return P;
+  return 1;
+}
 // Image elements of one strip: the larger of the pivoted (lane-major) and the
-// unpivoted (blocked) layouts; which one is built is decided by the LU.
-inline long long strip_image_elems(long long ns, int S, int KP) {
+// unpivoted (blocked maps plus segment transfer maps) layouts; which one is
+// built is decided by the LU.
+inline long long strip_image_elems(long long ns, int S, int KP, int K, int P) {
   const long long lane_major = (ns + HH_PAD) * (64LL * (1 + S) + 1);
-  const long long blocked = 2 * blocked_blocks(ns) * KP * 64;
+  const int nseg = (int)((ns + segment_rows((int)ns, P) - 1) / segment_rows((int)ns, P));
+  const long long blocked =
+      2 * blocked_blocks(ns) * KP * 64 + 2LL * std::max(nseg - 2, 0) * K * K;
   return lane_major > blocked ? lane_major : blocked;
 }
 // Single strip solve (test hook): rhs/x in FP64, strip-local order.

@@ -241,92 +241,152 @@ __device__ __forceinline__ void solve_upper(gptr<cx<T>> (&x)[C], gptr<const cx<T
   }
 }
 
+// Sum over the four 16-lane groups of the wave; every lane receives the same
+// (bitwise) result, (g0 + g1) + (g2 + g3).  v_permlane16_swap exchanges rows
+// 1 and 3 of its first operand with rows 0 and 2 of its second; with both
+// operands equal the two results hold the even and the odd rows.
+// v_permlane32_swap does the same with the two halves of the wave.
+__device__ __forceinline__ float sum4(float v) {
+  const unsigned u = __float_as_uint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const unsigned w = __float_as_uint(s);
+  const auto b = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+__device__ __forceinline__ double sum4(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto al = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto ah = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double s = __longlong_as_double(((long long)ah[0] << 32) | al[0]) +
+                   __longlong_as_double(((long long)ah[1] << 32) | al[1]);
+  const unsigned long long w = __double_as_longlong(s);
+  const unsigned wl = (unsigned)w, wh = (unsigned)(w >> 32);
+  const auto bl = __builtin_amdgcn_permlane32_swap(wl, wl, false, false);
+  const auto bh = __builtin_amdgcn_permlane32_swap(wh, wh, false, false);
+  return __longlong_as_double(((long long)bh[0] << 32) | bl[0]) +
+         __longlong_as_double(((long long)bh[1] << 32) | bl[1]);
+}
+
 // Blocked row substitution for an unpivoted strip (image layout in
 // factor.hip): out_i = d_i (in_i - sum_{c=1..K} T(i, c) out_{i-c}) in blocks
-// of B = HH_BLK outputs, each a dense map of the K previous outputs and the B
-// block inputs.  Lane l = r + B p accumulates KP terms of output r; the P = 64/B
-// partial sums are combined by lane shuffles, after which all P lanes of a row
-// hold the same (bitwise) sum.
+// of B = 16 outputs, each a dense map of the K previous outputs and the 16
+// block inputs.  Lane l = r + 16 p accumulates KP terms of output r, and the
+// four partial sums of a row are combined by lane swaps (sum4).
 //
-// The K previous outputs and the upcoming inputs live in a 256-entry LDS ring
-// (position i at slot i & 255) mirrored into slots 256..511, so the KP
-// consecutive reads of a lane never wrap and use immediate offsets.  The loop
-// runs in steps of U blocks (R = U B rows).  Everything a step needs from
-// memory is requested one step earlier, at the start of the previous step:
-// the maps of its U blocks (two register buffers, the loop unrolled by two
-// steps so that the buffers keep fixed registers) and 64 more inputs, which
-// enter the ring one step later (the ring then holds inputs up to row
-// jR + 191 - R, and no live position is 256 or more rows behind that).  The outputs of a step are written back at
-// the start of the next one.  Issuing all memory traffic of a step together
-// keeps the loop-carried waits short: whatever the hardware counters make the
-// loop head wait for was requested a whole step before.  The map array ends
+// Only the four terms of a lane that involve the previous block's outputs lie
+// on the chain from block to block; the other KP - 4 terms of block b+1
+// (its inputs and the outputs older than block b) are accumulated while block
+// b completes.  Outputs and inputs live in two 256-entry LDS rings (position i
+// at slot i & 255) whose first 64 slots are mirrored into slots 256..319, so
+// that the consecutive reads of a lane (at most 20) never wrap and use
+// immediate offsets.  init (LDS, K entries, or null for zeros) holds the
+// outputs of positions -K..-1, i.e. the state the recurrence starts from.
+//
+// The loop runs in steps of U blocks (R = 16 U rows).  Everything a step
+// needs from memory is requested NB - 1 steps earlier, at the start of a
+// previous step: the maps of its U blocks (NB register buffers, the loop
+// unrolled by NB steps so that the buffers keep fixed registers) and 64
+// inputs, which enter the input ring at its own start (step j commits rows
+// jR + 128 .. jR + 191, so the ring spans at most 192 rows).  The outputs of
+// a step are written back at the start of the next one.  Issuing all memory
+// traffic of a step together keeps the loop-carried waits short: whatever the
+// hardware counters make the loop head wait for was requested at least one
+// whole step before.  The map array ends
 // in zero blocks and reads past the end are clamped, so the body is free of
 // bounds tests (positions past ns meet only zero map entries: rows >= ns of a
 // map are zero and no row < ns depends on a later position).  Single wave:
 // the LDS accesses of one wave are performed in order, no barrier is needed.
 // Rows are read through src and written through dst (lanes past the end
 // write row ns-1 again, with the same value, so the write needs no branch).
-template <class T, int KP, int U, class Src, class Dst>
+template <class T, int KP, int U, int NB, class Src, class Dst>
 __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gptr<const cx<T>> G,
-                                              int ns, int K, cx<T>* ring, int lane) {
-  constexpr int B = HH_BLK, R = U * HH_BLK;
-  static_assert(R <= 64 && 64 % R == 0, "a step must divide 64 rows");
+                                              int ns, int K, cx<T>* ring, const cx<T>* init,
+                                              int lane) {
+  static_assert(HH_BLK == 16 && KP >= 8, "four lane groups of 16 rows, four chain terms each");
+  constexpr int R = U * 16, KO = KP - 8;
+  static_assert(R <= 64 && 64 % R == 0 && NB >= 2, "a step divides 64 rows");
+  cx<T>* oring = ring;
+  cx<T>* iring = ring + 320;
   const cx<T> zero = mk((T)0, (T)0);
-  const int r = lane % B, p = lane / B;
+  const int r = lane & 15, p = lane >> 4;
   const int nst = (ns + R - 1) / R;
-  auto put = [&](int i, cx<T> v) {
-    ring[i & 255] = v;
-    ring[(i & 255) + 256] = v;
+  auto put = [&](cx<T>* rg, int i, cx<T> v) {
+    const int k = i & 255;
+    rg[k] = v;
+    rg[k < 64 ? k + 256 : k] = v;
   };
 #pragma unroll
-  for (int q = 0; q < 8; ++q) ring[64 * q + lane] = zero;
-  put(lane, src.get(src.load(lane)));
-  put(64 + lane, src.get(src.load(64 + lane)));
-  // before step j, pend holds rows jR + 128 - R + lane
-  typename Src::P pend = src.load(128 - R + lane);
-  cx<T> g[2][U][KP];
+  for (int q = 0; q < 10; ++q) ring[64 * q + lane] = zero;
+  if (init && lane < K) put(oring, lane - K, init[lane]);
+  put(iring, lane, src.get(src.load(lane)));
+  put(iring, 64 + lane, src.get(src.load(64 + lane)));
+  // pend[j % NB] holds input rows jR + 128 + lane until step j commits them
+  typename Src::P pend[NB];
+  cx<T> g[NB][U][KP];
   gptr<const cx<T>> gp = G + lane;
 #pragma unroll
-  for (int u = 0; u < U; ++u)
+  for (int b = 0; b + 1 < NB; ++b) {
+    pend[b] = src.load(b * R + 128 + lane);
 #pragma unroll
-    for (int t = 0; t < KP; ++t) g[0][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
-  gp = gp + (long long)U * KP * 64;
-  for (int j0 = 0; j0 < nst; j0 += 2) {
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+      for (int t = 0; t < KP; ++t) g[b][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
+    gp = gp + (long long)U * KP * 64;
+  }
+  // terms of block i0 that do not involve the outputs of the block before it
+  auto rest = [&](const cx<T>(&gb)[KP], int i0) -> cx<T> {
+    const cx<T>* in = iring + ((i0 + 4 * p) & 255);
+    const cx<T>* old = oring + ((i0 - K + p * KO) & 255);
+    cx<T> a0 = gb[4] * in[0], a1 = gb[5] * in[1];
+    a0 = cfma(a0, gb[6], in[2]);
+    a1 = cfma(a1, gb[7], in[3]);
+#pragma unroll
+    for (int t = 0; t < KO; t += 2) {
+      a0 = cfma(a0, gb[8 + t], old[t]);
+      if (t + 1 < KO) a1 = cfma(a1, gb[9 + t], old[t + 1]);
+    }
+    return a0 + a1;
+  };
+  cx<T> rst = rest(g[0][0], 0);
+  const int nstr = (nst + NB - 1) / NB * NB;
+  for (int j0 = 0; j0 < nstr; j0 += NB) {
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
       const int j = j0 + h;
-      // requests for the next step: maps, inputs; write-back of the last step
+      // requests NB-1 steps ahead: maps and inputs; write-back of the last step
+      const int hn = (h + NB - 1) % NB;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int t = 0; t < KP; ++t) g[1 - h][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
+        for (int t = 0; t < KP; ++t) g[hn][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
       gp = gp + (long long)U * KP * 64;
-      put(j * R + 128 - R + lane, src.get(pend));
-      pend = src.load(j * R + 128 + lane);
+      put(iring, j * R + 128 + lane, src.get(pend[h]));
+      pend[hn] = src.load((j + NB - 1) * R + 128 + lane);
       if (j > 0) {
-        const int q = (j - 1) * R + lane % R, qs = q < ns ? q : ns - 1;
-        dst.put(qs, ring[qs & 255]);
+        const int q = (j - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
+        dst.put(qs, oring[qs & 255]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i0 = j * R + B * u;
-        const cx<T>* win = ring + ((i0 - K + p * KP) & 255);
-        cx<T> a0 = zero, a1 = zero;
-#pragma unroll
-        for (int t = 0; t < KP; t += 2) {
-          a0 = a0 + g[h][u][t] * win[t];
-          if (t + 1 < KP) a1 = a1 + g[h][u][t + 1] * win[t + 1];
-        }
-        cx<T> acc = a0 + a1;
-#pragma unroll
-        for (int off = B; off < 64; off <<= 1)
-          acc = acc + mk(__shfl_xor(acc.re, off, 64), __shfl_xor(acc.im, off, 64));
-        put(i0 + r, acc);
+        const int i0 = j * R + 16 * u;
+        const cx<T>* pv = oring + ((i0 - 16 + 4 * p) & 255);
+        cx<T> a0 = cfma(rst, g[h][u][0], pv[0]), a1 = g[h][u][1] * pv[1];
+        a0 = cfma(a0, g[h][u][2], pv[2]);
+        a1 = cfma(a1, g[h][u][3], pv[3]);
+        const cx<T> part = a0 + a1;
+        const cx<T> acc = mk(sum4(part.re), sum4(part.im));
+        if (u + 1 < U)
+          rst = rest(g[h][u + 1 < U ? u + 1 : u], i0 + 16);
+        else
+          rst = rest(g[(h + 1) % NB][0], i0 + 16);
+        put(oring, i0 + r, acc);
       }
     }
   }
-  const int q = (((nst + 1) & ~1) - 1) * R + lane % R, qs = q < ns ? q : ns - 1;
-  dst.put(qs, ring[qs & 255]);
+  const int q = (nstr - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
+  dst.put(qs, oring[qs & 255]);
 }
 
 // g = sum_d coef_d z[p + off_d] on interface node (i, j) = p.
@@ -343,6 +403,20 @@ __device__ __forceinline__ cx<T> transmission(gptr<const cx<T>> coef, gptr<cx<T>
     g = g + ld<T>(coef, d) * ld<T>(z, (long long)jj * n + ii);
   }
   return g;
+}
+
+// q = l w + t with 0 <= t < w, from a float estimate of q / w: the estimate is
+// off by at most one for q < 2^22, which one correction step absorbs.
+__device__ __forceinline__ void line_of(int q, int w, float winv, int& l, int& t) {
+  l = (int)((float)q * winv);
+  t = q - l * w;
+  if (t < 0) {
+    --l;
+    t += w;
+  } else if (t >= w) {
+    ++l;
+    t -= w;
+  }
 }
 
 // Streams of the blocked substitution.  load(i) issues the memory reads of
@@ -387,9 +461,11 @@ struct SrcGather {
     cx<T> e1, e2;
     bool f1, f2;
   };
+  float winv;  // 1 / w
   __device__ P load(int i) const {
     const int q = i < ns ? i : ns - 1;
-    const int l = q / w, t = q - l * w;
+    int l, t;
+    line_of(q, w, winv, l, t);
     const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
     P o;
     o.v = mk(r[p].re, r[p].im);
@@ -427,31 +503,137 @@ template <class T>
 struct DstScatter {
   gptr<cx<T>> z;
   int ns, w, n, a, dir;
+  float winv;  // 1 / w
   __device__ void put(int i, cx<T> v) const {
     const int q = ns - 1 - i;
-    const int l = q / w, t = q - l * w;
+    int l, t;
+    line_of(q, w, winv, l, t);
     const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
     st<T>(z, p, v);
   }
 };
 
-// One workgroup (one wave) runs one double sweep.  Per strip: the
+// Segment views for the parallel substitution: rows off..off+len-1 of a
+// stream as rows 0..len-1 (reads past the end clamped to the last row).
+template <class Src>
+struct SegSrc {
+  const Src& b;
+  int off, len;
+  using P = typename Src::P;
+  __device__ P load(int i) const { return b.load(off + (i < len ? i : len - 1)); }
+  __device__ auto get(const P& v) const { return b.get(v); }
+};
+template <class T, class Dst>
+struct SegDst {
+  const Dst& b;
+  int off;
+  __device__ void put(int i, cx<T> v) const { b.put(off + i, v); }
+};
+template <class T>
+struct DstTail {  // keeps only the last K rows of a segment (in LDS)
+  cx<T>* yt;
+  int len, K;
+  __device__ void put(int i, cx<T> v) const {
+    const int c = i - (len - K);
+    if (c >= 0) yt[c] = v;
+  }
+};
+
+// One triangular substitution of a strip by all P waves of the workgroup
+// (the recurrence is linear, so it splits exactly over segments of seg rows):
+//  1. every segment but the last runs from a zero state; segment 0 is then
+//     final and written out, the others keep only their last K outputs;
+//  2. wave 0 propagates the true states, state_{s+1} = tail_s + T_s state_s,
+//     with the transfer maps T_s staged into LDS;
+//  3. segments 1.. run again from their true state and are written out.
+// Phase 1 of a segment and phase 3 of the next one together cost two blocked
+// substitutions of seg rows, so the chain of one strip shortens from ns to
+// about 2 ns / P rows.  work: the LDS shared by the rings (phases 1 and 3,
+// 640 entries per wave) and the staged maps (phase 2); yt, stt: 64 entries
+// per segment.
+template <class T, int KP, int U, int NB, class Src, class Dst>
+__device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, const cx<T>* G,
+                                               const cx<T>* Tm, int ns, int K, int seg,
+                                               cx<T>* work, cx<T>* yt, cx<T>* stt) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
+  const int nseg = (ns + seg - 1) / seg;
+  cx<T>* ring = work + 640 * wv;
+  const int off = wv * seg, len = ns - off < seg ? ns - off : seg;
+  gptr<const cx<T>> Gw = (gptr<const cx<T>>)(G + (long long)(off / 16) * KP * 64);
+  if (wv == 0) {
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, 0, len}, SegDst<T, Dst>{dst, 0}, Gw, len, K, ring,
+                            (const cx<T>*)nullptr, lane);
+    if (nseg > 1 && lane < K) yt[lane] = ring[(len - K + lane) & 255];
+  } else if (wv < nseg - 1) {
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, DstTail<T>{yt + 64 * wv, len, K}, Gw, len,
+                            K, ring, (const cx<T>*)nullptr, lane);
+  }
+  if (nseg == 1) return;
+  __syncthreads();
+  const int nT = (nseg - 2) * K * K;
+  gptr<const cx<T>> Tg = (gptr<const cx<T>>)Tm;
+  for (int e0 = 0; e0 < nT; e0 += 8 * nthr) {
+    cx<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nthr + tid;
+      v[q] = ld<T>(Tg, e < nT ? e : nT - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nthr + tid;
+      if (e < nT) work[e] = v[q];
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {
+    for (int s = 1; s < nseg; ++s) {
+      cx<T> v = mk((T)0, (T)0);
+      if (lane < K) {
+        v = yt[64 * (s - 1) + lane];
+        if (s >= 2) {
+          const cx<T>* Tb = work + (long long)(s - 2) * K * K + lane;
+          const cx<T>* sp = stt + 64 * (s - 1);
+          cx<T> a1 = mk((T)0, (T)0);
+          int cp = 0;
+          for (; cp + 1 < K; cp += 2) {
+            v = cfma(v, Tb[cp * K], sp[cp]);
+            a1 = cfma(a1, Tb[(cp + 1) * K], sp[cp + 1]);
+          }
+          if (cp < K) v = cfma(v, Tb[cp * K], sp[cp]);
+          v = v + a1;
+        }
+      }
+      stt[64 * s + lane] = v;
+    }
+  }
+  __syncthreads();
+  if (wv >= 1 && wv < nseg)
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, SegDst<T, Dst>{dst, off}, Gw, len, K, ring,
+                            stt + 64 * wv, lane);
+}
+
+// One workgroup of P waves runs one double sweep.  Per strip: the
 // transmission data of its interfaces go to LDS (forward: g_{s,1} from the
 // current z, also kept for the backward pass; backward: the kept g_{s,1} and
 // g_{s,2} from the current z), then the forward substitution streams the
 // gathered right-hand side into the strip buffer and the back substitution
 // streams the solution from it into z.  Strips whose factorisation pivoted
-// take the lane-major path with explicit gather and scatter passes.
-// Dynamic LDS: the 512-entry ring and two node lines of transmission data.
-template <class T, int D, int S, int KP, int U>
-__global__ __launch_bounds__(64) void k_sweep(const SweepTask* __restrict__ tasks) {
+// take the lane-major path on wave 0, with explicit gather and scatter passes.
+// Dynamic LDS (complex elements): two node lines of transmission data, the
+// segment tails and states (64 P each), then the work area of solve_triangle.
+template <class T, int D, int S, int KP, int U, int NB, bool PIV>
+__global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tasks) {
   extern __shared__ char smem_raw[];
   const SweepTask& tk = tasks[blockIdx.x];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
+  const int P = nthr >> 6;
   const int n = uni(tk.n), N = uni(tk.N);
-  cx<T>* ring = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* gl1 = ring + 512;
+  cx<T>* gl1 = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* gl2 = gl1 + n;
+  cx<T>* yt = gl2 + n;
+  cx<T>* stt = yt + 64 * P;
+  cx<T>* work = stt + 64 * P;
   const cx<T>* img = uniptr((const cx<T>*)tk.img);
   const int* pivb = uniptr(tk.piv);
   const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
@@ -470,9 +652,9 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepTask* __restrict__ task
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off), piv_off = uni(sp->piv_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
-    const int pivoted = uni(pflag[uni(sp->gid)]);
+    const int pivoted = PIV ? uni(pflag[uni(sp->gid)]) : 0;
     const bool use2 = has2 && !fwd;
-    for (int l = lane; l < n; l += 64) {
+    for (int l = tid; l < n; l += nthr) {
       cx<T> e1 = zero, e2 = zero;
       if (has1) {
         if (fwd) {
@@ -492,74 +674,88 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepTask* __restrict__ task
       gl2[l] = e2;
     }
     __syncthreads();
-    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2};
+    const float winv = 1.0f / (float)w;
+    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2, winv};
     if (!pivoted) {
+      const int seg = uni(sp->seg), nseg = (ns + seg - 1) / seg;
       const cx<T>* GL = img + img_off;
       const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-      solve_blocked<T, KP, U>(gather, DstVec<T>{rho, ns, false}, (gptr<const cx<T>>)GL, ns, kl,
-                              ring, lane);
+      const cx<T>* TL = img + uni(sp->t_off);
+      const cx<T>* TU = TL + (long long)(nseg > 2 ? nseg - 2 : 0) * kl * kl;
+      solve_triangle<T, KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, TL, ns, kl, seg, work, yt,
+                               stt);
       __syncthreads();
-      solve_blocked<T, KP, U>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
-                              DstScatter<T>{z, ns, w, n, a, dir}, (gptr<const cx<T>>)GU, ns, kl,
-                              ring, lane);
-    } else {
+      solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
+                               DstScatter<T>{z, ns, w, n, a, dir, winv}, GU, TU, ns, kl, seg, work, yt,
+                               stt);
+    } else if (PIV && wv == 0) {
+      // single wave: its memory accesses are performed in order, the fences
+      // only keep the compiler from reordering them
       for (int q = lane; q < ns; q += 64) st<T>(rho, q, gather.get(gather.load(q)));
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       gptr<cx<T>> x[1] = {rho};
       gptr<const cx<T>> Lm[1] = {(gptr<const cx<T>>)(img + img_off)};
       gptr<const int> pv[1] = {(gptr<const int>)(pivb + piv_off)};
       solve_lower<T, 1, D>(x, Lm, pv, ns, lane);
-      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       const long long NP = ns + HH_PAD;
       gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64)};
       gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64 * (1 + S))};
       solve_upper<T, 1, D, S>(x, Um, rdg, ns, lane);
-      __syncthreads();
-      const DstScatter<T> out{z, ns, w, n, a, dir};
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      const DstScatter<T> out{z, ns, w, n, a, dir, winv};
       for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(rho, q));
     }
     __syncthreads();
   }
 }
 
-// One strip solve in FP64 in/out (test hook); work: ns elements of scratch.
-template <class T, int D, int S, int KP, int U>
-__global__ __launch_bounds__(64) void k_strip_solve(const StripDesc* __restrict__ strips, int si,
-                                                    const void* __restrict__ img,
-                                                    const int* __restrict__ pivb,
-                                                    const int* __restrict__ pflag,
-                                                    const c128* __restrict__ rhs, c128* __restrict__ x,
-                                                    cx<T>* __restrict__ work) {
-  __shared__ cx<T> ring[512];
+// One strip solve in FP64 in/out (test hook) by a workgroup of P waves, the
+// same substitutions as the sweep; work: ns elements of scratch.  Dynamic
+// LDS: tails, states and work area as in k_sweep.
+template <class T, int D, int S, int KP, int U, int NB>
+__global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict__ strips, int si,
+                                                     const void* __restrict__ img,
+                                                     const int* __restrict__ pivb,
+                                                     const int* __restrict__ pflag,
+                                                     const c128* __restrict__ rhs,
+                                                     c128* __restrict__ x,
+                                                     cx<T>* __restrict__ work) {
+  extern __shared__ char smem_raw[];
+  const int P = blockDim.x >> 6, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cx<T>* yt = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* stt = yt + 64 * P;
+  cx<T>* lds = stt + 64 * P;
   const StripDesc* sp = strips + si;
   const int ns = uni(sp->ns), kl = uni(sp->kl);
   const long long ioff = uni(sp->img_off), poff = uni(sp->piv_off);
   const int pivoted = uni(pflag[si]);
-  const int lane = threadIdx.x;
   const cx<T>* im = (const cx<T>*)img;
   gptr<cx<T>> wk = (gptr<cx<T>>)work;
   const SrcC128<T> in{(gptr<const c128>)rhs, ns};
   if (!pivoted) {
+    const int seg = uni(sp->seg), nseg = (ns + seg - 1) / seg;
     const cx<T>* GL = im + ioff;
     const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-    solve_blocked<T, KP, U>(in, DstVec<T>{wk, ns, false}, (gptr<const cx<T>>)GL, ns, kl, ring, lane);
+    const cx<T>* TL = im + uni(sp->t_off);
+    const cx<T>* TU = TL + (long long)(nseg > 2 ? nseg - 2 : 0) * kl * kl;
+    solve_triangle<T, KP, U, NB>(in, DstVec<T>{wk, ns, false}, GL, TL, ns, kl, seg, lds, yt, stt);
     __syncthreads();
-    solve_blocked<T, KP, U>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true},
-                            DstC128<T>{(gptr<c128>)x, ns}, (gptr<const cx<T>>)GU, ns, kl, ring,
-                            lane);
-  } else {
+    solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true},
+                             DstC128<T>{(gptr<c128>)x, ns}, GU, TU, ns, kl, seg, lds, yt, stt);
+  } else if (wv == 0) {
     for (int q = lane; q < ns; q += 64) st<T>(wk, q, in.get(in.load(q)));
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     gptr<cx<T>> xs[1] = {wk};
     gptr<const cx<T>> Lm[1] = {(gptr<const cx<T>>)(im + ioff)};
     gptr<const int> pv[1] = {(gptr<const int>)(pivb + poff)};
     solve_lower<T, 1, D>(xs, Lm, pv, ns, lane);
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     const long long NP = ns + HH_PAD;
     gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64)};
     gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64 * (1 + S))};
     solve_upper<T, 1, D, S>(xs, Um, rdg, ns, lane);
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     for (int q = lane; q < ns; q += 64) {
       const cx<T> v = ld<T>(wk, q);
       x[q] = mk((double)v.re, (double)v.im);
@@ -572,45 +768,62 @@ __global__ __launch_bounds__(64) void k_strip_solve(const StripDesc* __restrict_
 // Template choice.  D: coefficient prefetch depth of the pivoted path (deep
 // enough to cover memory latency, small enough to fit the register file);
 // KP: terms per lane of the blocked path (fixes S: KP <= 12 <=> kl <= 31);
-// U: blocks per step of the blocked path (two steps of maps are held in
-// registers).
+// U: blocks per step of the blocked path, NB: steps of maps held in registers
+// (requests run NB - 1 steps ahead).
 template <class T, int KP>
 struct SweepShape {
   static constexpr bool dbl = sizeof(T) == 8;
   static constexpr int S = KP <= 12 ? 1 : 2;
   static constexpr int D = S == 1 ? (dbl ? 16 : 32) : (dbl ? 8 : 16);
-  static constexpr int U = dbl ? (KP <= 10 ? 2 : 1) : (KP <= 10 ? 4 : 2);
+  static constexpr int U = !dbl && KP <= 12 ? 2 : 1;
+  static constexpr int NB = dbl && KP > 10 ? 2 : 3;
 };
 
-template <class T, int KP>
-static void launch_sweep_kp(const SweepTask* d, int ntasks, int nmax, hipStream_t st) {
+template <class T, int KP, bool PIV>
+static void launch_sweep_kp(const SweepTask* d, int ntasks, int P, int kmax, int nmax,
+                            hipStream_t st) {
   using Sh = SweepShape<T, KP>;
-  const void* fn = (const void*)k_sweep<T, Sh::D, Sh::S, KP, Sh::U>;
-  const size_t lds = (512 + 2 * (size_t)nmax) * sizeof(cx<T>);
+  const void* fn = (const void*)k_sweep<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB, PIV>;
+  const size_t lds = (size_t)sweep_lds_elems(P, kmax, nmax) * sizeof(cx<T>);
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_sweep<T, Sh::D, Sh::S, KP, Sh::U>), dim3(ntasks), dim3(64), lds, st, d);
+  hipLaunchKernelGGL((k_sweep<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB, PIV>), dim3(ntasks), dim3(64 * P),
+                     lds, st, d);
+}
+
+template <class T, int KP>
+static void launch_sweep_kp(const SweepTask* d, int ntasks, int P, int kmax, int nmax, bool piv,
+                            hipStream_t st) {
+  if (piv)
+    launch_sweep_kp<T, KP, true>(d, ntasks, P, kmax, nmax, st);
+  else
+    launch_sweep_kp<T, KP, false>(d, ntasks, P, kmax, nmax, st);
 }
 
 template <class T>
-static void launch_sweep_t(const SweepTask* d, int ntasks, int KP, int nmax, hipStream_t st) {
+static void launch_sweep_t(const SweepTask* d, int ntasks, int KP, int P, int kmax, int nmax,
+                           bool piv, hipStream_t st) {
   switch (KP) {
-    case 8: launch_sweep_kp<T, 8>(d, ntasks, nmax, st); break;
-    case 10: launch_sweep_kp<T, 10>(d, ntasks, nmax, st); break;
-    case 12: launch_sweep_kp<T, 12>(d, ntasks, nmax, st); break;
-    case 16: launch_sweep_kp<T, 16>(d, ntasks, nmax, st); break;
-    case 20: launch_sweep_kp<T, 20>(d, ntasks, nmax, st); break;
+    case 8: launch_sweep_kp<T, 8>(d, ntasks, P, kmax, nmax, piv, st); break;
+    case 10: launch_sweep_kp<T, 10>(d, ntasks, P, kmax, nmax, piv, st); break;
+    case 12: launch_sweep_kp<T, 12>(d, ntasks, P, kmax, nmax, piv, st); break;
+    case 16: launch_sweep_kp<T, 16>(d, ntasks, P, kmax, nmax, piv, st); break;
+    case 20: launch_sweep_kp<T, 20>(d, ntasks, P, kmax, nmax, piv, st); break;
     default: set_error("unsupported blocked term count %d", KP); throw ArgError();
   }
 }
 
-void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int nmax,
-                  hipStream_t st) {
+void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
+                  int nmax, bool pivots, hipStream_t st) {
   if (ntasks <= 0) return;
+  if (P < 1 || P > 8) {
+    set_error("unsupported segment count %d", P);
+    throw ArgError();
+  }
   if (precision == HH_FP64)
-    launch_sweep_t<double>(d_tasks, ntasks, KP, nmax, st);
+    launch_sweep_t<double>(d_tasks, ntasks, KP, P, kmax, nmax, pivots, st);
   else
-    launch_sweep_t<float>(d_tasks, ntasks, KP, nmax, st);
+    launch_sweep_t<float>(d_tasks, ntasks, KP, P, kmax, nmax, pivots, st);
   HH_HIP(hipGetLastError());
 }
 
@@ -619,7 +832,12 @@ static void launch_strip_kp(const hh_problem* pb, int si, const c128* rhs, c128*
                             hipStream_t st) {
   using Sh = SweepShape<T, KP>;
   const FactorSet& fs = pb->fs;
-  hipLaunchKernelGGL((k_strip_solve<T, Sh::D, Sh::S, KP, Sh::U>), dim3(1), dim3(64), 0, st,
+  const int P = fs.strips[si].segs;
+  const void* fn = (const void*)k_strip_solve<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB>;
+  const size_t lds = (size_t)sweep_lds_elems(P, fs.max_kl, 0) * sizeof(cx<T>);
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_strip_solve<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB>), dim3(1), dim3(64 * P), lds, st,
                      fs.d_strips, si, fs.img, fs.piv, fs.d_pflag, rhs, x, (cx<T>*)scratch);
 }
 
