@@ -29,8 +29,10 @@ namespace hh {
 
 namespace {
 
-constexpr int LU_THREADS = 256;
-constexpr int LU_EPT = 32;  // per-thread element budget: kl*2kl <= 256*32 -> kl <= 63
+constexpr int LU_WAVES = 4;
+constexpr int LU_THREADS = 64 * LU_WAVES;
+constexpr int LU_ROWS = (63 + LU_WAVES - 1) / LU_WAVES;  // rows of the window per wave (kl <= 63)
+constexpr int LU_CH = 16;  // column steps per staged chunk of entering rows
 
 template <class T>
 __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
@@ -43,107 +45,203 @@ __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
     }
   }
 }
-
+__device__ __forceinline__ float rdl(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdl(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 template <class T>
+__device__ __forceinline__ cx<T> rdlc(cx<T> v, int l) {
+  return mk(rdl(v.re, l), rdl(v.im, l));
+}
+
+// Column step j works on the (kl+1) x (2kl+1) window of rows j..j+kl and
+// columns j..j+2kl, kept in LDS with rotating physical rows and columns
+// (logical row r at (j + r) mod R, logical column c at (j + c) mod C).  Lane l
+// of every wave owns the physical columns l and l + 64; the window rows are
+// dealt out to the waves (row 1 + w + 8 i to wave w).  A step: every wave
+// reads the pivot column (lane r holds row r) and picks the pivot -- a
+// ballot against the diagonal settles the usual no-interchange case, only a
+// real interchange runs the shuffle reduction; lane r forms the multiplier of
+// row r; each wave updates its rows of the trailing window into registers
+// (row rp takes the old row 0: the interchange), retires the pivot row as a
+// row of U and the multipliers as a column of L, and after a barrier writes
+// them back, the retired column slot becoming the next fill column and the
+// retired row slot the entering row j+kl+1 (prefetched four steps ahead).
+template <class T>
+using lds_ptr = T __attribute__((address_space(3)))*;
+template <class T>
+__device__ __forceinline__ cx<T> ldw(lds_ptr<cx<T>> W, int i) {
+  return mk(W[i].re, W[i].im);
+}
+template <class T>
+__device__ __forceinline__ void stw(lds_ptr<cx<T>> W, int i, cx<T> v) {
+  W[i].re = v.re;
+  W[i].im = v.im;
+}
+
+template <class T, int NSL>
 __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restrict__ strips,
                                                         cx<T>* __restrict__ band,
                                                         int* __restrict__ pivbuf, int* err,
                                                         int* __restrict__ pflag) {
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
+  lds_ptr<cx<T>> W = (lds_ptr<cx<T>>)smem_raw;
   const StripDesc sd = strips[blockIdx.x];
   const int kl = sd.kl, kv = 2 * kl, R = kl + 1, C = kv + 1, ldab = sd.ldab, ns = sd.ns;
   cx<T>* ab = band + sd.band_off;
   int* piv = pivbuf + sd.piv_off;
   const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, so readlane(r) is scalar
   const cx<T> zero = mk((T)0, (T)0);
 
   // window at j = 0: logical (r, c) = physical (r, c)
   for (int e = tid; e < R * C; e += LU_THREADS) {
-    int r = e / C, c = e - r * C;
+    const int r = e / C, c = e - r * C;
     cx<T> v = zero;
     if (r < ns && c < ns && r - c <= kl && c - r <= kl) v = ab[(long long)c * ldab + kv + r - c];
-    W[r * C + c] = v;
+    stw(W, r * C + c, v);
   }
-  // entering row for the first steps: row j+kl+1, absolute columns j+1..j+1+kv
-  auto fetch_row = [&](int j) -> cx<T> {
-    int i = j + kl + 1, cabs = j + 1 + tid;
-    if (tid < C && i < ns && cabs < ns) return ab[(long long)cabs * ldab + kv + i - cabs];
-    return zero;
+  // entering row of step j (row j+kl+1) at physical column pc: after the
+  // step that slot holds logical column (pc - c0 - 1) mod C, c0 = j mod C
+  // (the load is unconditional, from a clamped address: a select between a
+  // global element and a local zero would become a flat load, which the LDS
+  // waits of every step would then have to wait for)
+  auto fetch = [&](int j, int c0, int pc) -> cx<T> {
+    const int i = j + kl + 1;
+    int cl = pc - c0 - 1;
+    cl = cl < 0 ? cl + C : cl;
+    const int col = j + 1 + cl;
+    const bool in = pc < C && i < ns && col < ns;
+    const long long at = in ? (long long)col * ldab + kv + i - col : 0;
+    const cx<T> v = ab[at];
+    return csel(in, v, zero);
   };
-  cx<T> nr[4];
+  auto wrap = [](int x, int m) { return x >= m ? x - m : x; };
+  // Entering rows are staged through LDS in chunks of LU_CH steps: the rows
+  // of chunk k+1 are loaded into registers (wave w: rows q = w mod LU_WAVES)
+  // while chunk k runs, so the column steps themselves issue no global loads
+  // and never wait for memory.
+  constexpr int QW = LU_CH / LU_WAVES;
+  lds_ptr<cx<T>> Sg = W + R * C;
+  cx<T> stg[QW][NSL];
+  auto load_chunk = [&](int jc, int cq) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) nr[u] = fetch_row(u);
+    for (int k = 0; k < QW; ++k) {
+      const int q = wv + LU_WAVES * k;
+      const int c0q = wrap(cq + q % C, C);
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) stg[k][s] = fetch(jc + q, c0q, lane + 64 * s);
+    }
+  };
+  load_chunk(0, 0);
+  int r0 = 0, c0 = 0, cn = LU_CH % C;  // cn = (jc + LU_CH) mod C
   __syncthreads();
 
-  const int nel = kl * kv;
-  // element list of this thread: e = tid + k*LU_THREADS -> (r, c) = (1 + e / kv, 1 + e % kv)
-  const int dr = LU_THREADS / kv, dc = LU_THREADS % kv;
-  const int r_first = 1 + tid / kv, c_first = 1 + tid % kv;
-  for (int j0 = 0; j0 < ns; j0 += 4) {
+  for (int jc = 0; jc < ns; jc += LU_CH) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = j0 + u;
+    for (int k = 0; k < QW; ++k) {
+      const int q = wv + LU_WAVES * k;
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        const int pc = lane + 64 * s;
+        if (pc < C) stw(Sg, q * C + pc, stg[k][s]);
+      }
+    }
+    load_chunk(jc + LU_CH, cn);
+    cn = wrap(cn + LU_CH % C, C);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < LU_CH; ++u) {
+      const int j = jc + u;
       if (j >= ns) break;
-      const int r0 = j % R, c0 = j % C;
-      auto prow = [&](int r) { int x = r0 + r; return x >= R ? x - R : x; };
-      auto pcol = [&](int c) { int x = c0 + c; return x >= C ? x - C : x; };
-      // ---- read phase: pivot search (every wave redundantly) and operands
+      auto prow = [&](int r) { return wrap(r0 + r, R); };
+      // ---- pivot column, pivot choice (redundantly in every wave)
       const int rmax = min(kl, ns - 1 - j);
-      T v = (T)-1;
-      int idx = 64;
-      if (lane <= rmax) {
-        v = cabs1(W[prow(lane) * C + c0]);
-        idx = lane;
+      const cx<T> val = csel(lane <= kl, ldw(W, prow(lane <= kl ? lane : kl) * C + c0), zero);
+      const T av = lane <= rmax ? cabs1(val) : (T)-1;
+      const T ad = rdl(av, 0);
+      int rp = 0;
+      if (__ballot(av > ad)) {  // a real interchange (rare): first index of the maximum
+        T v = av;
+        int idx = lane <= rmax ? lane : 64;
+        wave_argmax(v, idx);
+        rp = __builtin_amdgcn_readfirstlane(idx);
       }
-      wave_argmax(v, idx);
-      const int rp = idx;
       const int prp = prow(rp);
-      const cx<T> pv = W[prp * C + c0];
-      const bool singular = (pv.re == (T)0 && pv.im == (T)0);
-      const cx<T> ipv = singular ? zero : cinv(pv);
-      if (singular && tid == 0) atomicCAS(err, 0, (int)blockIdx.x + 1);
-      if (tid == 0) {
-        piv[j] = j + rp;
-        if (rp != 0) pflag[blockIdx.x] = 1;
-      }
-      // retire row j of U (pivot row) and column j of L
-      for (int c = tid; c < C; c += LU_THREADS)
-        if (j + c < ns) ab[(long long)(j + c) * ldab + kv - c] = W[prp * C + pcol(c)];
-      for (int r = 1 + tid; r <= rmax; r += LU_THREADS) {
-        int src = (r == rp) ? 0 : r;
-        ab[(long long)j * ldab + kv + r] = W[prow(src) * C + c0] * ipv;
-      }
-      cx<T> nv[LU_EPT];
-      {
-        int r = r_first, c = c_first;
+      const cx<T> pv = rdlc(val, rp);
+      const T pd = pv.re * pv.re + pv.im * pv.im;
+      const bool singular = pd == (T)0;
+      const T ipd = singular ? (T)0 : (T)1 / pd;
+      const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
+      // multiplier of (new) row r, which is the old row 0 if r == rp
+      const cx<T> v0 = rdlc(val, 0);
+      const cx<T> Lr = csel(lane >= 1 && lane <= rmax, csel(lane == rp, v0, val) * ipv, zero);
+      // pivot row (the new row of U) in the lane's columns
+      cx<T> ucol[NSL];
 #pragma unroll
-        for (int k = 0; k < LU_EPT; ++k) {
-          if (tid + k * LU_THREADS < nel) {
-            const int psrc = prow(r == rp ? 0 : r), pc = pcol(c);
-            cx<T> lr = W[psrc * C + c0] * ipv;
-            nv[k] = cfms(W[psrc * C + pc], lr, W[prp * C + pc]);
+      for (int s = 0; s < NSL; ++s) {
+        const int pc = lane + 64 * s;
+        ucol[s] = csel(pc < C, ldw(W, prp * C + (pc < C ? pc : C - 1)), zero);
+      }
+      if (wv == 0) {
+        if (lane == 0) {
+          piv[j] = j + rp;
+          if (rp != 0) pflag[blockIdx.x] = 1;
+          if (singular) atomicCAS(err, 0, (int)blockIdx.x + 1);
+        }
+        if (lane >= 1 && lane <= rmax) ab[(long long)j * ldab + kv + lane] = Lr;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) {
+          const int pc = lane + 64 * s;
+          int c = pc - c0;
+          c = c < 0 ? c + C : c;
+          if (pc < C && j + c < ns) ab[(long long)(j + c) * ldab + kv - c] = ucol[s];
+        }
+      }
+      // ---- trailing update of this wave's rows, into registers
+      cx<T> keep[LU_ROWS][NSL];
+#pragma unroll
+      for (int i = 0; i < LU_ROWS; ++i) {
+        const int r = 1 + wv + LU_WAVES * i;
+        if (r <= kl) {
+          const int src = prow(r == rp ? 0 : r);
+          const cx<T> l = rdlc(Lr, r);
+#pragma unroll
+          for (int s = 0; s < NSL; ++s) {
+            const int pc = lane + 64 * s;
+            const cx<T> w = csel(pc < C, ldw(W, src * C + (pc < C ? pc : C - 1)), zero);
+            keep[i][s] = csel(pc == c0, zero, cfms(w, l, ucol[s]));
           }
-          r += dr;
-          c += dc;
-          if (c > kv) { c -= kv; r += 1; }
         }
       }
       __syncthreads();
-      // ---- write phase: updated window, entering row, fill column
-      {
-        int r = r_first, c = c_first;
+      // ---- write back; the retired row slot takes the entering row
 #pragma unroll
-        for (int k = 0; k < LU_EPT; ++k) {
-          if (tid + k * LU_THREADS < nel) W[prow(r) * C + pcol(c)] = nv[k];
-          r += dr;
-          c += dc;
-          if (c > kv) { c -= kv; r += 1; }
+      for (int i = 0; i < LU_ROWS; ++i) {
+        const int r = 1 + wv + LU_WAVES * i;
+        if (r <= kl) {
+          const int pr = prow(r);
+#pragma unroll
+          for (int s = 0; s < NSL; ++s) {
+            const int pc = lane + 64 * s;
+            if (pc < C) stw(W, pr * C + pc, keep[i][s]);
+          }
         }
       }
-      if (tid < C) W[r0 * C + pcol(1 + tid < C ? 1 + tid : 1 + tid - C)] = nr[u];
-      for (int r = tid; r < kl; r += LU_THREADS) W[prow(1 + r) * C + c0] = zero;
-      nr[u] = fetch_row(j + 4);
+      if (wv == LU_WAVES - 1) {
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) {
+          const int pc = lane + 64 * s;
+          if (pc < C) stw(W, r0 * C + pc, ldw(Sg, u * C + pc));
+        }
+      }
+      r0 = wrap(r0 + 1, R);
+      c0 = wrap(c0 + 1, C);
       __syncthreads();
     }
   }
@@ -166,12 +264,13 @@ __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>*
   cx<T>* Um = Lm + (long long)NP * 64;
   cx<T>* rdg = Um + (long long)NP * 64 * S;
   int c = (l - (j & 63)) & 63;
-  Lm[e] = (j < ns && c >= 1 && c <= kl && j + c < ns) ? ab[(long long)j * ldab + kv + c] : zero;
+  const bool inl = j < ns && c >= 1 && c <= kl && j + c < ns;
+  Lm[e] = csel(inl, ab[inl ? (long long)j * ldab + kv + c : 0], zero);
   const int col = ns - 1 - j;  // step J = j of the back substitution
   cx<T> rd = zero;
   if (j < ns) {
     const cx<T> d = ab[(long long)col * ldab + kv];
-    rd = (d.re == (T)0 && d.im == (T)0) ? zero : cinv(d);
+    rd = csel(d.re == (T)0 && d.im == (T)0, zero, cinv(d));
   }
   for (int k = 0; k < S; ++k) {
     c = 64 * k + ((l - (j & 63)) & 63);
@@ -334,20 +433,32 @@ static dim3 transfer_grid(const FactorSet& fs) {
   return dim3((unsigned)((cells + 63) / 64), (unsigned)fs.strips.size(), 2);
 }
 
+// One or two column slots per lane: 2 kl + 1 <= 64 needs one.
+template <class T>
+static void launch_lu(const FactorSet& fs, size_t lds, hipStream_t st) {
+  const int nstr = (int)fs.strips.size();
+  const bool one = 2 * fs.max_kl + 1 <= 64;
+  const void* fn = one ? (const void*)k_band_lu<T, 1> : (const void*)k_band_lu<T, 2>;
+  HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (one)
+    hipLaunchKernelGGL((k_band_lu<T, 1>), dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
+                       (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+  else
+    hipLaunchKernelGGL((k_band_lu<T, 2>), dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
+                       (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+}
+
 void launch_band_lu(const hh_problem* pb, hipStream_t st) {
   const FactorSet& fs = pb->fs;
   HH_HIP(hipMemsetAsync(fs.img, 0, fs.img_elems * (fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64)), st));
   int nstr = (int)fs.strips.size();
   size_t esz = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
-  size_t lds = (size_t)(fs.max_kl + 1) * (2 * fs.max_kl + 1) * esz;
+  size_t lds = (size_t)(fs.max_kl + 1 + LU_CH) * (2 * fs.max_kl + 1) * esz;
   double bytes = 0;
   for (auto& s : fs.strips) bytes += 2.0 * (double)s.ns * s.ldab * esz;
   TimedRegion tr(FAM_FACTOR, st, bytes);
   if (fs.precision == HH_FP64) {
-    HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_band_lu<double>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
-                       (c128*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+    launch_lu<double>(fs, lds, st);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<double>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv,
@@ -357,10 +468,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
     hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
   } else {
-    HH_HIP(hipFuncSetAttribute((const void*)k_band_lu<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_band_lu<float>, dim3(nstr), dim3(LU_THREADS), lds, st, fs.d_strips,
-                       (c64*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+    launch_lu<float>(fs, lds, st);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<float>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv,

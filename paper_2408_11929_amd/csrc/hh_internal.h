@@ -50,6 +50,13 @@ template <class T>
 __host__ __device__ __forceinline__ cx<T> cfms(cx<T> a, cx<T> b, cx<T> c) {
   return mk(a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re);
 }
+// c ? a : b on the components.  (A conditional between two complex lvalues
+// would select between their addresses and load through the result; with
+// one of them in LDS or on the stack that becomes a flat load.)
+template <class T>
+__host__ __device__ __forceinline__ cx<T> csel(bool c, cx<T> a, cx<T> b) {
+  return mk(c ? a.re : b.re, c ? a.im : b.im);
+}
 // a + b * c as four fused multiply-adds
 __host__ __device__ __forceinline__ float fmac_(float x, float y, float z) { return __builtin_fmaf(x, y, z); }
 __host__ __device__ __forceinline__ double fmac_(double x, double y, double z) { return __builtin_fma(x, y, z); }

@@ -29,9 +29,10 @@ __global__ __launch_bounds__(256) void k_spmv(const SpmvTask* __restrict__ tasks
   const c128* A = tk.A;
   const c128 a0 = A[p], a1 = A[nn + p], an = A[2 * nn + p], an1 = A[3 * nn + p];
   const c128 zero = mk(0.0, 0.0);
-  const c128 b1 = p >= 1 ? A[nn + p - 1] : zero;
-  const c128 bn = p >= n ? A[2 * nn + p - n] : zero;
-  const c128 bn1 = p >= n + 1 ? A[3 * nn + p - n - 1] : zero;
+  // (the loads stay inside A for every p; the selects act on values)
+  const c128 b1 = csel(p >= 1, A[nn + p - 1], zero);
+  const c128 bn = csel(p >= n, A[2 * nn + p - n], zero);
+  const c128 bn1 = csel(p >= n + 1, A[3 * nn + p - n - 1], zero);
   for (int v = 0; v < tk.nvec; ++v) {
     const long long o = v * nn;
     c128 acc = a0 * ld_c128<T>(tk.x, o + p);

@@ -106,8 +106,8 @@ __device__ __forceinline__ void solve_lower(gptr<cx<T>> (&x)[C], gptr<const cx<T
   int pc[C], pn[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    b[c] = lane < ns ? ld<T>(x[c], lane) : zero;
-    nxtA[c] = 64 + lane < ns ? ld<T>(x[c], 64 + lane) : zero;
+    b[c] = csel(lane < ns, ld<T>(x[c], lane < ns ? lane : 0), zero);
+    nxtA[c] = csel(64 + lane < ns, ld<T>(x[c], 64 + lane < ns ? 64 + lane : 0), zero);
     nxt[c] = yout[c] = zero;
     pc[c] = lane < D ? piv[c][lane] : 0;
 #pragma unroll
@@ -119,7 +119,7 @@ __device__ __forceinline__ void solve_lower(gptr<cx<T>> (&x)[C], gptr<const cx<T
       for (int c = 0; c < C; ++c) {
         nxt[c] = nxtA[c];
         const int e = j0 + 128 + lane;
-        nxtA[c] = e < ns ? ld<T>(x[c], e) : zero;
+        nxtA[c] = csel(e < ns, ld<T>(x[c], e < ns ? e : 0), zero);
       }
     }
 #pragma unroll
@@ -177,10 +177,10 @@ __device__ __forceinline__ void solve_upper(gptr<cx<T>> (&x)[C], gptr<const cx<T
 #pragma unroll
     for (int k = 0; k < S; ++k) {
       const int E = 64 * k + lane;
-      b[c][k] = E < ns ? ld<T>(x[c], ns - 1 - E) : zero;
+      b[c][k] = csel(E < ns, ld<T>(x[c], E < ns ? ns - 1 - E : 0), zero);
     }
     const int E = 64 * S + lane;
-    nxtA[c] = E < ns ? ld<T>(x[c], ns - 1 - E) : zero;
+    nxtA[c] = csel(E < ns, ld<T>(x[c], E < ns ? ns - 1 - E : 0), zero);
     nxt[c] = braw[c] = rd[c] = zero;
 #pragma unroll
     for (int u = 0; u < D; ++u)
@@ -193,7 +193,7 @@ __device__ __forceinline__ void solve_upper(gptr<cx<T>> (&x)[C], gptr<const cx<T
       for (int c = 0; c < C; ++c) {
         nxt[c] = nxtA[c];
         const int E = J0 + 64 * S + 64 + lane;
-        nxtA[c] = E < ns ? ld<T>(x[c], ns - 1 - E) : zero;
+        nxtA[c] = csel(E < ns, ld<T>(x[c], E < ns ? ns - 1 - E : 0), zero);
         rd[c] = ld<T>(rdg[c], J0 + lane);
       }
     }
