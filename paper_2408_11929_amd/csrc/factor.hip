@@ -299,71 +299,83 @@ __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>*
 // block's outputs (row t = 0..3: out_{i0-16+4p+t}), four block inputs
 // (t = 4..7: in_{i0+4p+t-4}) and KO = KP - 8 of the older outputs
 // (t = 8..: out_{i0-K+p KO+t-8}, zero where that lies at or past i0-16).
-// grid = (blocks*(K+B) / 128, strips, 2).
+// One wave per (block, strip, triangle): the block's coefficients T(i, c) go
+// to LDS, lane l runs the recurrences of columns l and l + 64; a unit
+// "previous output" enters each row once, the rest is the block's own
+// recurrence (at most 15 terms per row).
 template <class T>
-__global__ __launch_bounds__(128) void k_build_blocked(const StripDesc* __restrict__ strips,
-                                                       const cx<T>* __restrict__ band,
-                                                       cx<T>* __restrict__ img,
-                                                       const int* __restrict__ pflag) {
-  if (pflag[blockIdx.y]) return;
+__global__ __launch_bounds__(64) void k_build_blocked(const StripDesc* __restrict__ strips,
+                                                      const cx<T>* __restrict__ band,
+                                                      cx<T>* __restrict__ img,
+                                                      const int* __restrict__ pflag) {
   constexpr int B = HH_BLK;
   static_assert(HH_BLK == 16, "the column split assumes four lane groups of 16 rows");
+  __shared__ c128 cf[B][64];  // cf[r][c - 1] = T(i0 + r, c), zero where undefined
+  __shared__ c128 dv[B];      // row scale d (1 for L, 1/U(j, j) for U, 0 past the end)
+  if (pflag[blockIdx.y]) return;
   const StripDesc sd = strips[blockIdx.y];
   const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab, KP = sd.KP;
-  const int nb = (ns + B - 1) / B, ncol = K + B;
-  const long long e = blockIdx.x * 128LL + threadIdx.x;
-  if (e >= (long long)nb * ncol) return;
-  const int b = (int)(e / ncol), k = (int)(e % ncol);
+  const int nb = (ns + B - 1) / B, b = blockIdx.x;
+  if (b >= nb) return;
+  const int lane = threadIdx.x;
   const bool upper = blockIdx.z == 1;
   const cx<T>* ab = band + sd.band_off;
   cx<T>* G = img + sd.img_off + (upper ? blocked_blocks(ns) * KP * 64 : 0);
-  c128 win[64 + B];
-  for (int q = 0; q < K; ++q) win[q] = mk(q == k ? 1.0 : 0.0, 0.0);
-  for (int i = 0; i < B; ++i) {
-    const int g = b * B + i;
-    c128 acc = mk(0.0, 0.0);
-    if (g < ns) {
-      acc = mk((k >= K && k - K == i) ? 1.0 : 0.0, 0.0);
-      for (int c = 1; c <= K && c <= g; ++c) {
-        c128 coef;
-        if (!upper) {
-          const cx<T> v = ab[(long long)(g - c) * ldab + kv + c];
-          coef = mk((double)v.re, (double)v.im);
-        } else {
-          const int j = ns - 1 - g;
-          const cx<T> v = ab[(long long)(j + c) * ldab + kv - c];
-          coef = mk((double)v.re, (double)v.im);
-        }
-        acc = cfms(acc, coef, win[K + i - c]);
-      }
-      // terms reaching before the strip start (g - c < 0) multiply the K
-      // "previous outputs" of block 0, which are zero by definition
-      if (upper) {
-        const int j = ns - 1 - g;
-        const cx<T> d = ab[(long long)j * ldab + kv];
-        const c128 dd = mk((double)d.re, (double)d.im);
-        acc = acc * cinv(dd);
-      }
-    }
-    win[K + i] = acc;
-  }
-  // lane group p and row t of column k (see above)
-  const int KO = KP - 8;
-  int p, t;
-  if (k >= K) {  // block input k - K
-    p = (k - K) / 4;
-    t = 4 + (k - K) % 4;
-  } else if (k >= K - B) {  // output of the previous block, i0 - K + k = i0 - 16 + j
-    const int j = k - (K - B);
-    p = j / 4;
-    t = j % 4;
-  } else {  // older output
-    p = k / KO;
-    t = 8 + k % KO;
-  }
+  const int i0 = b * B;
   for (int r = 0; r < B; ++r) {
-    const c128 v = win[K + r];
-    G[((long long)b * KP + t) * 64 + r + B * p] = mk((T)v.re, (T)v.im);
+    const int g = i0 + r, c = lane + 1;
+    c128 v = mk(0.0, 0.0);
+    if (c <= K && g < ns && g - c >= 0) {
+      const cx<T> x = upper ? ab[(long long)(ns - 1 - g + c) * ldab + kv - c]
+                            : ab[(long long)(g - c) * ldab + kv + c];
+      v = mk((double)x.re, (double)x.im);
+    }
+    cf[r][lane] = v;
+  }
+  if (lane < B) {
+    const int g = i0 + lane;
+    c128 d = mk(g < ns ? 1.0 : 0.0, 0.0);
+    if (upper && g < ns) {
+      const cx<T> x = ab[(long long)(ns - 1 - g) * ldab + kv];
+      d = cinv(mk((double)x.re, (double)x.im));
+    }
+    dv[lane] = d;
+  }
+  __syncthreads();
+  const int KO = KP - 8;
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int k = lane + 64 * sl;
+    if (k >= K + B) break;
+    c128 out[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      c128 acc = mk((k >= K && k - K == r) ? 1.0 : 0.0, 0.0);
+      if (k < K) {  // the unit previous output sits c = K + r - k rows back
+        const int c = K + r - k;
+        if (c <= K) acc = acc - cf[r][c - 1];
+      }
+#pragma unroll
+      for (int c = 1; c <= r; ++c)
+        if (c <= K) acc = cfms(acc, cf[r][c - 1], out[r - c]);
+      out[r] = acc * dv[r];
+    }
+    // lane group p and row t of column k (see above)
+    int p, t;
+    if (k >= K) {  // block input k - K
+      p = (k - K) / 4;
+      t = 4 + (k - K) % 4;
+    } else if (k >= K - B) {  // output of the previous block, i0 - K + k = i0 - 16 + j
+      const int j = k - (K - B);
+      p = j / 4;
+      t = j % 4;
+    } else {  // older output
+      p = k / KO;
+      t = 8 + k % KO;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      G[((long long)b * KP + t) * 64 + r + B * p] = mk((T)out[r].re, (T)out[r].im);
   }
 }
 
@@ -374,63 +386,73 @@ __global__ __launch_bounds__(128) void k_build_blocked(const StripDesc* __restri
 // where column c' of T_s is the tail of the recurrence over segment s started
 // from the unit state e_c' with zero inputs.  Stored for s = 1..nseg-2 as
 // T[((s-1) K + c') K + c] = tail row c, in the order in which the sweep
-// kernel stages them.  One thread per (segment, c'); FP64 recurrence from the
-// stored factors (same conventions as the blocked maps).  grid = (cells / 64,
-// strips, 2).
+// kernel stages them.  One wave per (segment, strip, triangle), lane c' runs
+// column c' in FP64 from the stored factors (same conventions as the blocked
+// maps) with its window of the last 64 outputs in LDS; the coefficients of
+// the next row are fetched while a row is computed.
 template <class T>
 __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restrict__ strips,
                                                        const cx<T>* __restrict__ band,
                                                        cx<T>* __restrict__ img,
                                                        const int* __restrict__ pflag) {
+  // win[i & 63][c'] = out_i of column c' < 63; column 63 holds the
+  // coefficients of the current row (entry K: the scale d)
+  __shared__ c128 win[64][64];
   if (pflag[blockIdx.y]) return;
   const StripDesc sd = strips[blockIdx.y];
   const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab, seg = sd.seg;
   const int nseg = (ns + seg - 1) / seg;
-  const long long e = blockIdx.x * 64LL + threadIdx.x;
-  if (e >= (long long)std::max(nseg - 2, 0) * K) return;
-  const int s = 1 + (int)(e / K), cp = (int)(e % K);
+  const int s = 1 + blockIdx.x;
+  if (s > nseg - 2) return;
+  const int lane = threadIdx.x;
   const bool upper = blockIdx.z == 1;
   const cx<T>* ab = band + sd.band_off;
   cx<T>* Tm = img + sd.t_off + (upper ? (long long)(nseg - 2) * K * K : 0);
-  c128 win[64];  // out_i at win[i & 63]
   const int s0 = s * seg, s1 = s0 + seg;
-  for (int q = 0; q < K; ++q) win[(s0 - K + q) & 63] = mk(q == cp ? 1.0 : 0.0, 0.0);
-  for (int i = s0; i < s1; ++i) {
-    c128 acc = mk(0.0, 0.0);
-    const int j = ns - 1 - i;
-    for (int c = 1; c <= K; ++c) {
-      const cx<T> v = upper ? ab[(long long)(j + c) * ldab + kv - c]
+  // lane c < K fetches T(i, c + 1), lane K the diagonal of row i (U only)
+  auto coef = [&](int i) -> c128 {
+    const int j = ns - 1 - i, c = lane + 1;
+    if (lane < K) {
+      const cx<T> x = upper ? ab[(long long)(j + c) * ldab + kv - c]
                             : ab[(long long)(i - c) * ldab + kv + c];
-      acc = cfms(acc, mk((double)v.re, (double)v.im), win[(i - c) & 63]);
+      return mk((double)x.re, (double)x.im);
     }
-    if (upper) {
-      const cx<T> d = ab[(long long)j * ldab + kv];
-      acc = acc * cinv(mk((double)d.re, (double)d.im));
+    if (lane == K && upper) {
+      const cx<T> x = ab[(long long)j * ldab + kv];
+      return mk((double)x.re, (double)x.im);
     }
-    win[i & 63] = acc;
-    if (i >= s1 - K) {
-      const int c = i - (s1 - K);
-      Tm[((long long)(s - 1) * K + cp) * K + c] = mk((T)acc.re, (T)acc.im);
-    }
+    return mk(lane == K ? 1.0 : 0.0, 0.0);
+  };
+  for (int q = 0; q < 64; ++q) win[q][lane] = mk(0.0, 0.0);
+  if (lane < K) win[(s0 - K + lane) & 63][lane] = mk(1.0, 0.0);
+  c128 nxt = coef(s0);
+  for (int i = s0; i < s1; ++i) {
+    __syncthreads();
+    win[lane][63] = (lane == K && upper) ? cinv(nxt) : nxt;
+    if (i + 1 < s1) nxt = coef(i + 1);
+    __syncthreads();
+    c128 acc = mk(0.0, 0.0);
+    for (int c = 1; c <= K; ++c) acc = cfms(acc, win[c - 1][63], win[(i - c) & 63][lane]);
+    acc = acc * win[K][63];
+    __syncthreads();
+    if (lane < 63) win[i & 63][lane] = acc;
+    if (lane < K && i >= s1 - K)
+      Tm[((long long)(s - 1) * K + lane) * K + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
   }
 }
 
 }  // namespace
 
 dim3 blocked_grid(const FactorSet& fs) {
-  long long cells = 0;
-  for (auto& sd : fs.strips)
-    cells = std::max(cells, (long long)((sd.ns + HH_BLK - 1) / HH_BLK) * (sd.kl + HH_BLK));
-  return dim3((unsigned)((cells + 127) / 128), (unsigned)fs.strips.size(), 2);
+  int blocks = 1;
+  for (auto& sd : fs.strips) blocks = std::max(blocks, (sd.ns + HH_BLK - 1) / HH_BLK);
+  return dim3((unsigned)blocks, (unsigned)fs.strips.size(), 2);
 }
 
 static dim3 transfer_grid(const FactorSet& fs) {
-  long long cells = 1;
-  for (auto& sd : fs.strips) {
-    const int nseg = (sd.ns + sd.seg - 1) / sd.seg;
-    cells = std::max(cells, (long long)std::max(nseg - 2, 0) * sd.kl);
-  }
-  return dim3((unsigned)((cells + 63) / 64), (unsigned)fs.strips.size(), 2);
+  int segs = 1;
+  for (auto& sd : fs.strips) segs = std::max(segs, (sd.ns + sd.seg - 1) / sd.seg - 2);
+  return dim3((unsigned)segs, (unsigned)fs.strips.size(), 2);
 }
 
 // One or two column slots per lane: 2 kl + 1 <= 64 needs one.
@@ -463,7 +485,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
     hipLaunchKernelGGL(k_build_image<double>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv,
                        fs.d_pflag);
-    hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(128), 0, st, fs.d_strips,
+    hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
     hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
@@ -473,7 +495,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
     hipLaunchKernelGGL(k_build_image<float>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv,
                        fs.d_pflag);
-    hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(128), 0, st, fs.d_strips,
+    hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
     hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
