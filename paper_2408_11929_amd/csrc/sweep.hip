@@ -241,24 +241,27 @@ __device__ __forceinline__ void solve_upper(gptr<cx<T>> (&x)[C], gptr<const cx<T
   }
 }
 
-// Sum over the four 16-lane groups of the wave; every lane receives the same
-// (bitwise) result, (g0 + g1) + (g2 + g3).  v_permlane16_swap exchanges rows
-// 1 and 3 of its first operand with rows 0 and 2 of its second; with both
-// operands equal the two results hold the even and the odd rows.
-// v_permlane32_swap does the same with the two halves of the wave.
-__device__ __forceinline__ float sum4(float v) {
-  const unsigned u = __float_as_uint(v);
-  const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+// Sum of a complex partial over the four 16-lane groups of the wave, both
+// parts in one pass.  v_permlane16_swap exchanges rows 1 and 3 of its first
+// operand with rows 0 and 2 of its second, so with (re, im) as operands the
+// two results hold the real parts of rows 0/2 and the imaginary parts of rows
+// 1/3, and the real parts of rows 1/3 and the imaginary parts of rows 0/2;
+// v_permlane32_swap then does the same with the two halves of the wave.  Lane
+// r + 16 p ends with the real part of the sum when p is even and the imaginary
+// part when p is odd, (g0 + g1) + (g2 + g3) in every lane.
+__device__ __forceinline__ float sum4c(float re, float im) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(re), __float_as_uint(im), false,
+                                                  false);
   const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
   const unsigned w = __float_as_uint(s);
   const auto b = __builtin_amdgcn_permlane32_swap(w, w, false, false);
   return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
-__device__ __forceinline__ double sum4(double v) {
-  const unsigned long long u = __double_as_longlong(v);
-  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
-  const auto al = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  const auto ah = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+__device__ __forceinline__ double sum4c(double re, double im) {
+  const unsigned long long ur = __double_as_longlong(re), ui = __double_as_longlong(im);
+  const auto al = __builtin_amdgcn_permlane16_swap((unsigned)ur, (unsigned)ui, false, false);
+  const auto ah = __builtin_amdgcn_permlane16_swap((unsigned)(ur >> 32), (unsigned)(ui >> 32), false,
+                                                   false);
   const double s = __longlong_as_double(((long long)ah[0] << 32) | al[0]) +
                    __longlong_as_double(((long long)ah[1] << 32) | al[1]);
   const unsigned long long w = __double_as_longlong(s);
@@ -273,7 +276,8 @@ __device__ __forceinline__ double sum4(double v) {
 // factor.hip): out_i = d_i (in_i - sum_{c=1..K} T(i, c) out_{i-c}) in blocks
 // of B = 16 outputs, each a dense map of the K previous outputs and the 16
 // block inputs.  Lane l = r + 16 p accumulates KP terms of output r, and the
-// four partial sums of a row are combined by lane swaps (sum4).
+// four partial sums of a row are combined by lane swaps (sum4c), after which
+// lanes with even p hold the real and lanes with odd p the imaginary part.
 //
 // Only the four terms of a lane that involve the previous block's outputs lie
 // on the chain from block to block; the other KP - 4 terms of block b+1
@@ -316,6 +320,12 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
     const int k = i & 255;
     rg[k] = v;
     rg[k < 64 ? k + 256 : k] = v;
+  };
+  auto put_part = [&](cx<T>* rg, int i, int part, T v) {  // one component of entry i
+    const int k = i & 255;
+    T* base = reinterpret_cast<T*>(rg) + part;
+    base[2 * k] = v;
+    base[2 * (k < 64 ? k + 256 : k)] = v;
   };
 #pragma unroll
   for (int q = 0; q < 10; ++q) ring[64 * q + lane] = zero;
@@ -376,12 +386,12 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
         a0 = cfma(a0, g[h][u][2], pv[2]);
         a1 = cfma(a1, g[h][u][3], pv[3]);
         const cx<T> part = a0 + a1;
-        const cx<T> acc = mk(sum4(part.re), sum4(part.im));
+        const T half = sum4c(part.re, part.im);  // real part (p even) or imaginary part (p odd)
         if (u + 1 < U)
           rst = rest(g[h][u + 1 < U ? u + 1 : u], i0 + 16);
         else
           rst = rest(g[(h + 1) % NB][0], i0 + 16);
-        put(oring, i0 + r, acc);
+        put_part(oring, i0 + r, p & 1, half);
       }
     }
   }
