@@ -112,7 +112,7 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       sd.band_off = band;
       band += (long long)sd.ns * sd.ldab;
       sd.segs = P;
-      sd.seg = segment_rows(sd.ns, P);
+      plan_layout(sd);
       sd.img_off = img;
       sd.t_off = img + 2 * blocked_blocks(sd.ns) * sd.KP * 64;
       img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P);
@@ -290,8 +290,16 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
     void* rho = dev_alloc((size_t)nvec * fs.max_ns * es);
     void* g1 = dev_alloc((size_t)nvec * fs.N * pb->n * es);
     void* zs = fs.precision == HH_FP64 ? (void*)z : dev_alloc((size_t)nvec * len * es);
-    // one right-hand side per workgroup
+    // one chain per right-hand side, one or plan_width(plan) workgroups per chain
     const int ntask = nvec;
+    const int plan = sweep_plan_for(ntask, fs.precision, fs.strips[0].segs, fs.max_kl, pb->n,
+                                    fs.any_pivot);
+    const int G = plan_width(plan);
+    hipStream_t st = pb->st[0];
+    // sync words: [0] abort, then one 128-byte line per chain
+    unsigned* sync = (unsigned*)dev_alloc((size_t)(ntask + 1) * 128);
+    void* xch = plan > 0 ? dev_alloc((size_t)ntask * G * 64 * es) : nullptr;
+    HH_HIP(hipMemsetAsync(sync, 0, (size_t)(ntask + 1) * 128, st));
     std::vector<SweepTask> tasks(ntask);
     for (int v = 0; v < nvec; ++v) {
       SweepTask& tk = tasks[v];
@@ -306,9 +314,10 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
       tk.tr = fs.tr;
       tk.n = pb->n;
       tk.N = fs.N;
+      tk.xch = xch ? (char*)xch + (size_t)v * G * 64 * es : nullptr;
+      tk.bar = sync + 32 * (v + 1);
     }
     SweepTask* d_tasks = (SweepTask*)dev_alloc(ntask * sizeof(SweepTask));
-    hipStream_t st = pb->st[0];
     HH_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntask * sizeof(SweepTask), hipMemcpyHostToDevice, st));
     {
       double bytes = 0;
@@ -319,14 +328,22 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
       }
       TimedRegion tr(FAM_SWEEP, st, bytes);
       launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].KP, fs.strips[0].segs, fs.max_kl,
-                   pb->n, fs.any_pivot, st);
+                   pb->n, fs.any_pivot, plan, sync, st);
     }
     if (fs.precision != HH_FP64) launch_widen((const c64*)zs, (c128*)z, nvec * len, st);
+    unsigned aborted = 0;
+    HH_HIP(hipMemcpyAsync(&aborted, sync, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HH_HIP(hipStreamSynchronize(st));
     dev_free(d_tasks);
     dev_free(rho);
     dev_free(g1);
+    dev_free(xch);
+    dev_free(sync);
     if (zs != (void*)z) dev_free(zs);
+    if (aborted) {
+      set_error("sweep workgroups of one chain did not meet within the time limit");
+      throw DeviceError();
+    }
     return HH_OK;
   });
 }

@@ -110,6 +110,8 @@ int nblk_for(long long len) {
 Engine::Engine(hipStream_t st) : st_(st) {}
 Engine::~Engine() {
   if (task_dev_) dev_free(task_dev_);
+  if (sync_) dev_free(sync_);
+  if (xch_) dev_free(xch_);
 }
 
 template <class TT>
@@ -224,6 +226,7 @@ void Engine::begin(std::vector<Solve*>& solves) {
     live.push_back(s);
   }
   if (live.empty()) return;
+  if (sync_) HH_HIP(hipMemsetAsync(sync_, 0, sizeof(unsigned), st_));  // clear a past abort
   // beta^2 = b^H b into NR slot 0, then v1 = b / beta
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
   std::vector<GramTask> gt;
@@ -290,13 +293,14 @@ void Engine::step(std::vector<Solve*>& solves) {
   for (Solve* s : live) ensure_capacity(s);
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
 
-  // 1. sweeps: every preconditioner of every solve, one workgroup per chain.
-  // Launch kinds are keyed by (precision, blocked term count KP, segments P,
-  // presence of pivoted strips).
+  // 1. sweeps: every preconditioner of every solve, one chain each.  Launch
+  // kinds are keyed by (precision, blocked term count KP, segments P, presence
+  // of pivoted strips); each kind then takes its segment plan.
   struct Kind {
     std::vector<SweepTask> tasks;
     int prec, KP, P, kmax, nmax;
     bool piv;
+    int plan;
   };
   std::vector<Kind> kinds;
   for (Solve* s : live) {
@@ -308,7 +312,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       return k.prec == fs.precision && k.KP == KP && k.P == P && k.piv == fs.any_pivot;
     });
     if (it == kinds.end()) {
-      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot});
+      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0});
       it = kinds.end() - 1;
     }
     it->kmax = std::max(it->kmax, fs.max_kl);
@@ -327,6 +331,42 @@ void Engine::step(std::vector<Solve*>& solves) {
       tk.n = pb->n;
       tk.N = fs.N;
       it->tasks.push_back(tk);
+    }
+  }
+  {
+    size_t chains = 0, xbytes = 0;
+    for (Kind& k : kinds) {
+      k.plan = wide_ok_ ? sweep_plan_for((int)k.tasks.size(), k.prec, k.P, k.kmax, k.nmax, k.piv) : 0;
+      if (k.plan == 0) continue;
+      chains += k.tasks.size();
+      xbytes += k.tasks.size() * (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);
+    }
+    if (chains > 0) {
+      const size_t sbytes = (chains + 1) * 128;
+      if (sbytes > sync_cap_) {
+        HH_HIP(hipStreamSynchronize(st_));
+        if (sync_) dev_free(sync_);
+        sync_cap_ = sbytes * 2;
+        sync_ = (unsigned*)dev_alloc(sync_cap_);
+        HH_HIP(hipMemsetAsync(sync_, 0, sync_cap_, st_));
+      }
+      if (xbytes > xch_cap_) {
+        HH_HIP(hipStreamSynchronize(st_));
+        if (xch_) dev_free(xch_);
+        xch_cap_ = xbytes * 2;
+        xch_ = dev_alloc(xch_cap_);
+      }
+      // arrival counters start from zero in every launch
+      HH_HIP(hipMemsetAsync(sync_ + 32, 0, chains * 128, st_));
+      size_t ci = 0, xo = 0;
+      for (Kind& k : kinds) {
+        if (k.plan == 0) continue;
+        for (SweepTask& tk : k.tasks) {
+          tk.bar = sync_ + 32 * (1 + ci++);
+          tk.xch = (char*)xch_ + xo;
+          xo += (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);
+        }
+      }
     }
   }
   std::vector<SweepTask*> dsw(kinds.size());
@@ -485,7 +525,8 @@ void Engine::step(std::vector<Solve*>& solves) {
     TimedRegion tr(FAM_SWEEP, st_, bytes);
     for (size_t q = 0; q < kinds.size(); ++q)
       launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].KP,
-                   kinds[q].P, kinds[q].kmax, kinds[q].nmax, kinds[q].piv, st_);
+                   kinds[q].P, kinds[q].kmax, kinds[q].nmax, kinds[q].piv, kinds[q].plan, sync_,
+                   st_);
   }
   {
     double bytes = 0;
@@ -527,7 +568,13 @@ void Engine::step(std::vector<Solve*>& solves) {
     flags[q].resize(s->t);
     HH_HIP(hipMemcpyAsync(flags[q].data(), s->flags, s->t * sizeof(int), hipMemcpyDeviceToHost, st_));
   }
+  if (sync_)
+    HH_HIP(hipMemcpyAsync(&abort_host_, sync_, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
   HH_HIP(hipStreamSynchronize(st_));
+  if (sync_ && abort_host_) {
+    set_error("sweep workgroups of one chain did not meet within the time limit");
+    throw DeviceError();
+  }
   for (size_t q = 0; q < live.size(); ++q) {
     Solve* s = live[q];
     HdLayout L(s->hcap, s->t);

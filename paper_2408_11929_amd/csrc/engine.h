@@ -100,6 +100,9 @@ class Engine {
   void finish(std::vector<Solve*>& solves);
   static void release(Solve* s);
   static size_t footprint(const hh_problem* pb, int t, int prec, int maxit);
+  // Whether sweeps may run on several workgroups per chain (the wide segment
+  // plan); engines that share the device with other engines keep it off.
+  void set_wide(bool on) { wide_ok_ = on; }
 
  private:
   hipStream_t st_;
@@ -111,6 +114,14 @@ class Engine {
   void upload();
   void ensure_capacity(Solve* s);
   size_t staged_ = 0;
+  // wide plan: sync words (word 0: abort, sticky until begin(); then one
+  // 128-byte line per chain) and the chains' exchange areas
+  bool wide_ok_ = true;
+  unsigned* sync_ = nullptr;
+  size_t sync_cap_ = 0;
+  void* xch_ = nullptr;
+  size_t xch_cap_ = 0;
+  unsigned abort_host_ = 0;
 };
 
 }  // namespace hh

@@ -380,16 +380,18 @@ __global__ __launch_bounds__(64) void k_build_blocked(const StripDesc* __restric
 }
 
 // Segment transfer maps of an unpivoted strip.  The substitutions split a
-// strip's rows into segments of sd.seg rows that are solved in parallel from a
-// zero state; the true state of segment s+1 (the K outputs before it) is then
-// the zero-state tail of segment s plus T_s times the state of segment s,
-// where column c' of T_s is the tail of the recurrence over segment s started
-// from the unit state e_c' with zero inputs.  Stored for s = 1..nseg-2 as
-// T[((s-1) K + c') K + c] = tail row c, in the order in which the sweep
-// kernel stages them.  One wave per (segment, strip, triangle), lane c' runs
-// column c' in FP64 from the stored factors (same conventions as the blocked
-// maps) with its window of the last 64 outputs in LDS; the coefficients of
-// the next row are fetched while a row is computed.
+// strip's rows into segments (one cut per segment plan) that are solved in
+// parallel from a zero state; the true state of segment s+1 (the K outputs
+// before it) is then the zero-state tail of segment s plus T_s times the state
+// of segment s, where column c' of T_s is the tail of the recurrence over
+// segment s started from the unit state e_c' with zero inputs.  A triangle's
+// maps are numbered plan by plan (segments 1..nseg-2 of plan p from
+// sd.pmap[p] on) and stored column-major, map m at (m K + c') K + c = tail
+// row c, the U maps sd.tmaps maps after the L maps.  One wave per (map,
+// strip, triangle), lane c' runs column c' in FP64 from the stored factors
+// (same conventions as the blocked maps) with its window of the last 64
+// outputs in LDS; the coefficients of the next row are fetched while a row is
+// computed.
 template <class T>
 __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restrict__ strips,
                                                        const cx<T>* __restrict__ band,
@@ -400,14 +402,20 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
   __shared__ c128 win[64][64];
   if (pflag[blockIdx.y]) return;
   const StripDesc sd = strips[blockIdx.y];
-  const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab, seg = sd.seg;
-  const int nseg = (ns + seg - 1) / seg;
-  const int s = 1 + blockIdx.x;
-  if (s > nseg - 2) return;
+  const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab;
+  int m = blockIdx.x, plan = 0;
+  for (; plan < HH_NPLAN; ++plan) {
+    const int c = plan_seg_maps(ns, sd.pseg[plan]);
+    if (m < c) break;
+    m -= c;
+  }
+  if (plan == HH_NPLAN) return;
+  const int seg = sd.pseg[plan], s = 1 + m;
   const int lane = threadIdx.x;
   const bool upper = blockIdx.z == 1;
   const cx<T>* ab = band + sd.band_off;
-  cx<T>* Tm = img + sd.t_off + (upper ? (long long)(nseg - 2) * K * K : 0);
+  cx<T>* Tm = img + sd.t_off +
+              ((upper ? (long long)sd.tmaps : 0LL) + sd.pmap[plan] + m) * K * K;
   const int s0 = s * seg, s1 = s0 + seg;
   // lane c < K fetches T(i, c + 1), lane K the diagonal of row i (U only)
   auto coef = [&](int i) -> c128 {
@@ -437,8 +445,67 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     __syncthreads();
     if (lane < 63) win[i & 63][lane] = acc;
     if (lane < K && i >= s1 - K)
-      Tm[((long long)(s - 1) * K + lane) * K + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
+      Tm[(long long)lane * K + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
   }
+}
+
+// Workgroup transfer maps of the plans that spread a triangle over more than
+// two workgroups: the map over the P segments jP .. jP+P-1 of workgroup j is
+// the product T_{jP+P-1} ... T_{jP} of their segment maps (map j - 1 from
+// sd.pwmap[p] on, same storage as the segment maps).  One workgroup of 64
+// lanes per (map, strip, triangle); the running product lives in LDS in FP64
+// (two K x K buffers), lane r forms row r of the next product sixteen columns
+// at a time.
+template <class T>
+__global__ __launch_bounds__(64) void k_build_wg_maps(const StripDesc* __restrict__ strips,
+                                                      cx<T>* __restrict__ img,
+                                                      const int* __restrict__ pflag) {
+  extern __shared__ c128 prod[];  // 2 K^2: current product, next product
+  if (pflag[blockIdx.y]) return;
+  const StripDesc sd = strips[blockIdx.y];
+  const int ns = sd.ns, K = sd.kl, P = sd.segs, K2 = K * K;
+  int j = blockIdx.x, plan = 0;
+  for (; plan < HH_NPLAN; ++plan) {
+    const int c = plan_wg_maps(ns, sd.pseg[plan], P, plan_width(plan));
+    if (j < c) break;
+    j -= c;
+  }
+  if (plan == HH_NPLAN) return;
+  ++j;  // workgroup j = 1 .. gu-2
+  const int lane = threadIdx.x;
+  const long long tri = blockIdx.z == 1 ? (long long)sd.tmaps : 0LL;
+  const cx<T>* seg_maps = img + sd.t_off + (tri + sd.pmap[plan]) * K2;  // T_s at (s - 1) K^2
+  cx<T>* out = img + sd.t_off + (tri + sd.pwmap[plan] + j - 1) * K2;
+  c128* cur = prod;
+  c128* nxt = prod + K2;
+  const cx<T>* A = seg_maps + (long long)(j * P - 1) * K2;
+  for (int e = lane; e < K2; e += 64) cur[e] = mk((double)A[e].re, (double)A[e].im);
+  __syncthreads();
+  for (int q = 1; q < P; ++q) {
+    const cx<T>* B = seg_maps + (long long)(j * P + q - 1) * K2;  // element (r, c'') at c'' K + r
+    for (int c0 = 0; c0 < K; c0 += 16) {
+      c128 acc[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc[t] = mk(0.0, 0.0);
+      if (lane < K) {
+        for (int cc = 0; cc < K; ++cc) {
+          const cx<T> bv = B[(long long)cc * K + lane];
+          const c128 b = mk((double)bv.re, (double)bv.im);
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (c0 + t < K) acc[t] = acc[t] + b * cur[(c0 + t) * K + cc];
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (c0 + t < K) nxt[(c0 + t) * K + lane] = acc[t];
+      }
+    }
+    __syncthreads();
+    c128* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  for (int e = lane; e < K2; e += 64) out[e] = mk((T)cur[e].re, (T)cur[e].im);
 }
 
 }  // namespace
@@ -450,9 +517,35 @@ dim3 blocked_grid(const FactorSet& fs) {
 }
 
 static dim3 transfer_grid(const FactorSet& fs) {
-  int segs = 1;
-  for (auto& sd : fs.strips) segs = std::max(segs, (sd.ns + sd.seg - 1) / sd.seg - 2);
-  return dim3((unsigned)segs, (unsigned)fs.strips.size(), 2);
+  int maps = 1;
+  for (auto& sd : fs.strips) {
+    int m = 0;
+    for (int p = 0; p < HH_NPLAN; ++p) m += plan_seg_maps(sd.ns, sd.pseg[p]);
+    maps = std::max(maps, m);
+  }
+  return dim3((unsigned)maps, (unsigned)fs.strips.size(), 2);
+}
+
+static dim3 wg_map_grid(const FactorSet& fs) {
+  int maps = 0;
+  for (auto& sd : fs.strips) {
+    int m = 0;
+    for (int p = 0; p < HH_NPLAN; ++p) m += plan_wg_maps(sd.ns, sd.pseg[p], sd.segs, plan_width(p));
+    maps = std::max(maps, m);
+  }
+  return dim3((unsigned)maps, (unsigned)fs.strips.size(), 2);
+}
+
+template <class T>
+static void launch_wg_maps(const FactorSet& fs, hipStream_t st) {
+  const dim3 grid = wg_map_grid(fs);
+  if (grid.x == 0) return;
+  const size_t lds = 2 * (size_t)fs.max_kl * fs.max_kl * sizeof(c128);
+  const void* fn = (const void*)k_build_wg_maps<T>;
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_build_wg_maps<T>, grid, dim3(64), lds, st, fs.d_strips, (cx<T>*)fs.img,
+                     fs.d_pflag);
 }
 
 // One or two column slots per lane: 2 kl + 1 <= 64 needs one.
@@ -489,6 +582,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
     hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
+    launch_wg_maps<double>(fs, st);
   } else {
     launch_lu<float>(fs, lds, st);
     HH_HIP(hipGetLastError());
@@ -499,6 +593,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
     hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
+    launch_wg_maps<float>(fs, st);
   }
   HH_HIP(hipGetLastError());
 }

@@ -108,6 +108,9 @@ struct ArgError {};
 struct MemError {};
 
 // ---------------------------------------------------------------- geometry
+// Segment plans of the parallel substitution (see sweep.hip): plan p spreads
+// each triangular substitution of a strip over plan_width(p) workgroups.
+constexpr int HH_NPLAN = 2;
 // One strip of one sweep direction (0 = x / LRL, 1 = y / BTB).
 struct StripDesc {
   int dir;        // 0 x, 1 y
@@ -128,8 +131,12 @@ struct StripDesc {
   long long tr1_off;   // complex elements into the transmission buffer (n*7), or -1
   long long tr2_off;
   int segs;            // segments of the parallel substitution (waves of a sweep workgroup)
-  int seg;             // rows per segment (a multiple of 64); the last may be shorter
-  long long t_off;     // complex elements into the solve image: segment transfer maps
+  int seg;             // rows per segment of plan 0 (a multiple of 64); the last may be shorter
+  int tmaps;           // transfer maps per triangle, all plans together
+  int pseg[HH_NPLAN];  // rows per segment of each plan
+  int pmap[HH_NPLAN];  // index of the plan's first segment map among the triangle's maps
+  int pwmap[HH_NPLAN]; // index of the plan's first workgroup map
+  long long t_off;     // complex elements into the solve image: transfer maps (L, then U)
 };
 
 // Zero steps appended to every strip's solve image and pivot list, so that the
@@ -237,14 +244,25 @@ struct SweepTask {
   const void* tr;
   int n;
   int N;
+  void* xch;      // wide plan: G * 64 elements of sweep precision (workgroup tails)
+  unsigned* bar;  // wide plan: arrival counter of the chain's workgroups, zero at launch
 };
 // All tasks share the precision, the blocked-term count KP (which fixes the
 // slot count S of the pivoted path) and the segment count P (waves per
 // workgroup); kmax and nmax = largest band half-width and n among the tasks
 // (they size the LDS); pivots: some strip of some task pivoted (selects the
-// kernel that carries the pivoted path).
+// kernel that carries the pivoted path).  plan: segment plan (0: one
+// workgroup per chain; otherwise plan_width(plan) workgroups per chain, which
+// needs pivots == false, xch and bar in every task, and abort: a device word
+// that a workgroup raises when its partners fail to arrive in time).
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
-                  int nmax, bool pivots, hipStream_t st);
+                  int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st);
+// Whether the wide plan can run: no pivoted strip, and its workgroup fits the LDS.
+bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
+// Plan for a launch of ntasks chains: the HH_SWEEP_PLAN environment variable
+// (0 or 1) when set, else the wide plan while ntasks * its width fits a quarter
+// of the compute units.
+int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots);
 // Blocked substitution: block size and terms per lane for band half-width kl.
 // KP terms per lane cover the K + HH_BLK columns of a block map over the 64/HH_BLK
 // lanes of one output row; KP <= 12 exactly when 2 kl + 1 <= 64 (one lane-major
@@ -261,6 +279,52 @@ __host__ __device__ inline long long blocked_blocks(long long ns) { return 4 * (
 __host__ __device__ inline int segment_rows(int ns, int P) {
   const int per = (ns + P - 1) / P;
   return (per + 63) / 64 * 64;
+}
+// Plan p: a triangle of ns rows is cut into segments of plan_seg rows, P per
+// workgroup over plan_width(p) workgroups.  Plan 0 is the one-workgroup split
+// (segments a multiple of 64 rows); the wide plan cuts 16-row aligned
+// segments.
+__host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : 8; }
+__host__ __device__ inline int plan_seg(int ns, int P, int p) {
+  if (p == 0) return segment_rows(ns, P);
+  const int S = plan_width(p) * P, per = (ns + S - 1) / S;
+  return (per + 15) / 16 * 16;
+}
+__host__ __device__ inline int plan_nseg(int ns, int seg) { return (ns + seg - 1) / seg; }
+// Segment transfer maps: segments 1 .. nseg-2 (segment 0 starts from the
+// true zero state and the state after the last one is never needed).
+__host__ __device__ inline int plan_seg_maps(int ns, int seg) {
+  const int v = plan_nseg(ns, seg) - 2;
+  return v > 0 ? v : 0;
+}
+// Workgroup transfer maps (over the P segments of workgroup g, g = 1 .. gu-2
+// with gu the workgroups that hold segments); only plans of more than two
+// workgroups need them.
+__host__ __device__ inline int plan_wg_maps(int ns, int seg, int P, int G) {
+  if (G <= 2) return 0;
+  const int gu = (plan_nseg(ns, seg) + P - 1) / P, v = gu - 2;
+  return v > 0 ? v : 0;
+}
+// Fills the plan fields of sd (ns and segs set) and returns the maps per triangle.
+inline int plan_layout(StripDesc& sd) {
+  int m = 0;
+  for (int p = 0; p < HH_NPLAN; ++p) {
+    sd.pseg[p] = plan_seg(sd.ns, sd.segs, p);
+    sd.pmap[p] = m;
+    m += plan_seg_maps(sd.ns, sd.pseg[p]);
+    sd.pwmap[p] = m;
+    m += plan_wg_maps(sd.ns, sd.pseg[p], sd.segs, plan_width(p));
+  }
+  sd.seg = sd.pseg[0];
+  sd.tmaps = m;
+  return m;
+}
+// LDS of a wide-plan workgroup (complex elements): rings sharing space with the
+// staged maps (its P segment maps and up to G - 2 workgroup maps), segment
+// tails (64 P), states (64 (P + 1)) and two node lines of transmission data.
+inline long long sweep_lds_elems_wide(int P, int G, int K, int n) {
+  const long long work = std::max(640LL * P, (long long)(P + G - 2) * K * K);
+  return work + 64LL * P + 64LL * (P + 1) + 2LL * n;
 }
 // LDS of a sweep workgroup of P waves (complex elements): per-wave rings
 // (phase 1 and 3) sharing space with the staged transfer maps (phase 2), the
@@ -281,9 +345,10 @@ inline int sweep_segments(int K, int n, size_t esz) {
 // built is decided by the LU.
 inline long long strip_image_elems(long long ns, int S, int KP, int K, int P) {
   const long long lane_major = (ns + HH_PAD) * (64LL * (1 + S) + 1);
-  const int nseg = (int)((ns + segment_rows((int)ns, P) - 1) / segment_rows((int)ns, P));
-  const long long blocked =
-      2 * blocked_blocks(ns) * KP * 64 + 2LL * std::max(nseg - 2, 0) * K * K;
+  StripDesc sd{};
+  sd.ns = (int)ns;
+  sd.segs = P;
+  const long long blocked = 2 * blocked_blocks(ns) * KP * 64 + 2LL * plan_layout(sd) * K * K;
   return lane_major > blocked ? lane_major : blocked;
 }
 // Single strip solve (test hook): rhs/x in FP64, strip-local order.

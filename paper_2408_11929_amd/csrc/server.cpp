@@ -272,6 +272,7 @@ int hh_server_create(size_t hbm_budget, int max_active, hh_server** out) {
     HH_HIP(hipGetDevice(&s->device));
     HH_HIP(hipStreamCreate(&s->st));
     s->engine = std::make_unique<Engine>(s->st);
+    s->engine->set_wide(false);  // slots share the device: one workgroup per chain
     s->th = std::thread([s] {
       try {
         s->loop();

@@ -27,6 +27,8 @@
 // complex multiply-subtract per lane with that lane's coefficient, which the
 // solve image provides as one coalesced 64-lane row per step.  Coefficient
 // rows are prefetched D steps ahead, window elements one 64-block ahead.
+#include <cstdlib>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -623,6 +625,38 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
                             stt + 64 * wv, lane);
 }
 
+// Transmission data of strip s, node lines l = 0..n-1, into LDS (all
+// threads of the workgroup): gl1 = Gamma_{s,1} data where has1 (forward:
+// formed from the current z and, if keep, stored to g1 for the backward
+// pass; backward: the stored data), gl2 = Gamma_{s,2} data from the current z
+// where use2.
+template <class T>
+__device__ __forceinline__ void strip_data(cx<T>* gl1, cx<T>* gl2, gptr<cx<T>> z, gptr<cx<T>> g1,
+                                           const cx<T>* trb, int s, int n, int a, int w, int dir,
+                                           bool has1, bool use2, bool fwd, bool keep,
+                                           long long t1off, long long t2off) {
+  const cx<T> zero = mk((T)0, (T)0);
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    cx<T> e1 = zero, e2 = zero;
+    if (has1) {
+      if (fwd) {
+        const int i = dir == 0 ? a : l, j = dir == 0 ? l : a;
+        e1 = transmission<T>((gptr<const cx<T>>)(trb + t1off + 7LL * l), z, i, j, n);
+        if (keep) st<T>(g1, (long long)s * n + l, e1);
+      } else {
+        e1 = ld<T>(g1, (long long)s * n + l);
+      }
+    }
+    if (use2) {
+      const int at = a + w - 1;
+      const int i = dir == 0 ? at : l, j = dir == 0 ? l : at;
+      e2 = transmission<T>((gptr<const cx<T>>)(trb + t2off + 7LL * l), z, i, j, n);
+    }
+    gl1[l] = e1;
+    gl2[l] = e2;
+  }
+}
+
 // One workgroup of P waves runs one double sweep.  Per strip: the
 // transmission data of its interfaces go to LDS (forward: g_{s,1} from the
 // current z, also kept for the backward pass; backward: the kept g_{s,1} and
@@ -653,7 +687,6 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
   gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
   gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
   const StripDesc* strips = uniptr(tk.ch.strips);
-  const cx<T> zero = mk((T)0, (T)0);
   for (int step = 0; step < 2 * N - 1; ++step) {
     const bool fwd = step < N;
     const int s = fwd ? step : 2 * N - 2 - step;
@@ -664,34 +697,16 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const int pivoted = PIV ? uni(pflag[uni(sp->gid)]) : 0;
     const bool use2 = has2 && !fwd;
-    for (int l = tid; l < n; l += nthr) {
-      cx<T> e1 = zero, e2 = zero;
-      if (has1) {
-        if (fwd) {
-          const int i = dir == 0 ? a : l, j = dir == 0 ? l : a;
-          e1 = transmission<T>((gptr<const cx<T>>)(trb + t1off + 7LL * l), z, i, j, n);
-          st<T>(g1, (long long)s * n + l, e1);
-        } else {
-          e1 = ld<T>(g1, (long long)s * n + l);
-        }
-      }
-      if (use2) {
-        const int at = a + w - 1;
-        const int i = dir == 0 ? at : l, j = dir == 0 ? l : at;
-        e2 = transmission<T>((gptr<const cx<T>>)(trb + t2off + 7LL * l), z, i, j, n);
-      }
-      gl1[l] = e1;
-      gl2[l] = e2;
-    }
+    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, has1 != 0, use2, fwd, fwd, t1off, t2off);
     __syncthreads();
     const float winv = 1.0f / (float)w;
     const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2, winv};
     if (!pivoted) {
-      const int seg = uni(sp->seg), nseg = (ns + seg - 1) / seg;
+      const int seg = uni(sp->seg);
       const cx<T>* GL = img + img_off;
       const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-      const cx<T>* TL = img + uni(sp->t_off);
-      const cx<T>* TU = TL + (long long)(nseg > 2 ? nseg - 2 : 0) * kl * kl;
+      const cx<T>* TL = img + uni(sp->t_off) + (long long)uni(sp->pmap[0]) * kl * kl;
+      const cx<T>* TU = TL + (long long)uni(sp->tmaps) * kl * kl;
       solve_triangle<T, KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, TL, ns, kl, seg, work, yt,
                                stt);
       __syncthreads();
@@ -720,6 +735,247 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
   }
 }
 
+// ---------------------------------------------------------------- wide plan
+// A chain on G workgroups.  The segment split of solve_triangle carries over
+// to G P segments (wave w of workgroup g solves segment c = g P + w), with
+// the state propagation in two levels:
+//  1. every segment but the last runs from a zero state and keeps its tail
+//     (segment 0 is final and written out);
+//  2. in every workgroup, wave 0 propagates zero-start states over its P
+//     segments with the segment maps; the state reached at the workgroup's
+//     end (its tail) goes to the chain's exchange area;
+//  3. all G workgroups meet (chain_wait); workgroup g forms its true start
+//     state S_g from the tails of workgroups 0..g-1 and the workgroup maps
+//     (S_1 = tail_0, S_{j+1} = tail_j + W_j S_j), then the true states of its
+//     segments with the segment maps;
+//  4. every segment but segment 0 runs again from its true state.
+// The workgroups meet again when a triangle's output is complete (the back
+// substitution reads rows that other workgroups wrote, the next strip's
+// transmission data read the solution), so a strip solve is four meetings.
+
+// Meeting of the G workgroups of one chain.  Every wave makes its global
+// writes visible at agent scope before the workgroup barrier; thread 0 then
+// counts the workgroup in and waits until all G have arrived.  The wait is
+// bounded: after `limit` ticks of the constant-rate clock, or as soon as
+// another workgroup has given up, thread 0 raises *abort and gives up.  After
+// the workgroup barrier every wave acquires at agent scope.  Returns false
+// once the chain is aborted, the same answer in every thread.
+struct ChainBar {
+  unsigned* cnt;    // arrivals so far (zero at launch)
+  unsigned* abort;  // raised by a workgroup that gave up
+  unsigned need;    // arrivals that complete the current meeting
+  unsigned G;
+  long long limit;
+  int* ok;  // LDS word
+};
+
+__device__ __forceinline__ bool chain_wait(ChainBar& b) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  b.need += b.G;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(b.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(b.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b.need) {
+      if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 > b.limit) {
+        __hip_atomic_store(b.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *b.ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *b.ok != 0;
+}
+
+// v = y + M x for lanes < K (zero above): M a K x K map stored column-major
+// (element (c, c') at c' K + c) in LDS, x and y in LDS.
+template <class T>
+__device__ __forceinline__ cx<T> map_apply(const cx<T>* M, const cx<T>* x, const cx<T>* y, int K,
+                                           int lane) {
+  cx<T> v = mk((T)0, (T)0);
+  if (lane < K) {
+    v = y[lane];
+    const cx<T>* Mb = M + lane;
+    cx<T> a1 = mk((T)0, (T)0);
+    int cp = 0;
+    for (; cp + 1 < K; cp += 2) {
+      v = cfma(v, Mb[cp * K], x[cp]);
+      a1 = cfma(a1, Mb[(cp + 1) * K], x[cp + 1]);
+    }
+    if (cp < K) v = cfma(v, Mb[cp * K], x[cp]);
+    v = v + a1;
+  }
+  return v;
+}
+
+// One triangular substitution of a strip by workgroup g of the chain's G
+// (steps 1-4 above).  Tm: the plan's segment maps (T_c at (c - 1) K^2), Wm:
+// its workgroup maps (W_j at (j - 1) K^2), xch: exchange area (64 entries per
+// workgroup).  LDS: work (rings, then the staged maps: segment maps of the
+// workgroup at (c - g P) K^2, workgroup maps 1..g-1 after P K^2), yt (64 P),
+// stt (64 (P + 1)).  Returns false when the chain was aborted.
+template <class T, int KP, int U, int NB, class Src, class Dst>
+__device__ __forceinline__ bool solve_triangle_wide(const Src& src, const Dst& dst,
+                                                    const cx<T>* G, const cx<T>* Tm,
+                                                    const cx<T>* Wm, int ns, int K, int seg,
+                                                    int g, cx<T>* work, cx<T>* yt, cx<T>* stt,
+                                                    gptr<cx<T>> xch, ChainBar& bar) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
+  const int P = nthr >> 6;
+  const int nseg = (ns + seg - 1) / seg, gu = (nseg + P - 1) / P;
+  const int c = g * P + wv;
+  cx<T>* ring = work + 640 * wv;
+  const int off = c * seg, len = c < nseg ? (ns - off < seg ? ns - off : seg) : 0;
+  gptr<const cx<T>> Gw = (gptr<const cx<T>>)(G + (long long)(off / 16) * KP * 64);
+  if (c == 0) {
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, 0, len}, SegDst<T, Dst>{dst, 0}, Gw, len, K, ring,
+                                (const cx<T>*)nullptr, lane);
+    if (nseg > 1 && lane < K) yt[lane] = ring[(len - K + lane) & 255];
+  } else if (c < nseg - 1) {
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, DstTail<T>{yt + 64 * wv, len, K}, Gw,
+                                len, K, ring, (const cx<T>*)nullptr, lane);
+  }
+  if (nseg == 1) return true;
+  __syncthreads();
+  const int K2 = K * K;
+  if (g < gu) {  // stage this workgroup's maps
+    const int c0 = g * P > 1 ? g * P : 1, c1 = g * P + P < nseg - 1 ? g * P + P : nseg - 1;
+    const int nA = c1 > c0 ? (c1 - c0) * K2 : 0, nB = g >= 2 ? (g - 1) * K2 : 0;
+    gptr<const cx<T>> A = (gptr<const cx<T>>)(Tm + (long long)(c0 - 1) * K2);
+    gptr<const cx<T>> B = (gptr<const cx<T>>)Wm;
+    cx<T>* dA = work + (c0 - g * P) * K2;
+    cx<T>* dB = work + P * K2;
+    for (int e0 = 0; e0 < nA + nB; e0 += 8 * nthr) {
+      cx<T> v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q * nthr + tid;
+        if (e < nA)
+          v[q] = ld<T>(A, e);
+        else if (e < nA + nB)
+          v[q] = ld<T>(B, e - nA);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q * nthr + tid;
+        if (e < nA)
+          dA[e] = v[q];
+        else if (e < nA + nB)
+          dB[e - nA] = v[q];
+      }
+    }
+  }
+  __syncthreads();
+  // zero-start states: stt[64 (w + 1)] = state after segment g P + w
+  if (wv == 0 && g < gu) {
+    for (int w = 0; w < P; ++w) {
+      const int cw = g * P + w;
+      if (cw > nseg - 2) break;
+      const cx<T> v = w == 0 ? (lane < K ? yt[lane] : mk((T)0, (T)0))
+                             : map_apply<T>(work + w * K2, stt + 64 * w, yt + 64 * w, K, lane);
+      stt[64 * (w + 1) + lane] = v;
+    }
+    if (g < gu - 1 && lane < K) st<T>(xch, (long long)g * 64 + lane, stt[64 * P + lane]);
+  }
+  if (!chain_wait(bar)) return false;
+  if (wv == 0 && g >= 1 && g < gu) {
+    // S_g in stt[0]: S_1 = tail_0, S_{j+1} = tail_j + W_j S_j (ping-pong with stt[64 P])
+    cx<T>* sa = stt;
+    cx<T>* sb = stt + 64 * P;
+    sa[lane] = lane < K ? ld<T>(xch, lane) : mk((T)0, (T)0);
+    for (int j = 1; j < g; ++j) {
+      const cx<T> t = lane < K ? ld<T>(xch, (long long)j * 64 + lane) : mk((T)0, (T)0);
+      sb[lane] = t;
+      const cx<T> v = map_apply<T>(work + (P + j - 1) * K2, sa, sb, K, lane);
+      sb[lane] = v;
+      cx<T>* tmp = sa;
+      sa = sb;
+      sb = tmp;
+    }
+    if (sa != stt) stt[lane] = sa[lane];
+    // true states of the workgroup's segments
+    for (int w = 0; w + 1 < P; ++w) {
+      const int cw = g * P + w;
+      if (cw + 1 > nseg - 1) break;
+      stt[64 * (w + 1) + lane] = map_apply<T>(work + w * K2, stt + 64 * w, yt + 64 * w, K, lane);
+    }
+  }
+  __syncthreads();
+  if (c >= 1 && c < nseg)
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, SegDst<T, Dst>{dst, off}, Gw, len, K,
+                                ring, stt + 64 * wv, lane);
+  return true;
+}
+
+// The double sweep of k_sweep on G workgroups per chain (unpivoted strips
+// only): workgroup g = blockIdx.x % G of chain blockIdx.x / G.  Every
+// workgroup forms the transmission data of all node lines itself (workgroup
+// 0 keeps the forward ones for the backward pass).  Dynamic LDS (complex
+// elements): two node lines, yt (64 P), stt (64 (P + 1)), work.
+template <class T, int KP, int U, int NB>
+__global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict__ tasks, int plan,
+                                                    unsigned* abort, long long limit) {
+  extern __shared__ char smem_raw[];
+  __shared__ int ok;
+  const int G = plan_width(plan);
+  const SweepTask& tk = tasks[blockIdx.x / G];
+  const int g = uni((int)(blockIdx.x % G));
+  const int P = blockDim.x >> 6;
+  const int n = uni(tk.n), N = uni(tk.N);
+  cx<T>* gl1 = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* gl2 = gl1 + n;
+  cx<T>* yt = gl2 + n;
+  cx<T>* stt = yt + 64 * P;
+  cx<T>* work = stt + 64 * (P + 1);
+  const cx<T>* img = uniptr((const cx<T>*)tk.img);
+  const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
+  gptr<cx<T>> z = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.z);
+  gptr<cx<T>> rho = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.rho);
+  gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
+  gptr<cx<T>> xch = (gptr<cx<T>>)uniptr((cx<T>*)tk.xch);
+  gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
+  const StripDesc* strips = uniptr(tk.ch.strips);
+  ChainBar bar{uniptr(tk.bar), abort, 0u, (unsigned)G, limit, &ok};
+  for (int step = 0; step < 2 * N - 1; ++step) {
+    const bool fwd = step < N;
+    const int s = fwd ? step : 2 * N - 2 - step;
+    const StripDesc* sp = strips + s;
+    const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
+    const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
+    const long long img_off = uni(sp->img_off);
+    const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
+    const bool use2 = has2 && !fwd;
+    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, has1 != 0, use2, fwd, fwd && g == 0,
+                  t1off, t2off);
+    __syncthreads();
+    const float winv = 1.0f / (float)w;
+    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2, winv};
+    const int seg = uni(sp->pseg[plan]);
+    const long long K2 = (long long)kl * kl, tm = uni(sp->tmaps);
+    const cx<T>* GL = img + img_off;
+    const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
+    const cx<T>* T0 = img + uni(sp->t_off);
+    const cx<T>* TL = T0 + uni(sp->pmap[plan]) * K2;
+    const cx<T>* WL = T0 + uni(sp->pwmap[plan]) * K2;
+    if (!solve_triangle_wide<T, KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, TL, WL, ns, kl,
+                                           seg, g, work, yt, stt, xch, bar))
+      return;
+    if (!chain_wait(bar)) return;
+    if (!solve_triangle_wide<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
+                                           DstScatter<T>{z, ns, w, n, a, dir, winv}, GU,
+                                           TL + tm * K2, WL + tm * K2, ns, kl, seg, g, work, yt,
+                                           stt, xch, bar))
+      return;
+    if (!chain_wait(bar)) return;
+  }
+}
+
 // One strip solve in FP64 in/out (test hook) by a workgroup of P waves, the
 // same substitutions as the sweep; work: ns elements of scratch.  Dynamic
 // LDS: tails, states and work area as in k_sweep.
@@ -744,11 +1000,11 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
   gptr<cx<T>> wk = (gptr<cx<T>>)work;
   const SrcC128<T> in{(gptr<const c128>)rhs, ns};
   if (!pivoted) {
-    const int seg = uni(sp->seg), nseg = (ns + seg - 1) / seg;
+    const int seg = uni(sp->seg);
     const cx<T>* GL = im + ioff;
     const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-    const cx<T>* TL = im + uni(sp->t_off);
-    const cx<T>* TU = TL + (long long)(nseg > 2 ? nseg - 2 : 0) * kl * kl;
+    const cx<T>* TL = im + uni(sp->t_off) + (long long)uni(sp->pmap[0]) * kl * kl;
+    const cx<T>* TU = TL + (long long)uni(sp->tmaps) * kl * kl;
     solve_triangle<T, KP, U, NB>(in, DstVec<T>{wk, ns, false}, GL, TL, ns, kl, seg, lds, yt, stt);
     __syncthreads();
     solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true},
@@ -823,17 +1079,96 @@ static void launch_sweep_t(const SweepTask* d, int ntasks, int KP, int P, int km
   }
 }
 
+// Device properties the wide plan needs: compute units and the rate of the
+// constant clock that bounds the waits of chain_wait (kHz).
+struct WideDev {
+  int cus = 0, khz = 0;
+};
+static WideDev wide_dev() {
+  int dev = 0;
+  HH_HIP(hipGetDevice(&dev));
+  static WideDev cache[64];
+  WideDev& d = cache[dev & 63];
+  if (d.cus == 0) {
+    HH_HIP(hipDeviceGetAttribute(&d.khz, hipDeviceAttributeWallClockRate, dev));
+    HH_HIP(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  return d;
+}
+
+static size_t wide_lds_bytes(int precision, int P, int kmax, int nmax) {
+  const size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
+  return (size_t)sweep_lds_elems_wide(P, plan_width(HH_NPLAN - 1), kmax, nmax) * es;
+}
+
+bool sweep_wide_fits(int precision, int P, int kmax, int nmax) {
+  return wide_lds_bytes(precision, P, kmax, nmax) <= 150 * 1024;
+}
+
+int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots) {
+  if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
+  const char* env = std::getenv("HH_SWEEP_PLAN");
+  if (env && *env) return std::atoi(env) > 0 ? HH_NPLAN - 1 : 0;
+  const int G = plan_width(HH_NPLAN - 1);
+  return (long long)ntasks * G <= wide_dev().cus / 2 ? HH_NPLAN - 1 : 0;
+}
+
+template <class T, int KP>
+static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int kmax, int nmax, int plan,
+                           unsigned* abort, hipStream_t st) {
+  using Sh = SweepShape<T, KP>;
+  const int G = plan_width(plan);
+  const void* fn = (const void*)k_sweep_wide<T, KP, Sh::U, Sh::NB>;
+  const size_t lds = (size_t)sweep_lds_elems_wide(P, G, kmax, nmax) * sizeof(cx<T>);
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  // bound of each wait: HH_SWEEP_WAIT_US microseconds when set, else 250 ms
+  const char* env = std::getenv("HH_SWEEP_WAIT_US");
+  const long long us = env && *env ? std::atoll(env) : 250000LL;
+  long long limit = (long long)wide_dev().khz * us / 1000;
+  void* args[] = {(void*)&d, (void*)&plan, (void*)&abort, (void*)&limit};
+  HH_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)(ntasks * G)), dim3(64 * P), args,
+                                    (unsigned)lds, st));
+}
+
+template <class T>
+static void launch_wide_t(const SweepTask* d, int ntasks, int KP, int P, int kmax, int nmax,
+                          int plan, unsigned* abort, hipStream_t st) {
+  switch (KP) {
+    case 8: launch_wide_kp<T, 8>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
+    case 10: launch_wide_kp<T, 10>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
+    case 12: launch_wide_kp<T, 12>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
+    case 16: launch_wide_kp<T, 16>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
+    case 20: launch_wide_kp<T, 20>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
+    default: set_error("unsupported blocked term count %d", KP); throw ArgError();
+  }
+}
+
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
-                  int nmax, bool pivots, hipStream_t st) {
+                  int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st) {
   if (ntasks <= 0) return;
   if (P < 1 || P > 8) {
     set_error("unsupported segment count %d", P);
     throw ArgError();
   }
-  if (precision == HH_FP64)
+  if (plan < 0 || plan >= HH_NPLAN || (plan > 0 && (pivots || !abort))) {
+    set_error("segment plan %d cannot run here", plan);
+    throw ArgError();
+  }
+  if (plan > 0) {
+    if (!sweep_wide_fits(precision, P, kmax, nmax)) {
+      set_error("the wide segment plan does not fit the LDS");
+      throw ArgError();
+    }
+    if (precision == HH_FP64)
+      launch_wide_t<double>(d_tasks, ntasks, KP, P, kmax, nmax, plan, abort, st);
+    else
+      launch_wide_t<float>(d_tasks, ntasks, KP, P, kmax, nmax, plan, abort, st);
+  } else if (precision == HH_FP64) {
     launch_sweep_t<double>(d_tasks, ntasks, KP, P, kmax, nmax, pivots, st);
-  else
+  } else {
     launch_sweep_t<float>(d_tasks, ntasks, KP, P, kmax, nmax, pivots, st);
+  }
   HH_HIP(hipGetLastError());
 }
 

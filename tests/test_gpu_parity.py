@@ -127,9 +127,13 @@ def test_strip_solves_match_lapack(n, N, omega, c, prec):
     pb.free()
 
 
+@pytest.mark.parametrize("plan", ["0", "1"])
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
 @pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + PIVOTING)
-def test_sweeps_match_oracle(n, N, omega, c, prec):
+def test_sweeps_match_oracle(n, N, omega, c, prec, plan, monkeypatch):
+    # plan 0: one workgroup per chain; plan 1: eight (where the strips did not
+    # pivot and the workgroup fits the LDS, else plan 0 again)
+    monkeypatch.setenv("HH_SWEEP_PLAN", plan)
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
     A = oasm.assemble(omega, c, n)
@@ -143,6 +147,27 @@ def test_sweeps_match_oracle(n, N, omega, c, prec):
             zr = S.apply(r[v])
             bar = tol if S32 is None else max(tol, 3 * rel(S32.apply(r[v]), zr))
             assert rel(z[v], zr) < bar
+    pb.free()
+
+
+def test_wide_sweep_gives_up_when_partners_are_late(monkeypatch):
+    # a zero wait bound makes the first workgroup to arrive at a meeting give
+    # up: the call reports the error instead of waiting, and the next call
+    # with the normal bound is correct again
+    n, N, omega, c = 64, 9, 30.0, [2.2, 1.1, 1.7, 2.9, 1.3]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP32)
+    r = rand((1, n * n), 6)
+    monkeypatch.setenv("HH_SWEEP_PLAN", "1")
+    monkeypatch.setenv("HH_SWEEP_WAIT_US", "0")
+    with pytest.raises(hh.HHError, match="did not meet"):
+        pb.sweep_apply(hh.HH_DIR_X, dev(r))
+    monkeypatch.delenv("HH_SWEEP_WAIT_US")
+    z = host(pb.sweep_apply(hh.HH_DIR_X, dev(r)))[0]
+    A = oasm.assemble(omega, c, n)
+    zr = osw.DoubleSweep(omega, c, n, N, ost.X, A=A).apply(r[0])
+    z32 = osw.DoubleSweep(omega, c, n, N, ost.X, A=A, precision="fp32").apply(r[0])
+    assert rel(z, zr) < max(1e-5, 3 * rel(z32, zr))
     pb.free()
 
 
