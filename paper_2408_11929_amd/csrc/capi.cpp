@@ -91,7 +91,10 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
   }
   REQUIRE(kl_max <= 63, "strip band half-width %d exceeds 63 (strips too wide)", kl_max);
   const int S = 2 * kl_max + 1 <= 64 ? 1 : 2;
-  const int P = sweep_segments(kl_max, n, precision == HH_FP64 ? sizeof(c128) : sizeof(c64));
+  const int P = sweep_segments(map_dim(blocked_kp(kl_max)), n,
+                               precision == HH_FP64 ? sizeof(c128) : sizeof(c64));
+  // the wide segment plan's maps are built only where that plan can run
+  const bool wide = sweep_wide_fits(precision, P, kl_max, n);
   for (int i = 0; i < fs.nd; ++i) {
     for (int s = 0; s < N; ++s) {
       StripDesc sd{};
@@ -112,10 +115,15 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       sd.band_off = band;
       band += (long long)sd.ns * sd.ldab;
       sd.segs = P;
+      sd.wide = wide;
       plan_layout(sd);
+      for (int p = 0; p < HH_NPLAN; ++p)
+        REQUIRE(sd.pseg[p] >= sd.kl, "segment of %d rows is shorter than the band half-width %d",
+                sd.pseg[p], sd.kl);
       sd.img_off = img;
       sd.t_off = img + 2 * blocked_blocks(sd.ns) * sd.KP * 64;
-      img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P);
+      sd.phi_off = sd.t_off + 2LL * sd.tmaps * map_dim(sd.KP) * map_dim(sd.KP);
+      img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P, wide);
       sd.piv_off = piv;
       piv += NP;
       sd.tr1_off = sd.has1 ? tr : -1;
@@ -293,7 +301,7 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
     // one chain per right-hand side, one or plan_width(plan) workgroups per chain
     const int ntask = nvec;
     const int plan = sweep_plan_for(ntask, fs.precision, fs.strips[0].segs, fs.max_kl, pb->n,
-                                    fs.any_pivot);
+                                    fs.any_pivot, fs.strips[0].wide != 0);
     const int G = plan_width(plan);
     hipStream_t st = pb->st[0];
     // sync words: [0] abort, then one 128-byte line per chain

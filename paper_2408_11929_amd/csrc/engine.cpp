@@ -301,6 +301,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     int prec, KP, P, kmax, nmax;
     bool piv;
     int plan;
+    bool wide;  // the wide plan's maps were built
   };
   std::vector<Kind> kinds;
   for (Solve* s : live) {
@@ -308,11 +309,13 @@ void Engine::step(std::vector<Solve*>& solves) {
     const FactorSet& fs = pb->fs;
     const size_t es = esz_of(fs.precision);
     const int KP = fs.strips[0].KP, P = fs.strips[0].segs;
+    const bool wide = fs.strips[0].wide != 0;
     auto it = std::find_if(kinds.begin(), kinds.end(), [&](const Kind& k) {
-      return k.prec == fs.precision && k.KP == KP && k.P == P && k.piv == fs.any_pivot;
+      return k.prec == fs.precision && k.KP == KP && k.P == P && k.piv == fs.any_pivot &&
+             k.wide == wide;
     });
     if (it == kinds.end()) {
-      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0});
+      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0, wide});
       it = kinds.end() - 1;
     }
     it->kmax = std::max(it->kmax, fs.max_kl);
@@ -336,7 +339,9 @@ void Engine::step(std::vector<Solve*>& solves) {
   {
     size_t chains = 0, xbytes = 0;
     for (Kind& k : kinds) {
-      k.plan = wide_ok_ ? sweep_plan_for((int)k.tasks.size(), k.prec, k.P, k.kmax, k.nmax, k.piv) : 0;
+      k.plan = wide_ok_ ? sweep_plan_for((int)k.tasks.size(), k.prec, k.P, k.kmax, k.nmax, k.piv,
+                                         k.wide)
+                        : 0;
       if (k.plan == 0) continue;
       chains += k.tasks.size();
       xbytes += k.tasks.size() * (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);

@@ -379,6 +379,14 @@ __global__ __launch_bounds__(64) void k_build_blocked(const StripDesc* __restric
   }
 }
 
+// Segments that k_build_transfer runs for plan p: those with a tail map
+// (1..nseg-2), and for the wide plan also the last one (its response only).
+__host__ __device__ inline int transfer_jobs(const StripDesc& sd, int p) {
+  const int nseg = plan_nseg(sd.ns, sd.pseg[p]);
+  if (p == HH_NPLAN - 1) return sd.wide && nseg > 1 ? nseg - 1 : 0;
+  return plan_seg_maps(sd.ns, sd.pseg[p]);
+}
+
 // Segment transfer maps of an unpivoted strip.  The substitutions split a
 // strip's rows into segments (one cut per segment plan) that are solved in
 // parallel from a zero state; the true state of segment s+1 (the K outputs
@@ -386,9 +394,12 @@ __global__ __launch_bounds__(64) void k_build_blocked(const StripDesc* __restric
 // of segment s, where column c' of T_s is the tail of the recurrence over
 // segment s started from the unit state e_c' with zero inputs.  A triangle's
 // maps are numbered plan by plan (segments 1..nseg-2 of plan p from
-// sd.pmap[p] on) and stored column-major, map m at (m K + c') K + c = tail
-// row c, the U maps sd.tmaps maps after the L maps.  One wave per (map,
-// strip, triangle), lane c' runs column c' in FP64 from the stored factors
+// sd.pmap[p] on) and stored column-major zero-padded to KM = map_dim(KP)
+// (map m at (m KM + c') KM + c = tail row c), the U maps sd.tmaps maps after
+// the L maps.  One wave per (map,
+// strip, triangle; the map is the slowest grid dimension, so that the long
+// segments of plan 0 are dispatched first), lane c' runs column c' in FP64
+// from the stored factors
 // (same conventions as the blocked maps) with its window of the last 64
 // outputs in LDS; the coefficients of the next row are fetched while a row is
 // computed.
@@ -396,27 +407,38 @@ template <class T>
 __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restrict__ strips,
                                                        const cx<T>* __restrict__ band,
                                                        cx<T>* __restrict__ img,
-                                                       const int* __restrict__ pflag) {
-  // win[i & 63][c'] = out_i of column c' < 63; column 63 holds the
-  // coefficients of the current row (entry K: the scale d)
-  __shared__ c128 win[64][64];
-  if (pflag[blockIdx.y]) return;
-  const StripDesc sd = strips[blockIdx.y];
+                                                       const int* __restrict__ pflag,
+                                                       int wstride) {
+  // win[(i & 63) W + c'] = out_i of column c' < K, W = max_kl + 1 (dynamic
+  // LDS, 64 W entries); column W - 1 holds the coefficients of the current
+  // row (entry K: the scale d)
+  extern __shared__ c128 win[];
+  const int W = wstride;
+  if (pflag[blockIdx.x]) return;
+  const StripDesc sd = strips[blockIdx.x];
   const int ns = sd.ns, K = sd.kl, kv = 2 * sd.kl, ldab = sd.ldab;
-  int m = blockIdx.x, plan = 0;
+  int m = blockIdx.z, plan = 0;
   for (; plan < HH_NPLAN; ++plan) {
-    const int c = plan_seg_maps(ns, sd.pseg[plan]);
+    const int c = transfer_jobs(sd, plan);
     if (m < c) break;
     m -= c;
   }
   if (plan == HH_NPLAN) return;
-  const int seg = sd.pseg[plan], s = 1 + m;
+  const int seg = sd.pseg[plan], s = 1 + m, nseg = plan_nseg(ns, seg);
   const int lane = threadIdx.x;
-  const bool upper = blockIdx.z == 1;
+  const bool upper = blockIdx.y == 1;
   const cx<T>* ab = band + sd.band_off;
+  // the tail map T_s exists for s <= nseg-2; the wide plan also keeps every
+  // row of the segment (its response Phi_s), the last segment included
+  const bool tmap = s <= nseg - 2;
+  const int KM = map_dim(sd.KP);
   cx<T>* Tm = img + sd.t_off +
-              ((upper ? (long long)sd.tmaps : 0LL) + sd.pmap[plan] + m) * K * K;
-  const int s0 = s * seg, s1 = s0 + seg;
+              ((upper ? (long long)sd.tmaps : 0LL) + sd.pmap[plan] + m) * KM * KM;
+  cx<T>* Ph = plan == HH_NPLAN - 1
+                  ? img + sd.phi_off + (upper ? plan_phi_elems(ns, sd.segs, K, KM) : 0LL) +
+                        (long long)(s - 1) * seg * KM
+                  : nullptr;
+  const int s0 = s * seg, s1 = s0 + seg < ns ? s0 + seg : ns;
   // lane c < K fetches T(i, c + 1), lane K the diagonal of row i (U only)
   auto coef = [&](int i) -> c128 {
     const int j = ns - 1 - i, c = lane + 1;
@@ -431,81 +453,158 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     }
     return mk(lane == K ? 1.0 : 0.0, 0.0);
   };
-  for (int q = 0; q < 64; ++q) win[q][lane] = mk(0.0, 0.0);
-  if (lane < K) win[(s0 - K + lane) & 63][lane] = mk(1.0, 0.0);
+  for (int q = 0; q < 64; ++q)
+    if (lane < W) win[q * W + lane] = mk(0.0, 0.0);
+  if (lane < K) win[((s0 - K + lane) & 63) * W + lane] = mk(1.0, 0.0);
   c128 nxt = coef(s0);
+  const int cw = W - 1;  // coefficient column
   for (int i = s0; i < s1; ++i) {
     __syncthreads();
-    win[lane][63] = (lane == K && upper) ? cinv(nxt) : nxt;
+    if (lane <= K) win[lane * W + cw] = (lane == K && upper) ? cinv(nxt) : nxt;
     if (i + 1 < s1) nxt = coef(i + 1);
     __syncthreads();
-    c128 acc = mk(0.0, 0.0);
-    for (int c = 1; c <= K; ++c) acc = cfms(acc, win[c - 1][63], win[(i - c) & 63][lane]);
-    acc = acc * win[K][63];
+    c128 acc = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
+    const int lc = lane < K ? lane : 0;
+    int c = 1;
+    for (; c + 1 <= K; c += 2) {
+      acc = cfms(acc, win[(c - 1) * W + cw], win[((i - c) & 63) * W + lc]);
+      acc1 = cfms(acc1, win[c * W + cw], win[((i - c - 1) & 63) * W + lc]);
+    }
+    if (c <= K) acc = cfms(acc, win[(c - 1) * W + cw], win[((i - c) & 63) * W + lc]);
+    acc = (acc + acc1) * win[K * W + cw];
     __syncthreads();
-    if (lane < 63) win[i & 63][lane] = acc;
-    if (lane < K && i >= s1 - K)
-      Tm[(long long)lane * K + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
+    if (lane < K) win[(i & 63) * W + lane] = acc;
+    if (tmap && lane < K && i >= s1 - K)
+      Tm[(long long)lane * KM + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
+    if (Ph && lane < K) Ph[(long long)lane * seg + (i - s0)] = mk((T)acc.re, (T)acc.im);
   }
 }
 
-// Workgroup transfer maps of the plans that spread a triangle over more than
-// two workgroups: the map over the P segments jP .. jP+P-1 of workgroup j is
-// the product T_{jP+P-1} ... T_{jP} of their segment maps (map j - 1 from
-// sd.pwmap[p] on, same storage as the segment maps).  One workgroup of 64
-// lanes per (map, strip, triangle); the running product lives in LDS in FP64
-// (two K x K buffers), lane r forms row r of the next product sixteen columns
-// at a time.
+// Products of segment maps for the wide plan (slots in plan_layout), formed
+// in FP64 from the stored maps.  Stage 0, for workgroup g (segments c = g P
+// + w): the running product T_{gP+q-1} ... T_{gP}, stored as Pi_{gP+q} for
+// q < P and as W_g for q = P (job 0 of the workgroup), and A1_c = T_c T_{c-1}
+// (job w + 1, w >= 2).  Stage 1: A2_c = A1_c A1_{c-2} (w >= 4) and, for
+// workgroup g, the running product W_{g-1} ... W_{j+1} = Psi_{j,g} for j =
+// g-2 down to 0.  One workgroup of 64 lanes per (job, strip, triangle); the
+// maps involved are copied into LDS (three KM x KM buffers in FP64,
+// column-major like the stored maps) and lane r forms row r of a product,
+// sixteen columns at a time.
 template <class T>
-__global__ __launch_bounds__(64) void k_build_wg_maps(const StripDesc* __restrict__ strips,
-                                                      cx<T>* __restrict__ img,
-                                                      const int* __restrict__ pflag) {
-  extern __shared__ c128 prod[];  // 2 K^2: current product, next product
+__global__ __launch_bounds__(64) void k_build_products(const StripDesc* __restrict__ strips,
+                                                       cx<T>* __restrict__ img,
+                                                       const int* __restrict__ pflag, int stage) {
+  extern __shared__ c128 sh[];  // 3 KM^2
   if (pflag[blockIdx.y]) return;
   const StripDesc sd = strips[blockIdx.y];
-  const int ns = sd.ns, K = sd.kl, P = sd.segs, K2 = K * K;
-  int j = blockIdx.x, plan = 0;
-  for (; plan < HH_NPLAN; ++plan) {
-    const int c = plan_wg_maps(ns, sd.pseg[plan], P, plan_width(plan));
-    if (j < c) break;
-    j -= c;
-  }
-  if (plan == HH_NPLAN) return;
-  ++j;  // workgroup j = 1 .. gu-2
-  const int lane = threadIdx.x;
+  if (!sd.wide) return;
+  const int plan = HH_NPLAN - 1, G = plan_width(plan);
+  const int ns = sd.ns, K = sd.kl, P = sd.segs, KM = map_dim(sd.KP), K2 = KM * KM;
+  const int nseg = plan_nseg(ns, sd.pseg[plan]), gu = (nseg + P - 1) / P;
+  const int t0 = sd.pmap[plan] - 1;  // slot of T_c is t0 + c
+  const int m = blockIdx.x, lane = threadIdx.x;
   const long long tri = blockIdx.z == 1 ? (long long)sd.tmaps : 0LL;
-  const cx<T>* seg_maps = img + sd.t_off + (tri + sd.pmap[plan]) * K2;  // T_s at (s - 1) K^2
-  cx<T>* out = img + sd.t_off + (tri + sd.pwmap[plan] + j - 1) * K2;
-  c128* cur = prod;
-  c128* nxt = prod + K2;
-  const cx<T>* A = seg_maps + (long long)(j * P - 1) * K2;
-  for (int e = lane; e < K2; e += 64) cur[e] = mk((double)A[e].re, (double)A[e].im);
-  __syncthreads();
-  for (int q = 1; q < P; ++q) {
-    const cx<T>* B = seg_maps + (long long)(j * P + q - 1) * K2;  // element (r, c'') at c'' K + r
+  const cx<T>* maps = img + sd.t_off + tri * K2;
+  cx<T>* outm = img + sd.t_off + tri * K2;
+  c128* X = sh;
+  c128* Y = sh + K2;
+  c128* Z = sh + 2 * K2;
+  auto load = [&](c128* d, int slot) {
+    const cx<T>* src = maps + (long long)slot * K2;
+    for (int e0 = 0; e0 < K2; e0 += 8 * 64) {
+      cx<T> v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q * 64 + lane;
+        v[q] = src[e < K2 ? e : K2 - 1];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q * 64 + lane;
+        if (e < K2) d[e] = mk((double)v[q].re, (double)v[q].im);
+      }
+    }
+    __syncthreads();
+  };
+  auto store = [&](int slot, const c128* src) {  // the K x K block; the padding stays zero
+    cx<T>* d = outm + (long long)slot * K2;
+    for (int e = lane; e < K2; e += 64)
+      if (e % KM < K && e / KM < K) d[e] = mk((T)src[e].re, (T)src[e].im);
+  };
+  auto mul = [&](c128* d, const c128* A, const c128* B) {  // d = A B (d distinct from A, B)
     for (int c0 = 0; c0 < K; c0 += 16) {
       c128 acc[16];
 #pragma unroll
       for (int t = 0; t < 16; ++t) acc[t] = mk(0.0, 0.0);
       if (lane < K) {
         for (int cc = 0; cc < K; ++cc) {
-          const cx<T> bv = B[(long long)cc * K + lane];
-          const c128 b = mk((double)bv.re, (double)bv.im);
+          const c128 a = A[cc * KM + lane];
 #pragma unroll
           for (int t = 0; t < 16; ++t)
-            if (c0 + t < K) acc[t] = acc[t] + b * cur[(c0 + t) * K + cc];
+            if (c0 + t < K) acc[t] = acc[t] + a * B[(c0 + t) * KM + cc];
         }
 #pragma unroll
         for (int t = 0; t < 16; ++t)
-          if (c0 + t < K) nxt[(c0 + t) * K + lane] = acc[t];
+          if (c0 + t < K) d[(c0 + t) * KM + lane] = acc[t];
       }
     }
     __syncthreads();
-    c128* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
+  };
+  if (stage == 0) {
+    const int g = m / (P + 1), k = m % (P + 1);
+    if (g >= gu) return;
+    if (k == 0) {
+      if (g == 0 || g * P > nseg - 2) return;
+      c128* cur = X;
+      c128* nxt = Y;
+      load(cur, t0 + g * P);
+      for (int q = 1;; ++q) {  // cur = T_{gP+q-1} ... T_{gP}
+        if (q < P) {
+          if (g * P + q > nseg - 1) break;
+          store(sd.pi_map + g * P + q - 1, cur);
+        } else {
+          if (g <= gu - 2) store(sd.pwmap[plan] + g - 1, cur);
+          break;
+        }
+        const int c = g * P + q;
+        if (c > nseg - 2) break;
+        load(Z, t0 + c);
+        mul(nxt, Z, cur);
+        c128* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+      }
+    } else {
+      const int w = k - 1, c = g * P + w;
+      if (w < 2 || c > nseg - 2) return;
+      load(X, t0 + c);
+      load(Y, t0 + c - 1);
+      mul(Z, X, Y);
+      store(sd.a1_map + c - 1, Z);
+    }
+  } else if (m < G * P) {
+    const int g = m / P, w = m % P, c = g * P + w;
+    if (g >= gu || w < 4 || c > nseg - 2) return;
+    load(X, sd.a1_map + c - 1);
+    load(Y, sd.a1_map + c - 3);
+    mul(Z, X, Y);
+    store(sd.a2_map + c - 1, Z);
+  } else {
+    const int g = m - G * P;
+    if (G < 3 || g < 2 || g > gu - 1) return;
+    c128* cur = X;
+    c128* nxt = Y;
+    load(cur, sd.pwmap[plan] + g - 2);  // W_{g-1}
+    store(sd.ps_map + g * G + g - 2, cur);
+    for (int j = g - 3; j >= 0; --j) {
+      load(Z, sd.pwmap[plan] + j);  // W_{j+1}
+      mul(nxt, cur, Z);
+      c128* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+      store(sd.ps_map + g * G + j, cur);
+    }
   }
-  for (int e = lane; e < K2; e += 64) out[e] = mk((T)cur[e].re, (T)cur[e].im);
 }
 
 }  // namespace
@@ -520,32 +619,32 @@ static dim3 transfer_grid(const FactorSet& fs) {
   int maps = 1;
   for (auto& sd : fs.strips) {
     int m = 0;
-    for (int p = 0; p < HH_NPLAN; ++p) m += plan_seg_maps(sd.ns, sd.pseg[p]);
+    for (int p = 0; p < HH_NPLAN; ++p) m += transfer_jobs(sd, p);
     maps = std::max(maps, m);
   }
-  return dim3((unsigned)maps, (unsigned)fs.strips.size(), 2);
+  return dim3((unsigned)fs.strips.size(), 2, (unsigned)maps);
 }
 
-static dim3 wg_map_grid(const FactorSet& fs) {
-  int maps = 0;
+static dim3 product_grid(const FactorSet& fs, int stage) {
+  int jobs = 0;
   for (auto& sd : fs.strips) {
-    int m = 0;
-    for (int p = 0; p < HH_NPLAN; ++p) m += plan_wg_maps(sd.ns, sd.pseg[p], sd.segs, plan_width(p));
-    maps = std::max(maps, m);
+    const int G = plan_width(HH_NPLAN - 1);
+    jobs = std::max(jobs, stage == 0 ? G * (sd.segs + 1) : G * sd.segs + G);
   }
-  return dim3((unsigned)maps, (unsigned)fs.strips.size(), 2);
+  return dim3((unsigned)jobs, (unsigned)fs.strips.size(), 2);
 }
 
 template <class T>
-static void launch_wg_maps(const FactorSet& fs, hipStream_t st) {
-  const dim3 grid = wg_map_grid(fs);
-  if (grid.x == 0) return;
-  const size_t lds = 2 * (size_t)fs.max_kl * fs.max_kl * sizeof(c128);
-  const void* fn = (const void*)k_build_wg_maps<T>;
+static void launch_products(const FactorSet& fs, hipStream_t st) {
+  if (!fs.strips[0].wide) return;
+  const int KM = map_dim(fs.strips[0].KP);
+  const size_t lds = 3 * (size_t)KM * KM * sizeof(c128);
+  const void* fn = (const void*)k_build_products<T>;
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_build_wg_maps<T>, grid, dim3(64), lds, st, fs.d_strips, (cx<T>*)fs.img,
-                     fs.d_pflag);
+  for (int stage = 0; stage < 2; ++stage)
+    hipLaunchKernelGGL(k_build_products<T>, product_grid(fs, stage), dim3(64), lds, st,
+                       fs.d_strips, (cx<T>*)fs.img, fs.d_pflag, stage);
 }
 
 // One or two column slots per lane: 2 kl + 1 <= 64 needs one.
@@ -580,9 +679,13 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
-    hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
-                       (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
-    launch_wg_maps<double>(fs, st);
+    HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               64 * (fs.max_kl + 1) * (int)sizeof(c128)));
+    hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64),
+                       64 * (size_t)(fs.max_kl + 1) * sizeof(c128), st, fs.d_strips,
+                       (const c128*)fs.band, (c128*)fs.img, fs.d_pflag, fs.max_kl + 1);
+    launch_products<double>(fs, st);
   } else {
     launch_lu<float>(fs, lds, st);
     HH_HIP(hipGetLastError());
@@ -591,9 +694,13 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
-    hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64), 0, st, fs.d_strips,
-                       (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
-    launch_wg_maps<float>(fs, st);
+    HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               64 * (fs.max_kl + 1) * (int)sizeof(c128)));
+    hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64),
+                       64 * (size_t)(fs.max_kl + 1) * sizeof(c128), st, fs.d_strips,
+                       (const c64*)fs.band, (c64*)fs.img, fs.d_pflag, fs.max_kl + 1);
+    launch_products<float>(fs, st);
   }
   HH_HIP(hipGetLastError());
 }

@@ -136,7 +136,11 @@ struct StripDesc {
   int pseg[HH_NPLAN];  // rows per segment of each plan
   int pmap[HH_NPLAN];  // index of the plan's first segment map among the triangle's maps
   int pwmap[HH_NPLAN]; // index of the plan's first workgroup map
+  int pi_map, a1_map, a2_map, ps_map;  // wide plan: products of maps (see plan_layout)
+  int wide;            // the wide plan's maps and responses are built (sweep_wide_fits)
   long long t_off;     // complex elements into the solve image: transfer maps (L, then U)
+  long long phi_off;   // complex elements into the solve image: segment responses of the
+                       // wide plan (L, then U; see plan_phi_elems)
 };
 
 // Zero steps appended to every strip's solve image and pivot list, so that the
@@ -257,12 +261,14 @@ struct SweepTask {
 // that a workgroup raises when its partners fail to arrive in time).
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
                   int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st);
-// Whether the wide plan can run: no pivoted strip, and its workgroup fits the LDS.
+// Whether the wide plan can run a factorisation (complex64 strips, band
+// half-width at most 31, eight segments per workgroup, LDS).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
-// Plan for a launch of ntasks chains: the HH_SWEEP_PLAN environment variable
-// (0 or 1) when set, else the wide plan while ntasks * its width fits a quarter
-// of the compute units.
-int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots);
+// Plan for a launch of ntasks chains: plan 0 where some strip pivoted, the
+// wide plan's maps were not built (built = false) or it cannot run, else the
+// HH_SWEEP_PLAN environment variable (0 or 1) when set, else the wide plan
+// while ntasks times its width is at most half the compute units.
+int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built);
 // Blocked substitution: block size and terms per lane for band half-width kl.
 // KP terms per lane cover the K + HH_BLK columns of a block map over the 64/HH_BLK
 // lanes of one output row; KP <= 12 exactly when 2 kl + 1 <= 64 (one lane-major
@@ -280,15 +286,18 @@ __host__ __device__ inline int segment_rows(int ns, int P) {
   const int per = (ns + P - 1) / P;
   return (per + 63) / 64 * 64;
 }
-// Plan p: a triangle of ns rows is cut into segments of plan_seg rows, P per
-// workgroup over plan_width(p) workgroups.  Plan 0 is the one-workgroup split
-// (segments a multiple of 64 rows); the wide plan cuts 16-row aligned
-// segments.
+// Plan p: a triangle of ns rows (band half-width K) is cut into segments of
+// plan_seg rows, P per workgroup over plan_width(p) workgroups.  Plan 0 is
+// the one-workgroup split (segments a multiple of 64 rows); the wide plan cuts
+// 16-row aligned segments.  Either way a segment is at least K rows long, so
+// that a segment's state (the K outputs before it) lies in the segment before
+// it, and every segment after the first starts at row K or later.
 __host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : 8; }
-__host__ __device__ inline int plan_seg(int ns, int P, int p) {
+__host__ __device__ inline int plan_seg(int ns, int P, int p, int K) {
   if (p == 0) return segment_rows(ns, P);
-  const int S = plan_width(p) * P, per = (ns + S - 1) / S;
-  return (per + 15) / 16 * 16;
+  const int S = plan_width(p) * P, per = (ns + S - 1) / S, least = (K + 15) / 16 * 16;
+  const int seg = (per + 15) / 16 * 16;
+  return seg > least ? seg : least;
 }
 __host__ __device__ inline int plan_nseg(int ns, int seg) { return (ns + seg - 1) / seg; }
 // Segment transfer maps: segments 1 .. nseg-2 (segment 0 starts from the
@@ -305,50 +314,83 @@ __host__ __device__ inline int plan_wg_maps(int ns, int seg, int P, int G) {
   const int gu = (plan_nseg(ns, seg) + P - 1) / P, v = gu - 2;
   return v > 0 ? v : 0;
 }
-// Fills the plan fields of sd (ns and segs set) and returns the maps per triangle.
+// Transfer maps and segment responses are stored zero-padded to KM = map_dim
+// state entries (KM >= K for every strip of a factorisation, fixed by its
+// blocked term count KP): a map is KM x KM, column-major.
+__host__ __device__ constexpr int map_dim(int KP) {
+  return KP <= 8 ? 16 : KP <= 10 ? 24 : KP <= 12 ? 32 : KP <= 16 ? 48 : 64;
+}
+// Segment responses of the wide plan (one triangle): for segments c = 1 ..
+// nseg-1, the outputs of the segment's rows started from the unit state e_k
+// with zero inputs, Phi_c[k][i] at ((c - 1) KM + k) seg + i (zero for k >= K).
+__host__ __device__ inline long long plan_phi_elems(int ns, int P, int K, int KM) {
+  const int p = HH_NPLAN - 1, seg = plan_seg(ns, P, p, K), nseg = plan_nseg(ns, seg);
+  return nseg > 1 ? (long long)(nseg - 1) * seg * KM : 0;
+}
+// Fills the plan fields of sd (ns, kl and segs set) and returns the maps per
+// triangle.  Map slots of a triangle: per plan its segment maps T_c (slot
+// pmap + c - 1) and workgroup maps W_g (pwmap + g - 1); then, for the wide
+// plan, products of consecutive segment maps within a workgroup, slot + c - 1
+// for segment c = g P + w:
+//   pi_map: Pi_c = T_{c-1} ... T_{gP} (w >= 1), the map from the workgroup's
+//           start state to segment c's start state;
+//   a1_map: T_c T_{c-1} (w >= 2);  a2_map: T_c ... T_{c-3} (w >= 4);
+// and ps_map + g G + j: Psi_{j,g} = W_{g-1} ... W_{j+1} (0 <= j <= g-2).
 inline int plan_layout(StripDesc& sd) {
   int m = 0;
+  const int pw = HH_NPLAN - 1;
   for (int p = 0; p < HH_NPLAN; ++p) {
-    sd.pseg[p] = plan_seg(sd.ns, sd.segs, p);
+    const bool on = p != pw || sd.wide;  // the wide plan only where it can run
+    sd.pseg[p] = plan_seg(sd.ns, sd.segs, p, sd.kl);
     sd.pmap[p] = m;
-    m += plan_seg_maps(sd.ns, sd.pseg[p]);
+    if (on) m += plan_seg_maps(sd.ns, sd.pseg[p]);
     sd.pwmap[p] = m;
-    m += plan_wg_maps(sd.ns, sd.pseg[p], sd.segs, plan_width(p));
+    if (on) m += plan_wg_maps(sd.ns, sd.pseg[p], sd.segs, plan_width(p));
   }
+  const int nseg = plan_nseg(sd.ns, sd.pseg[pw]), G = plan_width(pw);
+  const int per = sd.wide && nseg > 1 ? nseg - 1 : 0;
+  sd.pi_map = m;
+  sd.a1_map = m + per;
+  sd.a2_map = m + 2 * per;
+  sd.ps_map = m + 3 * per;
+  m += 3 * per + (sd.wide && G >= 3 && nseg > 1 ? G * G : 0);
   sd.seg = sd.pseg[0];
   sd.tmaps = m;
   return m;
 }
-// LDS of a wide-plan workgroup (complex elements): rings sharing space with the
-// staged maps (its P segment maps and up to G - 2 workgroup maps), segment
-// tails (64 P), states (64 (P + 1)) and two node lines of transmission data.
-inline long long sweep_lds_elems_wide(int P, int G, int K, int n) {
-  const long long work = std::max(640LL * P, (long long)(P + G - 2) * K * K);
-  return work + 64LL * P + 64LL * (P + 1) + 2LL * n;
+// LDS of a wide-plan workgroup (complex elements): the rings (640 P), three
+// vectors per wave (tails and states, scan exchange, partial sums: 64 each,
+// one more for the scan) and two node lines of transmission data.
+inline long long sweep_lds_elems_wide(int P, int n) {
+  return 640LL * P + 64LL * (3 * P + 1) + 2LL * n;
 }
 // LDS of a sweep workgroup of P waves (complex elements): per-wave rings
 // (phase 1 and 3) sharing space with the staged transfer maps (phase 2), the
 // segment tails and states, and two node lines of transmission data.
-inline long long sweep_lds_elems(int P, int K, int n) {
-  const long long work = std::max(640LL * P, (long long)std::max(P - 2, 0) * K * K);
+inline long long sweep_lds_elems(int P, int KM, int n) {
+  const long long work = std::max(640LL * P, (long long)std::max(P - 2, 0) * KM * KM);
   return work + 2LL * 64 * P + 2LL * n;
 }
 // Segments of the parallel substitution: the most (up to 8) whose workgroup
 // fits the LDS.
-inline int sweep_segments(int K, int n, size_t esz) {
+inline int sweep_segments(int KM, int n, size_t esz) {
   for (int P : {8, 6, 4, 3, 2})
-    if (sweep_lds_elems(P, K, n) * (long long)esz <= 150 * 1024) return P;
+    if (sweep_lds_elems(P, KM, n) * (long long)esz <= 150 * 1024) return P;
   return 1;
 }
 // Image elements of one strip: the larger of the pivoted (lane-major) and the
 // unpivoted (blocked maps plus segment transfer maps) layouts; which one is
 // built is decided by the LU.
-inline long long strip_image_elems(long long ns, int S, int KP, int K, int P) {
+inline long long strip_image_elems(long long ns, int S, int KP, int K, int P, bool wide) {
   const long long lane_major = (ns + HH_PAD) * (64LL * (1 + S) + 1);
   StripDesc sd{};
   sd.ns = (int)ns;
+  sd.kl = K;
   sd.segs = P;
-  const long long blocked = 2 * blocked_blocks(ns) * KP * 64 + 2LL * plan_layout(sd) * K * K;
+  sd.wide = wide;
+  const int KM = map_dim(KP);
+  const long long blocked = 2 * blocked_blocks(ns) * KP * 64 + 2LL * plan_layout(sd) * KM * KM +
+                            (wide ? 2 * plan_phi_elems((int)ns, P, K, KM) : 0);
   return lane_major > blocked ? lane_major : blocked;
 }
 // Single strip solve (test hook): rhs/x in FP64, strip-local order.

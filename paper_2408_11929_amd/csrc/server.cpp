@@ -50,11 +50,11 @@ size_t request_footprint(const hh_request& r) {
   }
   const int S = 2 * kl_max + 1 <= 64 ? 1 : 2;
   const int KP = blocked_kp(kl_max);
-  const int P = sweep_segments(kl_max, (int)n, es);
+  const int P = sweep_segments(map_dim(KP), (int)n, es);
   for (long long s = 0; s < N; ++s) {
     const long long a = std::max(0LL, s * m - 1), b = std::min(n - 1, (s + 1) * m + 1);
     const long long w = b - a + 1, ns = n * w, kl = w + 1;
-    img += strip_image_elems(ns, S, KP, (int)kl, P);
+    img += strip_image_elems(ns, S, KP, (int)kl, P, sweep_wide_fits(r.precision, P, kl_max, (int)n));
     band += ns * (3 * kl + 1);
     piv += ns + HH_PAD;
     ns_max = std::max(ns_max, ns);

@@ -367,6 +367,7 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
       const int j = j0 + h;
+      if (j >= nst) break;  // the unrolled group may overrun the last step
       // requests NB-1 steps ahead: maps and inputs; write-back of the last step
       const int hn = (h + NB - 1) % NB;
 #pragma unroll
@@ -397,7 +398,7 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
       }
     }
   }
-  const int q = (nstr - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
+  const int q = (nst - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
   dst.put(qs, oring[qs & 255]);
 }
 
@@ -498,6 +499,7 @@ struct DstVec {  // x[i] (rev: x[ns-1-i])
   int ns;
   bool rev;
   __device__ void put(int i, cx<T> v) const { st<T>(x, rev ? ns - 1 - i : i, v); }
+  __device__ cx<T> get(int i) const { return ld<T>(x, rev ? ns - 1 - i : i); }
 };
 template <class T>
 struct DstC128 {  // strip-local FP64 output, reversed order
@@ -516,13 +518,14 @@ struct DstScatter {
   gptr<cx<T>> z;
   int ns, w, n, a, dir;
   float winv;  // 1 / w
-  __device__ void put(int i, cx<T> v) const {
+  __device__ long long pos(int i) const {
     const int q = ns - 1 - i;
     int l, t;
     line_of(q, w, winv, l, t);
-    const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
-    st<T>(z, p, v);
+    return dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
   }
+  __device__ void put(int i, cx<T> v) const { st<T>(z, pos(i), v); }
+  __device__ cx<T> get(int i) const { return ld<T>(z, pos(i)); }
 };
 
 // Segment views for the parallel substitution: rows off..off+len-1 of a
@@ -540,6 +543,7 @@ struct SegDst {
   const Dst& b;
   int off;
   __device__ void put(int i, cx<T> v) const { b.put(off + i, v); }
+  __device__ cx<T> get(int i) const { return b.get(off + i); }
 };
 template <class T>
 struct DstTail {  // keeps only the last K rows of a segment (in LDS)
@@ -551,6 +555,34 @@ struct DstTail {  // keeps only the last K rows of a segment (in LDS)
   }
 };
 
+// v = y + M x in lane c < K (row c; zero in the other lanes), y being the
+// lane's own entry: M is KM x KM, column-major (element (c, c') at c' KM + c)
+// and zero beyond K, x is zero beyond K (both in LDS).  With KM <= 32 two
+// lanes share a row (lane c + 32 h sums the columns c' = h mod 2) and one lane
+// swap adds the halves.  Unrolled in chunks of columns (sized for the
+// register file): every LDS read has a fixed offset and a chunk's reads are
+// issued before its products.
+template <class T, int KM>
+__device__ __forceinline__ cx<T> map_apply(const cx<T>* M, const cx<T>* x, cx<T> y, int K,
+                                           int lane) {
+  constexpr int H = KM <= 32 ? 2 : 1, NC = KM / H;
+  constexpr int CH = sizeof(T) == 8 ? 4 : (NC <= 16 ? NC : 16);
+  static_assert(NC % CH == 0, "column chunks");
+  const cx<T> zero = mk((T)0, (T)0);
+  const int c = H == 2 ? (lane & 31) : lane, h = H == 2 ? (lane >> 5) : 0;
+  const cx<T>* Mb = M + h * KM + (c < KM ? c : 0);
+  const cx<T>* xb = x + h;
+  cx<T> a[4] = {zero, zero, zero, zero};
+  for (int q0 = 0; q0 < NC; q0 += CH) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      a[q & 3] = cfma(a[q & 3], Mb[(q0 + q) * H * KM], xb[(q0 + q) * H]);
+  }
+  cx<T> v = (a[0] + a[1]) + (a[2] + a[3]);
+  if (H == 2) v = v + mk(__shfl_xor(v.re, 32), __shfl_xor(v.im, 32));
+  return csel(lane < K, v + y, zero);
+}
+
 // One triangular substitution of a strip by all P waves of the workgroup
 // (the recurrence is linear, so it splits exactly over segments of seg rows):
 //  1. every segment but the last runs from a zero state; segment 0 is then
@@ -561,8 +593,8 @@ struct DstTail {  // keeps only the last K rows of a segment (in LDS)
 // Phase 1 of a segment and phase 3 of the next one together cost two blocked
 // substitutions of seg rows, so the chain of one strip shortens from ns to
 // about 2 ns / P rows.  work: the LDS shared by the rings (phases 1 and 3,
-// 640 entries per wave) and the staged maps (phase 2); yt, stt: 64 entries
-// per segment.
+// 640 entries per wave) and the staged maps (phase 2, KM x KM each); yt,
+// stt: 64 entries per segment.
 template <class T, int KP, int U, int NB, class Src, class Dst>
 __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, const cx<T>* G,
                                                const cx<T>* Tm, int ns, int K, int seg,
@@ -582,7 +614,8 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
   }
   if (nseg == 1) return;
   __syncthreads();
-  const int nT = (nseg - 2) * K * K;
+  constexpr int KM = map_dim(KP);
+  const int nT = (nseg - 2) * KM * KM;
   gptr<const cx<T>> Tg = (gptr<const cx<T>>)Tm;
   for (int e0 = 0; e0 < nT; e0 += 8 * nthr) {
     cx<T> v[8];
@@ -600,23 +633,9 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
   __syncthreads();
   if (wv == 0) {
     for (int s = 1; s < nseg; ++s) {
-      cx<T> v = mk((T)0, (T)0);
-      if (lane < K) {
-        v = yt[64 * (s - 1) + lane];
-        if (s >= 2) {
-          const cx<T>* Tb = work + (long long)(s - 2) * K * K + lane;
-          const cx<T>* sp = stt + 64 * (s - 1);
-          cx<T> a1 = mk((T)0, (T)0);
-          int cp = 0;
-          for (; cp + 1 < K; cp += 2) {
-            v = cfma(v, Tb[cp * K], sp[cp]);
-            a1 = cfma(a1, Tb[(cp + 1) * K], sp[cp + 1]);
-          }
-          if (cp < K) v = cfma(v, Tb[cp * K], sp[cp]);
-          v = v + a1;
-        }
-      }
-      stt[64 * s + lane] = v;
+      const cx<T> y = lane < K ? yt[64 * (s - 1) + lane] : mk((T)0, (T)0);
+      stt[64 * s + lane] =
+          s >= 2 ? map_apply<T, KM>(work + (s - 2) * KM * KM, stt + 64 * (s - 1), y, K, lane) : y;
     }
   }
   __syncthreads();
@@ -705,8 +724,9 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
       const int seg = uni(sp->seg);
       const cx<T>* GL = img + img_off;
       const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-      const cx<T>* TL = img + uni(sp->t_off) + (long long)uni(sp->pmap[0]) * kl * kl;
-      const cx<T>* TU = TL + (long long)uni(sp->tmaps) * kl * kl;
+      constexpr long long KM2 = (long long)map_dim(KP) * map_dim(KP);
+      const cx<T>* TL = img + uni(sp->t_off) + uni(sp->pmap[0]) * KM2;
+      const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
       solve_triangle<T, KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, TL, ns, kl, seg, work, yt,
                                stt);
       __syncthreads();
@@ -736,30 +756,39 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
 }
 
 // ---------------------------------------------------------------- wide plan
-// A chain on G workgroups.  The segment split of solve_triangle carries over
-// to G P segments (wave w of workgroup g solves segment c = g P + w), with
-// the state propagation in two levels:
-//  1. every segment but the last runs from a zero state and keeps its tail
-//     (segment 0 is final and written out);
-//  2. in every workgroup, wave 0 propagates zero-start states over its P
-//     segments with the segment maps; the state reached at the workgroup's
-//     end (its tail) goes to the chain's exchange area;
-//  3. all G workgroups meet (chain_wait); workgroup g forms its true start
-//     state S_g from the tails of workgroups 0..g-1 and the workgroup maps
-//     (S_1 = tail_0, S_{j+1} = tail_j + W_j S_j), then the true states of its
-//     segments with the segment maps;
-//  4. every segment but segment 0 runs again from its true state.
+// A chain on G workgroups (complex64 strips).  The rows of a triangle split
+// into G P segments (wave w of workgroup g solves segment c = g P + w).  The
+// recurrence is linear: the outputs of segment c are its zero-start outputs
+// plus Phi_c s_c, where s_c is the segment's true state (the K outputs
+// before it) and Phi_c its response to that state; the state after segment c
+// is tail_c + T_c s_c (T_c: the last K rows of Phi_c).  Phi, T and the
+// products of consecutive T's named below are formed at factorisation time.
+//  1. every segment runs from a zero state and writes its outputs (segment 0
+//     is then final); it keeps its tail;
+//  2. the zero-start states after each segment of a workgroup follow from an
+//     inclusive scan over its P segments (steps of distance 1, 2, 4 with the
+//     maps T_c, T_c T_{c-1} and T_c ... T_{c-3}, all waves at once); the last
+//     one, the workgroup's tail, goes to the chain's exchange area;
+//  3. the G workgroups meet (chain_wait); workgroup g forms its true start
+//     state S_g = sum_{j<g} Psi_{j,g} tail_j (Psi_{j,g} = W_{g-1} ... W_{j+1},
+//     W the workgroup maps, Psi_{g-1,g} = I; one product per wave), and the
+//     true states s_c = z_c + Pi_c S_g (z_c the zero-start state, Pi_c the
+//     product of the workgroup's maps before segment c);
+//  4. every segment but segment 0 adds Phi_c s_c to its outputs.
+// The maps of steps 2 and 3 are read into registers (one row per lane), those
+// of step 3 and the first rows of Phi_c while the workgroup waits to meet.
 // The workgroups meet again when a triangle's output is complete (the back
 // substitution reads rows that other workgroups wrote, the next strip's
 // transmission data read the solution), so a strip solve is four meetings.
 
-// Meeting of the G workgroups of one chain.  Every wave makes its global
-// writes visible at agent scope before the workgroup barrier; thread 0 then
-// counts the workgroup in and waits until all G have arrived.  The wait is
-// bounded: after `limit` ticks of the constant-rate clock, or as soon as
-// another workgroup has given up, thread 0 raises *abort and gives up.  After
-// the workgroup barrier every wave acquires at agent scope.  Returns false
-// once the chain is aborted, the same answer in every thread.
+// Meeting of the G workgroups of one chain, in two halves so that work can
+// go between them.  chain_arrive: every wave makes its global writes visible
+// at agent scope, the workgroup synchronises and thread 0 counts it in.
+// chain_wait: thread 0 waits until all G have arrived.  The wait is bounded:
+// after `limit` ticks of the constant-rate clock, or as soon as another
+// workgroup has given up, thread 0 raises *abort and gives up.  After the
+// workgroup barrier every wave acquires at agent scope.  Returns false once
+// the chain is aborted, the same answer in every thread.
 struct ChainBar {
   unsigned* cnt;    // arrivals so far (zero at launch)
   unsigned* abort;  // raised by a workgroup that gave up
@@ -769,12 +798,16 @@ struct ChainBar {
   int* ok;  // LDS word
 };
 
-__device__ __forceinline__ bool chain_wait(ChainBar& b) {
+__device__ __forceinline__ void chain_arrive(ChainBar& b) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   b.need += b.G;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     __hip_atomic_fetch_add(b.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool chain_wait(ChainBar& b) {
+  if (threadIdx.x == 0) {
     const long long t0 = wall_clock64();
     int ok = 1;
     while (__hip_atomic_load(b.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b.need) {
@@ -793,186 +826,228 @@ __device__ __forceinline__ bool chain_wait(ChainBar& b) {
   return *b.ok != 0;
 }
 
-// v = y + M x for lanes < K (zero above): M a K x K map stored column-major
-// (element (c, c') at c' K + c) in LDS, x and y in LDS.
-template <class T>
-__device__ __forceinline__ cx<T> map_apply(const cx<T>* M, const cx<T>* x, const cx<T>* y, int K,
-                                           int lane) {
-  cx<T> v = mk((T)0, (T)0);
-  if (lane < K) {
-    v = y[lane];
-    const cx<T>* Mb = M + lane;
-    cx<T> a1 = mk((T)0, (T)0);
-    int cp = 0;
-    for (; cp + 1 < K; cp += 2) {
-      v = cfma(v, Mb[cp * K], x[cp]);
-      a1 = cfma(a1, Mb[(cp + 1) * K], x[cp + 1]);
-    }
-    if (cp < K) v = cfma(v, Mb[cp * K], x[cp]);
-    v = v + a1;
-  }
-  return v;
+__device__ __forceinline__ bool chain_meet(ChainBar& b) {
+  chain_arrive(b);
+  return chain_wait(b);
 }
 
+// One row of a KM x KM map (KM <= 32, column-major, zero beyond K) held in
+// registers: lane c + 32 h holds the entries (c, h + 2 q), q < KM / 2.
+template <class T, int KM>
+struct MapRow {
+  static_assert(KM <= 32, "two lanes per row");
+  cx<T> v[KM / 2];
+};
+
+template <class T, int KM>
+__device__ __forceinline__ void map_row_load(MapRow<T, KM>& m, const cx<T>* M, int lane) {
+  gptr<const cx<T>> Mg = (gptr<const cx<T>>)M;
+  const int c = lane & 31, h = lane >> 5, cr = c < KM ? c : 0;
+#pragma unroll
+  for (int q = 0; q < KM / 2; ++q) m.v[q] = ld<T>(Mg, (long long)(h + 2 * q) * KM + cr);
+}
+
+// v = y + M x in lane c < K (zero in the other lanes), y being the lane's
+// own entry, M from registers, x in LDS and zero beyond K; the two halves of
+// a row are added by one lane swap.
+template <class T, int KM>
+__device__ __forceinline__ cx<T> map_apply_r(const MapRow<T, KM>& m, const cx<T>* x, cx<T> y,
+                                             int K, int lane) {
+  const cx<T> zero = mk((T)0, (T)0);
+  const cx<T>* xb = x + (lane >> 5);
+  cx<T> a[4] = {zero, zero, zero, zero};
+#pragma unroll
+  for (int q = 0; q < KM / 2; ++q) a[q & 3] = cfma(a[q & 3], m.v[q], xb[2 * q]);
+  cx<T> v = (a[0] + a[1]) + (a[2] + a[3]);
+  v = v + mk(__shfl_xor(v.re, 32), __shfl_xor(v.im, 32));
+  return csel(lane < K, v + y, zero);
+}
+
+// Map slots of one triangle for the wide plan (see plan_layout): maps[s] is
+// slot s; T_c at t0 + c, Pi_c at pi + c - 1, T_c T_{c-1} at a1 + c - 1,
+// T_c ... T_{c-3} at a2 + c - 1, Psi_{j,g} at ps + g G + j.
+struct WideMaps {
+  const cx<float>* maps;
+  int t0, pi, a1, a2, ps;
+};
+
 // One triangular substitution of a strip by workgroup g of the chain's G
-// (steps 1-4 above).  Tm: the plan's segment maps (T_c at (c - 1) K^2), Wm:
-// its workgroup maps (W_j at (j - 1) K^2), xch: exchange area (64 entries per
-// workgroup).  LDS: work (rings, then the staged maps: segment maps of the
-// workgroup at (c - g P) K^2, workgroup maps 1..g-1 after P K^2), yt (64 P),
-// stt (64 (P + 1)).  Returns false when the chain was aborted.
-template <class T, int KP, int U, int NB, class Src, class Dst>
+// (steps 1-4 above).  Phi: the segment responses (plan_phi_elems layout),
+// xch: exchange area (64 entries per workgroup).  LDS: the wave's ring (640
+// entries from ring), yt, kb, pw (64 entries per wave each: tails and
+// states, scan exchange, partial sums).  Returns false when the chain was
+// aborted.
+template <int KP, int U, int NB, class Src, class Dst>
 __device__ __forceinline__ bool solve_triangle_wide(const Src& src, const Dst& dst,
-                                                    const cx<T>* G, const cx<T>* Tm,
-                                                    const cx<T>* Wm, int ns, int K, int seg,
-                                                    int g, cx<T>* work, cx<T>* yt, cx<T>* stt,
-                                                    gptr<cx<T>> xch, ChainBar& bar) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
-  const int P = nthr >> 6;
+                                                    const c64* G, const WideMaps& mp,
+                                                    const c64* Phi, int ns, int K, int seg, int g,
+                                                    int Gw, c64* ring, c64* yt, c64* kb, c64* pw,
+                                                    gptr<c64> xch, ChainBar& bar) {
+  using T = float;
+  constexpr int KM = map_dim(KP);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, P = blockDim.x >> 6;
   const int nseg = (ns + seg - 1) / seg, gu = (nseg + P - 1) / P;
-  const int c = g * P + wv;
-  cx<T>* ring = work + 640 * wv;
+  const int c = g * P + w;
+  const c64 zero = mk(0.0f, 0.0f);
   const int off = c * seg, len = c < nseg ? (ns - off < seg ? ns - off : seg) : 0;
-  gptr<const cx<T>> Gw = (gptr<const cx<T>>)(G + (long long)(off / 16) * KP * 64);
-  if (c == 0) {
-    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, 0, len}, SegDst<T, Dst>{dst, 0}, Gw, len, K, ring,
-                                (const cx<T>*)nullptr, lane);
-    if (nseg > 1 && lane < K) yt[lane] = ring[(len - K + lane) & 255];
-  } else if (c < nseg - 1) {
-    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, DstTail<T>{yt + 64 * wv, len, K}, Gw,
-                                len, K, ring, (const cx<T>*)nullptr, lane);
+  const SegDst<T, Dst> out{dst, off};
+  auto mslot = [&](int s) { return mp.maps + (long long)s * KM * KM; };
+  // 1. zero-start solve
+  if (c < nseg) {
+    gptr<const c64> Gs = (gptr<const c64>)(G + (long long)(off / 16) * KP * 64);
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, out, Gs, len, K, ring,
+                                (const c64*)nullptr, lane);
+    if (c < nseg - 1 && lane < K) yt[64 * w + lane] = ring[(len - K + lane) & 255];
   }
   if (nseg == 1) return true;
-  __syncthreads();
-  const int K2 = K * K;
-  if (g < gu) {  // stage this workgroup's maps
-    const int c0 = g * P > 1 ? g * P : 1, c1 = g * P + P < nseg - 1 ? g * P + P : nseg - 1;
-    const int nA = c1 > c0 ? (c1 - c0) * K2 : 0, nB = g >= 2 ? (g - 1) * K2 : 0;
-    gptr<const cx<T>> A = (gptr<const cx<T>>)(Tm + (long long)(c0 - 1) * K2);
-    gptr<const cx<T>> B = (gptr<const cx<T>>)Wm;
-    cx<T>* dA = work + (c0 - g * P) * K2;
-    cx<T>* dB = work + P * K2;
-    for (int e0 = 0; e0 < nA + nB; e0 += 8 * nthr) {
-      cx<T> v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = e0 + q * nthr + tid;
-        if (e < nA)
-          v[q] = ld<T>(A, e);
-        else if (e < nA + nB)
-          v[q] = ld<T>(B, e - nA);
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = e0 + q * nthr + tid;
-        if (e < nA)
-          dA[e] = v[q];
-        else if (e < nA + nB)
-          dB[e - nA] = v[q];
-      }
+  // 2. scan of the zero-start states over the workgroup's segments
+  const bool has_t = c <= nseg - 2;  // segment c has a tail and (c >= 1) a map T_c
+  MapRow<T, KM> A0, A1, A2;
+  if (has_t && w >= 1) map_row_load(A0, mslot(mp.t0 + c), lane);
+  if (has_t && w >= 2) map_row_load(A1, mslot(mp.a1 + c - 1), lane);
+  if (has_t && w >= 4) map_row_load(A2, mslot(mp.a2 + c - 1), lane);
+  c64 b = has_t && lane < K ? yt[64 * w + lane] : zero;
+  for (int d = 1, lev = 0; d < P; d *= 2, ++lev) {
+    kb[64 * w + lane] = b;
+    __syncthreads();
+    if (has_t && w >= d) {
+      const c64* x = kb + 64 * (w - d);
+      b = lev == 0 ? map_apply_r(A0, x, b, K, lane)
+                   : (lev == 1 ? map_apply_r(A1, x, b, K, lane) : map_apply_r(A2, x, b, K, lane));
     }
+    __syncthreads();
   }
-  __syncthreads();
-  // zero-start states: stt[64 (w + 1)] = state after segment g P + w
-  if (wv == 0 && g < gu) {
-    for (int w = 0; w < P; ++w) {
-      const int cw = g * P + w;
-      if (cw > nseg - 2) break;
-      const cx<T> v = w == 0 ? (lane < K ? yt[lane] : mk((T)0, (T)0))
-                             : map_apply<T>(work + w * K2, stt + 64 * w, yt + 64 * w, K, lane);
-      stt[64 * (w + 1) + lane] = v;
-    }
-    if (g < gu - 1 && lane < K) st<T>(xch, (long long)g * 64 + lane, stt[64 * P + lane]);
+  kb[64 * w + lane] = b;  // zero-start state after segment c
+  if (w == P - 1 && g < gu - 1 && lane < K) st<T>(xch, (long long)g * 64 + lane, b);
+  chain_arrive(bar);
+  // maps of step 3 and the first rows of the correction, read while waiting
+  MapRow<T, KM> PI, PS;
+  if (g >= 1 && w >= 1 && c <= nseg - 1) map_row_load(PI, mslot(mp.pi + c - 1), lane);
+  if (g >= 2 && w <= g - 2) map_row_load(PS, mslot(mp.ps + g * Gw + w), lane);
+  const bool corr = c >= 1 && c < nseg;
+  gptr<const c64> Ph = (gptr<const c64>)(Phi + (long long)(corr ? c - 1 : 0) * seg * KM);
+  c64 ph0[KM];
+  {
+    const int ic = lane < len ? lane : (len > 0 ? len - 1 : 0);
+#pragma unroll
+    for (int k = 0; k < KM; ++k) ph0[k] = corr ? ld<T>(Ph, (long long)k * seg + ic) : zero;
   }
   if (!chain_wait(bar)) return false;
-  if (wv == 0 && g >= 1 && g < gu) {
-    // S_g in stt[0]: S_1 = tail_0, S_{j+1} = tail_j + W_j S_j (ping-pong with stt[64 P])
-    cx<T>* sa = stt;
-    cx<T>* sb = stt + 64 * P;
-    sa[lane] = lane < K ? ld<T>(xch, lane) : mk((T)0, (T)0);
-    for (int j = 1; j < g; ++j) {
-      const cx<T> t = lane < K ? ld<T>(xch, (long long)j * 64 + lane) : mk((T)0, (T)0);
-      sb[lane] = t;
-      const cx<T> v = map_apply<T>(work + (P + j - 1) * K2, sa, sb, K, lane);
-      sb[lane] = v;
-      cx<T>* tmp = sa;
-      sa = sb;
-      sb = tmp;
+  // 3. true states
+  c64 s = zero;
+  if (g == 0) {
+    if (w >= 1 && c < nseg) s = kb[64 * (w - 1) + lane];
+  } else if (g < gu) {
+    if (w < g) {
+      const c64 t = lane < K ? ld<T>(xch, (long long)w * 64 + lane) : zero;
+      c64 v = t;
+      if (w <= g - 2) {
+        yt[64 * w + lane] = t;
+        v = map_apply_r(PS, yt + 64 * w, zero, K, lane);
+      }
+      pw[64 * w + lane] = v;
     }
-    if (sa != stt) stt[lane] = sa[lane];
-    // true states of the workgroup's segments
-    for (int w = 0; w + 1 < P; ++w) {
-      const int cw = g * P + w;
-      if (cw + 1 > nseg - 1) break;
-      stt[64 * (w + 1) + lane] = map_apply<T>(work + w * K2, stt + 64 * w, yt + 64 * w, K, lane);
+    __syncthreads();
+    c64 S = zero;
+    for (int j = 0; j < g; ++j) S = S + pw[64 * j + lane];
+    if (w == 0) {
+      s = S;
+    } else if (c < nseg) {
+      yt[64 * w + lane] = S;
+      s = map_apply_r(PI, yt + 64 * w, kb[64 * (w - 1) + lane], K, lane);
     }
   }
-  __syncthreads();
-  if (c >= 1 && c < nseg)
-    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, SegDst<T, Dst>{dst, off}, Gw, len, K,
-                                ring, stt + 64 * wv, lane);
+  // 4. outputs += Phi_c s_c, 64 rows at a time (lane = row); the zero-start
+  // outputs come from the ring while the segment fits it
+  if (corr) {
+    yt[64 * w + lane] = s;
+    const c64* sc = yt + 64 * w;
+    for (int i0 = 0; i0 < len; i0 += 64) {
+      const int i = i0 + lane, ic = i < len ? i : len - 1;
+      c64 a[4] = {len <= 256 ? ring[ic & 255] : out.get(ic), zero, zero, zero};
+      if (i0 == 0) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) a[k & 3] = cfma(a[k & 3], ph0[k], sc[k]);
+      } else {
+        c64 pv[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) pv[k] = ld<T>(Ph, (long long)k * seg + ic);
+#pragma unroll
+        for (int k = 0; k < KM; ++k) a[k & 3] = cfma(a[k & 3], pv[k], sc[k]);
+      }
+      if (i < len) out.put(i, (a[0] + a[1]) + (a[2] + a[3]));
+    }
+  }
   return true;
 }
 
-// The double sweep of k_sweep on G workgroups per chain (unpivoted strips
-// only): workgroup g = blockIdx.x % G of chain blockIdx.x / G.  Every
-// workgroup forms the transmission data of all node lines itself (workgroup
-// 0 keeps the forward ones for the backward pass).  Dynamic LDS (complex
-// elements): two node lines, yt (64 P), stt (64 (P + 1)), work.
-template <class T, int KP, int U, int NB>
+// The double sweep of k_sweep on G workgroups per chain (complex64,
+// unpivoted strips): workgroup g = blockIdx.x % G of chain blockIdx.x / G.
+// Every workgroup forms the transmission data of all node lines itself
+// (workgroup 0 keeps the forward ones for the backward pass).  Dynamic LDS
+// (complex elements): two node lines, yt, kb, pw (64 P each), then the rings
+// (640 P).
+template <int KP, int U, int NB>
 __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict__ tasks, int plan,
                                                     unsigned* abort, long long limit) {
+  using T = float;
   extern __shared__ char smem_raw[];
   __shared__ int ok;
   const int G = plan_width(plan);
   const SweepTask& tk = tasks[blockIdx.x / G];
   const int g = uni((int)(blockIdx.x % G));
-  const int P = blockDim.x >> 6;
+  const int P = blockDim.x >> 6, w = threadIdx.x >> 6;
   const int n = uni(tk.n), N = uni(tk.N);
-  cx<T>* gl1 = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* gl2 = gl1 + n;
-  cx<T>* yt = gl2 + n;
-  cx<T>* stt = yt + 64 * P;
-  cx<T>* work = stt + 64 * (P + 1);
-  const cx<T>* img = uniptr((const cx<T>*)tk.img);
-  const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
-  gptr<cx<T>> z = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.z);
-  gptr<cx<T>> rho = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.rho);
-  gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
-  gptr<cx<T>> xch = (gptr<cx<T>>)uniptr((cx<T>*)tk.xch);
+  c64* gl1 = reinterpret_cast<c64*>(smem_raw);
+  c64* gl2 = gl1 + n;
+  c64* yt = gl2 + n;
+  c64* kb = yt + 64 * P;
+  c64* pw = kb + 64 * P;
+  c64* ring = pw + 64 * P + 640 * w;
+  const c64* img = uniptr((const c64*)tk.img);
+  const c64* trb = uniptr((const c64*)tk.tr);
+  gptr<c64> z = (gptr<c64>)uniptr((c64*)tk.ch.z);
+  gptr<c64> rho = (gptr<c64>)uniptr((c64*)tk.ch.rho);
+  gptr<c64> g1 = (gptr<c64>)uniptr((c64*)tk.ch.g1);
+  gptr<c64> xch = (gptr<c64>)uniptr((c64*)tk.xch);
   gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
   const StripDesc* strips = uniptr(tk.ch.strips);
   ChainBar bar{uniptr(tk.bar), abort, 0u, (unsigned)G, limit, &ok};
+  constexpr long long K2 = (long long)map_dim(KP) * map_dim(KP);
   for (int step = 0; step < 2 * N - 1; ++step) {
     const bool fwd = step < N;
     const int s = fwd ? step : 2 * N - 2 - step;
     const StripDesc* sp = strips + s;
-    const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
+    const int ns = uni(sp->ns), wd = uni(sp->w), kl = uni(sp->kl);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const bool use2 = has2 && !fwd;
-    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, has1 != 0, use2, fwd, fwd && g == 0,
+    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd, fwd && g == 0,
                   t1off, t2off);
     __syncthreads();
-    const float winv = 1.0f / (float)w;
-    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2, winv};
+    const float winv = 1.0f / (float)wd;
+    const SrcGather<T> gather{r, gl1, gl2, ns, wd, n, a, dir, has1 != 0, use2, winv};
     const int seg = uni(sp->pseg[plan]);
-    const long long K2 = (long long)kl * kl, tm = uni(sp->tmaps);
-    const cx<T>* GL = img + img_off;
-    const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-    const cx<T>* T0 = img + uni(sp->t_off);
-    const cx<T>* TL = T0 + uni(sp->pmap[plan]) * K2;
-    const cx<T>* WL = T0 + uni(sp->pwmap[plan]) * K2;
-    if (!solve_triangle_wide<T, KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, TL, WL, ns, kl,
-                                           seg, g, work, yt, stt, xch, bar))
+    const long long tm = uni(sp->tmaps);
+    const c64* GL = img + img_off;
+    const c64* GU = GL + blocked_blocks(ns) * KP * 64;
+    const c64* T0 = img + uni(sp->t_off);
+    const WideMaps mL{T0, uni(sp->pmap[plan]) - 1, uni(sp->pi_map), uni(sp->a1_map),
+                      uni(sp->a2_map), uni(sp->ps_map)};
+    WideMaps mU = mL;
+    mU.maps = T0 + tm * K2;
+    const c64* PL = img + uni(sp->phi_off);
+    const c64* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP));
+    if (!solve_triangle_wide<KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, mL, PL, ns, kl, seg,
+                                        g, G, ring, yt, kb, pw, xch, bar))
       return;
-    if (!chain_wait(bar)) return;
-    if (!solve_triangle_wide<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
-                                           DstScatter<T>{z, ns, w, n, a, dir, winv}, GU,
-                                           TL + tm * K2, WL + tm * K2, ns, kl, seg, g, work, yt,
-                                           stt, xch, bar))
+    if (!chain_meet(bar)) return;
+    if (!solve_triangle_wide<KP, U, NB>(SrcVec<T>{(gptr<const c64>)rho, ns, true},
+                                        DstScatter<T>{z, ns, wd, n, a, dir, winv}, GU, mU, PU, ns,
+                                        kl, seg, g, G, ring, yt, kb, pw, xch, bar))
       return;
-    if (!chain_wait(bar)) return;
+    if (!chain_meet(bar)) return;
   }
 }
 
@@ -1003,8 +1078,9 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
     const int seg = uni(sp->seg);
     const cx<T>* GL = im + ioff;
     const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
-    const cx<T>* TL = im + uni(sp->t_off) + (long long)uni(sp->pmap[0]) * kl * kl;
-    const cx<T>* TU = TL + (long long)uni(sp->tmaps) * kl * kl;
+    constexpr long long KM2 = (long long)map_dim(KP) * map_dim(KP);
+    const cx<T>* TL = im + uni(sp->t_off) + uni(sp->pmap[0]) * KM2;
+    const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
     solve_triangle<T, KP, U, NB>(in, DstVec<T>{wk, ns, false}, GL, TL, ns, kl, seg, lds, yt, stt);
     __syncthreads();
     solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true},
@@ -1050,7 +1126,7 @@ static void launch_sweep_kp(const SweepTask* d, int ntasks, int P, int kmax, int
                             hipStream_t st) {
   using Sh = SweepShape<T, KP>;
   const void* fn = (const void*)k_sweep<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB, PIV>;
-  const size_t lds = (size_t)sweep_lds_elems(P, kmax, nmax) * sizeof(cx<T>);
+  const size_t lds = (size_t)sweep_lds_elems(P, map_dim(KP), nmax) * sizeof(cx<T>);
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_sweep<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB, PIV>), dim3(ntasks), dim3(64 * P),
@@ -1096,30 +1172,32 @@ static WideDev wide_dev() {
   return d;
 }
 
-static size_t wide_lds_bytes(int precision, int P, int kmax, int nmax) {
-  const size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
-  return (size_t)sweep_lds_elems_wide(P, plan_width(HH_NPLAN - 1), kmax, nmax) * es;
+static size_t wide_lds_bytes(int P, int nmax) {
+  return (size_t)sweep_lds_elems_wide(P, nmax) * sizeof(c64);
 }
 
+// The wide plan runs complex64 strips whose maps fit two lanes per row, with
+// a wave per workgroup tail in step 3 (P >= G - 1).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax) {
-  return wide_lds_bytes(precision, P, kmax, nmax) <= 150 * 1024;
+  return precision == HH_FP32 && map_dim(blocked_kp(kmax)) <= 32 &&
+         P >= plan_width(HH_NPLAN - 1) - 1 && wide_lds_bytes(P, nmax) <= 150 * 1024;
 }
 
-int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots) {
-  if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
+int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built) {
+  if (pivots || !built || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
   const char* env = std::getenv("HH_SWEEP_PLAN");
   if (env && *env) return std::atoi(env) > 0 ? HH_NPLAN - 1 : 0;
   const int G = plan_width(HH_NPLAN - 1);
   return (long long)ntasks * G <= wide_dev().cus / 2 ? HH_NPLAN - 1 : 0;
 }
 
-template <class T, int KP>
-static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int kmax, int nmax, int plan,
+template <int KP>
+static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int nmax, int plan,
                            unsigned* abort, hipStream_t st) {
-  using Sh = SweepShape<T, KP>;
+  using Sh = SweepShape<float, KP>;
   const int G = plan_width(plan);
-  const void* fn = (const void*)k_sweep_wide<T, KP, Sh::U, Sh::NB>;
-  const size_t lds = (size_t)sweep_lds_elems_wide(P, G, kmax, nmax) * sizeof(cx<T>);
+  const void* fn = (const void*)k_sweep_wide<KP, Sh::U, Sh::NB>;
+  const size_t lds = wide_lds_bytes(P, nmax);
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   // bound of each wait: HH_SWEEP_WAIT_US microseconds when set, else 250 ms
@@ -1131,16 +1209,13 @@ static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int kmax, int 
                                     (unsigned)lds, st));
 }
 
-template <class T>
-static void launch_wide_t(const SweepTask* d, int ntasks, int KP, int P, int kmax, int nmax,
-                          int plan, unsigned* abort, hipStream_t st) {
+static void launch_wide(const SweepTask* d, int ntasks, int KP, int P, int nmax, int plan,
+                        unsigned* abort, hipStream_t st) {
   switch (KP) {
-    case 8: launch_wide_kp<T, 8>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
-    case 10: launch_wide_kp<T, 10>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
-    case 12: launch_wide_kp<T, 12>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
-    case 16: launch_wide_kp<T, 16>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
-    case 20: launch_wide_kp<T, 20>(d, ntasks, P, kmax, nmax, plan, abort, st); break;
-    default: set_error("unsupported blocked term count %d", KP); throw ArgError();
+    case 8: launch_wide_kp<8>(d, ntasks, P, nmax, plan, abort, st); break;
+    case 10: launch_wide_kp<10>(d, ntasks, P, nmax, plan, abort, st); break;
+    case 12: launch_wide_kp<12>(d, ntasks, P, nmax, plan, abort, st); break;
+    default: set_error("the wide segment plan does not take %d blocked terms", KP); throw ArgError();
   }
 }
 
@@ -1157,13 +1232,10 @@ void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, i
   }
   if (plan > 0) {
     if (!sweep_wide_fits(precision, P, kmax, nmax)) {
-      set_error("the wide segment plan does not fit the LDS");
+      set_error("the wide segment plan does not fit this factorisation");
       throw ArgError();
     }
-    if (precision == HH_FP64)
-      launch_wide_t<double>(d_tasks, ntasks, KP, P, kmax, nmax, plan, abort, st);
-    else
-      launch_wide_t<float>(d_tasks, ntasks, KP, P, kmax, nmax, plan, abort, st);
+    launch_wide(d_tasks, ntasks, KP, P, nmax, plan, abort, st);
   } else if (precision == HH_FP64) {
     launch_sweep_t<double>(d_tasks, ntasks, KP, P, kmax, nmax, pivots, st);
   } else {
@@ -1179,7 +1251,7 @@ static void launch_strip_kp(const hh_problem* pb, int si, const c128* rhs, c128*
   const FactorSet& fs = pb->fs;
   const int P = fs.strips[si].segs;
   const void* fn = (const void*)k_strip_solve<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB>;
-  const size_t lds = (size_t)sweep_lds_elems(P, fs.max_kl, 0) * sizeof(cx<T>);
+  const size_t lds = (size_t)sweep_lds_elems(P, map_dim(KP), 0) * sizeof(cx<T>);
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_strip_solve<T, Sh::D, Sh::S, KP, Sh::U, Sh::NB>), dim3(1), dim3(64 * P), lds, st,
