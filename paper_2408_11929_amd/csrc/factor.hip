@@ -247,6 +247,129 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restr
   }
 }
 
+// The same elimination by one wave with the window in registers, for
+// 2 kl + 1 <= 64 and kl < KR.  Lane l owns the physical column slot l of the
+// window of step j (logical column c = (l - c0) mod C, c0 = j mod C) and holds
+// its rows j + r in a[r], r <= kl.  A step:
+//  - lane c0 passes the pivot column through LDS so that lane r holds row r;
+//    the pivot test and the multipliers are as in k_band_lu, and the
+//    multipliers go back through LDS to every lane;
+//  - every lane swaps its rows 0 and rp when the step interchanges, stores
+//    its row-0 entry as the new row of U, and updates and shifts its rows at
+//    once: a[r-1] = a[r] - L_r a[0], which keeps every register index fixed;
+//  - the retired slot (lane c0) becomes column j + C, zero in the window but
+//    for the entering row j + kl + 1.
+// The registers past the window (r = kl+1 .. KR-1, whose multipliers are
+// zero) carry the entering rows of the next steps: the row entering at step
+// j + D, D = KR - 1 - kl, is put in a[KR-1] at step j and reaches a[kl]
+// when it enters, so no register is chosen by kl.  Entering rows are read
+// one chunk of CH steps ahead and pass through LDS.
+template <class T, int KR, int CH>
+__global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ strips,
+                                                  cx<T>* __restrict__ band,
+                                                  int* __restrict__ pivbuf, int* err,
+                                                  int* __restrict__ pflag) {
+  __shared__ cx<T> colb[64];      // pivot column, lane r = row r
+  __shared__ cx<T> lbuf[64];      // multipliers
+  __shared__ cx<T> ebuf[CH][64];  // entering rows of the current chunk
+  __shared__ cx<T> xbuf[KR][64];  // the window, for an interchange
+  const StripDesc sd = strips[blockIdx.x];
+  const int kl = sd.kl, kv = 2 * kl, C = kv + 1, ldab = sd.ldab, ns = sd.ns;
+  const int D = KR - 1 - kl;
+  cx<T>* ab = band + sd.band_off;
+  int* piv = pivbuf + sd.piv_off;
+  const int lane = threadIdx.x;
+  const cx<T> zero = mk((T)0, (T)0);
+  auto wrap = [](int x, int m) { return x >= m ? x - m : x; };
+  // entering row of step j (row j+kl+1) in this lane's slot, whose logical
+  // column after the step is (lane - c0 - 1) mod C (clamped load, then a select)
+  auto fetch = [&](int j) -> cx<T> {
+    const int i = j + kl + 1, c0j = j % C;
+    int cl = lane - c0j - 1;
+    cl = cl < 0 ? cl + C : cl;
+    const int col = j + 1 + cl;
+    const bool in = lane < C && i < ns && col < ns;
+    const cx<T> v = ab[in ? (long long)col * ldab + kv + i - col : 0];
+    return csel(in, v, zero);
+  };
+  cx<T> a[KR];
+#pragma unroll
+  for (int r = 0; r < KR; ++r) {
+    // rows of the first window, then the entering rows of steps 0 .. D-1
+    const bool in = lane < C && r <= kl && r < ns && lane < ns && r - lane <= kl && lane - r <= kl;
+    const cx<T> v = ab[in ? (long long)lane * ldab + kv + r - lane : 0];
+    a[r] = r <= kl ? csel(in, v, zero) : fetch(r - kl - 1);
+  }
+  cx<T> nxt[CH];
+#pragma unroll
+  for (int u = 0; u < CH; ++u) nxt[u] = fetch(D + u);
+  int c0 = 0;
+  for (int jc = 0; jc < ns; jc += CH) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) ebuf[u][lane] = nxt[u];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) nxt[u] = fetch(jc + CH + D + u);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int j = jc + u;
+      if (j >= ns) break;
+      const int rmax = min(kl, ns - 1 - j);
+      const cx<T> ein = ebuf[u][lane];  // enters a[KR-1] after this step
+      if (lane == c0) {
+#pragma unroll
+        for (int r = 0; r < KR; ++r) colb[r] = a[r];
+      }
+      const cx<T> val = csel(lane <= kl, colb[lane <= kl ? lane : 0], zero);
+      const T av = lane <= rmax ? cabs1(val) : (T)-1;
+      const T ad = rdl(av, 0);
+      int rp = 0;
+      if (__ballot(av > ad)) {  // a real interchange (rare): first index of the maximum
+        T v = av;
+        int idx = lane <= rmax ? lane : 64;
+        wave_argmax(v, idx);
+        rp = __builtin_amdgcn_readfirstlane(idx);
+      }
+      const cx<T> pv = rdlc(val, rp);
+      const T pd = pv.re * pv.re + pv.im * pv.im;
+      const bool singular = pd == (T)0;
+      const T ipd = singular ? (T)0 : (T)1 / pd;
+      const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
+      const cx<T> v0 = rdlc(val, 0);
+      const cx<T> Lr = csel(lane >= 1 && lane <= rmax, csel(lane == rp, v0, val) * ipv, zero);
+      lbuf[lane] = Lr;
+      if (lane == 0) {
+        piv[j] = j + rp;
+        if (rp != 0) pflag[blockIdx.x] = 1;
+        if (singular) atomicCAS(err, 0, (int)blockIdx.x + 1);
+      }
+      if (lane >= 1 && lane <= rmax) ab[(long long)j * ldab + kv + lane] = Lr;
+      if (rp != 0) {  // interchange rows 0 and rp in every column (rare), through LDS
+#pragma unroll
+        for (int r = 0; r < KR; ++r) xbuf[r][lane] = a[r];
+        const cx<T> t = xbuf[rp][lane];
+        xbuf[rp][lane] = xbuf[0][lane];
+        xbuf[0][lane] = t;
+#pragma unroll
+        for (int r = 0; r < KR; ++r) a[r] = xbuf[r][lane];
+      }
+      const cx<T> u0 = a[0];
+      {
+        int c = lane - c0;
+        c = c < 0 ? c + C : c;
+        if (lane < C && j + c < ns) ab[(long long)(j + c) * ldab + kv - c] = u0;
+      }
+      const bool ret = lane == c0;
+#pragma unroll
+      for (int r = 1; r < KR; ++r) {
+        const cx<T> v = cfms(a[r], lbuf[r], u0);
+        a[r - 1] = csel(ret && r - 1 < kl, zero, v);
+      }
+      a[KR - 1] = ein;
+      c0 = wrap(c0 + 1, C);
+    }
+  }
+}
+
 // Solve image of every strip (layout above).  grid = (NP*64 / 256, strips).
 template <class T>
 __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>* __restrict__ band,
@@ -648,9 +771,26 @@ static void launch_products(const FactorSet& fs, hipStream_t st) {
 }
 
 // One or two column slots per lane: 2 kl + 1 <= 64 needs one.
+// One wave with the window in registers where the band allows it (kl < KR),
+// else the LDS window on four waves (one or two column slots per lane).
+template <class T, int KR>
+static void launch_lu_w(const FactorSet& fs, hipStream_t st) {
+  constexpr int CH = sizeof(T) == 8 ? 8 : 16;
+  hipLaunchKernelGGL((k_band_lu_w<T, KR, CH>), dim3((unsigned)fs.strips.size()), dim3(64), 0, st,
+                     fs.d_strips, (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+}
+
 template <class T>
 static void launch_lu(const FactorSet& fs, size_t lds, hipStream_t st) {
   const int nstr = (int)fs.strips.size();
+  const int kl = fs.max_kl;
+  if (kl < 8) return launch_lu_w<T, 8>(fs, st);
+  if (kl < 12) return launch_lu_w<T, 12>(fs, st);
+  if (kl < 16) return launch_lu_w<T, 16>(fs, st);
+  if (kl < 20) return launch_lu_w<T, 20>(fs, st);
+  if (kl < 24) return launch_lu_w<T, 24>(fs, st);
+  if (kl < 28) return launch_lu_w<T, 28>(fs, st);
+  if (kl < 32) return launch_lu_w<T, 32>(fs, st);
   const bool one = 2 * fs.max_kl + 1 <= 64;
   const void* fn = one ? (const void*)k_band_lu<T, 1> : (const void*)k_band_lu<T, 2>;
   HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
