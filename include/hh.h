@@ -108,9 +108,10 @@ int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision);
  * HH_FP32 factors, r is rounded to complex64 and z holds the complex64 result
  * exactly.  dir is HH_DIR_X or HH_DIR_Y (must have been factored).
  * Each vector is one sweep chain.  Few chains (at most half the compute units
- * at eight workgroups each), none of whose strips pivoted, run on eight
- * workgroups per chain that meet four times per strip solve; the environment
- * variable HH_SWEEP_PLAN=0/1 forces one or eight (where possible), and
+ * at sixteen workgroups each) of complex64 strips none of which pivoted run on
+ * sixteen workgroups per chain that meet four times per strip solve; the
+ * environment variable HH_SWEEP_PLAN=0/1 forces one or sixteen (where
+ * possible), and
  * HH_SWEEP_WAIT_US bounds each meeting (default 250000): a chain whose
  * workgroups do not meet in time stops, and the call returns HH_EDEVICE. */
 int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_c128* z);
@@ -149,7 +150,7 @@ int hh_get_operator(const hh_problem* pb, hh_c128* diag);
  *   tol        > 0;  maxit >= 1
  *   stats      host pointer to nrhs hh_stats (may be NULL)
  * The sweeps of every RHS and direction run in one launch per iteration, one
- * chain each, on one or eight workgroups per chain as in hh_sweep_apply.
+ * chain each, on one or sixteen workgroups per chain as in hh_sweep_apply.
  * Returns HH_ENOCONV (x and stats still filled) if any RHS did not converge. */
 int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit,
                hh_c128* x, hh_stats* stats);

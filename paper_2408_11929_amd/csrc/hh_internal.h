@@ -262,7 +262,7 @@ struct SweepTask {
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
                   int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st);
 // Whether the wide plan can run a factorisation (complex64 strips, band
-// half-width at most 31, eight segments per workgroup, LDS).
+// half-width at most 31, at most two workgroup tails per wave, LDS).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
 // Plan for a launch of ntasks chains: plan 0 where some strip pivoted, the
 // wide plan's maps were not built (built = false) or it cannot run, else the
@@ -292,7 +292,7 @@ __host__ __device__ inline int segment_rows(int ns, int P) {
 // 16-row aligned segments.  Either way a segment is at least K rows long, so
 // that a segment's state (the K outputs before it) lies in the segment before
 // it, and every segment after the first starts at row K or later.
-__host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : 8; }
+__host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : 16; }
 __host__ __device__ inline int plan_seg(int ns, int P, int p, int K) {
   if (p == 0) return segment_rows(ns, P);
   const int S = plan_width(p) * P, per = (ns + S - 1) / S, least = (K + 15) / 16 * 16;

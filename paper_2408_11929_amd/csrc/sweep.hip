@@ -96,6 +96,38 @@ __device__ __forceinline__ cx<T> sel(bool c, cx<T> a, cx<T> b) {
   return mk(c ? a.re : b.re, c ? a.im : b.im);
 }
 
+// Access policies for vectors that workgroups of one chain share.  Plain:
+// ordinary loads and stores (one workgroup per chain).  Agent: complex64
+// loads and stores coherent at agent scope (relaxed atomics, one 64-bit
+// access each), so that a store is visible to every other workgroup once it
+// has completed and a load never returns a line cached before: the meetings
+// of a chain then order them with a wait for the stores and the arrival
+// counter alone, without writing back or invalidating the L2 caches.
+struct PlainAcc {
+  template <class T>
+  static __device__ __forceinline__ cx<T> load(gptr<const cx<T>> p, long long i) {
+    return ld<T>(p, i);
+  }
+  template <class T>
+  static __device__ __forceinline__ void store(gptr<cx<T>> p, long long i, cx<T> v) {
+    st<T>(p, i, v);
+  }
+};
+struct AgentAcc {
+  using u64g = unsigned long long __attribute__((address_space(1)))*;
+  using cu64g = const unsigned long long __attribute__((address_space(1)))*;
+  static __device__ __forceinline__ c64 load(gptr<const c64> p, long long i) {
+    const unsigned long long b =
+        __hip_atomic_load((cu64g)(p + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return mk(__uint_as_float((unsigned)b), __uint_as_float((unsigned)(b >> 32)));
+  }
+  static __device__ __forceinline__ void store(gptr<c64> p, long long i, c64 v) {
+    const unsigned long long b =
+        ((unsigned long long)__float_as_uint(v.im) << 32) | __float_as_uint(v.re);
+    __hip_atomic_store((u64g)(p + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
 // Forward substitution with the row interchanges of partial pivoting for C
 // chains: y = L^{-1} P b in place on x[c][0..ns).  Lm: solve-image rows
 // (64 per step, padded), piv: padded pivot lists.  ns is wave-uniform and
@@ -403,7 +435,7 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
 }
 
 // g = sum_d coef_d z[p + off_d] on interface node (i, j) = p.
-template <class T>
+template <class T, class A = PlainAcc>
 __device__ __forceinline__ cx<T> transmission(gptr<const cx<T>> coef, gptr<cx<T>> z, int i, int j,
                                               int n) {
   const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
@@ -413,7 +445,7 @@ __device__ __forceinline__ cx<T> transmission(gptr<const cx<T>> coef, gptr<cx<T>
   for (int d = 0; d < 7; ++d) {
     const int ii = i + di[d], jj = j + dj[d];
     if (ii < 0 || ii >= n || jj < 0 || jj >= n) continue;
-    g = g + ld<T>(coef, d) * ld<T>(z, (long long)jj * n + ii);
+    g = g + ld<T>(coef, d) * A::load((gptr<const cx<T>>)z, (long long)jj * n + ii);
   }
   return g;
 }
@@ -435,7 +467,7 @@ __device__ __forceinline__ void line_of(int q, int w, float winv, int& l, int& t
 // Streams of the blocked substitution.  load(i) issues the memory reads of
 // row i (clamped to the last row) and returns them raw; get() forms the value
 // when the row enters the ring, one step later.
-template <class T>
+template <class T, class A = PlainAcc>
 struct SrcVec {  // x[i] (rev: x[ns-1-i]) in the working precision
   gptr<const cx<T>> x;
   int ns;
@@ -443,7 +475,7 @@ struct SrcVec {  // x[i] (rev: x[ns-1-i]) in the working precision
   using P = cx<T>;
   __device__ P load(int i) const {
     i = i < ns ? i : ns - 1;
-    return ld<T>(x, rev ? ns - 1 - i : i);
+    return A::load(x, rev ? ns - 1 - i : i);
   }
   __device__ cx<T> get(const P& v) const { return v; }
 };
@@ -493,13 +525,13 @@ struct SrcGather {
     return o.f1 ? v + o.e1 : (o.f2 ? v + o.e2 : v);
   }
 };
-template <class T>
+template <class T, class A = PlainAcc>
 struct DstVec {  // x[i] (rev: x[ns-1-i])
   gptr<cx<T>> x;
   int ns;
   bool rev;
-  __device__ void put(int i, cx<T> v) const { st<T>(x, rev ? ns - 1 - i : i, v); }
-  __device__ cx<T> get(int i) const { return ld<T>(x, rev ? ns - 1 - i : i); }
+  __device__ void put(int i, cx<T> v) const { A::store(x, rev ? ns - 1 - i : i, v); }
+  __device__ cx<T> get(int i) const { return A::load((gptr<const cx<T>>)x, rev ? ns - 1 - i : i); }
 };
 template <class T>
 struct DstC128 {  // strip-local FP64 output, reversed order
@@ -513,7 +545,7 @@ struct DstC128 {  // strip-local FP64 output, reversed order
 };
 // Scatter of the strip solution over the global vector, reversed order (the
 // back substitution produces the last local row first).
-template <class T>
+template <class T, class A = PlainAcc>
 struct DstScatter {
   gptr<cx<T>> z;
   int ns, w, n, a, dir;
@@ -524,8 +556,8 @@ struct DstScatter {
     line_of(q, w, winv, l, t);
     return dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
   }
-  __device__ void put(int i, cx<T> v) const { st<T>(z, pos(i), v); }
-  __device__ cx<T> get(int i) const { return ld<T>(z, pos(i)); }
+  __device__ void put(int i, cx<T> v) const { A::store(z, pos(i), v); }
+  __device__ cx<T> get(int i) const { return A::load((gptr<const cx<T>>)z, pos(i)); }
 };
 
 // Segment views for the parallel substitution: rows off..off+len-1 of a
@@ -649,7 +681,7 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
 // formed from the current z and, if keep, stored to g1 for the backward
 // pass; backward: the stored data), gl2 = Gamma_{s,2} data from the current z
 // where use2.
-template <class T>
+template <class T, class A = PlainAcc>
 __device__ __forceinline__ void strip_data(cx<T>* gl1, cx<T>* gl2, gptr<cx<T>> z, gptr<cx<T>> g1,
                                            const cx<T>* trb, int s, int n, int a, int w, int dir,
                                            bool has1, bool use2, bool fwd, bool keep,
@@ -660,16 +692,16 @@ __device__ __forceinline__ void strip_data(cx<T>* gl1, cx<T>* gl2, gptr<cx<T>> z
     if (has1) {
       if (fwd) {
         const int i = dir == 0 ? a : l, j = dir == 0 ? l : a;
-        e1 = transmission<T>((gptr<const cx<T>>)(trb + t1off + 7LL * l), z, i, j, n);
-        if (keep) st<T>(g1, (long long)s * n + l, e1);
+        e1 = transmission<T, A>((gptr<const cx<T>>)(trb + t1off + 7LL * l), z, i, j, n);
+        if (keep) A::store(g1, (long long)s * n + l, e1);
       } else {
-        e1 = ld<T>(g1, (long long)s * n + l);
+        e1 = A::load((gptr<const cx<T>>)g1, (long long)s * n + l);
       }
     }
     if (use2) {
       const int at = a + w - 1;
       const int i = dir == 0 ? at : l, j = dir == 0 ? l : at;
-      e2 = transmission<T>((gptr<const cx<T>>)(trb + t2off + 7LL * l), z, i, j, n);
+      e2 = transmission<T, A>((gptr<const cx<T>>)(trb + t2off + 7LL * l), z, i, j, n);
     }
     gl1[l] = e1;
     gl2[l] = e2;
@@ -782,13 +814,14 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
 // transmission data read the solution), so a strip solve is four meetings.
 
 // Meeting of the G workgroups of one chain, in two halves so that work can
-// go between them.  chain_arrive: every wave makes its global writes visible
-// at agent scope, the workgroup synchronises and thread 0 counts it in.
-// chain_wait: thread 0 waits until all G have arrived.  The wait is bounded:
-// after `limit` ticks of the constant-rate clock, or as soon as another
-// workgroup has given up, thread 0 raises *abort and gives up.  After the
-// workgroup barrier every wave acquires at agent scope.  Returns false once
-// the chain is aborted, the same answer in every thread.
+// go between them.  Everything the workgroups exchange goes through AgentAcc
+// (agent-coherent loads and stores).  chain_arrive: every wave waits until
+// its stores have completed, the workgroup synchronises and thread 0 counts
+// it in.  chain_wait: thread 0 waits until all G have arrived, then the
+// workgroup synchronises.  The wait is bounded: after `limit` ticks of the
+// constant-rate clock, or as soon as another workgroup has given up, thread 0
+// raises *abort and gives up.  Returns false once the chain is aborted, the
+// same answer in every thread.
 struct ChainBar {
   unsigned* cnt;    // arrivals so far (zero at launch)
   unsigned* abort;  // raised by a workgroup that gave up
@@ -799,7 +832,7 @@ struct ChainBar {
 };
 
 __device__ __forceinline__ void chain_arrive(ChainBar& b) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);  // every memory access of this wave has completed
   __syncthreads();
   b.need += b.G;
   if (threadIdx.x == 0)
@@ -822,7 +855,6 @@ __device__ __forceinline__ bool chain_wait(ChainBar& b) {
     *b.ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *b.ok != 0;
 }
 
@@ -918,12 +950,14 @@ __device__ __forceinline__ bool solve_triangle_wide(const Src& src, const Dst& d
     __syncthreads();
   }
   kb[64 * w + lane] = b;  // zero-start state after segment c
-  if (w == P - 1 && g < gu - 1 && lane < K) st<T>(xch, (long long)g * 64 + lane, b);
+  if (w == P - 1 && g < gu - 1 && lane < K) AgentAcc::store(xch, (long long)g * 64 + lane, b);
   chain_arrive(bar);
   // maps of step 3 and the first rows of the correction, read while waiting
-  MapRow<T, KM> PI, PS;
+  // wave w takes the tails of workgroups w and w + P (G - 1 <= 2 P)
+  MapRow<T, KM> PI, PS0, PS1;
   if (g >= 1 && w >= 1 && c <= nseg - 1) map_row_load(PI, mslot(mp.pi + c - 1), lane);
-  if (g >= 2 && w <= g - 2) map_row_load(PS, mslot(mp.ps + g * Gw + w), lane);
+  if (g >= 2 && w <= g - 2) map_row_load(PS0, mslot(mp.ps + g * Gw + w), lane);
+  if (g >= 2 && w + P <= g - 2) map_row_load(PS1, mslot(mp.ps + g * Gw + w + P), lane);
   const bool corr = c >= 1 && c < nseg;
   gptr<const c64> Ph = (gptr<const c64>)(Phi + (long long)(corr ? c - 1 : 0) * seg * KM);
   c64 ph0[KM];
@@ -939,17 +973,32 @@ __device__ __forceinline__ bool solve_triangle_wide(const Src& src, const Dst& d
     if (w >= 1 && c < nseg) s = kb[64 * (w - 1) + lane];
   } else if (g < gu) {
     if (w < g) {
-      const c64 t = lane < K ? ld<T>(xch, (long long)w * 64 + lane) : zero;
-      c64 v = t;
-      if (w <= g - 2) {
-        yt[64 * w + lane] = t;
-        v = map_apply_r(PS, yt + 64 * w, zero, K, lane);
+      c64 t[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int j = w + P * k;
+        t[k] = csel(lane < K && j < g,
+                    AgentAcc::load((gptr<const c64>)xch, (long long)(j < g ? j : 0) * 64 + lane),
+                    zero);
+      }
+      c64 v = zero;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int j = w + P * k;
+        if (j < g) {
+          c64 vj = t[k];
+          if (j <= g - 2) {
+            yt[64 * w + lane] = t[k];
+            vj = map_apply_r(k == 0 ? PS0 : PS1, yt + 64 * w, zero, K, lane);
+          }
+          v = v + vj;
+        }
       }
       pw[64 * w + lane] = v;
     }
     __syncthreads();
     c64 S = zero;
-    for (int j = 0; j < g; ++j) S = S + pw[64 * j + lane];
+    for (int j = 0; j < (g < P ? g : P); ++j) S = S + pw[64 * j + lane];
     if (w == 0) {
       s = S;
     } else if (c < nseg) {
@@ -1023,8 +1072,8 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     const long long img_off = uni(sp->img_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const bool use2 = has2 && !fwd;
-    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd, fwd && g == 0,
-                  t1off, t2off);
+    strip_data<T, AgentAcc>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd,
+                            fwd && g == 0, t1off, t2off);
     __syncthreads();
     const float winv = 1.0f / (float)wd;
     const SrcGather<T> gather{r, gl1, gl2, ns, wd, n, a, dir, has1 != 0, use2, winv};
@@ -1039,13 +1088,13 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     mU.maps = T0 + tm * K2;
     const c64* PL = img + uni(sp->phi_off);
     const c64* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP));
-    if (!solve_triangle_wide<KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, mL, PL, ns, kl, seg,
-                                        g, G, ring, yt, kb, pw, xch, bar))
+    if (!solve_triangle_wide<KP, U, NB>(gather, DstVec<T, AgentAcc>{rho, ns, false}, GL, mL, PL,
+                                        ns, kl, seg, g, G, ring, yt, kb, pw, xch, bar))
       return;
     if (!chain_meet(bar)) return;
-    if (!solve_triangle_wide<KP, U, NB>(SrcVec<T>{(gptr<const c64>)rho, ns, true},
-                                        DstScatter<T>{z, ns, wd, n, a, dir, winv}, GU, mU, PU, ns,
-                                        kl, seg, g, G, ring, yt, kb, pw, xch, bar))
+    if (!solve_triangle_wide<KP, U, NB>(SrcVec<T, AgentAcc>{(gptr<const c64>)rho, ns, true},
+                                        DstScatter<T, AgentAcc>{z, ns, wd, n, a, dir, winv}, GU,
+                                        mU, PU, ns, kl, seg, g, G, ring, yt, kb, pw, xch, bar))
       return;
     if (!chain_meet(bar)) return;
   }
@@ -1177,10 +1226,10 @@ static size_t wide_lds_bytes(int P, int nmax) {
 }
 
 // The wide plan runs complex64 strips whose maps fit two lanes per row, with
-// a wave per workgroup tail in step 3 (P >= G - 1).
+// at most two workgroup tails per wave in step 3 (G - 1 <= 2 P).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax) {
   return precision == HH_FP32 && map_dim(blocked_kp(kmax)) <= 32 &&
-         P >= plan_width(HH_NPLAN - 1) - 1 && wide_lds_bytes(P, nmax) <= 150 * 1024;
+         plan_width(HH_NPLAN - 1) - 1 <= 2 * P && wide_lds_bytes(P, nmax) <= 150 * 1024;
 }
 
 int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built) {
