@@ -338,10 +338,47 @@ __device__ __forceinline__ double sum4c(double re, double im) {
 // the LDS accesses of one wave are performed in order, no barrier is needed.
 // Rows are read through src and written through dst (lanes past the end
 // write row ns-1 again, with the same value, so the write needs no branch).
+//
+// The reads that start the recurrence (the first 128 input rows, the inputs
+// and maps of the first NB - 1 steps) can be issued ahead, into a
+// BlockedPre, by blocked_fetch_maps and blocked_fetch_inputs; solve_blocked
+// issues them itself, solve_blocked_run takes them prefetched.
+template <class T, int KP, int U, int NB, class Src>
+struct BlockedPre {
+  typename Src::P in0, in1;  // rows lane and 64 + lane
+  typename Src::P pend[NB];  // pend[j % NB]: input rows jR + 128 + lane until step j
+  cx<T> g[NB][U][KP];
+  gptr<const cx<T>> gp;      // maps of the next step to request
+};
+
+template <class T, int KP, int U, int NB, class Src>
+__device__ __forceinline__ void blocked_fetch_maps(BlockedPre<T, KP, U, NB, Src>& pre,
+                                                   gptr<const cx<T>> G, int lane) {
+  pre.gp = G + lane;
+#pragma unroll
+  for (int b = 0; b + 1 < NB; ++b) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < KP; ++t) pre.g[b][u][t] = ld<T>(pre.gp, (long long)(u * KP + t) * 64);
+    pre.gp = pre.gp + (long long)U * KP * 64;
+  }
+}
+
+template <class T, int KP, int U, int NB, class Src>
+__device__ __forceinline__ void blocked_fetch_inputs(BlockedPre<T, KP, U, NB, Src>& pre,
+                                                     const Src& src, int lane) {
+  constexpr int R = U * 16;
+  pre.in0 = src.load(lane);
+  pre.in1 = src.load(64 + lane);
+#pragma unroll
+  for (int b = 0; b + 1 < NB; ++b) pre.pend[b] = src.load(b * R + 128 + lane);
+}
+
 template <class T, int KP, int U, int NB, class Src, class Dst>
-__device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gptr<const cx<T>> G,
-                                              int ns, int K, cx<T>* ring, const cx<T>* init,
-                                              int lane) {
+__device__ __forceinline__ void solve_blocked_run(BlockedPre<T, KP, U, NB, Src>& pre,
+                                                  const Src& src, const Dst& dst, int ns, int K,
+                                                  cx<T>* ring, const cx<T>* init, int lane) {
   static_assert(HH_BLK == 16 && KP >= 8, "four lane groups of 16 rows, four chain terms each");
   constexpr int R = U * 16, KO = KP - 8;
   static_assert(R <= 64 && 64 % R == 0 && NB >= 2, "a step divides 64 rows");
@@ -364,21 +401,11 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
 #pragma unroll
   for (int q = 0; q < 10; ++q) ring[64 * q + lane] = zero;
   if (init && lane < K) put(oring, lane - K, init[lane]);
-  put(iring, lane, src.get(src.load(lane)));
-  put(iring, 64 + lane, src.get(src.load(64 + lane)));
-  // pend[j % NB] holds input rows jR + 128 + lane until step j commits them
-  typename Src::P pend[NB];
-  cx<T> g[NB][U][KP];
-  gptr<const cx<T>> gp = G + lane;
-#pragma unroll
-  for (int b = 0; b + 1 < NB; ++b) {
-    pend[b] = src.load(b * R + 128 + lane);
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int t = 0; t < KP; ++t) g[b][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
-    gp = gp + (long long)U * KP * 64;
-  }
+  put(iring, lane, src.get(pre.in0));
+  put(iring, 64 + lane, src.get(pre.in1));
+  auto& pend = pre.pend;
+  auto& g = pre.g;
+  auto& gp = pre.gp;
   // terms of block i0 that do not involve the outputs of the block before it
   auto rest = [&](const cx<T>(&gb)[KP], int i0) -> cx<T> {
     const cx<T>* in = iring + ((i0 + 4 * p) & 255);
@@ -432,6 +459,16 @@ __device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gp
   }
   const int q = (nst - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
   dst.put(qs, oring[qs & 255]);
+}
+
+template <class T, int KP, int U, int NB, class Src, class Dst>
+__device__ __forceinline__ void solve_blocked(const Src& src, const Dst& dst, gptr<const cx<T>> G,
+                                              int ns, int K, cx<T>* ring, const cx<T>* init,
+                                              int lane) {
+  BlockedPre<T, KP, U, NB, Src> pre;
+  blocked_fetch_inputs(pre, src, lane);
+  blocked_fetch_maps(pre, G, lane);
+  solve_blocked_run(pre, src, dst, ns, K, ring, init, lane);
 }
 
 // g = sum_d coef_d z[p + off_d] on interface node (i, j) = p.
@@ -503,10 +540,12 @@ struct SrcGather {
   bool use1, use2;
   struct P {
     c128 v;
-    cx<T> e1, e2;
+    int l;
     bool f1, f2;
   };
   float winv;  // 1 / w
+  // the global read is issued at load, the transmission data (LDS) are read
+  // at get, so that loads may run ahead of the transmission data
   __device__ P load(int i) const {
     const int q = i < ns ? i : ns - 1;
     int l, t;
@@ -514,15 +553,15 @@ struct SrcGather {
     const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
     P o;
     o.v = mk(r[p].re, r[p].im);
-    o.e1 = gl1[l];
-    o.e2 = gl2[l];
+    o.l = l;
     o.f1 = use1 && t == 0;
     o.f2 = use2 && t == w - 1;
     return o;
   }
   __device__ cx<T> get(const P& o) const {
     const cx<T> v = mk((T)o.v.re, (T)o.v.im);
-    return o.f1 ? v + o.e1 : (o.f2 ? v + o.e2 : v);
+    const cx<T> e = csel(o.f1, gl1[o.l], gl2[o.l]);
+    return o.f1 || o.f2 ? v + e : v;
   }
 };
 template <class T, class A = PlainAcc>
@@ -904,17 +943,17 @@ struct WideMaps {
 };
 
 // One triangular substitution of a strip by workgroup g of the chain's G
-// (steps 1-4 above).  Phi: the segment responses (plan_phi_elems layout),
+// (steps 1-4 above), after between() (see step 1).  Phi: the segment
+// responses (plan_phi_elems layout),
 // xch: exchange area (64 entries per workgroup).  LDS: the wave's ring (640
 // entries from ring), yt, kb, pw (64 entries per wave each: tails and
 // states, scan exchange, partial sums).  Returns false when the chain was
 // aborted.
-template <int KP, int U, int NB, class Src, class Dst>
-__device__ __forceinline__ bool solve_triangle_wide(const Src& src, const Dst& dst,
-                                                    const c64* G, const WideMaps& mp,
-                                                    const c64* Phi, int ns, int K, int seg, int g,
-                                                    int Gw, c64* ring, c64* yt, c64* kb, c64* pw,
-                                                    gptr<c64> xch, ChainBar& bar) {
+template <int KP, int U, int NB, bool EARLY_INPUTS, class Src, class Dst, class Between>
+__device__ __forceinline__ bool solve_triangle_wide(
+    const Src& src, const Dst& dst, const c64* G, const Between& between,
+    const WideMaps& mp, const c64* Phi, int ns, int K, int seg, int g, int Gw, c64* ring, c64* yt,
+    c64* kb, c64* pw, gptr<c64> xch, ChainBar& bar) {
   using T = float;
   constexpr int KM = map_dim(KP);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, P = blockDim.x >> 6;
@@ -924,11 +963,20 @@ __device__ __forceinline__ bool solve_triangle_wide(const Src& src, const Dst& d
   const int off = c * seg, len = c < nseg ? (ns - off < seg ? ns - off : seg) : 0;
   const SegDst<T, Dst> out{dst, off};
   auto mslot = [&](int s) { return mp.maps + (long long)s * KM * KM; };
-  // 1. zero-start solve
+  // 1. zero-start solve.  Its first reads go out before between() runs (the
+  // caller's work that the triangle waits for: the maps always, the inputs
+  // when they do not depend on that work), so that their round trip overlaps
+  // it.
+  const SegSrc<Src> ssrc{src, off, len};
+  BlockedPre<T, KP, U, NB, SegSrc<Src>> pre;
   if (c < nseg) {
-    gptr<const c64> Gs = (gptr<const c64>)(G + (long long)(off / 16) * KP * 64);
-    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, out, Gs, len, K, ring,
-                                (const c64*)nullptr, lane);
+    blocked_fetch_maps(pre, (gptr<const c64>)(G + (long long)(off / 16) * KP * 64), lane);
+    if (EARLY_INPUTS) blocked_fetch_inputs(pre, ssrc, lane);
+  }
+  if (!between()) return false;
+  if (c < nseg) {
+    if (!EARLY_INPUTS) blocked_fetch_inputs(pre, ssrc, lane);
+    solve_blocked_run(pre, ssrc, out, len, K, ring, (const c64*)nullptr, lane);
     if (c < nseg - 1 && lane < K) yt[64 * w + lane] = ring[(len - K + lane) & 255];
   }
   if (nseg == 1) return true;
@@ -1045,7 +1093,7 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
   const int G = plan_width(plan);
   const SweepTask& tk = tasks[blockIdx.x / G];
   const int g = uni((int)(blockIdx.x % G));
-  const int P = blockDim.x >> 6, w = threadIdx.x >> 6;
+  const int P = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = uni(tk.n), N = uni(tk.N);
   c64* gl1 = reinterpret_cast<c64*>(smem_raw);
   c64* gl2 = gl1 + n;
@@ -1072,9 +1120,6 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     const long long img_off = uni(sp->img_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const bool use2 = has2 && !fwd;
-    strip_data<T, AgentAcc>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd,
-                            fwd && g == 0, t1off, t2off);
-    __syncthreads();
     const float winv = 1.0f / (float)wd;
     const SrcGather<T> gather{r, gl1, gl2, ns, wd, n, a, dir, has1 != 0, use2, winv};
     const int seg = uni(sp->pseg[plan]);
@@ -1088,13 +1133,25 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     mU.maps = T0 + tm * K2;
     const c64* PL = img + uni(sp->phi_off);
     const c64* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP));
-    if (!solve_triangle_wide<KP, U, NB>(gather, DstVec<T, AgentAcc>{rho, ns, false}, GL, mL, PL,
-                                        ns, kl, seg, g, G, ring, yt, kb, pw, xch, bar))
+    // forward substitution: the transmission data are formed while its
+    // first reads are out
+    auto form_data = [&]() {
+      strip_data<T, AgentAcc>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd,
+                              fwd && g == 0, t1off, t2off);
+      __syncthreads();
+      return true;
+    };
+    if (!solve_triangle_wide<KP, U, NB, true>(gather, DstVec<T, AgentAcc>{rho, ns, false}, GL,
+                                              form_data, mL, PL, ns, kl, seg, g, G, ring, yt, kb,
+                                              pw, xch, bar))
       return;
-    if (!chain_meet(bar)) return;
-    if (!solve_triangle_wide<KP, U, NB>(SrcVec<T, AgentAcc>{(gptr<const c64>)rho, ns, true},
-                                        DstScatter<T, AgentAcc>{z, ns, wd, n, a, dir, winv}, GU,
-                                        mU, PU, ns, kl, seg, g, G, ring, yt, kb, pw, xch, bar))
+    // back substitution: its inputs were written by every workgroup, so they
+    // are read after the meeting; its maps while the workgroups meet
+    auto meet = [&]() { return chain_meet(bar); };
+    if (!solve_triangle_wide<KP, U, NB, false>(SrcVec<T, AgentAcc>{(gptr<const c64>)rho, ns, true},
+                                               DstScatter<T, AgentAcc>{z, ns, wd, n, a, dir, winv},
+                                               GU, meet, mU, PU, ns, kl, seg, g, G, ring, yt, kb,
+                                               pw, xch, bar))
       return;
     if (!chain_meet(bar)) return;
   }
