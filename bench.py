@@ -269,7 +269,7 @@ def main():
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in
                                (("sweep", sweep), ("spmv", spmv), ("factor", factor),
                                 ("orth", orth))},
-        "roofline": {"kernel": "k_sweep_wide (double sweep, eight workgroups per chain, "
+        "roofline": {"kernel": "k_sweep_wide (double sweep, sixteen workgroups per chain, "
                                "complex64)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
