@@ -10,6 +10,8 @@
 // h^2/24 [[2,1,1],[1,2,1],[1,1,2]]; an edge of length h carries the impedance
 // form -i k h/6 [[2,1],[1,2]].  A node couples to the 7-point "/" stencil
 // (offsets 0, +-1, +-n, +-(n+1)).
+#include <cstdlib>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -129,10 +131,13 @@ __global__ void k_load_vector(int n, int nvec, const c128* __restrict__ f, c128*
 // Fill the band storage of every strip: element (q, q') of A_s at column q',
 // position kv + q - q' (kv = 2 kl), and the transmission stencils
 // (A_s - A) on the interface rows.  grid.y = strip index.
+// With redo given, only the strips marked 2 there are packed, and their
+// transmission stencils (unchanged) are left alone.
 template <class T>
 __global__ void k_pack_strips(int n, double omega, int L, const double* __restrict__ c,
                               const StripDesc* __restrict__ strips, cx<T>* __restrict__ band,
-                              cx<T>* __restrict__ tr) {
+                              cx<T>* __restrict__ tr, const int* __restrict__ redo) {
+  if (redo && redo[blockIdx.y] != 2) return;
   const StripDesc sd = strips[blockIdx.y];
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= sd.ns) return;
@@ -157,13 +162,26 @@ __global__ void k_pack_strips(int n, double omega, int L, const double* __restri
     int qq = sd.dir == 0 ? jj * sd.w + (ii - sd.a) : ii * sd.w + (jj - sd.a);
     ab[(long long)qq * sd.ldab + kv + q - qq] = mk((T)st[d].re, (T)st[d].im);
   }
-  bool side1 = (t == 0 && sd.has1), side2 = (t == sd.w - 1 && sd.has2);
+  bool side1 = (t == 0 && sd.has1 && !redo), side2 = (t == sd.w - 1 && sd.has2 && !redo);
   if (side1 || side2) {
     c128 g[7];
     node_stencil(i, j, n, 0, n - 1, 0, n - 1, omega, L, c, false, g);
     cx<T>* out = tr + (side1 ? sd.tr1_off : sd.tr2_off) + 7LL * l;
     for (int d = 0; d < 7; ++d) out[d] = mk((T)(st[d].re - g[d].re), (T)(st[d].im - g[d].im));
   }
+}
+
+// Zeroes the band of every strip marked 2 in redo.  grid.y = strip index.
+template <class T>
+__global__ void k_zero_marked(const StripDesc* __restrict__ strips, cx<T>* __restrict__ band,
+                              const int* __restrict__ redo) {
+  if (redo[blockIdx.y] != 2) return;
+  const StripDesc sd = strips[blockIdx.y];
+  const long long ne = (long long)sd.ns * sd.ldab;
+  cx<T>* ab = band + sd.band_off;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+       e += (long long)gridDim.x * blockDim.x)
+    ab[e] = mk((T)0, (T)0);
 }
 
 }  // namespace
@@ -194,11 +212,39 @@ void launch_pack_strips(const hh_problem* pb, hipStream_t st) {
   dim3 grid((unsigned)((fs.max_ns + bs - 1) / bs), (unsigned)fs.strips.size());
   if (fs.precision == HH_FP64)
     hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, pb->omega,
-                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c128*)fs.band, (c128*)fs.tr);
+                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c128*)fs.band, (c128*)fs.tr,
+                       (const int*)nullptr);
   else
     hipLaunchKernelGGL(k_pack_strips<float>, grid, dim3(bs), 0, st, pb->n, pb->omega,
-                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c64*)fs.band, (c64*)fs.tr);
+                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c64*)fs.band, (c64*)fs.tr,
+                       (const int*)nullptr);
   HH_HIP(hipGetLastError());
+}
+
+void launch_repack_marked(const hh_problem* pb, hipStream_t st) {
+  const FactorSet& fs = pb->fs;
+  const int bs = 256;
+  const dim3 zgrid(64, (unsigned)fs.strips.size());
+  const dim3 grid((unsigned)((fs.max_ns + bs - 1) / bs), (unsigned)fs.strips.size());
+  if (fs.precision == HH_FP64) {
+    hipLaunchKernelGGL(k_zero_marked<double>, zgrid, dim3(bs), 0, st, fs.d_strips,
+                       (c128*)fs.band, (const int*)fs.d_pflag);
+    hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, pb->omega,
+                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c128*)fs.band, (c128*)fs.tr,
+                       (const int*)fs.d_pflag);
+  } else {
+    hipLaunchKernelGGL(k_zero_marked<float>, zgrid, dim3(bs), 0, st, fs.d_strips,
+                       (c64*)fs.band, (const int*)fs.d_pflag);
+    hipLaunchKernelGGL(k_pack_strips<float>, grid, dim3(bs), 0, st, pb->n, pb->omega,
+                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c64*)fs.band, (c64*)fs.tr,
+                       (const int*)fs.d_pflag);
+  }
+  HH_HIP(hipGetLastError());
+}
+
+bool lu_interchanging_only() {
+  const char* env = std::getenv("HH_LU_INTERCHANGE");
+  return env && std::atoi(env) > 0;
 }
 
 }  // namespace hh

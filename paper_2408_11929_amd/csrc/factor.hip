@@ -58,6 +58,17 @@ template <class T>
 __device__ __forceinline__ cx<T> rdlc(cx<T> v, int l) {
   return mk(rdl(v.re, l), rdl(v.im, l));
 }
+// Lanes of one wave exchange data through LDS here.  Without this, such an
+// exchange is a data race to the compiler, which may then keep a lane's own
+// stores in registers and never load what other lanes wrote.  The fences
+// stop it from moving or forwarding LDS accesses across the point; at
+// wavefront scope they cost no wait, a wave's LDS accesses completing in
+// order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Column step j works on the (kl+1) x (2kl+1) window of rows j..j+kl and
 // columns j..j+2kl, kept in LDS with rotating physical rows and columns
@@ -264,15 +275,21 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restr
 // j + D, D = KR - 1 - kl, is put in a[KR-1] at step j and reaches a[kl]
 // when it enters, so no register is chosen by kl.  Entering rows are read
 // one chunk of CH steps ahead and pass through LDS.
+// With redo set, only the strips that k_band_lu_h marked (pflag = 2, band
+// packed again since) are factored.
 template <class T, int KR, int CH>
 __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ strips,
                                                   cx<T>* __restrict__ band,
                                                   int* __restrict__ pivbuf, int* err,
-                                                  int* __restrict__ pflag) {
+                                                  int* __restrict__ pflag, int redo) {
   __shared__ cx<T> colb[64];      // pivot column, lane r = row r
   __shared__ cx<T> lbuf[64];      // multipliers
   __shared__ cx<T> ebuf[CH][64];  // entering rows of the current chunk
   __shared__ cx<T> xbuf[KR][64];  // the window, for an interchange
+  if (redo) {
+    if (pflag[blockIdx.x] != 2) return;
+    if (threadIdx.x == 0) pflag[blockIdx.x] = 0;
+  }
   const StripDesc sd = strips[blockIdx.x];
   const int kl = sd.kl, kv = 2 * kl, C = kv + 1, ldab = sd.ldab, ns = sd.ns;
   const int D = KR - 1 - kl;
@@ -305,6 +322,7 @@ __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ 
   for (int u = 0; u < CH; ++u) nxt[u] = fetch(D + u);
   int c0 = 0;
   for (int jc = 0; jc < ns; jc += CH) {
+    wave_lds_sync();
 #pragma unroll
     for (int u = 0; u < CH; ++u) ebuf[u][lane] = nxt[u];
 #pragma unroll
@@ -315,10 +333,12 @@ __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ 
       if (j >= ns) break;
       const int rmax = min(kl, ns - 1 - j);
       const cx<T> ein = ebuf[u][lane];  // enters a[KR-1] after this step
+      wave_lds_sync();
       if (lane == c0) {
 #pragma unroll
         for (int r = 0; r < KR; ++r) colb[r] = a[r];
       }
+      wave_lds_sync();
       const cx<T> val = csel(lane <= kl, colb[lane <= kl ? lane : 0], zero);
       const T av = lane <= rmax ? cabs1(val) : (T)-1;
       const T ad = rdl(av, 0);
@@ -337,6 +357,7 @@ __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ 
       const cx<T> v0 = rdlc(val, 0);
       const cx<T> Lr = csel(lane >= 1 && lane <= rmax, csel(lane == rp, v0, val) * ipv, zero);
       lbuf[lane] = Lr;
+      wave_lds_sync();
       if (lane == 0) {
         piv[j] = j + rp;
         if (rp != 0) pflag[blockIdx.x] = 1;
@@ -346,9 +367,11 @@ __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ 
       if (rp != 0) {  // interchange rows 0 and rp in every column (rare), through LDS
 #pragma unroll
         for (int r = 0; r < KR; ++r) xbuf[r][lane] = a[r];
+        wave_lds_sync();
         const cx<T> t = xbuf[rp][lane];
         xbuf[rp][lane] = xbuf[0][lane];
         xbuf[0][lane] = t;
+        wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < KR; ++r) a[r] = xbuf[r][lane];
       }
@@ -366,6 +389,202 @@ __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ 
       }
       a[KR - 1] = ein;
       c0 = wrap(c0 + 1, C);
+    }
+  }
+}
+
+// Band LU of a strip whose partial pivoting makes no interchange, by one wave
+// with two lanes per column.  Without interchanges U keeps kl
+// superdiagonals, so step j only touches the M = kl + 1 columns j .. j + kl:
+// slot s (lanes s and s + 32) holds column j + ((s - c0) mod M), c0 = j mod M,
+// and half h of the wave holds window rows h R .. h R + R - 1 in a[0..R-1]
+// (rows j .. j + 2R - 1, 2R > kl; the rows past kl have not entered yet and
+// their multipliers are zero).  A step:
+//  - the pivot slot passes its column through LDS so that lane r holds row
+//    r; a ballot against the diagonal finds a step where partial pivoting
+//    (largest |Re| + |Im|, first index on ties) would interchange.  The strip
+//    is then marked (pflag = 2) and left at the end of the chunk; its band is
+//    packed again and k_band_lu_w factors it with interchanges;
+//  - lane r forms the multiplier of row r, stores it as L(j + r, j) and
+//    passes it through LDS to the half that holds row r;
+//  - half 0 stores its row 0 as row j of U; v_permlane32_swap hands that row
+//    to half 1, every lane updates and shifts its rows at once (a[k-1] =
+//    a[k] - L a[0]), a second swap moves row R from half 1 to half 0, and
+//    half 1 takes the row entering at the bottom;
+//  - the pivot slot takes column j + M, untouched by every earlier step: its
+//    rows j + 1 .. j + 2R come from the band, like the entering rows staged
+//    in LDS one chunk of CH steps ahead.
+// The stores of a step never overlap what later steps read from the band:
+// U rows and L columns lie at or left of the current step.
+template <class T>
+__device__ __forceinline__ cx<T> half0_to_both(cx<T> v);
+template <>
+__device__ __forceinline__ c64 half0_to_both(c64 v) {
+  const unsigned r = __float_as_uint(v.re), i = __float_as_uint(v.im);
+  return mk(__uint_as_float(__builtin_amdgcn_permlane32_swap(r, r, false, false)[0]),
+            __uint_as_float(__builtin_amdgcn_permlane32_swap(i, i, false, false)[0]));
+}
+template <>
+__device__ __forceinline__ c128 half0_to_both(c128 v) {
+  const unsigned long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
+  const unsigned rl = (unsigned)r, rh = (unsigned)(r >> 32), il = (unsigned)i, ih = (unsigned)(i >> 32);
+  const unsigned a = __builtin_amdgcn_permlane32_swap(rl, rl, false, false)[0];
+  const unsigned b = __builtin_amdgcn_permlane32_swap(rh, rh, false, false)[0];
+  const unsigned c = __builtin_amdgcn_permlane32_swap(il, il, false, false)[0];
+  const unsigned d = __builtin_amdgcn_permlane32_swap(ih, ih, false, false)[0];
+  return mk(__longlong_as_double(((long long)b << 32) | a), __longlong_as_double(((long long)d << 32) | c));
+}
+template <class T>
+__device__ __forceinline__ cx<T> half1_to_both(cx<T> v);
+template <>
+__device__ __forceinline__ c64 half1_to_both(c64 v) {
+  const unsigned r = __float_as_uint(v.re), i = __float_as_uint(v.im);
+  return mk(__uint_as_float(__builtin_amdgcn_permlane32_swap(r, r, false, false)[1]),
+            __uint_as_float(__builtin_amdgcn_permlane32_swap(i, i, false, false)[1]));
+}
+template <>
+__device__ __forceinline__ c128 half1_to_both(c128 v) {
+  const unsigned long long r = __double_as_longlong(v.re), i = __double_as_longlong(v.im);
+  const unsigned rl = (unsigned)r, rh = (unsigned)(r >> 32), il = (unsigned)i, ih = (unsigned)(i >> 32);
+  const unsigned a = __builtin_amdgcn_permlane32_swap(rl, rl, false, false)[1];
+  const unsigned b = __builtin_amdgcn_permlane32_swap(rh, rh, false, false)[1];
+  const unsigned c = __builtin_amdgcn_permlane32_swap(il, il, false, false)[1];
+  const unsigned d = __builtin_amdgcn_permlane32_swap(ih, ih, false, false)[1];
+  return mk(__longlong_as_double(((long long)b << 32) | a), __longlong_as_double(((long long)d << 32) | c));
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+template <class T, int R, int CH>
+__global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ strips,
+                                                  cx<T>* __restrict__ band,
+                                                  int* __restrict__ pivbuf, int* err,
+                                                  int* __restrict__ pflag) {
+  constexpr int R2 = 2 * R;
+  constexpr int NE = CH / 2;              // staged entering-row entries per lane (M <= 32)
+  constexpr int NB = (CH * R2 + 63) / 64;  // staged entering-column entries per lane
+  __shared__ cx<T> colb[32];               // pivot column, entry r = window row r
+  __shared__ cx<T> ebuf[CH * 32 + 64];     // entering rows [step][logical column], spill slots
+  __shared__ cx<T> nbuf[NB * 64];          // entering columns [step][window row]
+  const StripDesc sd = strips[blockIdx.x];
+  const int kl = sd.kl, kv = 2 * kl, M = kl + 1, ldab = sd.ldab, ns = sd.ns;
+  cx<T>* ab = band + sd.band_off;
+  int* piv = pivbuf + sd.piv_off;
+  const int lane = threadIdx.x, h = lane >> 5, s = lane & 31;
+  const bool act = s < M;
+  const cx<T> zero = mk((T)0, (T)0);
+  auto wrap = [](int x, int m) { return x >= m ? x - m : x; };
+  // Staging of the chunk that starts at step jn: entry (u, c) of the entering
+  // rows is A(jn + u + 2R, jn + u + 1 + c), the row that enters after step
+  // jn + u in logical column c of the next step (zero left of the band);
+  // entry (u, r) of the entering columns is A(jn + u + 1 + r, jn + u + M).
+  // Each is A at band position jn ldab + off, so the offsets, the last row
+  // or column an entry needs and its LDS slot are fixed per lane.
+  int eoff[NE], elast[NE], epos[NE], noff[NB], nlast[NB];
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int e = lane + 64 * t, u = e / M, c = e - u * M;
+    const bool ok = u < CH && c >= R2 - 1 - kl;  // row - column = 2R - 1 - c <= kl
+    eoff[t] = (u + 1 + c) * (ldab - 1) + kv + u + R2;
+    elast[t] = ok ? u + R2 : 1 << 30;           // the row; the column is left of it
+    epos[t] = u < CH ? u * 32 + c : CH * 32 + lane;
+  }
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const int e = lane + 64 * t, u = e / R2, r = e - u * R2;
+    const bool ok = u < CH && r <= 2 * kl;  // row - column = 1 + r - M <= kl
+    noff[t] = (u + M) * (ldab - 1) + kv + u + 1 + r;
+    nlast[t] = ok ? max(u + 1 + r, u + M) : 1 << 30;
+  }
+  cx<T> ne[NE], nn[NB];
+  auto fetch = [&](int jn) {
+    const long long base = (long long)jn * ldab;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const bool in = jn + elast[t] < ns;
+      const cx<T> v = ab[in ? base + eoff[t] : 0];
+      ne[t] = csel(in, v, zero);
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const bool in = jn + nlast[t] < ns;
+      const cx<T> v = ab[in ? base + noff[t] : 0];
+      nn[t] = csel(in, v, zero);
+    }
+  };
+  cx<T> a[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = h * R + k;
+    const bool in = act && i < ns && s < ns && i - s <= kl && s - i <= kl;
+    const cx<T> v = ab[in ? (long long)s * ldab + kv + i - s : 0];
+    a[k] = csel(in, v, zero);
+  }
+  fetch(0);
+  // the pivot slot, the column of this slot, its logical column after the step
+  int c0 = 0, col = s, lcn = !act || s == 0 ? (act ? M - 1 : 0) : s - 1;
+  int badv = 0;  // this lane saw a step that needs an interchange or a zero pivot
+  if (s == 0) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) colb[h * R + k] = a[k];
+  }
+  const int nsteps = (ns + CH - 1) / CH * CH;  // steps past ns change nothing
+  for (int jc = 0; jc < nsteps; jc += CH) {
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < NE; ++t) ebuf[epos[t]] = ne[t];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) nbuf[lane + 64 * t] = nn[t];
+    fetch(jc + CH);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int j = jc + u;
+      const int rmax = min(kl, ns - 1 - j);
+      wave_lds_sync();
+      // the pivot column as written by its slot: lane r's row, and every row
+      // of this lane's half
+      const cx<T> val = colb[s];
+      cx<T> lr[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) lr[k] = colb[h * R + k];
+      const cx<T> pv = rdlc(lr[0], 0);
+      const T pd = pv.re * pv.re + pv.im * pv.im;
+      const T ipd = pd == (T)0 ? (T)0 : recip(pd);
+      const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
+      const T av = lane <= rmax ? cabs1(val) : (T)-1;
+      badv |= (int)(av > rdl(av, 0)) | (int)(pd == (T)0 && j < ns);
+      if (lane >= 1 && lane <= rmax) ab[(long long)j * ldab + kv + lane] = val * ipv;
+      if (h == 0 && act && col < ns && j < ns) ab[(long long)col * (ldab - 1) + kv + j] = a[0];
+      // row k of the half loses L(k) u0 = col(k) (u0 / pivot): the pivot
+      // column is zero in the rows that have not entered and past the matrix
+      const cx<T> w = half0_to_both(a[0]) * ipv;
+      cx<T> t[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) t[k] = cfms(a[k], lr[k], w);
+      const cx<T> up = half1_to_both(t[0]);
+      const cx<T> ein = ebuf[u * 32 + lcn];
+#pragma unroll
+      for (int k = 0; k + 1 < R; ++k) a[k] = t[k + 1];
+      a[R - 1] = csel(h == 0, up, ein);
+      // the next pivot slot passes its column before the retired slot
+      // reloads, so that the reload's wait overlaps the next step's
+      const int c1 = wrap(c0 + 1, M);
+      if (s == c1) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) colb[h * R + k] = a[k];
+      }
+      if (s == c0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) a[k] = nbuf[u * R2 + h * R + k];
+        col += M;
+      }
+      c0 = c1;
+      lcn = lcn == 0 ? M - 1 : lcn - 1;
+    }
+    if (lane < CH && jc + lane < ns) piv[jc + lane] = jc + lane;
+    if (__any(badv)) {
+      if (lane == 0) pflag[blockIdx.x] = 2;
+      return;
     }
   }
 }
@@ -770,27 +989,66 @@ static void launch_products(const FactorSet& fs, hipStream_t st) {
                        fs.d_strips, (cx<T>*)fs.img, fs.d_pflag, stage);
 }
 
-// One or two column slots per lane: 2 kl + 1 <= 64 needs one.
-// One wave with the window in registers where the band allows it (kl < KR),
-// else the LDS window on four waves (one or two column slots per lane).
+// kl < 32: the two-lanes-per-column kernel on every strip; the strips it
+// marks are packed again and factored with interchanges by the one-wave
+// register kernel (kl < KR); the launches find nothing to do when no strip
+// was marked.  Larger bands: the LDS window on four waves (one or two column
+// slots per lane: 2 kl + 1 <= 64 needs one).
+template <class T, int R>
+static void launch_lu_h(const FactorSet& fs, hipStream_t st) {
+  constexpr int CH = sizeof(T) == 8 ? 8 : 16;
+  hipLaunchKernelGGL((k_band_lu_h<T, R, CH>), dim3((unsigned)fs.strips.size()), dim3(64), 0, st,
+                     fs.d_strips, (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+}
 template <class T, int KR>
-static void launch_lu_w(const FactorSet& fs, hipStream_t st) {
+static void launch_lu_w(const FactorSet& fs, hipStream_t st, int redo) {
   constexpr int CH = sizeof(T) == 8 ? 8 : 16;
   hipLaunchKernelGGL((k_band_lu_w<T, KR, CH>), dim3((unsigned)fs.strips.size()), dim3(64), 0, st,
-                     fs.d_strips, (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+                     fs.d_strips, (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag, redo);
+}
+template <class T>
+static void launch_lu_h_any(const FactorSet& fs, hipStream_t st) {
+  switch ((fs.max_kl + 2) / 2) {  // smallest R with 2 R > kl
+    case 1: return launch_lu_h<T, 1>(fs, st);
+    case 2: return launch_lu_h<T, 2>(fs, st);
+    case 3: return launch_lu_h<T, 3>(fs, st);
+    case 4: return launch_lu_h<T, 4>(fs, st);
+    case 5: return launch_lu_h<T, 5>(fs, st);
+    case 6: return launch_lu_h<T, 6>(fs, st);
+    case 7: return launch_lu_h<T, 7>(fs, st);
+    case 8: return launch_lu_h<T, 8>(fs, st);
+    case 9: return launch_lu_h<T, 9>(fs, st);
+    case 10: return launch_lu_h<T, 10>(fs, st);
+    case 11: return launch_lu_h<T, 11>(fs, st);
+    case 12: return launch_lu_h<T, 12>(fs, st);
+    case 13: return launch_lu_h<T, 13>(fs, st);
+    case 14: return launch_lu_h<T, 14>(fs, st);
+    case 15: return launch_lu_h<T, 15>(fs, st);
+    default: return launch_lu_h<T, 16>(fs, st);
+  }
+}
+template <class T>
+static void launch_lu_w_any(const FactorSet& fs, hipStream_t st, int redo) {
+  const int kl = fs.max_kl;
+  if (kl < 8) return launch_lu_w<T, 8>(fs, st, redo);
+  if (kl < 12) return launch_lu_w<T, 12>(fs, st, redo);
+  if (kl < 16) return launch_lu_w<T, 16>(fs, st, redo);
+  if (kl < 20) return launch_lu_w<T, 20>(fs, st, redo);
+  if (kl < 24) return launch_lu_w<T, 24>(fs, st, redo);
+  if (kl < 28) return launch_lu_w<T, 28>(fs, st, redo);
+  return launch_lu_w<T, 32>(fs, st, redo);
 }
 
 template <class T>
-static void launch_lu(const FactorSet& fs, size_t lds, hipStream_t st) {
+static void launch_lu(const hh_problem* pb, size_t lds, hipStream_t st) {
+  const FactorSet& fs = pb->fs;
   const int nstr = (int)fs.strips.size();
-  const int kl = fs.max_kl;
-  if (kl < 8) return launch_lu_w<T, 8>(fs, st);
-  if (kl < 12) return launch_lu_w<T, 12>(fs, st);
-  if (kl < 16) return launch_lu_w<T, 16>(fs, st);
-  if (kl < 20) return launch_lu_w<T, 20>(fs, st);
-  if (kl < 24) return launch_lu_w<T, 24>(fs, st);
-  if (kl < 28) return launch_lu_w<T, 28>(fs, st);
-  if (kl < 32) return launch_lu_w<T, 32>(fs, st);
+  if (fs.max_kl < 32) {
+    if (lu_interchanging_only()) return launch_lu_w_any<T>(fs, st, 0);
+    launch_lu_h_any<T>(fs, st);
+    launch_repack_marked(pb, st);
+    return launch_lu_w_any<T>(fs, st, 1);
+  }
   const bool one = 2 * fs.max_kl + 1 <= 64;
   const void* fn = one ? (const void*)k_band_lu<T, 1> : (const void*)k_band_lu<T, 2>;
   HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -812,7 +1070,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
   for (auto& s : fs.strips) bytes += 2.0 * (double)s.ns * s.ldab * esz;
   TimedRegion tr(FAM_FACTOR, st, bytes);
   if (fs.precision == HH_FP64) {
-    launch_lu<double>(fs, lds, st);
+    launch_lu<double>(pb, lds, st);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<double>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv,
@@ -827,7 +1085,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag, fs.max_kl + 1);
     launch_products<double>(fs, st);
   } else {
-    launch_lu<float>(fs, lds, st);
+    launch_lu<float>(pb, lds, st);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<float>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv,

@@ -226,6 +226,11 @@ void launch_assemble(int n, double omega, int nlayers, const double* d_c, c128* 
                      hipStream_t st);
 void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st);
 void launch_pack_strips(const hh_problem* pb, hipStream_t st);
+// Zeroes and packs again the bands of the strips whose pflag is 2 (marked by
+// the LU that assumes no interchange).
+void launch_repack_marked(const hh_problem* pb, hipStream_t st);
+// HH_LU_INTERCHANGE=1: factor every strip with the interchanging LU kernel.
+bool lu_interchanging_only();
 
 // factor.hip
 void launch_band_lu(const hh_problem* pb, hipStream_t st);
