@@ -158,6 +158,7 @@ void factor_launch(hh_problem* pb, hipStream_t st) {
                         hipMemcpyHostToDevice, st));
   HH_HIP(hipMemsetAsync(fs.d_err, 0, 2 * sizeof(int), st));
   HH_HIP(hipMemsetAsync(fs.d_pflag, 0, fs.strips.size() * sizeof(int), st));
+  fs.batch_maps = fs.eager_batch_maps || !fs.strips[0].wide;
   launch_pack_strips(pb, st);
   launch_band_lu(pb, st);
   HH_HIP(hipMemcpyAsync(fs.h_err.data(), fs.d_err, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -170,8 +171,10 @@ void factor_launch(hh_problem* pb, hipStream_t st) {
 // and reports a zero pivot.
 int factor_finish(hh_problem* pb) {
   FactorSet& fs = pb->fs;
-  dev_free(fs.band);
-  fs.band = nullptr;
+  if (fs.batch_maps) {
+    dev_free(fs.band);
+    fs.band = nullptr;
+  }
   fs.any_pivot = std::any_of(fs.h_pflag.begin(), fs.h_pflag.end(), [](int f) { return f != 0; });
   if (fs.h_err[0]) {
     const StripDesc& sd = fs.strips[fs.h_err[0] - 1];
@@ -179,6 +182,16 @@ int factor_finish(hh_problem* pb) {
     return HH_ESINGULAR;
   }
   return HH_OK;
+}
+
+void ensure_batch_maps(hh_problem* pb, hipStream_t st) {
+  FactorSet& fs = pb->fs;
+  if (fs.batch_maps) return;
+  launch_transfer(fs, 1, st);
+  HH_HIP(hipStreamSynchronize(st));
+  dev_free(fs.band);
+  fs.band = nullptr;
+  fs.batch_maps = true;
 }
 
 // New problem handle with the operator assembled asynchronously on its stream.
@@ -279,6 +292,7 @@ int hh_strip_solve(hh_problem* pb, unsigned dir, int s, const hh_c128* rhs, hh_c
     REQUIRE(s >= 1 && s <= pb->fs.N, "strip index out of range");
     const int si = i * pb->fs.N + s - 1;
     const size_t es = pb->fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
+    ensure_batch_maps(pb, pb->st[0]);  // the strip solve runs segment plan 0
     void* work = dev_alloc(pb->fs.strips[si].ns * es);
     launch_strip_solve(pb, si, (const c128*)rhs, (c128*)x, work, pb->st[0]);
     HH_HIP(hipStreamSynchronize(pb->st[0]));
@@ -304,6 +318,7 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
                                     fs.any_pivot, fs.strips[0].wide != 0);
     const int G = plan_width(plan);
     hipStream_t st = pb->st[0];
+    if (plan == 0) ensure_batch_maps(pb, st);
     // sync words: [0] abort, then one 128-byte line per chain
     unsigned* sync = (unsigned*)dev_alloc((size_t)(ntask + 1) * 128);
     void* xch = plan > 0 ? dev_alloc((size_t)ntask * G * 64 * es) : nullptr;

@@ -302,6 +302,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     bool piv;
     int plan;
     bool wide;  // the wide plan's maps were built
+    std::vector<hh_problem*> pbs;  // problems with tasks in this kind
   };
   std::vector<Kind> kinds;
   for (Solve* s : live) {
@@ -315,9 +316,10 @@ void Engine::step(std::vector<Solve*>& solves) {
              k.wide == wide;
     });
     if (it == kinds.end()) {
-      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0, wide});
+      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0, wide, {}});
       it = kinds.end() - 1;
     }
+    if (std::find(it->pbs.begin(), it->pbs.end(), s->pb) == it->pbs.end()) it->pbs.push_back(s->pb);
     it->kmax = std::max(it->kmax, fs.max_kl);
     it->nmax = std::max(it->nmax, pb->n);
     for (int i = 0; i < s->t; ++i) {
@@ -342,7 +344,10 @@ void Engine::step(std::vector<Solve*>& solves) {
       k.plan = wide_ok_ ? sweep_plan_for((int)k.tasks.size(), k.prec, k.P, k.kmax, k.nmax, k.piv,
                                          k.wide)
                         : 0;
-      if (k.plan == 0) continue;
+      if (k.plan == 0) {
+        for (hh_problem* q : k.pbs) ensure_batch_maps(q, st_);
+        continue;
+      }
       chains += k.tasks.size();
       xbytes += k.tasks.size() * (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);
     }

@@ -750,7 +750,7 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
                                                        const cx<T>* __restrict__ band,
                                                        cx<T>* __restrict__ img,
                                                        const int* __restrict__ pflag,
-                                                       int wstride) {
+                                                       int wstride, int planmask) {
   // win[(i & 63) W + c'] = out_i of column c' < K, W = max_kl + 1 (dynamic
   // LDS, 64 W entries); column W - 1 holds the coefficients of the current
   // row (entry K: the scale d)
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     if (m < c) break;
     m -= c;
   }
-  if (plan == HH_NPLAN) return;
+  if (plan == HH_NPLAN || !(planmask >> plan & 1)) return;
   const int seg = sd.pseg[plan], s = 1 + m, nseg = plan_nseg(ns, seg);
   const int lane = threadIdx.x;
   const bool upper = blockIdx.y == 1;
@@ -1060,6 +1060,25 @@ static void launch_lu(const hh_problem* pb, size_t lds, hipStream_t st) {
                        (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
 }
 
+// Transfer maps of the segment plans in planmask (bit p: plan p).
+void launch_transfer(const FactorSet& fs, int planmask, hipStream_t st) {
+  const size_t lds = 64 * (size_t)(fs.max_kl + 1) * sizeof(c128);
+  if (fs.precision == HH_FP64) {
+    HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64), lds, st,
+                       fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.d_pflag,
+                       fs.max_kl + 1, planmask);
+  } else {
+    HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64), lds, st,
+                       fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.d_pflag,
+                       fs.max_kl + 1, planmask);
+  }
+  HH_HIP(hipGetLastError());
+}
+
 void launch_band_lu(const hh_problem* pb, hipStream_t st) {
   const FactorSet& fs = pb->fs;
   HH_HIP(hipMemsetAsync(fs.img, 0, fs.img_elems * (fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64)), st));
@@ -1077,12 +1096,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
-    HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               64 * (fs.max_kl + 1) * (int)sizeof(c128)));
-    hipLaunchKernelGGL(k_build_transfer<double>, transfer_grid(fs), dim3(64),
-                       64 * (size_t)(fs.max_kl + 1) * sizeof(c128), st, fs.d_strips,
-                       (const c128*)fs.band, (c128*)fs.img, fs.d_pflag, fs.max_kl + 1);
+    launch_transfer(fs, fs.batch_maps ? 3 : 2, st);
     launch_products<double>(fs, st);
   } else {
     launch_lu<float>(pb, lds, st);
@@ -1092,12 +1106,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
-    HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               64 * (fs.max_kl + 1) * (int)sizeof(c128)));
-    hipLaunchKernelGGL(k_build_transfer<float>, transfer_grid(fs), dim3(64),
-                       64 * (size_t)(fs.max_kl + 1) * sizeof(c128), st, fs.d_strips,
-                       (const c64*)fs.band, (c64*)fs.img, fs.d_pflag, fs.max_kl + 1);
+    launch_transfer(fs, fs.batch_maps ? 3 : 2, st);
     launch_products<float>(fs, st);
   }
   HH_HIP(hipGetLastError());

@@ -156,7 +156,7 @@ struct FactorSet {
   int dir_id[2] = {-1, -1}; // direction (0/1) of preconditioner slot 0/1
   std::vector<StripDesc> strips;  // dir-major: strips[d*N + s]
   StripDesc* d_strips = nullptr;  // device copy
-  void* band = nullptr;            // LU work buffer, freed after the image is built
+  void* band = nullptr;            // LU work buffer, freed once every map is built
   void* img = nullptr;             // solve image, complex<precision> elements
   int* piv = nullptr;
   void* tr = nullptr;              // transmission stencils, complex<precision>
@@ -165,6 +165,12 @@ struct FactorSet {
   std::array<int, 2> h_err{{0, 0}};  // host copy, valid once the factor stream completed
   std::vector<int> h_pflag;           // host copy of d_pflag, likewise
   bool any_pivot = false;             // some strip pivoted (set by factor_finish)
+  // The transfer maps of segment plan 0 (one workgroup per chain) serve
+  // batched sweeps only; where the wide plan exists they are built from the
+  // kept band when a launch first takes plan 0 (ensure_batch_maps), unless
+  // eager_batch_maps asks for them with the factorisation.
+  bool eager_batch_maps = false;
+  bool batch_maps = true;             // plan 0's transfer maps are built or queued
   size_t band_elems = 0, img_elems = 0, piv_elems = 0, tr_elems = 0;
   int max_ns = 0, max_kl = 0;
   size_t bytes() const;
@@ -234,6 +240,10 @@ bool lu_interchanging_only();
 
 // factor.hip
 void launch_band_lu(const hh_problem* pb, hipStream_t st);
+void launch_transfer(const FactorSet& fs, int planmask, hipStream_t st);
+// Builds plan 0's transfer maps on st if the factorisation left them out,
+// waits for them and frees the band.
+void ensure_batch_maps(hh_problem* pb, hipStream_t st);
 
 // sweep.hip
 // One preconditioner application (one direction, one right-hand side).

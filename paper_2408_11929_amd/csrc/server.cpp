@@ -124,6 +124,7 @@ void hh_server::admit(Request* r) {
   r->b = (c128*)dev_alloc((size_t)q.nsrc * len * sizeof(c128));
   launch_load_vector(q.n, q.nsrc, (const c128*)q.f, r->b, ps);
   factor_setup(r->pb, q.dirs, q.nstrips, q.precision);
+  r->pb->fs.eager_batch_maps = true;  // the server's sweeps take plan 0
   factor_launch(r->pb, ps);
   HH_HIP(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
   HH_HIP(hipEventRecord(r->ready, ps));

@@ -1,6 +1,12 @@
 """Serving loop (continuous batching) through the C ABI: each result is the same
 alone and in the mix, admission respects the HBM budget, and a request that
-fails to converge does not disturb the others."""
+fails to converge does not disturb the others.
+
+The server runs every sweep on one workgroup per chain (segment plan 0); a
+lone solve would take the wide plan for a single complex64 right-hand side,
+which is the same method in another rounding order, so the lone reference
+is pinned to plan 0 (HH_SWEEP_PLAN=0) for the bitwise comparison."""
+import os
 import time
 
 import numpy as np
@@ -28,11 +34,20 @@ def sources(n, nsrc, seed):
 
 
 def alone(n, N, omega, c, f, prec, tol, maxit):
-    pb = hh.Problem(omega, c, n)
-    b = pb.load_vector(f)
-    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
-    x, st, rc = pb.mpgmres(b, tol=tol, maxit=maxit)
-    pb.free()
+    """The request solved on its own, with the server's segment plan."""
+    old = os.environ.get("HH_SWEEP_PLAN")
+    os.environ["HH_SWEEP_PLAN"] = "0"
+    try:
+        pb = hh.Problem(omega, c, n)
+        b = pb.load_vector(f)
+        pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+        x, st, rc = pb.mpgmres(b, tol=tol, maxit=maxit)
+        pb.free()
+    finally:
+        if old is None:
+            del os.environ["HH_SWEEP_PLAN"]
+        else:
+            os.environ["HH_SWEEP_PLAN"] = old
     return x.cpu().numpy(), st, rc
 
 
