@@ -101,8 +101,14 @@ HdLayout::HdLayout(int m, int t) {
 
 namespace {
 size_t esz_of(int prec) { return prec == HH_FP64 ? sizeof(c128) : sizeof(c64); }
-int nblk_for(long long len) {
-  long long b = (len + 4095) / 4096;
+// Row blocks of the Gram products with nlive solves in the launch: about
+// 512 rows each (two rows per thread) for up to eight solves, so that a
+// single solve spreads over the chip, proportionally longer blocks for more
+// (a batch fills the chip with its solves); at most 256 blocks.  nblk_for(len)
+// (nlive = 1) sizes the partial-sum buffers.
+int nblk_for(long long len, size_t nlive = 1) {
+  const long long rows = 512LL * (long long)std::max<size_t>(1, nlive / 8);
+  const long long b = (len + rows - 1) / rows;
   return (int)std::max(1LL, std::min(b, 256LL));
 }
 }  // namespace
@@ -245,7 +251,7 @@ void Engine::begin(std::vector<Solve*>& solves) {
     g.ldo = 1;
     g.px = 1;
     g.ty = 1;
-    g.nblk = nblk_for(s->len);
+    g.nblk = nblk_for(s->len, live.size());
     g.accumulate = 0;
     gt.push_back(g);
     NormTask q{};
@@ -416,7 +422,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     g.ldo = m + t;
     g.px = m + t;
     g.ty = t;
-    g.nblk = nblk_for(s->len);
+    g.nblk = nblk_for(s->len, live.size());
     g.accumulate = 0;
     g1.push_back(g);
     g.px = m;
@@ -466,7 +472,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         g.ldo = t;
         g.px = c;
         g.ty = 1;
-        g.nblk = nblk_for(s->len);
+        g.nblk = nblk_for(s->len, live.size());
         mg[c * 3 + pass].push_back(g);
         UpdTask u{};
         u.X = W;
@@ -489,7 +495,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       g.ldo = 1;
       g.px = 1;
       g.ty = 1;
-      g.nblk = nblk_for(s->len);
+      g.nblk = nblk_for(s->len, live.size());
       mg[c * 3 + 2].push_back(g);
       NormTask q{};
       q.y = wc;
@@ -674,7 +680,7 @@ void Engine::finish(std::vector<Solve*>& solves) {
     g.ldo = 1;
     g.px = 1;
     g.ty = 1;
-    g.nblk = nblk_for(s->len);
+    g.nblk = nblk_for(s->len, fin.size());
     gt.push_back(g);
     maxlen = std::max(maxlen, s->len);
     maxblk = std::max(maxblk, g.nblk);

@@ -107,16 +107,26 @@ __global__ __launch_bounds__(256) void k_gram_partial(const GramTask* __restrict
   }
 }
 
-// out[i + c*ldo] (=|+=) sum over blocks of part; grid = (ceil(px*ty/256), tasks)
+// out[i + c*ldo] (=|+=) sum over blocks of part: one wave per entry, lane l
+// summing blocks l, l + 64, ..., then a fixed-order wave sum.
+// grid = (ceil(px*ty/4), tasks)
 __global__ __launch_bounds__(256) void k_gram_reduce(const GramTask* __restrict__ tasks) {
   const GramTask tk = tasks[blockIdx.y];
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6), ln = threadIdx.x & 63;
   if (e >= tk.px * tk.ty) return;
   const int i = e / tk.ty, c = e - i * tk.ty;
-  c128 s = mk(0.0, 0.0);
-  for (int b = 0; b < tk.nblk; ++b) s = s + tk.part[((long long)b * tk.px + i) * tk.ty + c];
-  c128* o = tk.out + i + (long long)c * tk.ldo;
-  *o = tk.accumulate ? *o + s : s;
+  double sr = 0.0, si = 0.0;
+  for (int b = ln; b < tk.nblk; b += 64) {
+    const c128 v = tk.part[((long long)b * tk.px + i) * tk.ty + c];
+    sr += v.re;
+    si += v.im;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (ln == 0) {
+    c128* o = tk.out + i + (long long)c * tk.ldo;
+    *o = tk.accumulate ? *o + mk(sr, si) : mk(sr, si);
+  }
 }
 
 // Y[:, c] -= X C[:, c]; C (px x ty, column stride ldc) on the device.
@@ -204,7 +214,7 @@ void launch_gram(const GramTask* d_tasks, int ntasks, int max_nblk, int max_px, 
     throw ArgError();
   }
   HH_HIP(hipGetLastError());
-  dim3 g2((unsigned)((max_px * max_ty + 255) / 256), (unsigned)ntasks);
+  dim3 g2((unsigned)((max_px * max_ty + 3) / 4), (unsigned)ntasks);
   hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, st, d_tasks);
   HH_HIP(hipGetLastError());
 }
