@@ -721,6 +721,9 @@ __global__ __launch_bounds__(64) void k_build_blocked(const StripDesc* __restric
   }
 }
 
+// Rows of k_build_transfer's output window: a power of two above the band.
+__host__ __device__ inline int transfer_ring(int kl) { return kl < 32 ? 32 : 64; }
+
 // Segments that k_build_transfer runs for plan p: those with a tail map
 // (1..nseg-2), and for the wide plan also the last one (its response only).
 __host__ __device__ inline int transfer_jobs(const StripDesc& sd, int p) {
@@ -751,9 +754,9 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
                                                        cx<T>* __restrict__ img,
                                                        const int* __restrict__ pflag,
                                                        int wstride, int planmask) {
-  // win[(i & 63) W + c'] = out_i of column c' < K, W = max_kl + 1 (dynamic
-  // LDS, 64 W entries); column W - 1 holds the coefficients of the current
-  // row (entry K: the scale d)
+  // win[(i mod RS) W + c'] = out_i of column c' < K, W = max_kl + 1, then
+  // the coefficients of CR rows, row u at cb[u W ..] (entry K: the scale d)
+  // (dynamic LDS, (RS + CR) W entries)
   extern __shared__ c128 win[];
   const int W = wstride;
   if (pflag[blockIdx.x]) return;
@@ -795,30 +798,47 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     }
     return mk(lane == K ? 1.0 : 0.0, 0.0);
   };
-  for (int q = 0; q < 64; ++q)
+  // Each lane's recurrence touches only its own column of the window, so
+  // the rows run without barriers; the coefficients come CR rows at a time
+  // through cb, loaded one chunk ahead.
+  constexpr int CR = 16;
+  const int RS = transfer_ring(W - 1), rm = RS - 1;
+  c128* cb = win + RS * W;
+  c128 cr[CR];
+  auto fetch = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < CR; ++u) cr[u] = i0 + u < s1 ? coef(i0 + u) : mk(0.0, 0.0);
+  };
+  for (int q = 0; q < RS; ++q)
     if (lane < W) win[q * W + lane] = mk(0.0, 0.0);
-  if (lane < K) win[((s0 - K + lane) & 63) * W + lane] = mk(1.0, 0.0);
-  c128 nxt = coef(s0);
-  const int cw = W - 1;  // coefficient column
-  for (int i = s0; i < s1; ++i) {
-    __syncthreads();
-    if (lane <= K) win[lane * W + cw] = (lane == K && upper) ? cinv(nxt) : nxt;
-    if (i + 1 < s1) nxt = coef(i + 1);
-    __syncthreads();
-    c128 acc = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
-    const int lc = lane < K ? lane : 0;
-    int c = 1;
-    for (; c + 1 <= K; c += 2) {
-      acc = cfms(acc, win[(c - 1) * W + cw], win[((i - c) & 63) * W + lc]);
-      acc1 = cfms(acc1, win[c * W + cw], win[((i - c - 1) & 63) * W + lc]);
+  if (lane < K) win[((s0 - K + lane) & rm) * W + lane] = mk(1.0, 0.0);
+  fetch(s0);
+  const int lc = lane < W ? lane : W - 1;  // lanes past K read columns no lane writes
+  for (int i0 = s0; i0 < s1; i0 += CR) {
+    __syncthreads();  // the previous chunk's coefficients have been read
+    if (lane <= K) {
+#pragma unroll
+      for (int u = 0; u < CR; ++u) cb[u * W + lane] = (lane == K && upper) ? cinv(cr[u]) : cr[u];
     }
-    if (c <= K) acc = cfms(acc, win[(c - 1) * W + cw], win[((i - c) & 63) * W + lc]);
-    acc = (acc + acc1) * win[K * W + cw];
+    fetch(i0 + CR);
     __syncthreads();
-    if (lane < K) win[(i & 63) * W + lane] = acc;
-    if (tmap && lane < K && i >= s1 - K)
-      Tm[(long long)lane * KM + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
-    if (Ph && lane < K) Ph[(long long)lane * seg + (i - s0)] = mk((T)acc.re, (T)acc.im);
+    const int un = s1 - i0 < CR ? s1 - i0 : CR;
+    for (int u = 0; u < un; ++u) {
+      const int i = i0 + u;
+      const c128* cf = cb + u * W;
+      c128 acc = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
+      int c = 1;
+      for (; c + 1 <= K; c += 2) {
+        acc = cfms(acc, cf[c - 1], win[((i - c) & rm) * W + lc]);
+        acc1 = cfms(acc1, cf[c], win[((i - c - 1) & rm) * W + lc]);
+      }
+      if (c <= K) acc = cfms(acc, cf[c - 1], win[((i - c) & rm) * W + lc]);
+      acc = (acc + acc1) * cf[K];
+      if (lane < K) win[(i & rm) * W + lane] = acc;
+      if (tmap && lane < K && i >= s1 - K)
+        Tm[(long long)lane * KM + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
+      if (Ph && lane < K) Ph[(long long)lane * seg + (i - s0)] = mk((T)acc.re, (T)acc.im);
+    }
   }
 }
 
@@ -828,14 +848,14 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
 // q < P and as W_g for q = P (job 0 of the workgroup), and A1_c = T_c T_{c-1}
 // (job w + 1, w >= 2).  Stage 1: A2_c = A1_c A1_{c-2} (w >= 4) and, for
 // workgroup g, the running product W_{g-1} ... W_{j+1} = Psi_{j,g} for j =
-// g-2 down to 0.  One workgroup of 64 lanes per (job, strip, triangle); the
+// g-2 down to 0.  One workgroup of 256 threads per (job, strip, triangle); the
 // maps involved are copied into LDS (three KM x KM buffers in FP64,
-// column-major like the stored maps) and lane r forms row r of a product,
-// sixteen columns at a time.
+// column-major like the stored maps) and the 256 threads share the entries
+// of a product.
 template <class T>
-__global__ __launch_bounds__(64) void k_build_products(const StripDesc* __restrict__ strips,
-                                                       cx<T>* __restrict__ img,
-                                                       const int* __restrict__ pflag, int stage) {
+__global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restrict__ strips,
+                                                        cx<T>* __restrict__ img,
+                                                        const int* __restrict__ pflag, int stage) {
   extern __shared__ c128 sh[];  // 3 KM^2
   if (pflag[blockIdx.y]) return;
   const StripDesc sd = strips[blockIdx.y];
@@ -844,7 +864,7 @@ __global__ __launch_bounds__(64) void k_build_products(const StripDesc* __restri
   const int ns = sd.ns, K = sd.kl, P = sd.segs, KM = map_dim(sd.KP), K2 = KM * KM;
   const int nseg = plan_nseg(ns, sd.pseg[plan]), gu = (nseg + P - 1) / P;
   const int t0 = sd.pmap[plan] - 1;  // slot of T_c is t0 + c
-  const int m = blockIdx.x, lane = threadIdx.x;
+  const int m = blockIdx.x, tid = threadIdx.x;
   const long long tri = blockIdx.z == 1 ? (long long)sd.tmaps : 0LL;
   const cx<T>* maps = img + sd.t_off + tri * K2;
   cx<T>* outm = img + sd.t_off + tri * K2;
@@ -853,16 +873,16 @@ __global__ __launch_bounds__(64) void k_build_products(const StripDesc* __restri
   c128* Z = sh + 2 * K2;
   auto load = [&](c128* d, int slot) {
     const cx<T>* src = maps + (long long)slot * K2;
-    for (int e0 = 0; e0 < K2; e0 += 8 * 64) {
-      cx<T> v[8];
+    for (int e0 = 0; e0 < K2; e0 += 4 * 256) {
+      cx<T> v[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = e0 + q * 64 + lane;
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * 256 + tid;
         v[q] = src[e < K2 ? e : K2 - 1];
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = e0 + q * 64 + lane;
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * 256 + tid;
         if (e < K2) d[e] = mk((double)v[q].re, (double)v[q].im);
       }
     }
@@ -870,25 +890,17 @@ __global__ __launch_bounds__(64) void k_build_products(const StripDesc* __restri
   };
   auto store = [&](int slot, const c128* src) {  // the K x K block; the padding stays zero
     cx<T>* d = outm + (long long)slot * K2;
-    for (int e = lane; e < K2; e += 64)
+    for (int e = tid; e < K2; e += 256)
       if (e % KM < K && e / KM < K) d[e] = mk((T)src[e].re, (T)src[e].im);
   };
-  auto mul = [&](c128* d, const c128* A, const c128* B) {  // d = A B (d distinct from A, B)
-    for (int c0 = 0; c0 < K; c0 += 16) {
-      c128 acc[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) acc[t] = mk(0.0, 0.0);
-      if (lane < K) {
-        for (int cc = 0; cc < K; ++cc) {
-          const c128 a = A[cc * KM + lane];
-#pragma unroll
-          for (int t = 0; t < 16; ++t)
-            if (c0 + t < K) acc[t] = acc[t] + a * B[(c0 + t) * KM + cc];
-        }
-#pragma unroll
-        for (int t = 0; t < 16; ++t)
-          if (c0 + t < K) d[(c0 + t) * KM + lane] = acc[t];
-      }
+  // d = A B over the K x K blocks (d distinct from A, B): thread e % 256
+  // forms entry (e mod K, e / K)
+  auto mul = [&](c128* d, const c128* A, const c128* B) {
+    for (int e = tid; e < K * K; e += 256) {
+      const int c = e / K, r = e - c * K;
+      c128 acc = mk(0.0, 0.0);
+      for (int cc = 0; cc < K; ++cc) acc = cfma(acc, A[cc * KM + r], B[c * KM + cc]);
+      d[c * KM + r] = acc;
     }
     __syncthreads();
   };
@@ -985,7 +997,7 @@ static void launch_products(const FactorSet& fs, hipStream_t st) {
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   for (int stage = 0; stage < 2; ++stage)
-    hipLaunchKernelGGL(k_build_products<T>, product_grid(fs, stage), dim3(64), lds, st,
+    hipLaunchKernelGGL(k_build_products<T>, product_grid(fs, stage), dim3(256), lds, st,
                        fs.d_strips, (cx<T>*)fs.img, fs.d_pflag, stage);
 }
 
@@ -1062,7 +1074,7 @@ static void launch_lu(const hh_problem* pb, size_t lds, hipStream_t st) {
 
 // Transfer maps of the segment plans in planmask (bit p: plan p).
 void launch_transfer(const FactorSet& fs, int planmask, hipStream_t st) {
-  const size_t lds = 64 * (size_t)(fs.max_kl + 1) * sizeof(c128);
+  const size_t lds = (size_t)(transfer_ring(fs.max_kl) + 16) * (fs.max_kl + 1) * sizeof(c128);
   if (fs.precision == HH_FP64) {
     HH_HIP(hipFuncSetAttribute((const void*)k_build_transfer<double>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
