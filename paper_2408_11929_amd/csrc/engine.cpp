@@ -113,6 +113,23 @@ int nblk_for(long long len, size_t nlive = 1) {
 }
 }  // namespace
 
+void PinnedBuf::reserve(size_t n, bool keep) {
+  if (n <= cap) return;
+  const size_t nc = std::max<size_t>(n * 2, 4096);
+  void* q = nullptr;
+  HH_HIP(hipHostMalloc(&q, nc, hipHostMallocDefault));
+  if (keep && p) std::memcpy(q, p, cap);
+  if (p) {
+    HH_HIP(hipDeviceSynchronize());  // no copy may still use the old buffer (grows are rare)
+    HH_HIP(hipHostFree(p));
+  }
+  p = (unsigned char*)q;
+  cap = nc;
+}
+PinnedBuf::~PinnedBuf() {
+  if (p) (void)hipHostFree(p);
+}
+
 Engine::Engine(hipStream_t st) : st_(st) {}
 Engine::~Engine() {
   if (task_dev_) dev_free(task_dev_);
@@ -123,8 +140,8 @@ Engine::~Engine() {
 template <class TT>
 TT* Engine::stage(const std::vector<TT>& v, size_t& off) {
   size_t bytes = (v.size() * sizeof(TT) + 255) & ~size_t(255);
-  if (task_host_.size() < off + bytes) task_host_.resize((off + bytes) * 2);
-  std::memcpy(task_host_.data() + off, v.data(), v.size() * sizeof(TT));
+  task_host_.reserve(off + bytes, true);
+  std::memcpy(task_host_.p + off, v.data(), v.size() * sizeof(TT));
   TT* d = reinterpret_cast<TT*>(off);  // resolved in upload()
   off += bytes;
   return d;
@@ -132,14 +149,14 @@ TT* Engine::stage(const std::vector<TT>& v, size_t& off) {
 
 // Copies the staged host descriptors to the device in one transfer.
 void Engine::upload() {
-  if (task_host_.size() < staged_) task_host_.resize(staged_);
+  task_host_.reserve(staged_, true);
   if (staged_ > task_cap_) {
     HH_HIP(hipStreamSynchronize(st_));
     if (task_dev_) dev_free(task_dev_);
     task_cap_ = staged_ * 2;
     task_dev_ = dev_alloc(task_cap_);
   }
-  if (staged_) HH_HIP(hipMemcpyAsync(task_dev_, task_host_.data(), staged_, hipMemcpyHostToDevice, st_));
+  if (staged_) HH_HIP(hipMemcpyAsync(task_dev_, task_host_.p, staged_, hipMemcpyHostToDevice, st_));
 }
 
 #define DEV(ptr) reinterpret_cast<std::remove_reference_t<decltype(ptr)>>((char*)task_dev_ + (size_t)(ptr))
@@ -575,19 +592,40 @@ void Engine::step(std::vector<Solve*>& solves) {
   }
 
   // ---- coefficients to the host, least squares, selection
+  // one pinned area: per solve its coefficients and flags, then the abort word
+  std::vector<size_t> hoff(live.size()), foff(live.size());
+  size_t dl = 0;
+  for (size_t q = 0; q < live.size(); ++q) {
+    hoff[q] = dl;
+    dl += HdLayout(live[q]->hcap, live[q]->t).total * sizeof(c128);
+    foff[q] = dl;
+    dl += (live[q]->t * sizeof(int) + 15) & ~size_t(15);
+  }
+  const size_t aoff = dl;
+  dl_host_.reserve(dl + sizeof(unsigned), false);
+  for (size_t q = 0; q < live.size(); ++q) {
+    Solve* s = live[q];
+    HdLayout L(s->hcap, s->t);
+    HH_HIP(hipMemcpyAsync(dl_host_.p + hoff[q], s->Hd, L.total * sizeof(c128),
+                          hipMemcpyDeviceToHost, st_));
+    HH_HIP(hipMemcpyAsync(dl_host_.p + foff[q], s->flags, s->t * sizeof(int),
+                          hipMemcpyDeviceToHost, st_));
+  }
+  if (sync_)
+    HH_HIP(hipMemcpyAsync(dl_host_.p + aoff, sync_, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
+  HH_HIP(hipStreamSynchronize(st_));
   std::vector<std::vector<int>> flags(live.size());
   for (size_t q = 0; q < live.size(); ++q) {
     Solve* s = live[q];
     HdLayout L(s->hcap, s->t);
     s->hbuf.resize(L.total);
-    HH_HIP(hipMemcpyAsync(s->hbuf.data(), s->Hd, L.total * sizeof(c128), hipMemcpyDeviceToHost, st_));
+    std::memcpy(s->hbuf.data(), dl_host_.p + hoff[q], L.total * sizeof(c128));
     flags[q].resize(s->t);
-    HH_HIP(hipMemcpyAsync(flags[q].data(), s->flags, s->t * sizeof(int), hipMemcpyDeviceToHost, st_));
+    std::memcpy(flags[q].data(), dl_host_.p + foff[q], s->t * sizeof(int));
   }
-  if (sync_)
-    HH_HIP(hipMemcpyAsync(&abort_host_, sync_, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
-  HH_HIP(hipStreamSynchronize(st_));
-  if (sync_ && abort_host_) {
+  unsigned abort_host = 0;
+  if (sync_) std::memcpy(&abort_host, dl_host_.p + aoff, sizeof(unsigned));
+  if (sync_ && abort_host) {
     set_error("sweep workgroups of one chain did not meet within the time limit");
     throw DeviceError();
   }

@@ -88,6 +88,19 @@ struct HdLayout {
   HdLayout(int m, int t);
 };
 
+// Growable pinned host buffer, so that copies to and from it run as direct
+// transfers.  A grow waits for the device before it frees the old buffer;
+// keep copies the old contents.
+struct PinnedBuf {
+  unsigned char* p = nullptr;
+  size_t cap = 0;
+  void reserve(size_t n, bool keep);
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf();
+};
+
 class Engine {
  public:
   explicit Engine(hipStream_t st);
@@ -108,7 +121,8 @@ class Engine {
   hipStream_t st_;
   void* task_dev_ = nullptr;
   size_t task_cap_ = 0;
-  std::vector<unsigned char> task_host_;
+  PinnedBuf task_host_;  // staged descriptors
+  PinnedBuf dl_host_;    // one iteration's coefficients, flags and abort word
   template <class TT>
   TT* stage(const std::vector<TT>& v, size_t& off);
   void upload();
@@ -121,7 +135,6 @@ class Engine {
   size_t sync_cap_ = 0;
   void* xch_ = nullptr;
   size_t xch_cap_ = 0;
-  unsigned abort_host_ = 0;
 };
 
 }  // namespace hh
