@@ -521,9 +521,12 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
     a[k] = csel(in, v, zero);
   }
   fetch(0);
-  // the pivot slot, the column of this slot, its logical column after the step
+  // the pivot slot, the column of this slot and its U-row offset (row 0 at
+  // ab[uoff + j]), its logical column after the step
   int c0 = 0, col = s, lcn = !act || s == 0 ? (act ? M - 1 : 0) : s - 1;
-  int badv = 0;  // this lane saw a step that needs an interchange or a zero pivot
+  long long uoff = (long long)col * (ldab - 1) + kv;
+  // positive once this lane saw a step that needs an interchange or a zero pivot
+  T badm = (T)-1;
   if (s == 0) {
 #pragma unroll
     for (int k = 0; k < R; ++k) colb[h * R + k] = a[k];
@@ -541,23 +544,20 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
       const int j = jc + u;
       const int rmax = min(kl, ns - 1 - j);
       wave_lds_sync();
-      // the pivot column as written by its slot: lane r's row, and every row
-      // of this lane's half
+      // the pivot column as written by its slot: the pivot, lane r's row,
+      // and every row of this lane's half
+      const cx<T> pv = colb[0];
       const cx<T> val = colb[s];
       cx<T> lr[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) lr[k] = colb[h * R + k];
-      const cx<T> pv = rdlc(lr[0], 0);
       const T pd = pv.re * pv.re + pv.im * pv.im;
       const T ipd = pd == (T)0 ? (T)0 : recip(pd);
       const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
-      const T av = lane <= rmax ? cabs1(val) : (T)-1;
-      badv |= (int)(av > rdl(av, 0)) | (int)(pd == (T)0 && j < ns);
-      if (lane >= 1 && lane <= rmax) ab[(long long)j * ldab + kv + lane] = val * ipv;
-      if (h == 0 && act && col < ns && j < ns) ab[(long long)col * (ldab - 1) + kv + j] = a[0];
       // row k of the half loses L(k) u0 = col(k) (u0 / pivot): the pivot
       // column is zero in the rows that have not entered and past the matrix
-      const cx<T> w = half0_to_both(a[0]) * ipv;
+      const cx<T> a0 = a[0];
+      const cx<T> w = half0_to_both(a0) * ipv;
       cx<T> t[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) t[k] = cfms(a[k], lr[k], w);
@@ -567,7 +567,8 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
       for (int k = 0; k + 1 < R; ++k) a[k] = t[k + 1];
       a[R - 1] = csel(h == 0, up, ein);
       // the next pivot slot passes its column before the retired slot
-      // reloads, so that the reload's wait overlaps the next step's
+      // reloads, so that the reload's wait overlaps the next step's; the
+      // stores and the pivot test are off that chain
       const int c1 = wrap(c0 + 1, M);
       if (s == c1) {
 #pragma unroll
@@ -576,13 +577,23 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
       if (s == c0) {
 #pragma unroll
         for (int k = 0; k < R; ++k) a[k] = nbuf[u * R2 + h * R + k];
+      }
+      const T av = lane <= rmax ? cabs1(val) : (T)-1;
+      // a running maximum, which the compiler keeps as one accumulator (an
+      // OR of the steps' comparisons it would keep alive to the chunk end)
+      const T d = pd == (T)0 && j < ns ? (T)1 : av - cabs1(pv);
+      badm = fmax(badm, d);
+      if (lane >= 1 && lane <= rmax) ab[(long long)j * ldab + kv + lane] = val * ipv;
+      if (h == 0 && act && col < ns && j < ns) ab[uoff + j] = a0;
+      if (s == c0) {
         col += M;
+        uoff += (long long)M * (ldab - 1);
       }
       c0 = c1;
       lcn = lcn == 0 ? M - 1 : lcn - 1;
     }
     if (lane < CH && jc + lane < ns) piv[jc + lane] = jc + lane;
-    if (__any(badv)) {
+    if (__any(badm > (T)0)) {
       if (lane == 0) pflag[blockIdx.x] = 2;
       return;
     }
