@@ -882,14 +882,18 @@ __device__ __forceinline__ bool chain_wait(ChainBar& b) {
   if (threadIdx.x == 0) {
     const long long t0 = wall_clock64();
     int ok = 1;
-    while (__hip_atomic_load(b.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b.need) {
-      if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > b.limit) {
+    // a poll is one round trip to L2; the abort word and the clock are
+    // looked at every eighth poll only, so that they do not double it
+    for (unsigned it = 0;
+         __hip_atomic_load(b.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b.need; ++it) {
+      if ((it & 7) == 0 &&
+          (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+           wall_clock64() - t0 > b.limit)) {
         __hip_atomic_store(b.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
     *b.ok = ok;
   }
@@ -924,14 +928,19 @@ __device__ __forceinline__ void map_row_load(MapRow<T, KM>& m, const cx<T>* M, i
 template <class T, int KM>
 __device__ __forceinline__ cx<T> map_apply_r(const MapRow<T, KM>& m, const cx<T>* x, cx<T> y,
                                              int K, int lane) {
+  static_assert(sizeof(T) == 4, "complex64 maps");
   const cx<T> zero = mk((T)0, (T)0);
   const cx<T>* xb = x + (lane >> 5);
   cx<T> a[4] = {zero, zero, zero, zero};
 #pragma unroll
   for (int q = 0; q < KM / 2; ++q) a[q & 3] = cfma(a[q & 3], m.v[q], xb[2 * q]);
-  cx<T> v = (a[0] + a[1]) + (a[2] + a[3]);
-  v = v + mk(__shfl_xor(v.re, 32), __shfl_xor(v.im, 32));
-  return csel(lane < K, v + y, zero);
+  const cx<T> v = (a[0] + a[1]) + (a[2] + a[3]);
+  // v_permlane32_swap gives every lane the row's entries of both halves
+  const auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.re), __float_as_uint(v.re), false, false);
+  const auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.im), __float_as_uint(v.im), false, false);
+  const cx<T> sum = mk(__uint_as_float(sr[0]) + __uint_as_float(sr[1]),
+                       __uint_as_float(si[0]) + __uint_as_float(si[1]));
+  return csel(lane < K, sum + y, zero);
 }
 
 // Map slots of one triangle for the wide plan (see plan_layout): maps[s] is
@@ -943,15 +952,16 @@ struct WideMaps {
 };
 
 // One triangular substitution of a strip by workgroup g of the chain's G
-// (steps 1-4 above), after between() (see step 1).  Phi: the segment
+// (steps 1-4 above), after before() and after() (see step 1).  Phi: the segment
 // responses (plan_phi_elems layout),
 // xch: exchange area (64 entries per workgroup).  LDS: the wave's ring (640
 // entries from ring), yt, kb, pw (64 entries per wave each: tails and
 // states, scan exchange, partial sums).  Returns false when the chain was
 // aborted.
-template <int KP, int U, int NB, bool EARLY_INPUTS, class Src, class Dst, class Between>
+template <int KP, int U, int NB, bool EARLY_INPUTS, class Src, class Dst, class Before,
+          class After>
 __device__ __forceinline__ bool solve_triangle_wide(
-    const Src& src, const Dst& dst, const c64* G, const Between& between,
+    const Src& src, const Dst& dst, const c64* G, const Before& before, const After& after,
     const WideMaps& mp, const c64* Phi, int ns, int K, int seg, int g, int Gw, c64* ring, c64* yt,
     c64* kb, c64* pw, gptr<c64> xch, ChainBar& bar) {
   using T = float;
@@ -963,17 +973,19 @@ __device__ __forceinline__ bool solve_triangle_wide(
   const int off = c * seg, len = c < nseg ? (ns - off < seg ? ns - off : seg) : 0;
   const SegDst<T, Dst> out{dst, off};
   auto mslot = [&](int s) { return mp.maps + (long long)s * KM * KM; };
-  // 1. zero-start solve.  Its first reads go out before between() runs (the
-  // caller's work that the triangle waits for: the maps always, the inputs
-  // when they do not depend on that work), so that their round trip overlaps
-  // it.
+  // 1. zero-start solve.  Its first reads go out between before() and
+  // after() (the caller's work that the triangle waits for: the maps always,
+  // the inputs when they do not depend on that work), so that their round
+  // trip overlaps it; a meeting's arrival, which waits for every access of
+  // the wave, belongs in before().
+  if (!before()) return false;
   const SegSrc<Src> ssrc{src, off, len};
   BlockedPre<T, KP, U, NB, SegSrc<Src>> pre;
   if (c < nseg) {
     blocked_fetch_maps(pre, (gptr<const c64>)(G + (long long)(off / 16) * KP * 64), lane);
     if (EARLY_INPUTS) blocked_fetch_inputs(pre, ssrc, lane);
   }
-  if (!between()) return false;
+  if (!after()) return false;
   if (c < nseg) {
     if (!EARLY_INPUTS) blocked_fetch_inputs(pre, ssrc, lane);
     solve_blocked_run(pre, ssrc, out, len, K, ring, (const c64*)nullptr, lane);
@@ -1133,27 +1145,36 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     mU.maps = T0 + tm * K2;
     const c64* PL = img + uni(sp->phi_off);
     const c64* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP));
-    // forward substitution: the transmission data are formed while its
-    // first reads are out
+    // forward substitution: its first reads (maps, residual) go out before
+    // the wait for the previous strip's meeting, the transmission data that
+    // need that strip's solution after it
+    auto none = []() { return true; };
     auto form_data = [&]() {
+      if (step > 0 && !chain_wait(bar)) return false;
       strip_data<T, AgentAcc>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd,
                               fwd && g == 0, t1off, t2off);
       __syncthreads();
       return true;
     };
     if (!solve_triangle_wide<KP, U, NB, true>(gather, DstVec<T, AgentAcc>{rho, ns, false}, GL,
-                                              form_data, mL, PL, ns, kl, seg, g, G, ring, yt, kb,
-                                              pw, xch, bar))
+                                              none, form_data, mL, PL, ns, kl, seg, g, G, ring,
+                                              yt, kb, pw, xch, bar))
       return;
     // back substitution: its inputs were written by every workgroup, so they
-    // are read after the meeting; its maps while the workgroups meet
-    auto meet = [&]() { return chain_meet(bar); };
+    // are read after the meeting; its maps between the arrival and the wait
+    auto arrive = [&]() {
+      chain_arrive(bar);
+      return true;
+    };
+    auto wait = [&]() { return chain_wait(bar); };
     if (!solve_triangle_wide<KP, U, NB, false>(SrcVec<T, AgentAcc>{(gptr<const c64>)rho, ns, true},
                                                DstScatter<T, AgentAcc>{z, ns, wd, n, a, dir, winv},
-                                               GU, meet, mU, PU, ns, kl, seg, g, G, ring, yt, kb,
-                                               pw, xch, bar))
+                                               GU, arrive, wait, mU, PU, ns, kl, seg, g, G, ring,
+                                               yt, kb, pw, xch, bar))
       return;
-    if (!chain_meet(bar)) return;
+    // the strip's outputs are complete: the next strip waits for this
+    // arrival in its forward substitution; the last needs no meeting
+    if (step < 2 * N - 2) chain_arrive(bar);
   }
 }
 
