@@ -616,6 +616,16 @@ struct SegDst {
   __device__ void put(int i, cx<T> v) const { b.put(off + i, v); }
   __device__ cx<T> get(int i) const { return b.get(off + i); }
 };
+template <class T, class Dst>
+struct SegDstIf {  // SegDst whose stores are dropped unless on
+  const Dst& b;
+  int off;
+  bool on;
+  __device__ void put(int i, cx<T> v) const {
+    if (on) b.put(off + i, v);
+  }
+  __device__ cx<T> get(int i) const { return b.get(off + i); }
+};
 template <class T>
 struct DstTail {  // keeps only the last K rows of a segment (in LDS)
   cx<T>* yt;
@@ -988,7 +998,11 @@ __device__ __forceinline__ bool solve_triangle_wide(
   if (!after()) return false;
   if (c < nseg) {
     if (!EARLY_INPUTS) blocked_fetch_inputs(pre, ssrc, lane);
-    solve_blocked_run(pre, ssrc, out, len, K, ring, (const c64*)nullptr, lane);
+    // a segment that step 4 corrects from its ring keeps its zero-start
+    // outputs there only: their stores would be overwritten unread, and the
+    // meeting's arrival would wait for them
+    const SegDstIf<T, Dst> zout{dst, off, c == 0 || len > 256};
+    solve_blocked_run(pre, ssrc, zout, len, K, ring, (const c64*)nullptr, lane);
     if (c < nseg - 1 && lane < K) yt[64 * w + lane] = ring[(len - K + lane) & 255];
   }
   if (nseg == 1) return true;
