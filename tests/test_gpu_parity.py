@@ -102,9 +102,16 @@ def test_load_vector_and_spmv(n, N, omega, c):
     pb.free()
 
 
+@pytest.mark.parametrize("lu", ["", "1"])
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
 @pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + PIVOTING)
-def test_strip_solves_match_lapack(n, N, omega, c, prec):
+def test_strip_solves_match_lapack(n, N, omega, c, prec, lu, monkeypatch):
+    # lu "": strips of band half-width < 32 are factored by the kernel that
+    # assumes no interchange, those that need one (PIVOTING) packed again and
+    # factored with interchanges; "1" (HH_LU_INTERCHANGE): every strip by the
+    # interchanging kernel
+    if lu:
+        monkeypatch.setenv("HH_LU_INTERCHANGE", lu)
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
     tol = 1e-12 if prec == hh.HH_FP64 else 1e-5
