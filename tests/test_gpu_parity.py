@@ -53,6 +53,12 @@ WIDE = [
     (65, 2, 40.0, [1.0, 1.6]),
     (97, 2, 50.0, [1.3, 0.9, 2.0]),
 ]
+# narrow strips (two intervals each: band half-widths 5-6) and strips shorter
+# than one staged chunk of LU column steps
+NARROW = [
+    (33, 16, 18.0, [1.0, 2.0]),
+    (9, 4, 6.0, [1.0]),
+]
 # under-resolved meshes whose strip factorisations pivot: every strip of the
 # first, only the x strips of the second (the y strips take the blocked path)
 PIVOTING = [
@@ -104,7 +110,7 @@ def test_load_vector_and_spmv(n, N, omega, c):
 
 @pytest.mark.parametrize("lu", ["", "1"])
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
-@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + PIVOTING)
+@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + NARROW + PIVOTING)
 def test_strip_solves_match_lapack(n, N, omega, c, prec, lu, monkeypatch):
     # lu "": strips of band half-width < 32 are factored by the kernel that
     # assumes no interchange, those that need one (PIVOTING) packed again and
@@ -136,7 +142,7 @@ def test_strip_solves_match_lapack(n, N, omega, c, prec, lu, monkeypatch):
 
 @pytest.mark.parametrize("plan", ["0", "1"])
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
-@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + PIVOTING)
+@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + NARROW + PIVOTING)
 def test_sweeps_match_oracle(n, N, omega, c, prec, plan, monkeypatch):
     # plan 0: one workgroup per chain; plan 1: eight (where the strips did not
     # pivot and the workgroup fits the LDS, else plan 0 again)
