@@ -539,7 +539,9 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
 #pragma unroll
     for (int t = 0; t < NB; ++t) nbuf[lane + 64 * t] = nn[t];
     fetch(jc + CH);
-#pragma unroll
+    // four steps per unrolled body: a whole chunk keeps so many per-step
+    // constants alive that they spill to lanes of a VGPR
+#pragma unroll 4
     for (int u = 0; u < CH; ++u) {
       const int j = jc + u;
       const int rmax = min(kl, ns - 1 - j);
