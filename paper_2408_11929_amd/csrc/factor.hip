@@ -797,7 +797,7 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
                         (long long)(s - 1) * seg * KM
                   : nullptr;
   const int s0 = s * seg, s1 = s0 + seg < ns ? s0 + seg : ns;
-  // lane c < K fetches T(i, c + 1), lane K the diagonal of row i (U only)
+  // lane c < K fetches T(i, c + 1)
   auto coef = [&](int i) -> c128 {
     const int j = ns - 1 - i, c = lane + 1;
     if (lane < K) {
@@ -805,22 +805,26 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
                             : ab[(long long)(i - c) * ldab + kv + c];
       return mk((double)x.re, (double)x.im);
     }
-    if (lane == K && upper) {
-      const cx<T> x = ab[(long long)j * ldab + kv];
-      return mk((double)x.re, (double)x.im);
-    }
-    return mk(lane == K ? 1.0 : 0.0, 0.0);
+    return mk(0.0, 0.0);
+  };
+  // the diagonal U(j, j) of row i, j = ns - 1 - i (U only)
+  auto diag = [&](int i) -> c128 {
+    const cx<T> x = ab[(long long)(ns - 1 - i) * ldab + kv];
+    return mk((double)x.re, (double)x.im);
   };
   // Each lane's recurrence touches only its own column of the window, so
   // the rows run without barriers; the coefficients come CR rows at a time
-  // through cb, loaded one chunk ahead.
+  // through cb, loaded one chunk ahead: lane c < K the row's T(i, c + 1),
+  // lane u < CR the scale of row i0 + u (the reciprocal of the diagonal for
+  // U, all CR of them at once; 1 for L).
   constexpr int CR = 16;
   const int RS = transfer_ring(W - 1), rm = RS - 1;
   c128* cb = win + RS * W;
-  c128 cr[CR];
+  c128 cr[CR], dg;
   auto fetch = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < CR; ++u) cr[u] = i0 + u < s1 ? coef(i0 + u) : mk(0.0, 0.0);
+    dg = upper && lane < CR && i0 + lane < s1 ? diag(i0 + lane) : mk(1.0, 0.0);
   };
   for (int q = 0; q < RS; ++q)
     if (lane < W) win[q * W + lane] = mk(0.0, 0.0);
@@ -829,10 +833,11 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
   const int lc = lane < W ? lane : W - 1;  // lanes past K read columns no lane writes
   for (int i0 = s0; i0 < s1; i0 += CR) {
     __syncthreads();  // the previous chunk's coefficients have been read
-    if (lane <= K) {
+    if (lane < K) {
 #pragma unroll
-      for (int u = 0; u < CR; ++u) cb[u * W + lane] = (lane == K && upper) ? cinv(cr[u]) : cr[u];
+      for (int u = 0; u < CR; ++u) cb[u * W + lane] = cr[u];
     }
+    if (lane < CR) cb[lane * W + K] = upper ? cinv(dg) : dg;
     fetch(i0 + CR);
     __syncthreads();
     const int un = s1 - i0 < CR ? s1 - i0 : CR;
