@@ -226,15 +226,24 @@ def main():
     if not args.no_batch:
         bcfg = wl.layered_321_batch(64)
         fb = torch.from_numpy(bcfg.f()).to("cuda")
+        hh.hh_timing_enable(True)
+        hh.hh_timing_reset()
         torch.cuda.synchronize()
         tb = time.perf_counter()
         stb, rcb = one_solve(hh, torch, bcfg, fb, hh.HH_FP32)
         torch.cuda.synchronize()
         tb = time.perf_counter() - tb
+        kb = {k: hh.hh_timing_get(k) for k in ("sweep", "spmv", "factor", "orth")}
+        hh.hh_timing_enable(False)
         batched = {"workload": bcfg.name, "rhs": 64, "seconds": tb, "solves_per_s": 64 / tb,
                    "iterations_max": max(s["iterations"] for s in stb),
                    "res_true_max": max(s["res_true"] for s in stb),
-                   "all_converged": all(s["converged"] for s in stb)}
+                   "all_converged": all(s["converged"] for s in stb),
+                   "kernel_ms": {k: v["ms"] for k, v in kb.items()},
+                   # algorithmic HBM rate of the multi-source sweeps and products
+                   "hbm_gbs": {k: kb[k]["bytes"] / 1e6 / kb[k]["ms"] if kb[k]["ms"] > 0 else 0.0
+                               for k in ("sweep", "spmv")}}
+        batched["hbm_frac"] = {k: v / HBM_PEAK_GBS for k, v in batched["hbm_gbs"].items()}
 
     serving = None if args.no_serve else serving_run(hh, torch)
 

@@ -782,7 +782,10 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     m -= c;
   }
   if (plan == HH_NPLAN || !(planmask >> plan & 1)) return;
-  const int seg = sd.pseg[plan], s = 1 + m, nseg = plan_nseg(ns, seg);
+  // (plan is not known at compile time: these come from global memory rather
+  // than from a private copy indexed at run time)
+  const int seg = strips[blockIdx.x].pseg[plan], pmap = strips[blockIdx.x].pmap[plan];
+  const int s = 1 + m, nseg = plan_nseg(ns, seg);
   const int lane = threadIdx.x;
   const bool upper = blockIdx.y == 1;
   const cx<T>* ab = band + sd.band_off;
@@ -791,7 +794,7 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
   const bool tmap = s <= nseg - 2;
   const int KM = map_dim(sd.KP);
   cx<T>* Tm = img + sd.t_off +
-              ((upper ? (long long)sd.tmaps : 0LL) + sd.pmap[plan] + m) * KM * KM;
+              ((upper ? (long long)sd.tmaps : 0LL) + pmap + m) * KM * KM;
   cx<T>* Ph = plan == HH_NPLAN - 1
                   ? img + sd.phi_off + (upper ? plan_phi_elems(ns, sd.segs, K, KM) : 0LL) +
                         (long long)(s - 1) * seg * KM
@@ -826,37 +829,71 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     for (int u = 0; u < CR; ++u) cr[u] = i0 + u < s1 ? coef(i0 + u) : mk(0.0, 0.0);
     dg = upper && lane < CR && i0 + lane < s1 ? diag(i0 + lane) : mk(1.0, 0.0);
   };
+  // The response rows of a chunk go out from the window once the chunk is
+  // done, sixteen lanes per column so that each column's rows are written as
+  // one contiguous run (rows f0 .. f0 + fn - 1; the ring keeps a chunk's rows
+  // until the chunk after next).
+  auto flush = [&](int f0, int fn) {
+    for (int e = lane; e < K * CR; e += 64) {
+      const int c = e / CR, u = e % CR;
+      if (u < fn) {
+        const c128 v = win[((f0 + u) & rm) * W + c];
+        Ph[(long long)c * seg + (f0 + u - s0)] = mk((T)v.re, (T)v.im);
+      }
+    }
+  };
   for (int q = 0; q < RS; ++q)
     if (lane < W) win[q * W + lane] = mk(0.0, 0.0);
   if (lane < K) win[((s0 - K + lane) & rm) * W + lane] = mk(1.0, 0.0);
   fetch(s0);
-  const int lc = lane < W ? lane : W - 1;  // lanes past K read columns no lane writes
+  // The workgroup is one wave (64 threads), so ordering its LDS accesses
+  // needs no barrier: wave_lds_sync keeps the coefficient loads of the next
+  // chunk and the stores in flight while the rows run.
   for (int i0 = s0; i0 < s1; i0 += CR) {
-    __syncthreads();  // the previous chunk's coefficients have been read
+    wave_lds_sync();  // the previous chunk's coefficients and rows are done
     if (lane < K) {
 #pragma unroll
       for (int u = 0; u < CR; ++u) cb[u * W + lane] = cr[u];
     }
     if (lane < CR) cb[lane * W + K] = upper ? cinv(dg) : dg;
+    // after the coefficient registers are consumed, so that waiting for
+    // them does not wait for these stores as well
+    if (Ph && i0 > s0) flush(i0 - CR, CR);
     fetch(i0 + CR);
-    __syncthreads();
+    wave_lds_sync();
     const int un = s1 - i0 < CR ? s1 - i0 : CR;
-    for (int u = 0; u < un; ++u) {
-      const int i = i0 + u;
-      const c128* cf = cb + u * W;
-      c128 acc = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
-      int c = 1;
-      for (; c + 1 <= K; c += 2) {
-        acc = cfms(acc, cf[c - 1], win[((i - c) & rm) * W + lc]);
-        acc1 = cfms(acc1, cf[c], win[((i - c - 1) & rm) * W + lc]);
+    // lanes past K have no column: they stay out of the rows, which keeps the
+    // LDS reads to the K live lanes
+    if (lane < K) {
+      for (int u = 0; u < un; ++u) {
+        const int i = i0 + u;
+        const c128* cf = cb + u * W;
+        // eight terms at a time, their LDS reads issued together, into four
+        // partial sums
+        c128 a[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+        int c = 1;
+        for (; c + 7 <= K; c += 8) {
+          c128 wv[8], fv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            wv[q] = win[((i - c - q) & rm) * W + lane];
+            fv[q] = cf[c - 1 + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) a[q & 3] = cfms(a[q & 3], fv[q], wv[q]);
+        }
+        for (; c <= K; ++c) a[0] = cfms(a[0], cf[c - 1], win[((i - c) & rm) * W + lane]);
+        const c128 acc = ((a[0] + a[1]) + (a[2] + a[3])) * cf[K];
+        win[(i & rm) * W + lane] = acc;
+        if (tmap && i >= s1 - K)
+          Tm[(long long)lane * KM + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
       }
-      if (c <= K) acc = cfms(acc, cf[c - 1], win[((i - c) & rm) * W + lc]);
-      acc = (acc + acc1) * cf[K];
-      if (lane < K) win[(i & rm) * W + lane] = acc;
-      if (tmap && lane < K && i >= s1 - K)
-        Tm[(long long)lane * KM + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
-      if (Ph && lane < K) Ph[(long long)lane * seg + (i - s0)] = mk((T)acc.re, (T)acc.im);
     }
+  }
+  if (Ph) {
+    wave_lds_sync();
+    const int fl = s0 + (s1 - s0 - 1) / CR * CR;  // the last chunk
+    flush(fl, s1 - fl);
   }
 }
 
