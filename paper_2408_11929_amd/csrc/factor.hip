@@ -900,27 +900,29 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
 // Products of segment maps for the wide plan (slots in plan_layout), formed
 // in FP64 from the stored maps.  Stage 0, for workgroup g (segments c = g P
 // + w): the running product T_{gP+q-1} ... T_{gP}, stored as Pi_{gP+q} for
-// q < P and as W_g for q = P (job 0 of the workgroup), and A1_c = T_c T_{c-1}
-// (job w + 1, w >= 2).  Stage 1: A2_c = A1_c A1_{c-2} (w >= 4) and, for
+// q < P and as W_g for q = P (the chain of workgroup g), and A1_c = T_c
+// T_{c-1} (w >= 2).  Stage 1: A2_c = A1_c A1_{c-2} (w >= 4) and, for
 // workgroup g, the running product W_{g-1} ... W_{j+1} = Psi_{j,g} for j =
-// g-2 down to 0.  One workgroup of 256 threads per (job, strip, triangle); the
-// maps involved are copied into LDS (three KM x KM buffers in FP64,
-// column-major like the stored maps) and the 256 threads share the entries
-// of a product.
+// g-2 down to 0 (its chain).  One workgroup of 256 threads per (strip,
+// triangle, job); jobs 0 .. G-1 of a stage are the chains, so that with the
+// job as the slowest grid index every chain is dispatched before the single
+// products.  The maps involved are copied into LDS (three KM x KM buffers in
+// FP64, column-major like the stored maps) and the 256 threads share the
+// entries of a product.
 template <class T>
 __global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restrict__ strips,
                                                         cx<T>* __restrict__ img,
                                                         const int* __restrict__ pflag, int stage) {
   extern __shared__ c128 sh[];  // 3 KM^2
-  if (pflag[blockIdx.y]) return;
-  const StripDesc sd = strips[blockIdx.y];
+  if (pflag[blockIdx.x]) return;
+  const StripDesc sd = strips[blockIdx.x];
   if (!sd.wide) return;
   const int plan = HH_NPLAN - 1, G = plan_width(plan);
   const int ns = sd.ns, K = sd.kl, P = sd.segs, KM = map_dim(sd.KP), K2 = KM * KM;
   const int nseg = plan_nseg(ns, sd.pseg[plan]), gu = (nseg + P - 1) / P;
   const int t0 = sd.pmap[plan] - 1;  // slot of T_c is t0 + c
-  const int m = blockIdx.x, tid = threadIdx.x;
-  const long long tri = blockIdx.z == 1 ? (long long)sd.tmaps : 0LL;
+  const int m = blockIdx.z, tid = threadIdx.x;
+  const long long tri = blockIdx.y == 1 ? (long long)sd.tmaps : 0LL;
   const cx<T>* maps = img + sd.t_off + tri * K2;
   cx<T>* outm = img + sd.t_off + tri * K2;
   c128* X = sh;
@@ -960,7 +962,8 @@ __global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restr
     __syncthreads();
   };
   if (stage == 0) {
-    const int g = m / (P + 1), k = m % (P + 1);
+    // job m < G: the chain of workgroup m (k = 0); else A1 job k = 1 + (m - G) mod P
+    const int g = m < G ? m : (m - G) / P, k = m < G ? 0 : 1 + (m - G) % P;
     if (g >= gu) return;
     if (k == 0) {
       if (g == 0 || g * P > nseg - 2) return;
@@ -991,15 +994,15 @@ __global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restr
       mul(Z, X, Y);
       store(sd.a1_map + c - 1, Z);
     }
-  } else if (m < G * P) {
-    const int g = m / P, w = m % P, c = g * P + w;
+  } else if (m >= G) {
+    const int g = (m - G) / P, w = (m - G) % P, c = g * P + w;
     if (g >= gu || w < 4 || c > nseg - 2) return;
     load(X, sd.a1_map + c - 1);
     load(Y, sd.a1_map + c - 3);
     mul(Z, X, Y);
     store(sd.a2_map + c - 1, Z);
   } else {
-    const int g = m - G * P;
+    const int g = m;
     if (G < 3 || g < 2 || g > gu - 1) return;
     c128* cur = X;
     c128* nxt = Y;
@@ -1040,7 +1043,7 @@ static dim3 product_grid(const FactorSet& fs, int stage) {
     const int G = plan_width(HH_NPLAN - 1);
     jobs = std::max(jobs, stage == 0 ? G * (sd.segs + 1) : G * sd.segs + G);
   }
-  return dim3((unsigned)jobs, (unsigned)fs.strips.size(), 2);
+  return dim3((unsigned)fs.strips.size(), 2, (unsigned)jobs);
 }
 
 template <class T>
