@@ -240,7 +240,7 @@ def main():
                    "res_true_max": max(s["res_true"] for s in stb),
                    "all_converged": all(s["converged"] for s in stb),
                    "kernel_ms": {k: v["ms"] for k, v in kb.items()},
-                   # algorithmic HBM rate of the multi-source sweeps and products
+                   # algorithmic HBM rates of the batch's sweeps and sparse products (GB/s)
                    "hbm_gbs": {k: kb[k]["bytes"] / 1e6 / kb[k]["ms"] if kb[k]["ms"] > 0 else 0.0
                                for k in ("sweep", "spmv")}}
         batched["hbm_frac"] = {k: v / HBM_PEAK_GBS for k, v in batched["hbm_gbs"].items()}
