@@ -100,13 +100,36 @@ struct Pending {
   double bytes;
 };
 std::vector<Pending> g_pending;
+// Events are reused rather than created per region (creation costs host time
+// inside the iteration loop).  They only time work, so they skip the
+// system-scope fence: no cache write-back and invalidation at each record.
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+  {
+    std::lock_guard<std::mutex> lk(g_t_mu);
+    if (!g_event_pool.empty()) {
+      hipEvent_t e = g_event_pool.back();
+      g_event_pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+  return e;
+}
 }  // namespace
 
 bool timing_on() { return g_t_on; }
 
 TimedRegion::TimedRegion(int family, hipStream_t s, double b) : fam(family), st(s), bytes(b) {
   if (!g_t_on) return;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  e0 = take_event();
+  e1 = take_event();
+  if (!e0 || !e1) {
+    std::lock_guard<std::mutex> lk(g_t_mu);
+    for (hipEvent_t e : {e0, e1})
+      if (e) g_event_pool.push_back(e);
     e0 = e1 = nullptr;
     return;
   }
@@ -129,8 +152,8 @@ void timing_flush() {
       g_fam[p.fam].ms += ms;
       g_fam[p.fam].bytes += p.bytes;
     }
-    (void)hipEventDestroy(p.e0);
-    (void)hipEventDestroy(p.e1);
+    g_event_pool.push_back(p.e0);
+    g_event_pool.push_back(p.e1);
   }
   g_pending.clear();
 }
