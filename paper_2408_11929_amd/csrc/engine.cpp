@@ -361,6 +361,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       it->tasks.push_back(tk);
     }
   }
+  size_t wide_chains = 0;
   {
     size_t chains = 0, xbytes = 0;
     for (Kind& k : kinds) {
@@ -382,6 +383,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         sync_cap_ = sbytes * 2;
         sync_ = (unsigned*)dev_alloc(sync_cap_);
         HH_HIP(hipMemsetAsync(sync_, 0, sync_cap_, st_));
+        sync_clear_ = sync_cap_ / 128 - 1;
       }
       if (xbytes > xch_cap_) {
         HH_HIP(hipStreamSynchronize(st_));
@@ -389,8 +391,11 @@ void Engine::step(std::vector<Solve*>& solves) {
         xch_cap_ = xbytes * 2;
         xch_ = dev_alloc(xch_cap_);
       }
-      // arrival counters start from zero in every launch
-      HH_HIP(hipMemsetAsync(sync_ + 32, 0, chains * 128, st_));
+      // arrival counters start from zero in every launch; normally the
+      // previous launch's lines were cleared behind it (below)
+      if (chains > sync_clear_) HH_HIP(hipMemsetAsync(sync_ + 32, 0, chains * 128, st_));
+      sync_clear_ = 0;
+      wide_chains = chains;
       size_t ci = 0, xo = 0;
       for (Kind& k : kinds) {
         if (k.plan == 0) continue;
@@ -560,6 +565,12 @@ void Engine::step(std::vector<Solve*>& solves) {
       launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].KP,
                    kinds[q].P, kinds[q].kmax, kinds[q].nmax, kinds[q].piv, kinds[q].plan, sync_,
                    st_);
+  }
+  if (wide_chains > 0) {
+    // zero the counters for the next launch now, behind this one on the
+    // stream, rather than between the host's update and the next sweep
+    HH_HIP(hipMemsetAsync(sync_ + 32, 0, wide_chains * 128, st_));
+    sync_clear_ = wide_chains;
   }
   {
     double bytes = 0;

@@ -133,6 +133,7 @@ class Engine {
   bool wide_ok_ = true;
   unsigned* sync_ = nullptr;
   size_t sync_cap_ = 0;
+  size_t sync_clear_ = 0;  // chain lines zeroed since their last launch
   void* xch_ = nullptr;
   size_t xch_cap_ = 0;
 };
