@@ -25,6 +25,14 @@ Reading c8: the backward solve on strip s reuses the g_{s,1} that was formed
 from v_{s-1} in the forward sweep, as eq. (3b) states.  The alternative
 (recomputing it from the current global vector) is kept behind a flag.
 
+Single sweeps (Sec. 4, the LR, RL, BT and TB preconditioners of Table 1):
+one pass of eq. (2) only.  The forward order (LR in x, BT in y) solves
+s = 1..N with the data of the previous solve on Gamma_{s,1} and zero data on
+Gamma_{s,2}; the reverse order (RL, TB) solves s = N..1 with the data of the
+previous solve on Gamma_{s,2} and zero data on Gamma_{s,1}.  Each is N strip
+solves, and in the overlaps the most recent solve wins (the highest-index
+strip for the forward order, the lowest for the reverse order).
+
 Strip solves use LAPACK band LU with partial pivoting (zgbtrf / zgbtrs, or
 cgbtrf / cgbtrs for the complex64 diagnostic), standing in for the sparse
 direct solver of Sec. 4.
@@ -151,3 +159,47 @@ class DoubleSweep:
             e[p] = 1
             out[:, p] = self.apply(e)
         return out
+
+
+class SingleSweep(DoubleSweep):
+    """M^{-1} of one single sweep (Sec. 4, Table 1): order 'forward' is LR
+    (direction 'x') or BT ('y'), order 'reverse' is RL ('x') or TB ('y').
+    Same strips, strip matrices and transmission data as the double sweep."""
+
+    def __init__(self, omega, c_layers, n, N, direction, order="forward", A=None,
+                 precision="fp64"):
+        if order not in ("forward", "reverse"):
+            raise ValueError("order must be 'forward' or 'reverse'")
+        super().__init__(omega, c_layers, n, N, direction, A=A, precision=precision)
+        self.order = order
+
+    def apply(self, r):
+        """z = M^{-1} r: N strip solves in the sweep's order, each with the
+        transmission data of the previous solve on the interface it faces."""
+        N = self.N
+        r = np.asarray(r).astype(self.dtype)
+        z = np.zeros(self.n * self.n, dtype=self.dtype)
+        if self.order == "forward":
+            for s in range(N):            # Gamma_{s,1} data of v_{s-1}, zero on Gamma_{s,2}
+                z[self.idx[s]] = self.solvers[s].solve(r[self.idx[s]] + self.transmission(s, 1, z))
+        else:
+            for s in range(N - 1, -1, -1):  # Gamma_{s,2} data of v_{s+1}, zero on Gamma_{s,1}
+                z[self.idx[s]] = self.solvers[s].solve(r[self.idx[s]] + self.transmission(s, 2, z))
+        return z
+
+    def strip_solve_count(self):
+        return self.N
+
+
+def preconditioner(omega, c_layers, n, N, name, A=None, precision="fp64"):
+    """The preconditioner named as in Sec. 4: LRL, BTB (double sweeps), LR, RL,
+    BT, TB (single sweeps)."""
+    table = {"LRL": (st.X, None), "BTB": (st.Y, None),
+             "LR": (st.X, "forward"), "RL": (st.X, "reverse"),
+             "BT": (st.Y, "forward"), "TB": (st.Y, "reverse")}
+    if name not in table:
+        raise ValueError(f"unknown preconditioner {name!r}")
+    d, order = table[name]
+    if order is None:
+        return DoubleSweep(omega, c_layers, n, N, d, A=A, precision=precision)
+    return SingleSweep(omega, c_layers, n, N, d, order=order, A=A, precision=precision)

@@ -162,3 +162,21 @@ def test_direct_band_and_sparse_agree():
     x3 = spla.spsolve(A.tocsc(), b)
     assert np.linalg.norm(x1 - x3) < 1e-10 * np.linalg.norm(x3)
     assert np.linalg.norm(x2 - x3) < 1e-10 * np.linalg.norm(x3)
+
+
+@pytest.mark.parametrize("names", [("LR", "RL"), ("LR", "BT", "RL", "TB")])
+def test_single_sweep_combinations_reach_the_direct_solution(names):
+    # Table 1's single-sweep combinations: the cross rule for t = 2 (LR+RL) and
+    # the sum rule for t = 4 (LR+BT+RL+TB), run to a tight tolerance.
+    n, N, omega, c = 33, 4, 16.0, [1.0, 2.0, 1.5]
+    A = asm.assemble(omega, c, n)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
+    b = asm.source_load(n, f)
+    precs = [sw.preconditioner(omega, c, n, N, nm, A=A).apply for nm in names]
+    res = mp.mpgmres(A, precs, b, tol=1e-10, maxit=100)
+    assert res.converged
+    hist = np.asarray(res.res_hist)
+    assert np.all(hist[1:] <= hist[:-1] * (1 + 1e-14))
+    xd = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(res.x - xd) < 1e-7 * np.linalg.norm(xd)

@@ -271,3 +271,89 @@ def test_complex64_diagnostic_close_to_fp64():
     assert z32.dtype == np.complex64
     err = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
     assert 1e-9 < err < 1e-4
+
+
+# ---------------------------------------------------------------- single sweeps
+# LR / RL / BT / TB of Sec. 4 (Table 1): one pass of eq. (2) in either order.
+
+@pytest.mark.parametrize("direction", [st.X, st.Y])
+@pytest.mark.parametrize("order", ["forward", "reverse"])
+def test_single_sweep_one_strip_is_exact_inverse(direction, order):
+    n, omega, c = 13, 11.0, [1.0, 1.7, 2.3]
+    S = sw.SingleSweep(omega, c, n, 1, direction, order=order)
+    r = _rand(n * n, 31)
+    z = S.apply(r)
+    assert np.linalg.norm(S.A @ z - r) < 1e-12 * np.linalg.norm(r)
+
+
+def _block_system_single(S, r):
+    """One pass of eq. (2) as a block lower-triangular system in v_1..v_N (in the
+    sweep's order), solved at once by a sparse direct solver; each node then
+    takes the value of the last strip in the sweep's order that contains it."""
+    N, n = S.N, S.n
+    order = list(range(N)) if S.order == "forward" else list(range(N - 1, -1, -1))
+    side = 1 if S.order == "forward" else 2
+    sizes = [len(S.idx[s]) for s in order]
+    offs = np.cumsum([0] + sizes)
+    big = sp.lil_matrix((offs[-1], offs[-1]), dtype=complex)
+    rhs = np.zeros(offs[-1], dtype=complex)
+    eye = sp.identity(n * n, format="csr")
+    for k, s in enumerate(order):
+        B = sp.coo_matrix(S.As[s])
+        big[offs[k] + B.row, offs[k] + B.col] = B.data
+        rhs[offs[k]:offs[k + 1]] = r[S.idx[s]]
+        if k > 0:
+            prev = order[k - 1]
+            rows = S.rows1[s] if side == 1 else S.rows2[s]
+            keep = sp.diags(np.isin(np.arange(len(S.idx[s])), rows).astype(float))
+            full = S.As[s] @ eye[S.idx[s]] - S.A[S.idx[s]]
+            m = len(S.idx[prev])
+            ext = sp.csr_matrix((np.ones(m), (S.idx[prev], np.arange(m))), shape=(n * n, m))
+            C = sp.coo_matrix(-(keep @ full @ ext))
+            big[offs[k] + C.row, offs[k - 1] + C.col] = C.data
+    sol = spla.spsolve(big.tocsc(), rhs)
+    z = np.zeros(n * n, dtype=complex)
+    for k, s in enumerate(order):                    # later strips overwrite
+        z[S.idx[s]] = sol[offs[k]:offs[k + 1]]
+    return z
+
+
+@pytest.mark.parametrize("direction,N,order", [(st.X, 3, "forward"), (st.X, 3, "reverse"),
+                                               (st.Y, 4, "forward"), (st.Y, 2, "reverse")])
+def test_single_sweep_matches_block_triangular_system(direction, N, order):
+    n, omega, c = 13, 9.0, [1.0, 2.2, 1.6]
+    S = sw.SingleSweep(omega, c, n, N, direction, order=order)
+    for seed in range(2):
+        r = _rand(n * n, 40 + seed)
+        z = S.apply(r)
+        zb = _block_system_single(S, r)
+        assert np.linalg.norm(z - zb) < 1e-11 * np.linalg.norm(zb)
+
+
+@pytest.mark.parametrize("direction", [st.X, st.Y])
+def test_reverse_sweep_is_rotated_forward_sweep(direction):
+    # The half-turn (i, j) -> (n-1-i, n-1-j) maps the "/" triangulation, the
+    # impedance boundary and, for a constant speed, the operator onto
+    # themselves, and strip s onto strip N+1-s with its two interfaces
+    # exchanged: RL = Rot o LR o Rot (Rot reverses the node order).
+    n, N, omega = 17, 4, 10.0
+    F = sw.SingleSweep(omega, [1.0], n, N, direction, order="forward")
+    B = sw.SingleSweep(omega, [1.0], n, N, direction, order="reverse")
+    r = _rand(n * n, 6)
+    zb = B.apply(r)
+    zf = F.apply(r[::-1])[::-1]
+    assert np.linalg.norm(zb - zf) < 1e-12 * np.linalg.norm(zb)
+    # and the reverse sweep is a different operator from the forward one
+    assert np.linalg.norm(zb - F.apply(r)) > 1e-3 * np.linalg.norm(zb)
+
+
+def test_preconditioner_names():
+    n, N, omega = 13, 3, 8.0
+    r = _rand(n * n, 8)
+    for name, cls, d in [("LRL", sw.DoubleSweep, st.X), ("BTB", sw.DoubleSweep, st.Y),
+                         ("LR", sw.SingleSweep, st.X), ("RL", sw.SingleSweep, st.X),
+                         ("BT", sw.SingleSweep, st.Y), ("TB", sw.SingleSweep, st.Y)]:
+        P = sw.preconditioner(omega, [1.0], n, N, name)
+        assert type(P) is cls and P.direction == d
+        assert P.strip_solve_count() == (2 * N - 1 if cls is sw.DoubleSweep else N)
+        assert np.all(np.isfinite(P.apply(r)))
