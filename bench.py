@@ -116,6 +116,23 @@ def serving_run(hh, torch, count=24, rate=8.0, max_active=16, budget_gb=96):
             "res_true_max": max(done[t]["res_true_max"] for t in tickets)}
 
 
+def serve_sweep(hh, torch, count=64, max_active=16, budget_gb=96):
+    """The serving stream at arrival rates 0.25, 0.5, 0.75 and 1.0 times its
+    capacity, the capacity being measured first in a closed loop (every
+    request submitted at once)."""
+    closed = serving_run(hh, torch, count=count, rate=1e9, max_active=max_active,
+                         budget_gb=budget_gb)
+    cap = closed["requests_per_s"]
+    runs = []
+    for frac in (0.25, 0.5, 0.75, 1.0):
+        r = serving_run(hh, torch, count=count, rate=frac * cap, max_active=max_active,
+                        budget_gb=budget_gb)
+        r["load"] = frac
+        runs.append(r)
+    return {"serve_sweep": True, "requests_per_run": count, "closed_loop": closed,
+            "capacity_requests_per_s": cap, "runs": runs}
+
+
 def kernel_probe(hh, torch):
     """Short run for hardware-counter passes: one 512 MiB device copy (the
     calibration kernel: 512 MiB read, 512 MiB written) and one complex64 solve
@@ -134,20 +151,12 @@ def kernel_probe(hh, torch):
     print(json.dumps({"probe": "done", "iterations": st[0]["iterations"]}))
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The oracle (FP64, NumPy/SciPy) on this host's cores: whole solves of the
-    same workload until about budget_s seconds of CPU work have been spent."""
-    import numpy as np  # noqa: F401
+def _oracle_solves(cfg, budget_s, max_solves):
     from oracle import assemble as oasm
     from oracle import mpgmres as omp
     from oracle import strips as ost
     from oracle import sweep as osw
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)   # one core: the count reported below
-    except Exception:
-        limiter = None
-    times = []
+    times, res = [], None
     t_start = time.perf_counter()
     while True:
         t0 = time.perf_counter()
@@ -157,15 +166,42 @@ def cpu_baseline(cfg, budget_s=20.0):
         SY = osw.DoubleSweep(cfg.omega, cfg.c_layers, cfg.n, cfg.nstrips, ost.Y, A=A)
         res = omp.mpgmres(A, [SX.apply, SY.apply], b, tol=cfg.tol, maxit=cfg.maxit)
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s or len(times) >= 5:
+        if time.perf_counter() - t_start > budget_s or len(times) >= max_solves:
             break
-    if limiter is not None:
-        limiter.unregister()
-    return {"value": len(times) / sum(times), "unit": "solves/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{len(times)} whole solves (assembly, strip LU, MPGMRES) of the benchmark "
-                      f"workload, FP64 NumPy/SciPy, {res.iterations} iterations each",
-            "iterations": res.iterations}
+    return times, res
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    """The oracle (FP64, NumPy/SciPy) on this host: whole solves of the same
+    workload until about budget_s seconds have been spent, once with the BLAS
+    and LAPACK thread pools on every usable core (the reported value) and once
+    on one core."""
+    cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
+    out = {}
+    for label, ncore in (("all", cores), ("one", 1)):
+        limiter = threadpool_limits(limits=ncore) if threadpool_limits else None
+        times, res = _oracle_solves(cfg, budget_s, 5)
+        if limiter is not None:
+            limiter.unregister()
+        out[label] = (len(times) / sum(times), len(times), res.iterations)
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    v, k, its = out["all"]
+    return {"value": v, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} whole solves (assembly, strip LU, MPGMRES) of the benchmark workload, "
+                      f"FP64 NumPy/SciPy with BLAS/LAPACK threads = {cores}, {its} iterations each",
+            "one_core": {"value": out["one"][0], "solves": out["one"][1]},
+            "cpu_model": cpu, "iterations": its}
 
 
 def main():
@@ -176,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-source batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only the serving stream at 0.25-1.0 x its measured capacity")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only the short run used for hardware-counter passes")
     args = ap.parse_args()
@@ -192,6 +230,9 @@ def main():
 
     if args.kernel_probe:
         kernel_probe(hh, torch)
+        return
+    if args.serve_sweep:
+        print(json.dumps(serve_sweep(hh, torch)))
         return
 
     cfg = wl.layered_321()
@@ -247,6 +288,20 @@ def main():
 
     serving = None if args.no_serve else serving_run(hh, torch)
 
+    # both precisions on the same segment plan (one workgroup per chain), so
+    # that the ratio measures the precision alone
+    os.environ["HH_SWEEP_PLAN"] = "0"
+    try:
+        eq_steps = max(2, min(args.steps, 3))
+        lat32e, _ = timed_steps(hh, torch, cfg, f_dev, hh.HH_FP32, eq_steps)
+        lat64e, _ = timed_steps(hh, torch, cfg, f_dev, hh.HH_FP64, eq_steps)
+    finally:
+        del os.environ["HH_SWEEP_PLAN"]
+    equal_plan = {"plan": "one workgroup per chain (HH_SWEEP_PLAN=0) for both",
+                  "c64_solves_per_s": len(lat32e) / sum(lat32e),
+                  "c128_solves_per_s": len(lat64e) / sum(lat64e),
+                  "ratio": sum(lat64e) / sum(lat32e)}
+
     value = args.steps / wall32
     achieved = sweep["bytes"] / 1e9 / (sweep["ms"] / 1e3) if sweep["ms"] > 0 else 0.0
     traffic = traffic_record(os.path.join(ROOT, "paper_2408_11929_amd", "csrc", "sweep.hip"))
@@ -273,6 +328,7 @@ def main():
                                       "p99": 1e3 * percentile(lat64, 0.99)},
                        "iterations": st64[0]["iterations"], "res_true": st64[0]["res_true"]},
         "speedup_vs_plain_fp64": (args.steps / wall32) / (args.steps / wall64),
+        "speedup_equal_plan": equal_plan,
         "batched": batched,
         "serving": serving,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in

@@ -47,6 +47,14 @@ extern "C" {
 #define HH_DIR_X 1u        /* LRL: strips in x, swept left to right and back  */
 #define HH_DIR_Y 2u        /* BTB: strips in y, swept bottom to top and back  */
 
+/* Preconditioner kinds (Sec. 4, Table 1): double sweeps and single sweeps. */
+#define HH_PRE_LRL 1       /* x: left to right, then back to the left        */
+#define HH_PRE_BTB 2       /* y: bottom to top, then back to the bottom      */
+#define HH_PRE_LR 3        /* x: one forward sweep, left to right            */
+#define HH_PRE_RL 4        /* x: one forward sweep, right to left            */
+#define HH_PRE_BT 5        /* y: one forward sweep, bottom to top            */
+#define HH_PRE_TB 6        /* y: one forward sweep, top to bottom            */
+
 #define HH_FP64 0          /* strip factors and sweeps in complex128          */
 #define HH_FP32 1          /* strip factors and sweeps in complex64           */
 
@@ -80,6 +88,30 @@ typedef struct {
  *   out        receives a new problem handle (free with hh_free)
  * Errors: HH_EINVAL for bad arguments, HH_ENOMEM, HH_EDEVICE. */
 int hh_assemble(double omega, int nlayers, const double* c_layers, int n, hh_problem** out);
+
+/* Wave-speed field of eq. (1) (k = omega / c) for hh_assemble_field: either
+ * a function c(x, y) that the library samples on the host at every triangle
+ * centroid and every mesh-edge midpoint (4 n^2 calls or so; it must return a
+ * positive finite speed), or, with speed == NULL, the layer table of
+ * hh_assemble. */
+typedef double (*hh_speed_fn)(double x, double y, void* ctx);
+typedef struct {
+  hh_speed_fn speed;        /* or NULL: use nlayers / c_layers                */
+  void* ctx;                /* passed to speed                                */
+  int nlayers;              /* equal horizontal layers, layer 0 at the bottom */
+  const double* c_layers;   /* host pointer, nlayers speeds                   */
+} hh_cfield;
+
+/* hh_assemble for a general speed field (eq. (1)): the P1 operator with the
+ * wave number omega / c(centroid) on each triangle and omega / c(midpoint) on
+ * each edge (boundary edges in A, interface edges in the strip operators of
+ * eq. (4)).  f: NULL, or a device pointer to n*n hh_c128 nodal source values;
+ * then b = -M f is formed and kept with the problem, and hh_mpgmres with
+ * b == NULL and nrhs == 1 solves for it.  Errors: HH_EINVAL (also for a
+ * speed that is not positive and finite at a sample point), HH_ENOMEM,
+ * HH_EDEVICE. */
+int hh_assemble_field(double omega, const hh_cfield* c, int n, const hh_c128* f,
+                      hh_problem** out);
 
 /* Right-hand side of eq. (1) for nodal sources: b = -M f (P1 mass matrix M),
  * impedance data g = 0.  f and b are device pointers to nvec x n*n hh_c128
@@ -116,6 +148,23 @@ int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision);
  * workgroups do not meet in time stops, and the call returns HH_EDEVICE. */
 int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_c128* z);
 
+/* z = M^{-1} r for the preconditioner `kind` (HH_PRE_*): the double sweeps
+ * as in hh_sweep_apply, or a single sweep (Sec. 4, the LR, RL, BT and TB of
+ * Table 1): one pass of eq. (2), N strip solves, each strip taking the
+ * transmission data of the previous solve on the interface that faces it and
+ * zero data on the other; in the overlaps the most recent solve wins.  LR and
+ * BT go from strip 1 to N, RL and TB from N to 1.  The kind's direction must
+ * have been factored; r, z, nvec and errors as in hh_sweep_apply. */
+int hh_precond_apply(hh_problem* pb, int kind, int nvec, const hh_c128* r, hh_c128* z);
+
+/* Chooses the t preconditioners M_1..M_t that hh_mpgmres combines, in order
+ * (Sec. 3; the combinations of Sec. 4 such as LRL+BTB, LR+RL or
+ * LR+BT+RL+TB).  kinds: host pointer to t HH_PRE_* values, 1 <= t <= 4, each
+ * of a factored direction (a kind may repeat).  hh_factor_sweeps resets the
+ * choice to the double sweeps of its directions (LRL, then BTB).
+ * Errors: HH_EINVAL. */
+int hh_set_preconditioners(hh_problem* pb, int t, const int* kinds);
+
 /* One strip solve x = A_s^{-1} rhs with the stored factors (strip s is
  * 1-based, vectors in the strip's local order q = long*w + short, where w is
  * the strip width in mesh lines).  rhs, x: device pointers of
@@ -138,15 +187,19 @@ int hh_get_operator(const hh_problem* pb, hh_c128* diag);
 /* ---- selective MPGMRES: Sec. 3 with the selection rule of Sec. 4 -----------
  * Solves A x = b for nrhs independent right-hand sides that share the
  * factored sweeps (one MPGMRES per RHS, batched on the device).  x0 = 0, no
- * restart; iteration k applies every factored sweep once (the t = 2 cross
- * rule: LRL is applied to the basis vector that came from BTB's column and
- * vice versa; t = 1 is right-preconditioned GMRES).  The new block is
+ * restart; iteration k applies each of the t chosen preconditioners once
+ * (hh_set_preconditioners; by default the double sweeps of the factored
+ * directions).  Selection (Sec. 4): for t = 2 the cross rule (M_1 is applied
+ * to the basis vector that came from M_2's column and vice versa); for t > 2
+ * every M_i is applied to the sum of the new basis vectors; t = 1 is
+ * right-preconditioned GMRES.  The new block is
  * orthogonalised by two passes of block classical Gram-Schmidt and a
  * reorthogonalised modified Gram-Schmidt inside the block; the small least
  * squares problem is solved on the host in FP64.  Stops when the
  * least-squares residual is <= tol ||b||_2.  SpMV, Gram-Schmidt, least
  * squares and the final residual check are FP64 whatever the strip precision.
- *   b, x       device pointers, nrhs x n*n hh_c128 (x is overwritten)
+ *   b, x       device pointers, nrhs x n*n hh_c128 (x is overwritten); b may
+ *              be NULL for the one right-hand side given to hh_assemble_field
  *   tol        > 0;  maxit >= 1
  *   stats      host pointer to nrhs hh_stats (may be NULL)
  * The sweeps of every RHS and direction run in one launch per iteration, one
@@ -157,6 +210,32 @@ int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit
 
 /* Releases the handle and all its device memory.  NULL is accepted. */
 int hh_free(hh_problem* pb);
+
+/* ---- device memory and streams from the caller ------------------------------
+ * hh_set_allocator: every device buffer the library needs from now on
+ * (operators, strip factors, Krylov bases, scratch) comes from alloc(bytes,
+ * ctx) and goes back through free_fn(p, ctx), e.g. a framework's caching
+ * allocator; both NULL restores the library's own cache over hipMalloc.  The
+ * library frees a buffer only after the work that used it has completed on
+ * its streams.  alloc must return device memory of the current device (NULL
+ * on failure: the call that needed it returns HH_ENOMEM) and may be called
+ * from the serving thread.  Only while the library holds no device memory
+ * (every problem and server freed), else HH_EINVAL. */
+int hh_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* p, void* ctx),
+                     void* ctx);
+
+/* hh_set_streams: problems created from now on run their work on the
+ * caller's HIP streams (hipStream_t handles, passed as void*): x carries
+ * assembly, factorisation, sweeps (both directions share one launch) and the
+ * MPGMRES iteration; y is kept as the problem's second stream.  One of them
+ * may be NULL (the other is used for both); both NULL restores streams that
+ * each problem creates and destroys.  The library does not destroy caller
+ * streams, and calls stay synchronous with respect to the host. */
+int hh_set_streams(void* x, void* y);
+
+/* Releases the library's cached free device blocks and pooled timing events
+ * (e.g. before the process exits).  Live handles are not affected. */
+int hh_release_caches(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hh_last_error(void);

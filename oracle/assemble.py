@@ -26,7 +26,9 @@ horizontal layers, layer 0 at the bottom.  The element wave number is taken
 at the triangle centroid, the edge wave number at the edge midpoint.  A
 sample height y = P / (6 (n-1)) lies in layer min(floor(P L / (6(n-1))), L-1),
 evaluated in exact integer arithmetic so that a height on a layer interface
-is classified without rounding.
+is classified without rounding.  A general speed field c(x, y) (a Python
+callable in place of the layer list) is sampled at the same points: the
+triangle centroids and the edge midpoints, k = omega / c there.
 
 The element matrices are computed here from the vertex coordinates (gradients
 of the barycentric functions), not from the tabulated right-triangle forms.
@@ -51,6 +53,18 @@ def wavenumber(omega, c_layers, n, P):
     """k = omega / c at sample heights y = P / (6 (n-1)) (eq. (1), k = omega/c)."""
     c = np.asarray(c_layers, dtype=np.float64)
     return omega / c[layer_of(P, n, len(c))]
+
+
+def sampled_wavenumber(omega, c_field, n, P, pts):
+    """k = omega / c at the sample points pts (S, 2) in units of h: a layer list
+    is read at the heights y = P / (6 (n-1)), a callable c(x, y) at the points."""
+    if not callable(c_field):
+        return wavenumber(omega, c_field, n, P)
+    h = 1.0 / (n - 1)
+    c = np.array([float(c_field(x * h, y * h)) for x, y in pts], dtype=np.float64)
+    if np.any(~np.isfinite(c)) or np.any(c <= 0):
+        raise ValueError("the speed field must be positive and finite")
+    return omega / c
 
 
 def _cells(n, window):
@@ -147,6 +161,8 @@ def _scatter(n, idx, vals):
 def operator_parts(omega, c_layers, n, window=None):
     """(K, M_{k^2}, M_{Gamma,k}) assembled over the window's triangles.
 
+    c_layers: the layer speeds, or a callable speed field c(x, y).
+
     The boundary term covers all four sides of the window rectangle with the
     impedance edge form, whether the side is part of the physical boundary or
     an artificial strip interface (eq. (4) uses the same zeroth-order
@@ -157,12 +173,12 @@ def operator_parts(omega, c_layers, n, window=None):
     tri, Pt = triangles(n, window)
     ids = node_id(n, tri[..., 0], tri[..., 1])
     Ke, Me = element_matrices(tri, h)
-    kt = wavenumber(omega, c_layers, n, Pt)
+    kt = sampled_wavenumber(omega, c_layers, n, Pt, tri.mean(axis=1))      # centroids
     K = _scatter(n, ids, Ke)
     Mk2 = _scatter(n, ids, Me * (kt ** 2)[:, None, None])
     e, Pe, _ = boundary_edges(n, window)
     eids = node_id(n, e[..., 0], e[..., 1])
-    ke = wavenumber(omega, c_layers, n, Pe)
+    ke = sampled_wavenumber(omega, c_layers, n, Pe, e.mean(axis=1))        # midpoints
     Mg = _scatter(n, eids, edge_mass(e, h) * ke[:, None, None])
     return K, Mk2, Mg
 

@@ -7,13 +7,15 @@ functions carry the C names; vectors are torch tensors on the GPU
 (complex128, contiguous) whose device pointers are handed to the library.
 Nothing here computes: it marshals arguments and raises on error codes.
 """
+import atexit
 import ctypes
 
 import numpy as np
 
 from . import _lib
 from ._lib import (HH_DIR_X, HH_DIR_Y, HH_EBUDGET, HH_EDEVICE, HH_EINVAL, HH_ENOCONV,
-                   HH_ENOMEM, HH_ESINGULAR, HH_FP32, HH_FP64, HH_OK, HH_PENDING, HHError)
+                   HH_ENOMEM, HH_ESINGULAR, HH_FP32, HH_FP64, HH_OK, HH_PENDING, HH_PRE_BT,
+                   HH_PRE_BTB, HH_PRE_LR, HH_PRE_LRL, HH_PRE_RL, HH_PRE_TB, PRE_KINDS, HHError)
 
 _L = None
 
@@ -64,6 +66,25 @@ class Problem:
         self.n = int(n)
         self.omega = float(omega)
         self.c_layers = c
+
+    @classmethod
+    def from_field(cls, omega, speed, n, f=None):
+        """hh_assemble_field: speed is a callable c(x, y) (sampled by the library at
+        the triangle centroids and edge midpoints); f an optional nodal source
+        (device tensor of n*n complex128) whose b = -M f the problem keeps."""
+        fn = _lib.SPEED_FN(lambda x, y, ctx: float(speed(x, y)))
+        field = _lib.hh_cfield(fn, None, 0, None)
+        h = ctypes.c_void_p()
+        fp = _dev(f, "f") if f is not None else None
+        _sync()
+        _check(lib().hh_assemble_field(float(omega), ctypes.byref(field), int(n), fp,
+                                       ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.n = int(n)
+        self.omega = float(omega)
+        self.c_layers = None
+        return self
 
     @property
     def handle(self):
@@ -123,6 +144,22 @@ class Problem:
         _check(lib().hh_sweep_apply(self.handle, int(direction), nvec, _dev(r, "r"), _dev(z, "z")))
         return z
 
+    def precond_apply(self, kind, r, z=None):
+        """z = M^{-1} r for a preconditioner kind (HH_PRE_* or its name, e.g. "RL")."""
+        kind = PRE_KINDS[kind] if isinstance(kind, str) else int(kind)
+        nvec = r.shape[0] if r.dim() == 2 else 1
+        if z is None:
+            z = r.new_empty(r.shape)
+        _sync()
+        _check(lib().hh_precond_apply(self.handle, kind, nvec, _dev(r, "r"), _dev(z, "z")))
+        return z
+
+    def set_preconditioners(self, kinds):
+        """The preconditioners M_1..M_t combined by mpgmres, e.g. ["LR", "BT", "RL", "TB"]."""
+        ks = [PRE_KINDS[k] if isinstance(k, str) else int(k) for k in kinds]
+        arr = (ctypes.c_int * len(ks))(*ks)
+        _check(lib().hh_set_preconditioners(self.handle, len(ks), arr))
+
     # -- operator and solver
     def spmv(self, x, y=None):
         nvec = x.shape[0] if x.dim() == 2 else 1
@@ -133,21 +170,83 @@ class Problem:
         return y
 
     def mpgmres(self, b, tol=1e-6, maxit=200, x=None):
-        """Returns (x, stats, rc) with stats a list of dicts, rc HH_OK or HH_ENOCONV."""
-        nrhs = b.shape[0] if b.dim() == 2 else 1
+        """Returns (x, stats, rc) with stats a list of dicts, rc HH_OK or HH_ENOCONV.
+        b None: the right-hand side given to from_field."""
+        import torch
+        nrhs = 1 if b is None else (b.shape[0] if b.dim() == 2 else 1)
         if x is None:
-            x = b.new_empty(b.shape)
+            x = (torch.empty((1, self.n * self.n), dtype=torch.complex128, device="cuda")
+                 if b is None else b.new_empty(b.shape))
         st = (_lib.hh_stats * nrhs)()
         _sync()
-        rc = _check(lib().hh_mpgmres(self.handle, nrhs, _dev(b, "b"), float(tol), int(maxit),
+        bp = None if b is None else _dev(b, "b")
+        rc = _check(lib().hh_mpgmres(self.handle, nrhs, bp, float(tol), int(maxit),
                                      _dev(x, "x"), st), allowed=(HH_OK, HH_ENOCONV))
         stats = [{k: getattr(s, k) for k, _ in _lib.hh_stats._fields_} for s in st]
         return x, stats, rc
 
 
+# -- device memory and streams from torch (hh_set_allocator, hh_set_streams)
+_torch_hooks = None
+
+
+def use_torch(memory=True, streams=True):
+    """Routes the library's device memory through torch's caching allocator and
+    its work onto torch's current stream (for problems created afterwards).
+    Memory can only be switched while the library holds none."""
+    global _torch_hooks
+    import torch
+    if memory:
+        def _alloc(size, ctx):
+            return torch.cuda.caching_allocator_alloc(int(size), device=torch.cuda.current_device())
+
+        def _free(p, ctx):
+            torch.cuda.caching_allocator_delete(p)
+
+        hooks = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+        _check(lib().hh_set_allocator(hooks[0], hooks[1], None))
+        _torch_hooks = hooks            # the callbacks must outlive their use
+    if streams:
+        s = torch.cuda.current_stream().cuda_stream
+        _check(lib().hh_set_streams(ctypes.c_void_p(s), ctypes.c_void_p(s)))
+
+
+def use_library_defaults(memory=True, streams=True):
+    """Undoes use_torch: the library's own allocator cache and streams."""
+    global _torch_hooks
+    if memory:
+        _check(lib().hh_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None))
+        _torch_hooks = None
+    if streams:
+        _check(lib().hh_set_streams(None, None))
+
+
+def hh_release_caches():
+    _check(lib().hh_release_caches())
+
+
+@atexit.register
+def _release_at_exit():
+    # hand the cached device blocks and timing events back while the runtime
+    # is still up, rather than leaving them to process teardown
+    if _L is not None:
+        try:
+            _L.hh_release_caches()
+        except Exception:
+            pass
+
+
 # C-named entry points
 def hh_assemble(omega, c_layers, n):
     return Problem(omega, c_layers, n)
+
+
+def hh_assemble_field(omega, speed, n, f=None):
+    return Problem.from_field(omega, speed, n, f)
+
+
+def hh_set_streams(x, y):
+    _check(lib().hh_set_streams(ctypes.c_void_p(x) if x else None, ctypes.c_void_p(y) if y else None))
 
 
 def hh_load_vector(pb, f, b=None):
@@ -160,6 +259,14 @@ def hh_factor_sweeps(pb, dirs, nstrips, precision):
 
 def hh_sweep_apply(pb, direction, r, z=None):
     return pb.sweep_apply(direction, r, z)
+
+
+def hh_precond_apply(pb, kind, r, z=None):
+    return pb.precond_apply(kind, r, z)
+
+
+def hh_set_preconditioners(pb, kinds):
+    return pb.set_preconditioners(kinds)
 
 
 def hh_strip_solve(pb, direction, s, rhs, x=None):

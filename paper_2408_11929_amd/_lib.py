@@ -23,6 +23,14 @@ HH_DIR_X = 1
 HH_DIR_Y = 2
 HH_FP64 = 0
 HH_FP32 = 1
+HH_PRE_LRL = 1
+HH_PRE_BTB = 2
+HH_PRE_LR = 3
+HH_PRE_RL = 4
+HH_PRE_BT = 5
+HH_PRE_TB = 6
+PRE_KINDS = {"LRL": HH_PRE_LRL, "BTB": HH_PRE_BTB, "LR": HH_PRE_LR, "RL": HH_PRE_RL,
+             "BT": HH_PRE_BT, "TB": HH_PRE_TB}
 
 ERROR_NAMES = {HH_EINVAL: "HH_EINVAL", HH_ENOMEM: "HH_ENOMEM", HH_ESINGULAR: "HH_ESINGULAR",
                HH_ENOCONV: "HH_ENOCONV", HH_EDEVICE: "HH_EDEVICE", HH_EBUDGET: "HH_EBUDGET"}
@@ -42,6 +50,16 @@ class hh_request(ctypes.Structure):
                 ("maxit", ctypes.c_int)]
 
 
+SPEED_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class hh_cfield(ctypes.Structure):
+    _fields_ = [("speed", SPEED_FN), ("ctx", ctypes.c_void_p), ("nlayers", ctypes.c_int),
+                ("c_layers", ctypes.POINTER(ctypes.c_double))]
+
+
 class hh_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations_max", ctypes.c_int),
                 ("res_true_max", ctypes.c_double), ("t_submit", ctypes.c_double),
@@ -56,9 +74,15 @@ U = ctypes.c_uint
 # name -> (restype, argtypes); the full exported surface of include/hh.h
 PROTOTYPES = {
     "hh_assemble": (I, [D, I, ctypes.POINTER(D), I, ctypes.POINTER(P)]),
+    "hh_assemble_field": (I, [D, ctypes.POINTER(hh_cfield), I, P, ctypes.POINTER(P)]),
+    "hh_set_allocator": (I, [ALLOC_FN, FREE_FN, P]),
+    "hh_set_streams": (I, [P, P]),
+    "hh_release_caches": (I, []),
     "hh_load_vector": (I, [P, I, P, P]),
     "hh_factor_sweeps": (I, [P, U, I, I]),
     "hh_sweep_apply": (I, [P, U, I, P, P]),
+    "hh_precond_apply": (I, [P, I, I, P, P]),
+    "hh_set_preconditioners": (I, [P, I, ctypes.POINTER(I)]),
     "hh_strip_solve": (I, [P, U, I, P, P]),
     "hh_strip_info": (I, [P, U, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
     "hh_spmv": (I, [P, I, P, P]),

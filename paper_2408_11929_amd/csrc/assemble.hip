@@ -32,12 +32,29 @@ __device__ __forceinline__ double wave_number(long long P, int n, int L, const d
   return omega / c[l];
 }
 
+// Wave numbers of the triangles and edges (eq. (1), k = omega / c): from the
+// layer table at the sample heights, or read from the tables a speed field
+// was sampled into (Medium::kt, kv, kh).
+__device__ __forceinline__ double k_triangle(const Medium& m, int n, int ci, int cj, int t) {
+  if (m.kt) return m.kt[2 * ((long long)cj * (n - 1) + ci) + t];
+  return wave_number(6LL * cj + (t == 0 ? 2 : 4), n, m.L, m.c, m.omega);
+}
+// edge (i, j) - (i + 1, j)
+__device__ __forceinline__ double k_hedge(const Medium& m, int n, int i, int j) {
+  if (m.kh) return m.kh[(long long)j * (n - 1) + i];
+  return wave_number(6LL * j, n, m.L, m.c, m.omega);
+}
+// edge (i, j) - (i, j + 1)
+__device__ __forceinline__ double k_vedge(const Medium& m, int n, int i, int j) {
+  if (m.kv) return m.kv[(long long)j * n + i];
+  return wave_number(6LL * j + 3, n, m.L, m.c, m.omega);
+}
+
 // 7-point stencil of row (i, j) of the operator assembled over the cells of the
 // window [cx0, cx1) x [cy0, cy1) with the impedance edge form on all four
 // window sides.  mass_only: unit-weight mass matrix (for the load vector).
 __device__ void node_stencil(int i, int j, int n, int cx0, int cx1, int cy0, int cy1,
-                             double omega, int L, const double* c, bool mass_only,
-                             c128 out[7]) {
+                             const Medium& md, bool mass_only, c128 out[7]) {
   const double h = 1.0 / (n - 1);
   for (int d = 0; d < 7; ++d) out[d] = mk(0.0, 0.0);
   const double Ks[3][3] = {{0.5, -0.5, 0.0}, {-0.5, 1.0, -0.5}, {0.0, -0.5, 0.5}};
@@ -57,7 +74,7 @@ __device__ void node_stencil(int i, int j, int n, int cx0, int cx1, int cy0, int
         for (int v = 0; v < 3; ++v)
           if (vx[v] == i && vy[v] == j) a = v;
         if (a < 0) continue;
-        double k = wave_number(6LL * cj + (t == 0 ? 2 : 4), n, L, c, omega);
+        double k = mass_only ? 1.0 : k_triangle(md, n, ci, cj, t);
         double k2 = mass_only ? 1.0 : k * k;
         for (int b = 0; b < 3; ++b) {
           double mab = m0 * (a == b ? 2.0 : 1.0);
@@ -71,34 +88,31 @@ __device__ void node_stencil(int i, int j, int n, int cx0, int cx1, int cy0, int
   if (mass_only) return;
   // impedance edges on the window sides
   const double e0 = h / 6.0;
-  auto edge = [&](int bi, int bj, long long P) {
-    double k = wave_number(P, n, L, c, omega);
+  auto edge = [&](int bi, int bj, double k) {
     out[3].im -= k * e0 * 2.0;
     out[slot_of(bi - i, bj - j)].im -= k * e0;
   };
   if (j == cy0 || j == cy1) {            // bottom / top side
     if (i >= cx0 && i <= cx1) {
-      long long P = 6LL * j;
-      if (i - 1 >= cx0) edge(i - 1, j, P);
-      if (i + 1 <= cx1) edge(i + 1, j, P);
+      if (i - 1 >= cx0) edge(i - 1, j, k_hedge(md, n, i - 1, j));
+      if (i + 1 <= cx1) edge(i + 1, j, k_hedge(md, n, i, j));
     }
   }
   if (i == cx0 || i == cx1) {            // left / right side
     if (j >= cy0 && j <= cy1) {
-      if (j - 1 >= cy0) edge(i, j - 1, 6LL * (j - 1) + 3);
-      if (j + 1 <= cy1) edge(i, j + 1, 6LL * j + 3);
+      if (j - 1 >= cy0) edge(i, j - 1, k_vedge(md, n, i, j - 1));
+      if (j + 1 <= cy1) edge(i, j + 1, k_vedge(md, n, i, j));
     }
   }
 }
 
-__global__ void k_assemble(int n, double omega, int L, const double* __restrict__ c,
-                           c128* __restrict__ A) {
+__global__ void k_assemble(int n, Medium md, c128* __restrict__ A) {
   long long nn = (long long)n * n;
   long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (p >= nn) return;
   int i = (int)(p % n), j = (int)(p / n);
   c128 st[7];
-  node_stencil(i, j, n, 0, n - 1, 0, n - 1, omega, L, c, false, st);
+  node_stencil(i, j, n, 0, n - 1, 0, n - 1, md, false, st);
   A[p] = st[3];
   A[nn + p] = st[4];
   A[2 * nn + p] = st[5];
@@ -111,7 +125,7 @@ __global__ void k_load_vector(int n, int nvec, const c128* __restrict__ f, c128*
   if (p >= nn) return;
   int i = (int)(p % n), j = (int)(p / n);
   c128 st[7];
-  node_stencil(i, j, n, 0, n - 1, 0, n - 1, 0.0, 1, nullptr, true, st);
+  node_stencil(i, j, n, 0, n - 1, 0, n - 1, Medium{}, true, st);
   const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
   const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
   for (int v = 0; v < nvec; ++v) {
@@ -134,7 +148,7 @@ __global__ void k_load_vector(int n, int nvec, const c128* __restrict__ f, c128*
 // With redo given, only the strips marked 2 there are packed, and their
 // transmission stencils (unchanged) are left alone.
 template <class T>
-__global__ void k_pack_strips(int n, double omega, int L, const double* __restrict__ c,
+__global__ void k_pack_strips(int n, Medium md,
                               const StripDesc* __restrict__ strips, cx<T>* __restrict__ band,
                               cx<T>* __restrict__ tr, const int* __restrict__ redo) {
   if (redo && redo[blockIdx.y] != 2) return;
@@ -151,7 +165,7 @@ __global__ void k_pack_strips(int n, double omega, int L, const double* __restri
     cx0 = 0; cx1 = n - 1; cy0 = sd.a; cy1 = sd.a + sd.w - 1;
   }
   c128 st[7];
-  node_stencil(i, j, n, cx0, cx1, cy0, cy1, omega, L, c, false, st);
+  node_stencil(i, j, n, cx0, cx1, cy0, cy1, md, false, st);
   const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
   const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
   const int kv = 2 * sd.kl;
@@ -165,7 +179,7 @@ __global__ void k_pack_strips(int n, double omega, int L, const double* __restri
   bool side1 = (t == 0 && sd.has1 && !redo), side2 = (t == sd.w - 1 && sd.has2 && !redo);
   if (side1 || side2) {
     c128 g[7];
-    node_stencil(i, j, n, 0, n - 1, 0, n - 1, omega, L, c, false, g);
+    node_stencil(i, j, n, 0, n - 1, 0, n - 1, md, false, g);
     cx<T>* out = tr + (side1 ? sd.tr1_off : sd.tr2_off) + 7LL * l;
     for (int d = 0; d < 7; ++d) out[d] = mk((T)(st[d].re - g[d].re), (T)(st[d].im - g[d].im));
   }
@@ -186,12 +200,21 @@ __global__ void k_zero_marked(const StripDesc* __restrict__ strips, cx<T>* __res
 
 }  // namespace
 
-void launch_assemble(int n, double omega, int nlayers, const double* d_c, c128* d_A,
-                     hipStream_t st) {
+Medium medium_of(const hh_problem* pb) {
+  Medium m{};
+  m.omega = pb->omega;
+  m.L = (int)pb->c.size();
+  m.c = pb->d_c;
+  m.kt = pb->d_kt;
+  m.kv = pb->d_kv;
+  m.kh = pb->d_kh;
+  return m;
+}
+
+void launch_assemble(int n, const Medium& md, c128* d_A, hipStream_t st) {
   long long nn = (long long)n * n;
   int bs = 256;
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((nn + bs - 1) / bs)), dim3(bs), 0, st, n, omega,
-                     nlayers, d_c, d_A);
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((nn + bs - 1) / bs)), dim3(bs), 0, st, n, md, d_A);
   HH_HIP(hipGetLastError());
 }
 
@@ -211,12 +234,12 @@ void launch_pack_strips(const hh_problem* pb, hipStream_t st) {
   int bs = 256;
   dim3 grid((unsigned)((fs.max_ns + bs - 1) / bs), (unsigned)fs.strips.size());
   if (fs.precision == HH_FP64)
-    hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, pb->omega,
-                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c128*)fs.band, (c128*)fs.tr,
+    hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, medium_of(pb),
+                       fs.d_strips, (c128*)fs.band, (c128*)fs.tr,
                        (const int*)nullptr);
   else
-    hipLaunchKernelGGL(k_pack_strips<float>, grid, dim3(bs), 0, st, pb->n, pb->omega,
-                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c64*)fs.band, (c64*)fs.tr,
+    hipLaunchKernelGGL(k_pack_strips<float>, grid, dim3(bs), 0, st, pb->n, medium_of(pb),
+                       fs.d_strips, (c64*)fs.band, (c64*)fs.tr,
                        (const int*)nullptr);
   HH_HIP(hipGetLastError());
 }
@@ -229,14 +252,14 @@ void launch_repack_marked(const hh_problem* pb, hipStream_t st) {
   if (fs.precision == HH_FP64) {
     hipLaunchKernelGGL(k_zero_marked<double>, zgrid, dim3(bs), 0, st, fs.d_strips,
                        (c128*)fs.band, (const int*)fs.d_pflag);
-    hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, pb->omega,
-                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c128*)fs.band, (c128*)fs.tr,
+    hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, medium_of(pb),
+                       fs.d_strips, (c128*)fs.band, (c128*)fs.tr,
                        (const int*)fs.d_pflag);
   } else {
     hipLaunchKernelGGL(k_zero_marked<float>, zgrid, dim3(bs), 0, st, fs.d_strips,
                        (c64*)fs.band, (const int*)fs.d_pflag);
-    hipLaunchKernelGGL(k_pack_strips<float>, grid, dim3(bs), 0, st, pb->n, pb->omega,
-                       (int)pb->c.size(), pb->d_c, fs.d_strips, (c64*)fs.band, (c64*)fs.tr,
+    hipLaunchKernelGGL(k_pack_strips<float>, grid, dim3(bs), 0, st, pb->n, medium_of(pb),
+                       fs.d_strips, (c64*)fs.band, (c64*)fs.tr,
                        (const int*)fs.d_pflag);
   }
   HH_HIP(hipGetLastError());

@@ -65,6 +65,34 @@ int dir_slot(const hh_problem* pb, unsigned dir) {
   throw ArgError();
 }
 
+// Factored slot and sweep order of a preconditioner kind (HH_PRE_*).
+void kind_slot(const hh_problem* pb, int kind, int& slot, int& mode) {
+  REQUIRE(kind >= HH_PRE_LRL && kind <= HH_PRE_TB, "unknown preconditioner kind %d", kind);
+  const bool y = kind == HH_PRE_BTB || kind == HH_PRE_BT || kind == HH_PRE_TB;
+  slot = dir_slot(pb, y ? HH_DIR_Y : HH_DIR_X);
+  mode = kind == HH_PRE_LRL || kind == HH_PRE_BTB ? SWEEP_DOUBLE
+         : kind == HH_PRE_LR || kind == HH_PRE_BT ? SWEEP_FORWARD
+                                                  : SWEEP_REVERSE;
+}
+
+// z = M^{-1} r for nvec vectors with the strips of factored slot i in the
+// given sweep order (one chain per vector), on scratch from the allocator.
+void sweep_apply(hh_problem* pb, int i, int mode, int nvec, const c128* r, c128* z) {
+  if (nvec == 0) return;
+  const int plan = sweep_plan_of(pb, nvec);
+  size_t bytes = 0;
+  sweep_layout(pb, nvec, plan, nullptr, &bytes);
+  void* base = dev_alloc(bytes);
+  try {
+    sweep_apply_core(pb, i, mode, nvec, r, z, plan, sweep_layout(pb, nvec, plan, (char*)base, &bytes));
+  } catch (...) {
+    (void)hipStreamSynchronize(pb->st[0]);
+    dev_free(base);
+    throw;
+  }
+  dev_free(base);
+}
+
 }  // namespace
 
 namespace hh {
@@ -83,6 +111,11 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
   fs.precision = precision;
   if (dirs & HH_DIR_X) fs.dir_id[fs.nd++] = 0;
   if (dirs & HH_DIR_Y) fs.dir_id[fs.nd++] = 1;
+  fs.npre = fs.nd;  // LRL, then BTB: the ordered combination of Sec. 4
+  for (int i = 0; i < fs.nd; ++i) {
+    fs.pre_slot[i] = i;
+    fs.pre_mode[i] = SWEEP_DOUBLE;
+  }
   long long band = 0, img = 0, piv = 0, tr = 0;
   int kl_max = 0;
   for (int s = 0; s < N; ++s) {
@@ -122,7 +155,12 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
                 sd.pseg[p], sd.kl);
       sd.img_off = img;
       sd.t_off = img + 2 * blocked_blocks(sd.ns) * sd.KP * 64;
-      sd.phi_off = sd.t_off + 2LL * sd.tmaps * map_dim(sd.KP) * map_dim(sd.KP);
+      sd.phi_off[0] = 0;
+      long long po = sd.t_off + 2LL * sd.tmaps * map_dim(sd.KP) * map_dim(sd.KP);
+      for (int p = 1; p < HH_NPLAN; ++p) {
+        sd.phi_off[p] = po;
+        if (wide) po += 2 * plan_phi_elems(sd.ns, P, sd.kl, map_dim(sd.KP), p);
+      }
       img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P, wide);
       sd.piv_off = piv;
       piv += NP;
@@ -187,47 +225,201 @@ int factor_finish(hh_problem* pb) {
 void ensure_batch_maps(hh_problem* pb, hipStream_t st) {
   FactorSet& fs = pb->fs;
   if (fs.batch_maps) return;
-  launch_transfer(fs, 1, st);
+  launch_transfer(fs, HH_BATCH_PLANS, st);
+  launch_products(fs, HH_BATCH_PLANS, st);
   HH_HIP(hipStreamSynchronize(st));
   dev_free(fs.band);
   fs.band = nullptr;
   fs.batch_maps = true;
 }
 
-// New problem handle with the operator assembled asynchronously on its stream.
-hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n) {
+int sweep_plan_of(const hh_problem* pb, int nvec) {
+  const FactorSet& fs = pb->fs;
+  return sweep_plan_for(nvec, fs.precision, fs.strips[0].segs, fs.max_kl, pb->n, fs.any_pivot,
+                        fs.strips[0].wide != 0);
+}
+
+SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, size_t* total) {
+  const FactorSet& fs = pb->fs;
+  const size_t es = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
+  const size_t len = (size_t)pb->n * pb->n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  SweepBuffers b{};
+  b.tasks = (SweepTask*)take((size_t)nvec * sizeof(SweepTask));
+  b.sync = (unsigned*)take((size_t)(nvec + 1) * 128);  // [0] abort, then a line per chain
+  b.rho = take((size_t)nvec * fs.max_ns * es);
+  b.g1 = take((size_t)nvec * fs.N * pb->n * es);
+  b.zs = fs.precision == HH_FP64 ? nullptr : take((size_t)nvec * len * es);
+  b.xch = plan > 0 ? take((size_t)nvec * plan_width(plan) * 64 * es) : nullptr;
+  *total = off;
+  return b;
+}
+
+void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, c128* z,
+                      int plan, const SweepBuffers& b) {
+  const FactorSet& fs = pb->fs;
+  const long long len = (long long)pb->n * pb->n;
+  const size_t es = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
+  void* zs = fs.precision == HH_FP64 ? (void*)z : b.zs;
+  const int G = plan_width(plan);
+  hipStream_t st = pb->st[0];
+  if (plan != HH_PLAN_WIDE) ensure_batch_maps(pb, st);
+  launch_zero(b.sync, (size_t)(nvec + 1) * 128, st);
+  // descriptors staged on the stack for up to 64 chains (no host allocation)
+  SweepTask few[64];
+  std::vector<SweepTask> many(nvec > 64 ? nvec : 0);
+  SweepTask* tasks = nvec > 64 ? many.data() : few;
+  for (int v = 0; v < nvec; ++v) {
+    SweepTask& tk = tasks[v];
+    tk = SweepTask{};
+    tk.ch.strips = fs.d_strips + (size_t)i * fs.N;
+    tk.ch.r = r + v * len;
+    tk.ch.z = (char*)zs + v * len * es;
+    tk.ch.rho = (char*)b.rho + (size_t)v * fs.max_ns * es;
+    tk.ch.g1 = (char*)b.g1 + (size_t)v * fs.N * pb->n * es;
+    tk.img = fs.img;
+    tk.piv = fs.piv;
+    tk.pflag = fs.d_pflag;
+    tk.tr = fs.tr;
+    tk.n = pb->n;
+    tk.N = fs.N;
+    tk.xch = b.xch ? (char*)b.xch + (size_t)v * G * 64 * es : nullptr;
+    tk.bar = b.sync + 32 * (v + 1);
+    tk.mode = mode;
+  }
+  HH_HIP(hipMemcpyAsync(b.tasks, tasks, nvec * sizeof(SweepTask), hipMemcpyHostToDevice, st));
+  {
+    double bytes = 0;
+    for (int q = 0; q < fs.N; ++q) {
+      const StripDesc& sd = fs.strips[(size_t)i * fs.N + q];
+      const double solves = mode != SWEEP_DOUBLE ? 1.0 : q == fs.N - 1 ? 1.0 : 2.0;
+      bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
+    }
+    TimedRegion tr(FAM_SWEEP, st, bytes);
+    launch_sweep(b.tasks, nvec, fs.precision, fs.strips[0].KP, fs.strips[0].segs, fs.max_kl,
+                 pb->n, fs.any_pivot, plan, b.sync, st);
+  }
+  if (fs.precision != HH_FP64) launch_widen((const c64*)zs, z, nvec * len, st);
+  unsigned aborted = 0;
+  HH_HIP(hipMemcpyAsync(&aborted, b.sync, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HH_HIP(hipStreamSynchronize(st));
+  if (aborted) {
+    set_error("sweep workgroups of one chain did not meet within the time limit");
+    throw DeviceError();
+  }
+}
+
+namespace {
+// A problem handle with its streams (the caller's, if hh_set_streams gave
+// any) and the operator storage; the caller fills the medium and assembles.
+std::unique_ptr<hh_problem> problem_shell(double omega, int n) {
   REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
   REQUIRE(n >= 3 && n <= 8193, "n must be in [3, 8193]");
-  REQUIRE(nlayers >= 1 && c_layers != nullptr, "need at least one layer speed");
-  for (int l = 0; l < nlayers; ++l)
-    REQUIRE(std::isfinite(c_layers[l]) && c_layers[l] > 0, "layer speed %d is not positive", l);
   std::unique_ptr<hh_problem> pb(new hh_problem());
   pb->n = n;
   pb->omega = omega;
-  pb->c.assign(c_layers, c_layers + nlayers);
   HH_HIP(hipGetDevice(&pb->device));
-  HH_HIP(hipStreamCreate(&pb->st[0]));
-  HH_HIP(hipStreamCreate(&pb->st[1]));
-  pb->d_c = (double*)dev_alloc(nlayers * sizeof(double));
+  hipStream_t x = nullptr, y = nullptr;
+  if (caller_streams(x, y)) {
+    pb->own_streams = false;
+    pb->st[0] = x ? x : y;
+    pb->st[1] = y ? y : x;
+  } else {
+    HH_HIP(hipStreamCreate(&pb->st[0]));
+    HH_HIP(hipStreamCreate(&pb->st[1]));
+  }
+  return pb;
+}
+
+void problem_assemble(hh_problem* pb) {
+  const int n = pb->n;
   pb->d_A = (c128*)dev_alloc((size_t)4 * n * n * sizeof(c128));
-  HH_HIP(hipMemcpyAsync(pb->d_c, pb->c.data(), nlayers * sizeof(double), hipMemcpyHostToDevice,
-                        pb->st[0]));
-  {
-    TimedRegion tr(FAM_ASSEMBLE, pb->st[0], (double)n * n * 64.0);
-    launch_assemble(n, omega, nlayers, pb->d_c, pb->d_A, pb->st[0]);
+  TimedRegion tr(FAM_ASSEMBLE, pb->st[0], (double)n * n * 64.0);
+  launch_assemble(n, medium_of(pb), pb->d_A, pb->st[0]);
+}
+}  // namespace
+
+// New problem handle with the operator assembled asynchronously on its stream.
+hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n) {
+  REQUIRE(nlayers >= 1 && c_layers != nullptr, "need at least one layer speed");
+  for (int l = 0; l < nlayers; ++l)
+    REQUIRE(std::isfinite(c_layers[l]) && c_layers[l] > 0, "layer speed %d is not positive", l);
+  std::unique_ptr<hh_problem> pb = problem_shell(omega, n);
+  try {
+    pb->c.assign(c_layers, c_layers + nlayers);
+    pb->d_c = (double*)dev_alloc(nlayers * sizeof(double));
+    HH_HIP(hipMemcpyAsync(pb->d_c, pb->c.data(), nlayers * sizeof(double), hipMemcpyHostToDevice,
+                          pb->st[0]));
+    problem_assemble(pb.get());
+  } catch (...) {
+    problem_destroy(pb.release());
+    throw;
+  }
+  return pb.release();
+}
+
+// Wave numbers omega / c of a speed field sampled on the host at the triangle
+// centroids and the edge midpoints (the layout of hh_problem::d_kt, d_kv, d_kh).
+hh_problem* problem_create_field(double omega, double (*speed)(double, double, void*), void* ctx,
+                                 int n) {
+  REQUIRE(speed != nullptr, "the speed field has no function");
+  REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
+  REQUIRE(n >= 3 && n <= 8193, "n must be in [3, 8193]");
+  const double h = 1.0 / (n - 1);
+  const long long m = n - 1;
+  std::vector<double> kt(2 * m * m), kv((size_t)m * n), kh((size_t)m * n);
+  auto k_at = [&](double x, double y) {
+    const double c = speed(x, y, ctx);
+    REQUIRE(std::isfinite(c) && c > 0, "the speed field is not positive and finite at (%g, %g)", x, y);
+    return omega / c;
+  };
+  for (long long cj = 0; cj < m; ++cj)
+    for (long long ci = 0; ci < m; ++ci) {
+      // lower {(i,j),(i+1,j),(i+1,j+1)} and upper {(i,j),(i+1,j+1),(i,j+1)}
+      kt[2 * (cj * m + ci)] = k_at((3 * ci + 2) * h / 3.0, (3 * cj + 1) * h / 3.0);
+      kt[2 * (cj * m + ci) + 1] = k_at((3 * ci + 1) * h / 3.0, (3 * cj + 2) * h / 3.0);
+    }
+  for (long long j = 0; j < m; ++j)
+    for (long long i = 0; i < n; ++i) kv[j * n + i] = k_at(i * h, (j + 0.5) * h);
+  for (long long j = 0; j < n; ++j)
+    for (long long i = 0; i < m; ++i) kh[j * m + i] = k_at((i + 0.5) * h, j * h);
+  std::unique_ptr<hh_problem> pb = problem_shell(omega, n);
+  try {
+    pb->c.assign(1, 1.0);
+    pb->d_kt = (double*)dev_alloc(kt.size() * sizeof(double));
+    pb->d_kv = (double*)dev_alloc(kv.size() * sizeof(double));
+    pb->d_kh = (double*)dev_alloc(kh.size() * sizeof(double));
+    HH_HIP(hipMemcpyAsync(pb->d_kt, kt.data(), kt.size() * sizeof(double), hipMemcpyHostToDevice, pb->st[0]));
+    HH_HIP(hipMemcpyAsync(pb->d_kv, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice, pb->st[0]));
+    HH_HIP(hipMemcpyAsync(pb->d_kh, kh.data(), kh.size() * sizeof(double), hipMemcpyHostToDevice, pb->st[0]));
+    problem_assemble(pb.get());
+    HH_HIP(hipStreamSynchronize(pb->st[0]));  // the host tables go out of scope
+  } catch (...) {
+    problem_destroy(pb.release());
+    throw;
   }
   return pb.release();
 }
 
 void problem_destroy(hh_problem* pb) {
   if (!pb) return;
-  (void)hipStreamSynchronize(pb->st[0]);
-  (void)hipStreamSynchronize(pb->st[1]);
+  for (hipStream_t s : pb->st)
+    if (s) (void)hipStreamSynchronize(s);
   free_factors(pb->fs);
   dev_free(pb->d_A);
   dev_free(pb->d_c);
-  (void)hipStreamDestroy(pb->st[0]);
-  (void)hipStreamDestroy(pb->st[1]);
+  dev_free(pb->d_kt);
+  dev_free(pb->d_kv);
+  dev_free(pb->d_kh);
+  dev_free(pb->d_b);
+  if (pb->own_streams)
+    for (hipStream_t s : pb->st)
+      if (s) (void)hipStreamDestroy(s);
   delete pb;
 }
 
@@ -249,6 +441,50 @@ int hh_assemble(double omega, int nlayers, const double* c_layers, int n, hh_pro
       return HH_EDEVICE;
     }
     *out = pb;
+    return HH_OK;
+  });
+}
+
+int hh_assemble_field(double omega, const hh_cfield* c, int n, const hh_c128* f,
+                      hh_problem** out) {
+  return guard([&]() {
+    REQUIRE(out != nullptr && c != nullptr, "out or c is NULL");
+    *out = nullptr;
+    hh_problem* pb = c->speed ? problem_create_field(omega, c->speed, c->ctx, n)
+                              : problem_create(omega, c->nlayers, c->c_layers, n);
+    try {
+      if (f) {
+        pb->d_b = (c128*)dev_alloc((size_t)n * n * sizeof(c128));
+        launch_load_vector(n, 1, (const c128*)f, pb->d_b, pb->st[0]);
+      }
+      HH_HIP(hipStreamSynchronize(pb->st[0]));
+    } catch (...) {
+      problem_destroy(pb);
+      throw;
+    }
+    *out = pb;
+    return HH_OK;
+  });
+}
+
+int hh_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* p, void* ctx),
+                     void* ctx) {
+  return guard([&]() {
+    REQUIRE((alloc == nullptr) == (free_fn == nullptr), "give both functions or neither");
+    REQUIRE(set_allocator(alloc, free_fn, ctx),
+            "the library still holds device memory: free every problem and server first");
+    return HH_OK;
+  });
+}
+
+int hh_set_streams(void* x, void* y) {
+  set_caller_streams((hipStream_t)x, (hipStream_t)y);
+  return HH_OK;
+}
+
+int hh_release_caches(void) {
+  return guard([&]() {
+    runtime_release_caches();
     return HH_OK;
   });
 }
@@ -304,68 +540,33 @@ int hh_strip_solve(hh_problem* pb, unsigned dir, int s, const hh_c128* rhs, hh_c
 int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_c128* z) {
   return guard([&]() {
     REQUIRE(pb && r && z && nvec >= 0, "invalid arguments");
-    const int i = dir_slot(pb, dir);
-    if (nvec == 0) return HH_OK;
-    const FactorSet& fs = pb->fs;
-    const long long len = (long long)pb->n * pb->n;
-    const size_t es = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
-    void* rho = dev_alloc((size_t)nvec * fs.max_ns * es);
-    void* g1 = dev_alloc((size_t)nvec * fs.N * pb->n * es);
-    void* zs = fs.precision == HH_FP64 ? (void*)z : dev_alloc((size_t)nvec * len * es);
-    // one chain per right-hand side, one or plan_width(plan) workgroups per chain
-    const int ntask = nvec;
-    const int plan = sweep_plan_for(ntask, fs.precision, fs.strips[0].segs, fs.max_kl, pb->n,
-                                    fs.any_pivot, fs.strips[0].wide != 0);
-    const int G = plan_width(plan);
-    hipStream_t st = pb->st[0];
-    if (plan == 0) ensure_batch_maps(pb, st);
-    // sync words: [0] abort, then one 128-byte line per chain
-    unsigned* sync = (unsigned*)dev_alloc((size_t)(ntask + 1) * 128);
-    void* xch = plan > 0 ? dev_alloc((size_t)ntask * G * 64 * es) : nullptr;
-    HH_HIP(hipMemsetAsync(sync, 0, (size_t)(ntask + 1) * 128, st));
-    std::vector<SweepTask> tasks(ntask);
-    for (int v = 0; v < nvec; ++v) {
-      SweepTask& tk = tasks[v];
-      tk.ch.strips = fs.d_strips + (size_t)i * fs.N;
-      tk.ch.r = (const c128*)r + v * len;
-      tk.ch.z = (char*)zs + v * len * es;
-      tk.ch.rho = (char*)rho + (size_t)v * fs.max_ns * es;
-      tk.ch.g1 = (char*)g1 + (size_t)v * fs.N * pb->n * es;
-      tk.img = fs.img;
-      tk.piv = fs.piv;
-      tk.pflag = fs.d_pflag;
-      tk.tr = fs.tr;
-      tk.n = pb->n;
-      tk.N = fs.N;
-      tk.xch = xch ? (char*)xch + (size_t)v * G * 64 * es : nullptr;
-      tk.bar = sync + 32 * (v + 1);
-    }
-    SweepTask* d_tasks = (SweepTask*)dev_alloc(ntask * sizeof(SweepTask));
-    HH_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntask * sizeof(SweepTask), hipMemcpyHostToDevice, st));
-    {
-      double bytes = 0;
-      for (int q = 0; q < fs.N; ++q) {
-        const StripDesc& sd = fs.strips[(size_t)i * fs.N + q];
-        const double solves = q == fs.N - 1 ? 1.0 : 2.0;
-        bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
-      }
-      TimedRegion tr(FAM_SWEEP, st, bytes);
-      launch_sweep(d_tasks, ntask, fs.precision, fs.strips[0].KP, fs.strips[0].segs, fs.max_kl,
-                   pb->n, fs.any_pivot, plan, sync, st);
-    }
-    if (fs.precision != HH_FP64) launch_widen((const c64*)zs, (c128*)z, nvec * len, st);
-    unsigned aborted = 0;
-    HH_HIP(hipMemcpyAsync(&aborted, sync, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-    HH_HIP(hipStreamSynchronize(st));
-    dev_free(d_tasks);
-    dev_free(rho);
-    dev_free(g1);
-    dev_free(xch);
-    dev_free(sync);
-    if (zs != (void*)z) dev_free(zs);
-    if (aborted) {
-      set_error("sweep workgroups of one chain did not meet within the time limit");
-      throw DeviceError();
+    sweep_apply(pb, dir_slot(pb, dir), SWEEP_DOUBLE, nvec, (const c128*)r, (c128*)z);
+    return HH_OK;
+  });
+}
+
+int hh_precond_apply(hh_problem* pb, int kind, int nvec, const hh_c128* r, hh_c128* z) {
+  return guard([&]() {
+    REQUIRE(pb && r && z && nvec >= 0, "invalid arguments");
+    int slot = 0, mode = 0;
+    kind_slot(pb, kind, slot, mode);
+    sweep_apply(pb, slot, mode, nvec, (const c128*)r, (c128*)z);
+    return HH_OK;
+  });
+}
+
+int hh_set_preconditioners(hh_problem* pb, int t, const int* kinds) {
+  return guard([&]() {
+    REQUIRE(pb != nullptr && kinds != nullptr, "invalid arguments");
+    REQUIRE(pb->fs.precision >= 0, "hh_factor_sweeps has not been called");
+    REQUIRE(t >= 1 && t <= HH_MAXPRE, "t = %d preconditioners: between 1 and %d", t, HH_MAXPRE);
+    int slot[HH_MAXPRE], mode[HH_MAXPRE];
+    for (int i = 0; i < t; ++i) kind_slot(pb, kinds[i], slot[i], mode[i]);
+    FactorSet& fs = pb->fs;
+    fs.npre = t;
+    for (int i = 0; i < t; ++i) {
+      fs.pre_slot[i] = slot[i];
+      fs.pre_mode[i] = mode[i];
     }
     return HH_OK;
   });
@@ -406,7 +607,12 @@ int hh_get_operator(const hh_problem* pb, hh_c128* diag) {
 int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit, hh_c128* x,
                hh_stats* stats) {
   return guard([&]() {
-    REQUIRE(pb && b && x && nrhs >= 0, "invalid arguments");
+    REQUIRE(pb && x && nrhs >= 0, "invalid arguments");
+    if (!b) {
+      REQUIRE(pb->d_b != nullptr && nrhs == 1,
+              "b is NULL: only one right-hand side, given to hh_assemble_field, can be implied");
+      b = (const hh_c128*)pb->d_b;
+    }
     REQUIRE(pb->fs.precision >= 0, "hh_factor_sweeps has not been called");
     REQUIRE(std::isfinite(tol) && tol > 0, "tol must be positive");
     REQUIRE(maxit >= 1, "maxit must be >= 1");

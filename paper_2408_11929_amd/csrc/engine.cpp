@@ -135,6 +135,7 @@ Engine::~Engine() {
   if (task_dev_) dev_free(task_dev_);
   if (sync_) dev_free(sync_);
   if (xch_) dev_free(xch_);
+  if (ones_) dev_free(ones_);
 }
 
 template <class TT>
@@ -171,6 +172,7 @@ size_t Engine::footprint(const hh_problem* pb, int t, int prec, int maxit) {
   b += (size_t)nblk_for(len) * (cols + t) * t * sizeof(c128);    // partial sums
   b += (size_t)t * (pb->fs.max_ns + (size_t)pb->fs.N * pb->n) * esz_of(prec);
   b += (size_t)cols * t * sizeof(c128);
+  if (t > 2) b += (size_t)len * sizeof(c128);                    // summed sweep input
   return b;
 }
 
@@ -183,6 +185,8 @@ void Engine::release(Solve* s) {
   dev_free(s->rho);
   dev_free(s->g1);
   dev_free(s->ydev);
+  dev_free(s->sumv);
+  s->sumv = nullptr;
   s->V = nullptr;
   s->Z = nullptr;
   s->Hd = nullptr;
@@ -191,6 +195,12 @@ void Engine::release(Solve* s) {
   s->rho = s->g1 = nullptr;
   s->ydev = nullptr;
 }
+
+size_t Engine::iteration_bytes(const Solve* s) {
+  return (size_t)s->len * s->t * (sizeof(c128) + esz_of(s->prec));
+}
+
+struct GrowRefused {};
 
 // Grows V, Z and the coefficient scratch so that the next iteration fits.
 void Engine::ensure_capacity(Solve* s) {
@@ -202,8 +212,26 @@ void Engine::ensure_capacity(Solve* s) {
     it_cap = std::min(it_cap, s->maxit);
     it_cap = std::max(it_cap, s->k + 1);
     int vcap = 1 + it_cap * t, zcap = it_cap * t;
-    c128* V = (c128*)dev_alloc((size_t)s->len * vcap * sizeof(c128));
-    void* Z = dev_alloc((size_t)s->len * zcap * es);
+    // budget: iterations beyond the charged ones, and while the old bases are
+    // copied, the old bases a second time
+    const long long old_bytes =
+        s->V ? (long long)(s->len * s->vcap * sizeof(c128) + s->len * s->zcap * es) : 0;
+    const long long extra =
+        it_cap > s->charged_its ? (long long)(it_cap - s->charged_its) * (long long)iteration_bytes(s) : 0;
+    if (grow_ && (extra > 0 || old_bytes > 0)) {
+      if (!grow_(s, extra + old_bytes)) throw GrowRefused();
+    }
+    c128* V = nullptr;
+    void* Z = nullptr;
+    try {
+      V = (c128*)dev_alloc((size_t)s->len * vcap * sizeof(c128));
+      Z = dev_alloc((size_t)s->len * zcap * es);
+    } catch (...) {
+      dev_free(V);
+      if (grow_ && (extra > 0 || old_bytes > 0)) grow_(s, -(extra + old_bytes));
+      throw;
+    }
+    s->charged_its = std::max(s->charged_its, it_cap);
     if (s->V) {
       HH_HIP(hipMemcpyAsync(V, s->V, (size_t)s->len * s->m * sizeof(c128), hipMemcpyDeviceToDevice, st_));
       HH_HIP(hipMemcpyAsync(Z, s->Z, (size_t)s->len * s->k * t * es, hipMemcpyDeviceToDevice, st_));
@@ -211,6 +239,7 @@ void Engine::ensure_capacity(Solve* s) {
       dev_free(s->V);
       dev_free(s->Z);
     }
+    if (grow_ && old_bytes > 0) grow_(s, -old_bytes);
     s->V = V;
     s->Z = Z;
     s->vcap = vcap;
@@ -229,6 +258,22 @@ void Engine::ensure_capacity(Solve* s) {
   }
 }
 
+void Engine::ensure_all(std::vector<Solve*>& solves) {
+  for (Solve* s : solves) {
+    if (s->done) continue;
+    try {
+      ensure_capacity(s);
+    } catch (const GrowRefused&) {
+      set_error("a solve's Krylov bases would exceed the HBM budget");
+      s->fail = HH_EBUDGET;
+      s->done = true;
+    } catch (const MemError&) {
+      s->fail = HH_ENOMEM;
+      s->done = true;
+    }
+  }
+}
+
 // ------------------------------------------------------------ begin
 void Engine::begin(std::vector<Solve*>& solves) {
   std::vector<Solve*> live;
@@ -237,14 +282,17 @@ void Engine::begin(std::vector<Solve*>& solves) {
     s->m = 1;
     s->done = s->converged = s->breakdown = s->finalized = false;
     s->deflated = 0;
+    s->fail = 0;
     const FactorSet& fs = s->pb->fs;
-    s->t = fs.nd;
+    s->t = fs.npre;
     s->prec = fs.precision;
+    s->sum_input = false;
     const size_t es = esz_of(s->prec);
-    ensure_capacity(s);
+    ensure_capacity(s);  // the first bases fit the iterations charged at admission
     if (!s->flags) s->flags = (int*)dev_alloc(4 * sizeof(int));
     if (!s->rho) s->rho = dev_alloc((size_t)s->t * fs.max_ns * es + 256);
     if (!s->g1) s->g1 = dev_alloc((size_t)s->t * fs.N * s->pb->n * es + 256);
+    if (s->t > 2 && !s->sumv) s->sumv = (c128*)dev_alloc((size_t)s->len * sizeof(c128));
     HH_HIP(hipMemcpyAsync(s->V, s->b, (size_t)s->len * sizeof(c128), hipMemcpyDeviceToDevice, st_));
     live.push_back(s);
   }
@@ -309,11 +357,11 @@ void Engine::begin(std::vector<Solve*>& solves) {
 
 // ------------------------------------------------------------ step
 void Engine::step(std::vector<Solve*>& solves) {
+  ensure_all(solves);
   std::vector<Solve*> live;
   for (Solve* s : solves)
     if (!s->done) live.push_back(s);
   if (live.empty()) return;
-  for (Solve* s : live) ensure_capacity(s);
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
 
   // 1. sweeps: every preconditioner of every solve, one chain each.  Launch
@@ -347,8 +395,9 @@ void Engine::step(std::vector<Solve*>& solves) {
     it->nmax = std::max(it->nmax, pb->n);
     for (int i = 0; i < s->t; ++i) {
       SweepTask tk{};
-      tk.ch.strips = fs.d_strips + (size_t)i * fs.N;
-      tk.ch.r = s->V + (size_t)s->inputs[i] * s->len;
+      tk.ch.strips = fs.d_strips + (size_t)fs.pre_slot[i] * fs.N;
+      tk.mode = fs.pre_mode[i];
+      tk.ch.r = s->sum_input ? s->sumv : s->V + (size_t)s->inputs[i] * s->len;
       tk.ch.z = (char*)s->Z + ((size_t)s->k * s->t + i) * s->len * es;
       tk.ch.rho = (char*)s->rho + (size_t)i * fs.max_ns * es;
       tk.ch.g1 = (char*)s->g1 + (size_t)i * fs.N * pb->n * es;
@@ -368,10 +417,9 @@ void Engine::step(std::vector<Solve*>& solves) {
       k.plan = wide_ok_ ? sweep_plan_for((int)k.tasks.size(), k.prec, k.P, k.kmax, k.nmax, k.piv,
                                          k.wide)
                         : 0;
-      if (k.plan == 0) {
+      if (k.plan != HH_PLAN_WIDE)
         for (hh_problem* q : k.pbs) ensure_batch_maps(q, st_);
-        continue;
-      }
+      if (k.plan == 0) continue;
       chains += k.tasks.size();
       xbytes += k.tasks.size() * (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);
     }
@@ -409,6 +457,33 @@ void Engine::step(std::vector<Solve*>& solves) {
   }
   std::vector<SweepTask*> dsw(kinds.size());
   for (size_t q = 0; q < kinds.size(); ++q) dsw[q] = stage(kinds[q].tasks, staged_);
+
+  // 0. t > 2 (sum rule): the sweeps' input is the sum of the previous
+  // iteration's t new basis vectors (deflated ones are zero)
+  std::vector<CombTask> sums;
+  long long sumlen = 0;
+  for (Solve* s : live) {
+    if (!s->sum_input) continue;
+    CombTask c{};
+    c.Z = s->V + (size_t)(s->m - s->t) * s->len;
+    c.y = nullptr;  // the staged ones, below
+    c.x = s->sumv;
+    c.len = s->len;
+    c.ncols = s->t;
+    sums.push_back(c);
+    sumlen = std::max(sumlen, s->len);
+  }
+  CombTask* dsums = nullptr;
+  if (!sums.empty()) {
+    if (!ones_) {
+      ones_ = (c128*)dev_alloc(HH_MAXPRE * sizeof(c128));
+      const std::vector<c128> h(HH_MAXPRE, mk(1.0, 0.0));
+      HH_HIP(hipMemcpyAsync(ones_, h.data(), HH_MAXPRE * sizeof(c128), hipMemcpyHostToDevice, st_));
+      HH_HIP(hipStreamSynchronize(st_));
+    }
+    for (CombTask& c : sums) c.y = ones_;
+    dsums = stage(sums, staged_);
+  }
 
   // 2. SpMV: W = A Z_k into the basis slots m..m+t-1
   std::vector<SpmvTask> sp[2];
@@ -542,6 +617,7 @@ void Engine::step(std::vector<Solve*>& solves) {
   upload();
 
   // ---- launches
+  if (dsums) launch_combine(DEV(dsums), (int)sums.size(), sumlen, HH_FP64, st_);
   {
     // algorithmic bytes: each (problem, direction) factor read once per strip
     // solve of the launch, plus FP64 input and sweep-precision output per task
@@ -554,8 +630,8 @@ void Engine::step(std::vector<Solve*>& solves) {
       if (first) seen.push_back(s->pb);
       for (int i = 0; i < s->t; ++i)
         for (int q = 0; q < fs.N; ++q) {
-          const StripDesc& sd = fs.strips[(size_t)i * fs.N + q];
-          const double solves = q == fs.N - 1 ? 1.0 : 2.0;
+          const StripDesc& sd = fs.strips[(size_t)fs.pre_slot[i] * fs.N + q];
+          const double solves = fs.pre_mode[i] != SWEEP_DOUBLE ? 1.0 : q == fs.N - 1 ? 1.0 : 2.0;
           if (first) bytes += solves * (double)sd.ns * sd.ldab * es;
           bytes += solves * (double)sd.ns * (sizeof(c128) + es);
         }
@@ -661,6 +737,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     s->k += 1;
     s->m += t;
     s->res_est = s->ls.residual() / s->beta;
+    s->sum_input = false;
     if (s->res_est <= s->tol) {
       s->done = true;
       s->converged = true;
@@ -672,6 +749,8 @@ void Engine::step(std::vector<Solve*>& solves) {
     } else if (t == 2 && kept.size() == 2) {
       s->inputs[0] = kept[1];  // LRL gets the vector from BTB's column (Sec. 4)
       s->inputs[1] = kept[0];
+    } else if (t > 2 && kept.size() >= 2) {
+      s->sum_input = true;     // every M_i gets the sum of the new vectors (Sec. 4)
     } else {
       for (int i = 0; i < t; ++i) s->inputs[i] = kept[0];
     }

@@ -10,6 +10,7 @@
 #pragma once
 
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "hh_internal.h"
@@ -69,9 +70,14 @@ struct Solve {
   void* rho = nullptr;    // sweep scratch, t chains
   void* g1 = nullptr;
   c128* ydev = nullptr;
+  c128* sumv = nullptr;   // t > 2: the sum of the new basis vectors (sweep input)
   int inputs[4] = {0, 0, 0, 0};
+  bool sum_input = false; // the next sweeps read sumv (formed at the next step)
   LeastSquares ls;
   bool done = false, converged = false, breakdown = false, finalized = false;
+  int fail = 0;           // stopped early: HH_EBUDGET (growth refused) or HH_ENOMEM
+  void* owner = nullptr;  // the caller's tag (the server's request)
+  int charged_its = 0;    // iterations of Krylov memory charged to the owner's budget
   int deflated = 0;
   double res_est = 0, res_true = 0;
   std::vector<zd> hbuf;   // host copy of Hd
@@ -116,6 +122,13 @@ class Engine {
   // Whether sweeps may run on several workgroups per chain (the wide segment
   // plan); engines that share the device with other engines keep it off.
   void set_wide(bool on) { wide_ok_ = on; }
+  // Budget hook for the growth of a solve's Krylov bases past the iterations
+  // charged to it (Solve::charged_its): called with the extra device bytes
+  // (negative to give some back); false refuses the growth, and that solve
+  // alone stops with fail = HH_EBUDGET.  Without a hook growth is unlimited.
+  void set_grow_hook(std::function<bool(Solve*, long long)> h) { grow_ = std::move(h); }
+  // Device bytes of one iteration's Krylov columns (V and Z) of a solve.
+  static size_t iteration_bytes(const Solve* s);
 
  private:
   hipStream_t st_;
@@ -127,6 +140,10 @@ class Engine {
   TT* stage(const std::vector<TT>& v, size_t& off);
   void upload();
   void ensure_capacity(Solve* s);
+  // ensure_capacity for every solve, stopping (fail) the ones whose growth
+  // is refused or cannot be allocated, without touching the others.
+  void ensure_all(std::vector<Solve*>& solves);
+  std::function<bool(Solve*, long long)> grow_;
   size_t staged_ = 0;
   // wide plan: sync words (word 0: abort, sticky until begin(); then one
   // 128-byte line per chain) and the chains' exchange areas
@@ -136,6 +153,7 @@ class Engine {
   size_t sync_clear_ = 0;  // chain lines zeroed since their last launch
   void* xch_ = nullptr;
   size_t xch_cap_ = 0;
+  c128* ones_ = nullptr;  // HH_MAXPRE ones: coefficients of the sum rule's combination
 };
 
 }  // namespace hh

@@ -738,10 +738,10 @@ __global__ __launch_bounds__(64) void k_build_blocked(const StripDesc* __restric
 __host__ __device__ inline int transfer_ring(int kl) { return kl < 32 ? 32 : 64; }
 
 // Segments that k_build_transfer runs for plan p: those with a tail map
-// (1..nseg-2), and for the wide plan also the last one (its response only).
+// (1..nseg-2), and for plans 1 and 2 also the last one (its response only).
 __host__ __device__ inline int transfer_jobs(const StripDesc& sd, int p) {
   const int nseg = plan_nseg(sd.ns, sd.pseg[p]);
-  if (p == HH_NPLAN - 1) return sd.wide && nseg > 1 ? nseg - 1 : 0;
+  if (p >= 1) return sd.wide && nseg > 1 ? nseg - 1 : 0;
   return plan_seg_maps(sd.ns, sd.pseg[p]);
 }
 
@@ -795,10 +795,10 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
   const int KM = map_dim(sd.KP);
   cx<T>* Tm = img + sd.t_off +
               ((upper ? (long long)sd.tmaps : 0LL) + pmap + m) * KM * KM;
-  cx<T>* Ph = plan == HH_NPLAN - 1
-                  ? img + sd.phi_off + (upper ? plan_phi_elems(ns, sd.segs, K, KM) : 0LL) +
-                        (long long)(s - 1) * seg * KM
-                  : nullptr;
+  cx<T>* Ph = plan >= 1 ? img + strips[blockIdx.x].phi_off[plan] +
+                             (upper ? plan_phi_elems(ns, sd.segs, K, KM, plan) : 0LL) +
+                             (long long)(s - 1) * seg * KM
+                       : nullptr;
   const int s0 = s * seg, s1 = s0 + seg < ns ? s0 + seg : ns;
   // lane c < K fetches T(i, c + 1)
   auto coef = [&](int i) -> c128 {
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
   }
 }
 
-// Products of segment maps for the wide plan (slots in plan_layout), formed
+// Products of segment maps for plan p >= 1 (slots in plan_layout), formed
 // in FP64 from the stored maps.  Stage 0, for workgroup g (segments c = g P
 // + w): the running product T_{gP+q-1} ... T_{gP}, stored as Pi_{gP+q} for
 // q < P and as W_g for q = P (the chain of workgroup g), and A1_c = T_c
@@ -912,12 +912,15 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
 template <class T>
 __global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restrict__ strips,
                                                         cx<T>* __restrict__ img,
-                                                        const int* __restrict__ pflag, int stage) {
+                                                        const int* __restrict__ pflag, int stage,
+                                                        int plan) {
   extern __shared__ c128 sh[];  // 3 KM^2
   if (pflag[blockIdx.x]) return;
   const StripDesc sd = strips[blockIdx.x];
   if (!sd.wide) return;
-  const int plan = HH_NPLAN - 1, G = plan_width(plan);
+  const int G = plan_width(plan);
+  const int pi_map = sd.pi_map[plan], a1_map = sd.a1_map[plan], a2_map = sd.a2_map[plan];
+  const int ps_map = sd.ps_map[plan];
   const int ns = sd.ns, K = sd.kl, P = sd.segs, KM = map_dim(sd.KP), K2 = KM * KM;
   const int nseg = plan_nseg(ns, sd.pseg[plan]), gu = (nseg + P - 1) / P;
   const int t0 = sd.pmap[plan] - 1;  // slot of T_c is t0 + c
@@ -973,7 +976,7 @@ __global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restr
       for (int q = 1;; ++q) {  // cur = T_{gP+q-1} ... T_{gP}
         if (q < P) {
           if (g * P + q > nseg - 1) break;
-          store(sd.pi_map + g * P + q - 1, cur);
+          store(pi_map + g * P + q - 1, cur);
         } else {
           if (g <= gu - 2) store(sd.pwmap[plan] + g - 1, cur);
           break;
@@ -992,29 +995,29 @@ __global__ __launch_bounds__(256) void k_build_products(const StripDesc* __restr
       load(X, t0 + c);
       load(Y, t0 + c - 1);
       mul(Z, X, Y);
-      store(sd.a1_map + c - 1, Z);
+      store(a1_map + c - 1, Z);
     }
   } else if (m >= G) {
     const int g = (m - G) / P, w = (m - G) % P, c = g * P + w;
     if (g >= gu || w < 4 || c > nseg - 2) return;
-    load(X, sd.a1_map + c - 1);
-    load(Y, sd.a1_map + c - 3);
+    load(X, a1_map + c - 1);
+    load(Y, a1_map + c - 3);
     mul(Z, X, Y);
-    store(sd.a2_map + c - 1, Z);
+    store(a2_map + c - 1, Z);
   } else {
     const int g = m;
     if (G < 3 || g < 2 || g > gu - 1) return;
     c128* cur = X;
     c128* nxt = Y;
     load(cur, sd.pwmap[plan] + g - 2);  // W_{g-1}
-    store(sd.ps_map + g * G + g - 2, cur);
+    store(ps_map + g * G + g - 2, cur);
     for (int j = g - 3; j >= 0; --j) {
       load(Z, sd.pwmap[plan] + j);  // W_{j+1}
       mul(nxt, cur, Z);
       c128* tmp = cur;
       cur = nxt;
       nxt = tmp;
-      store(sd.ps_map + g * G + j, cur);
+      store(ps_map + g * G + j, cur);
     }
   }
 }
@@ -1037,26 +1040,37 @@ static dim3 transfer_grid(const FactorSet& fs) {
   return dim3((unsigned)fs.strips.size(), 2, (unsigned)maps);
 }
 
-static dim3 product_grid(const FactorSet& fs, int stage) {
+static dim3 product_grid(const FactorSet& fs, int stage, int plan) {
   int jobs = 0;
   for (auto& sd : fs.strips) {
-    const int G = plan_width(HH_NPLAN - 1);
+    const int G = plan_width(plan);
     jobs = std::max(jobs, stage == 0 ? G * (sd.segs + 1) : G * sd.segs + G);
   }
   return dim3((unsigned)fs.strips.size(), 2, (unsigned)jobs);
 }
 
 template <class T>
-static void launch_products(const FactorSet& fs, hipStream_t st) {
+static void launch_products_t(const FactorSet& fs, int planmask, hipStream_t st) {
   if (!fs.strips[0].wide) return;
   const int KM = map_dim(fs.strips[0].KP);
   const size_t lds = 3 * (size_t)KM * KM * sizeof(c128);
   const void* fn = (const void*)k_build_products<T>;
   if (lds > 64 * 1024)
     HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  for (int stage = 0; stage < 2; ++stage)
-    hipLaunchKernelGGL(k_build_products<T>, product_grid(fs, stage), dim3(256), lds, st,
-                       fs.d_strips, (cx<T>*)fs.img, fs.d_pflag, stage);
+  for (int plan = 1; plan < HH_NPLAN; ++plan) {
+    if (!(planmask >> plan & 1)) continue;
+    for (int stage = 0; stage < 2; ++stage)
+      hipLaunchKernelGGL(k_build_products<T>, product_grid(fs, stage, plan), dim3(256), lds, st,
+                         fs.d_strips, (cx<T>*)fs.img, fs.d_pflag, stage, plan);
+  }
+}
+
+void launch_products(const FactorSet& fs, int planmask, hipStream_t st) {
+  if (fs.precision == HH_FP64)
+    launch_products_t<double>(fs, planmask, st);
+  else
+    launch_products_t<float>(fs, planmask, st);
+  HH_HIP(hipGetLastError());
 }
 
 // kl < 32: the two-lanes-per-column kernel on every strip; the strips it
@@ -1166,8 +1180,8 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
-    launch_transfer(fs, fs.batch_maps ? 3 : 2, st);
-    launch_products<double>(fs, st);
+    launch_transfer(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+    launch_products(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
   } else {
     launch_lu<float>(pb, lds, st);
     HH_HIP(hipGetLastError());
@@ -1176,8 +1190,8 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
                        fs.d_pflag);
     hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
                        (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
-    launch_transfer(fs, fs.batch_maps ? 3 : 2, st);
-    launch_products<float>(fs, st);
+    launch_transfer(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+    launch_products(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
   }
   HH_HIP(hipGetLastError());
 }

@@ -110,7 +110,13 @@ struct MemError {};
 // ---------------------------------------------------------------- geometry
 // Segment plans of the parallel substitution (see sweep.hip): plan p spreads
 // each triangular substitution of a strip over plan_width(p) workgroups.
-constexpr int HH_NPLAN = 2;
+// Plan 0: one workgroup per chain; plan 1 (HH_PLAN_WIDE): sixteen, for a few
+// chains; plan 2 (HH_PLAN_PAIR): two, for batches of up to one chain per two
+// compute units.  Plans 1 and 2 share the kernel and the kinds of maps
+// (segment responses and map products), each with its own segment cut.
+constexpr int HH_NPLAN = 3;
+constexpr int HH_PLAN_WIDE = 1;
+constexpr int HH_PLAN_PAIR = 2;
 // One strip of one sweep direction (0 = x / LRL, 1 = y / BTB).
 struct StripDesc {
   int dir;        // 0 x, 1 y
@@ -136,11 +142,12 @@ struct StripDesc {
   int pseg[HH_NPLAN];  // rows per segment of each plan
   int pmap[HH_NPLAN];  // index of the plan's first segment map among the triangle's maps
   int pwmap[HH_NPLAN]; // index of the plan's first workgroup map
-  int pi_map, a1_map, a2_map, ps_map;  // wide plan: products of maps (see plan_layout)
-  int wide;            // the wide plan's maps and responses are built (sweep_wide_fits)
+  // plans p >= 1: slots of the products of maps (see plan_layout; index 0 unused)
+  int pi_map[HH_NPLAN], a1_map[HH_NPLAN], a2_map[HH_NPLAN], ps_map[HH_NPLAN];
+  int wide;            // the maps and responses of plans 1 and 2 exist (sweep_wide_fits)
   long long t_off;     // complex elements into the solve image: transfer maps (L, then U)
-  long long phi_off;   // complex elements into the solve image: segment responses of the
-                       // wide plan (L, then U; see plan_phi_elems)
+  long long phi_off[HH_NPLAN];  // plans p >= 1: complex elements into the solve image of the
+                                // segment responses (L, then U; see plan_phi_elems)
 };
 
 // Zero steps appended to every strip's solve image and pivot list, so that the
@@ -148,12 +155,24 @@ struct StripDesc {
 constexpr int HH_PAD = 64;
 
 // Strip factors of every strip of every factored direction.
+// Sweep orders of a preconditioner (Sec. 2 and Sec. 4): the double sweep
+// (LRL, BTB), the forward single sweep (LR, BT) and the reverse single sweep
+// (RL, TB).
+enum SweepMode { SWEEP_DOUBLE = 0, SWEEP_FORWARD = 1, SWEEP_REVERSE = 2 };
+constexpr int HH_MAXPRE = 4;  // preconditioners of one MPGMRES (t)
+
 struct FactorSet {
   int N = 0;
   unsigned dirs = 0;
   int precision = -1;       // HH_FP64 / HH_FP32, -1 = not factored
-  int nd = 0;               // number of directions
-  int dir_id[2] = {-1, -1}; // direction (0/1) of preconditioner slot 0/1
+  int nd = 0;               // number of factored directions
+  int dir_id[2] = {-1, -1}; // direction (0/1) of factored slot 0/1 (strips[slot*N + s])
+  // The preconditioners M_1..M_t of MPGMRES in order: the factored slot whose
+  // strips they use and their sweep order.  hh_factor_sweeps sets the double
+  // sweeps of the factored directions (LRL, then BTB).
+  int npre = 0;
+  int pre_slot[HH_MAXPRE] = {0, 0, 0, 0};
+  int pre_mode[HH_MAXPRE] = {0, 0, 0, 0};
   std::vector<StripDesc> strips;  // dir-major: strips[d*N + s]
   StripDesc* d_strips = nullptr;  // device copy
   void* band = nullptr;            // LU work buffer, freed once every map is built
@@ -165,12 +184,12 @@ struct FactorSet {
   std::array<int, 2> h_err{{0, 0}};  // host copy, valid once the factor stream completed
   std::vector<int> h_pflag;           // host copy of d_pflag, likewise
   bool any_pivot = false;             // some strip pivoted (set by factor_finish)
-  // The transfer maps of segment plan 0 (one workgroup per chain) serve
-  // batched sweeps only; where the wide plan exists they are built from the
-  // kept band when a launch first takes plan 0 (ensure_batch_maps), unless
-  // eager_batch_maps asks for them with the factorisation.
+  // The maps of segment plans 0 and 2 (one and two workgroups per chain)
+  // serve batched sweeps only; where plans 1 and 2 exist they are built from
+  // the kept band when a launch first takes plan 0 or 2 (ensure_batch_maps),
+  // unless eager_batch_maps asks for them with the factorisation.
   bool eager_batch_maps = false;
-  bool batch_maps = true;             // plan 0's transfer maps are built or queued
+  bool batch_maps = true;             // the maps of plans 0 and 2 are built or queued
   size_t band_elems = 0, img_elems = 0, piv_elems = 0, tr_elems = 0;
   int max_ns = 0, max_kl = 0;
   size_t bytes() const;
@@ -183,9 +202,18 @@ struct hh_problem {
   double omega = 0;
   std::vector<double> c;
   double* d_c = nullptr;           // layer speeds on the device
+  // A sampled speed field (hh_assemble_field): wave numbers omega / c of the
+  // triangles (2 per cell, lower then upper, cell (ci, cj) at 2 (cj (n-1) + ci)),
+  // of the edges (i, j)-(i, j+1) at j n + i and of the edges (i, j)-(i+1, j) at
+  // j (n-1) + i; null for a layered medium.
+  double* d_kt = nullptr;
+  double* d_kv = nullptr;
+  double* d_kh = nullptr;
+  hh::c128* d_b = nullptr;         // right-hand side b = -M f given at assembly, or null
   hh::c128* d_A = nullptr;         // 4 * n*n upper diagonals
   hh::FactorSet fs;
   hipStream_t st[2] = {nullptr, nullptr};
+  bool own_streams = true;         // false: the caller's (hh_set_streams), not destroyed
   hipEvent_t ev[2] = {nullptr, nullptr};
   int device = 0;
   size_t bytes() const;
@@ -212,6 +240,19 @@ struct TimedRegion {
 enum { FAM_SWEEP = 0, FAM_SPMV, FAM_FACTOR, FAM_ORTH, FAM_ASSEMBLE, FAM_COUNT };
 void timing_flush();
 
+// ---------------------------------------------------------------- media
+// What the assembly kernels need to know of the wave speed (eq. (1), k = omega
+// / c): the layer table, or the sampled wave numbers of a speed field (see
+// hh_problem::d_kt, d_kv, d_kh; when kt is set, kv and kh are too).
+struct Medium {
+  double omega;
+  int L;
+  const double* c;
+  const double* kt;
+  const double* kv;
+  const double* kh;
+};
+
 // ---------------------------------------------------------------- problems
 // Internal halves of hh_assemble / hh_factor_sweeps / hh_free (capi.cpp),
 // also driven asynchronously by the serving loop.
@@ -219,17 +260,28 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision);
 void factor_launch(hh_problem* pb, hipStream_t st);
 int factor_finish(hh_problem* pb);
 hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n);
+// The same for a speed field sampled by a host callback at the triangle
+// centroids and edge midpoints.
+hh_problem* problem_create_field(double omega, double (*speed)(double, double, void*), void* ctx,
+                                 int n);
 void problem_destroy(hh_problem* pb);
 
 // ---------------------------------------------------------------- memory
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 size_t dev_live_bytes();
+bool set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* ctx);
+// Releases the cached free blocks and the pooled timing events.
+void runtime_release_caches();
+// Streams for problems created from now on (hh_set_streams): both null means
+// the problems create and own their streams.
+void set_caller_streams(hipStream_t x, hipStream_t y);
+bool caller_streams(hipStream_t& x, hipStream_t& y);
 
 // ---------------------------------------------------------------- kernels
 // assemble.hip
-void launch_assemble(int n, double omega, int nlayers, const double* d_c, c128* d_A,
-                     hipStream_t st);
+Medium medium_of(const hh_problem* pb);
+void launch_assemble(int n, const Medium& md, c128* d_A, hipStream_t st);
 void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st);
 void launch_pack_strips(const hh_problem* pb, hipStream_t st);
 // Zeroes and packs again the bands of the strips whose pflag is 2 (marked by
@@ -241,7 +293,13 @@ bool lu_interchanging_only();
 // factor.hip
 void launch_band_lu(const hh_problem* pb, hipStream_t st);
 void launch_transfer(const FactorSet& fs, int planmask, hipStream_t st);
-// Builds plan 0's transfer maps on st if the factorisation left them out,
+// Map products of the plans p >= 1 in planmask (bit p: plan p).
+void launch_products(const FactorSet& fs, int planmask, hipStream_t st);
+// Plans whose maps a factorisation builds at once (the rest, plans 0 and 2,
+// when a batch first needs them): bit p for plan p.
+constexpr int HH_EAGER_PLANS = 1 << HH_PLAN_WIDE;
+constexpr int HH_BATCH_PLANS = (1 << 0) | (1 << HH_PLAN_PAIR);
+// Builds the maps of plans 0 and 2 on st if the factorisation left them out,
 // waits for them and frees the band.
 void ensure_batch_maps(hh_problem* pb, hipStream_t st);
 
@@ -265,6 +323,7 @@ struct SweepTask {
   int N;
   void* xch;      // wide plan: G * 64 elements of sweep precision (workgroup tails)
   unsigned* bar;  // wide plan: arrival counter of the chain's workgroups, zero at launch
+  int mode;       // SweepMode: double sweep, forward or reverse single sweep
 };
 // All tasks share the precision, the blocked-term count KP (which fixes the
 // slot count S of the pivoted path) and the segment count P (waves per
@@ -284,6 +343,12 @@ bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
 // HH_SWEEP_PLAN environment variable (0 or 1) when set, else the wide plan
 // while ntasks times its width is at most half the compute units.
 int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built);
+// Whether plan p can run a launch of ntasks chains: plan 0 always; plans 1
+// and 2 on complex64 strips none of which pivoted (sweep_wide_fits), when all
+// ntasks * plan_width(p) workgroups fit the device at once (occupancy), plan 2
+// once its maps are built (built = the batch maps).
+bool sweep_plan_fits(int plan, int ntasks, int precision, int KP, int P, int kmax, int nmax,
+                     bool pivots, bool built);
 // Blocked substitution: block size and terms per lane for band half-width kl.
 // KP terms per lane cover the K + HH_BLK columns of a block map over the 64/HH_BLK
 // lanes of one output row; KP <= 12 exactly when 2 kl + 1 <= 64 (one lane-major
@@ -307,7 +372,7 @@ __host__ __device__ inline int segment_rows(int ns, int P) {
 // 16-row aligned segments.  Either way a segment is at least K rows long, so
 // that a segment's state (the K outputs before it) lies in the segment before
 // it, and every segment after the first starts at row K or later.
-__host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : 16; }
+__host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : p == HH_PLAN_WIDE ? 16 : 2; }
 __host__ __device__ inline int plan_seg(int ns, int P, int p, int K) {
   if (p == 0) return segment_rows(ns, P);
   const int S = plan_width(p) * P, per = (ns + S - 1) / S, least = (K + 15) / 16 * 16;
@@ -335,40 +400,42 @@ __host__ __device__ inline int plan_wg_maps(int ns, int seg, int P, int G) {
 __host__ __device__ constexpr int map_dim(int KP) {
   return KP <= 8 ? 16 : KP <= 10 ? 24 : KP <= 12 ? 32 : KP <= 16 ? 48 : 64;
 }
-// Segment responses of the wide plan (one triangle): for segments c = 1 ..
+// Segment responses of plan p >= 1 (one triangle): for segments c = 1 ..
 // nseg-1, the outputs of the segment's rows started from the unit state e_k
 // with zero inputs, Phi_c[k][i] at ((c - 1) KM + k) seg + i (zero for k >= K).
-__host__ __device__ inline long long plan_phi_elems(int ns, int P, int K, int KM) {
-  const int p = HH_NPLAN - 1, seg = plan_seg(ns, P, p, K), nseg = plan_nseg(ns, seg);
+__host__ __device__ inline long long plan_phi_elems(int ns, int P, int K, int KM, int p) {
+  const int seg = plan_seg(ns, P, p, K), nseg = plan_nseg(ns, seg);
   return nseg > 1 ? (long long)(nseg - 1) * seg * KM : 0;
 }
 // Fills the plan fields of sd (ns, kl and segs set) and returns the maps per
 // triangle.  Map slots of a triangle: per plan its segment maps T_c (slot
-// pmap + c - 1) and workgroup maps W_g (pwmap + g - 1); then, for the wide
-// plan, products of consecutive segment maps within a workgroup, slot + c - 1
-// for segment c = g P + w:
+// pmap + c - 1) and workgroup maps W_g (pwmap + g - 1); then, per plan p >= 1,
+// products of consecutive segment maps within a workgroup, slot + c - 1 for
+// segment c = g P + w:
 //   pi_map: Pi_c = T_{c-1} ... T_{gP} (w >= 1), the map from the workgroup's
 //           start state to segment c's start state;
 //   a1_map: T_c T_{c-1} (w >= 2);  a2_map: T_c ... T_{c-3} (w >= 4);
 // and ps_map + g G + j: Psi_{j,g} = W_{g-1} ... W_{j+1} (0 <= j <= g-2).
 inline int plan_layout(StripDesc& sd) {
   int m = 0;
-  const int pw = HH_NPLAN - 1;
   for (int p = 0; p < HH_NPLAN; ++p) {
-    const bool on = p != pw || sd.wide;  // the wide plan only where it can run
+    const bool on = p == 0 || sd.wide;  // plans 1 and 2 only where they can run
     sd.pseg[p] = plan_seg(sd.ns, sd.segs, p, sd.kl);
     sd.pmap[p] = m;
     if (on) m += plan_seg_maps(sd.ns, sd.pseg[p]);
     sd.pwmap[p] = m;
     if (on) m += plan_wg_maps(sd.ns, sd.pseg[p], sd.segs, plan_width(p));
   }
-  const int nseg = plan_nseg(sd.ns, sd.pseg[pw]), G = plan_width(pw);
-  const int per = sd.wide && nseg > 1 ? nseg - 1 : 0;
-  sd.pi_map = m;
-  sd.a1_map = m + per;
-  sd.a2_map = m + 2 * per;
-  sd.ps_map = m + 3 * per;
-  m += 3 * per + (sd.wide && G >= 3 && nseg > 1 ? G * G : 0);
+  sd.pi_map[0] = sd.a1_map[0] = sd.a2_map[0] = sd.ps_map[0] = 0;
+  for (int p = 1; p < HH_NPLAN; ++p) {
+    const int nseg = plan_nseg(sd.ns, sd.pseg[p]), G = plan_width(p);
+    const int per = sd.wide && nseg > 1 ? nseg - 1 : 0;
+    sd.pi_map[p] = m;
+    sd.a1_map[p] = m + per;
+    sd.a2_map[p] = m + 2 * per;
+    sd.ps_map[p] = m + 3 * per;
+    m += 3 * per + (sd.wide && G >= 3 && nseg > 1 ? G * G : 0);
+  }
   sd.seg = sd.pseg[0];
   sd.tmaps = m;
   return m;
@@ -404,10 +471,36 @@ inline long long strip_image_elems(long long ns, int S, int KP, int K, int P, bo
   sd.segs = P;
   sd.wide = wide;
   const int KM = map_dim(KP);
-  const long long blocked = 2 * blocked_blocks(ns) * KP * 64 + 2LL * plan_layout(sd) * KM * KM +
-                            (wide ? 2 * plan_phi_elems((int)ns, P, K, KM) : 0);
+  long long phi = 0;
+  for (int p = 1; wide && p < HH_NPLAN; ++p) phi += 2 * plan_phi_elems((int)ns, P, K, KM, p);
+  const long long blocked = 2 * blocked_blocks(ns) * KP * 64 + 2LL * plan_layout(sd) * KM * KM + phi;
   return lane_major > blocked ? lane_major : blocked;
 }
+// Scratch of one preconditioner application (sweep_apply_core): the task
+// descriptors, the sync words ([0] abort, then one 128-byte line per chain),
+// the strip buffers rho and g1, the complex64 staging of z (complex64 strips
+// only) and the wide plan's exchange areas.
+struct SweepBuffers {
+  SweepTask* tasks;
+  unsigned* sync;
+  void* rho;
+  void* g1;
+  void* zs;
+  void* xch;
+};
+// Segment plan of an application to nvec vectors.
+int sweep_plan_of(const hh_problem* pb, int nvec);
+// The buffers carved from base (256-byte aligned parts); *total receives the
+// bytes they take (base may be nullptr to size them only).
+SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, size_t* total);
+// z = M^{-1} r for nvec vectors with the strips of factored slot i in sweep
+// order mode, on the given scratch; waits for the stream.  Allocates nothing
+// unless the plan-0 transfer maps have to be built first (ensure_batch_maps).
+void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, c128* z,
+                      int plan, const SweepBuffers& b);
+// Zeroes bytes (a multiple of 4) with a fill kernel on st.
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+
 // Single strip solve (test hook): rhs/x in FP64, strip-local order.
 void launch_strip_solve(const hh_problem* pb, int strip_index, const c128* rhs, c128* x,
                         void* scratch, hipStream_t st);

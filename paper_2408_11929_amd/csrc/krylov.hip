@@ -267,6 +267,18 @@ __global__ void k_widen(const c64* __restrict__ a, c128* __restrict__ b, long lo
 }
 }  // namespace
 
+__global__ __launch_bounds__(256) void k_zero(unsigned* __restrict__ p, long long n) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const long long n = (long long)(bytes / 4);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (unsigned*)p, n);
+  HH_HIP(hipGetLastError());
+}
+
 void launch_widen(const c64* a, c128* b, long long n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);

@@ -31,6 +31,10 @@ namespace {
 std::mutex g_mem_mu;
 std::multimap<size_t, void*> g_free;
 std::map<void*, size_t> g_live;
+// caller's allocator (hh_set_allocator): blocks go straight to and from it
+void* (*g_user_alloc)(size_t, void*) = nullptr;
+void (*g_user_free)(void*, void*) = nullptr;
+void* g_user_ctx = nullptr;
 
 size_t round_size(size_t b) {
   const size_t big = size_t(2) << 20;
@@ -42,6 +46,24 @@ size_t round_size(size_t b) {
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   size_t sz = round_size(bytes);
+  void* (*ua)(size_t, void*) = nullptr;
+  void* uctx = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    ua = g_user_alloc;
+    uctx = g_user_ctx;
+  }
+  if (ua) {
+    // the caller's allocator, called outside the library's lock
+    void* p = ua(sz, uctx);
+    if (!p) {
+      set_error("the caller's allocator returned no memory for %zu bytes", sz);
+      throw MemError();
+    }
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_live[p] = sz;
+    return p;
+  }
   std::lock_guard<std::mutex> lk(g_mem_mu);
   auto it = g_free.find(sz);
   void* p = nullptr;
@@ -69,11 +91,36 @@ void* dev_alloc(size_t bytes) {
 
 void dev_free(void* p) {
   if (!p) return;
+  void (*uf)(void*, void*) = nullptr;
+  void* uctx = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) return;
+    const size_t sz = it->second;
+    g_live.erase(it);
+    if (g_user_free) {
+      uf = g_user_free;
+      uctx = g_user_ctx;
+    } else {
+      g_free.emplace(sz, p);
+    }
+  }
+  if (uf) uf(p, uctx);
+}
+
+// Installs (or with null functions removes) the caller's allocator.  Only
+// while the library holds no device memory, so that every block returns to
+// the allocator it came from; the library's cached blocks are released.
+bool set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
   std::lock_guard<std::mutex> lk(g_mem_mu);
-  auto it = g_live.find(p);
-  if (it == g_live.end()) return;
-  g_free.emplace(it->second, p);
-  g_live.erase(it);
+  if (!g_live.empty()) return false;
+  for (auto& kv : g_free) (void)hipFree(kv.second);
+  g_free.clear();
+  g_user_alloc = alloc;
+  g_user_free = alloc ? free_fn : nullptr;
+  g_user_ctx = alloc ? ctx : nullptr;
+  return true;
 }
 
 size_t dev_live_bytes() {
@@ -81,6 +128,24 @@ size_t dev_live_bytes() {
   size_t s = 0;
   for (auto& kv : g_live) s += kv.second;
   return s;
+}
+
+namespace {
+std::mutex g_st_mu;
+hipStream_t g_caller_st[2] = {nullptr, nullptr};
+}  // namespace
+
+void set_caller_streams(hipStream_t x, hipStream_t y) {
+  std::lock_guard<std::mutex> lk(g_st_mu);
+  g_caller_st[0] = x;
+  g_caller_st[1] = y;
+}
+
+bool caller_streams(hipStream_t& x, hipStream_t& y) {
+  std::lock_guard<std::mutex> lk(g_st_mu);
+  x = g_caller_st[0];
+  y = g_caller_st[1];
+  return x != nullptr || y != nullptr;
 }
 
 void dev_trim() {
@@ -121,6 +186,16 @@ hipEvent_t take_event() {
 }  // namespace
 
 bool timing_on() { return g_t_on; }
+
+void runtime_release_caches() {
+  timing_flush();
+  {
+    std::lock_guard<std::mutex> lk(g_t_mu);
+    for (hipEvent_t e : g_event_pool) (void)hipEventDestroy(e);
+    g_event_pool.clear();
+  }
+  dev_trim();
+}
 
 TimedRegion::TimedRegion(int family, hipStream_t s, double b) : fam(family), st(s), bytes(b) {
   if (!g_t_on) return;

@@ -29,14 +29,18 @@ using namespace hh;
 
 namespace {
 
-constexpr int kReserveIterations = 32;  // Krylov reservation charged at admission
+// Krylov iterations charged at admission; a solve that runs longer charges
+// each growth of its bases when it happens (Engine::set_grow_hook), and a
+// growth that would exceed the budget stops that solve alone (HH_EBUDGET).
+constexpr int kReserveIterations = 32;
 
 size_t esz(int prec) { return prec == HH_FP64 ? sizeof(c128) : sizeof(c64); }
 
 // Device bytes a request holds while running: operator, strip image, pivots,
 // transmission stencils, the LU work buffer (released after factorisation but
 // charged throughout), right-hand sides, and per solve the Krylov bases for
-// min(maxit, kReserveIterations) iterations plus sweep scratch.
+// min(maxit, kReserveIterations) iterations plus sweep scratch.  Growth past
+// those iterations is charged when it happens.
 size_t request_footprint(const hh_request& r) {
   const long long n = r.n, len = n * n, N = r.nstrips;
   const int nd = ((r.dirs & HH_DIR_X) ? 1 : 0) + ((r.dirs & HH_DIR_Y) ? 1 : 0);
@@ -135,6 +139,8 @@ void hh_server::retire(Request* r) {
   int imax = 0;
   double rmax = 0;
   int status = r->status == HH_PENDING ? HH_OK : r->status;
+  for (auto& s : r->solves)
+    if (s->fail && (status == HH_OK || status == HH_ENOCONV)) status = s->fail;
   for (auto& s : r->solves) {
     imax = std::max(imax, s->k);
     rmax = std::max(rmax, s->res_true);
@@ -203,6 +209,8 @@ void hh_server::loop() {
         s->len = len;
         s->tol = r->req.tol;
         s->maxit = r->req.maxit;
+        s->owner = r;
+        s->charged_its = std::min(r->req.maxit, kReserveIterations);
         joining.push_back(s.get());
         r->solves.push_back(std::move(s));
       }
@@ -273,7 +281,17 @@ int hh_server_create(size_t hbm_budget, int max_active, hh_server** out) {
     HH_HIP(hipGetDevice(&s->device));
     HH_HIP(hipStreamCreate(&s->st));
     s->engine = std::make_unique<Engine>(s->st);
-    s->engine->set_wide(false);  // slots share the device: one workgroup per chain
+    // one workgroup per chain whatever the mix: a plan chosen by the number
+    // of chains in flight would make a result depend on what else runs
+    s->engine->set_wide(false);
+    s->engine->set_grow_hook([s](Solve* sv, long long delta) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (delta > 0 && s->used + (size_t)delta > s->budget) return false;
+      s->used = (size_t)((long long)s->used + delta);
+      static_cast<Request*>(sv->owner)->footprint =
+          (size_t)((long long)static_cast<Request*>(sv->owner)->footprint + delta);
+      return true;
+    });
     s->th = std::thread([s] {
       try {
         s->loop();
@@ -297,7 +315,7 @@ int hh_submit(hh_server* srv, const hh_request* req, uint64_t* ticket) {
       !std::isfinite(q.omega) || !(q.tol > 0) || q.maxit < 1 || q.dirs < 1 || q.dirs > 3 ||
       (q.precision != HH_FP64 && q.precision != HH_FP32) || q.nstrips < 1 ||
       (q.n - 1) % q.nstrips != 0 || (q.nstrips > 1 && (q.n - 1) / q.nstrips < 2) ||
-      (q.n - 1) / q.nstrips + 5 > 63) {
+      (q.n - 1) / q.nstrips + 4 > 63) {  // band half-width of an interior strip
     set_error("invalid request fields");
     return HH_EINVAL;
   }

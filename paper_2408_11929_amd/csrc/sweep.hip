@@ -28,6 +28,7 @@
 // solve image provides as one coalesced 64-lane row per step.  Coefficient
 // rows are prefetched D steps ahead, window elements one 64-block ahead.
 #include <cstdlib>
+#include <map>
 
 #include "hh_internal.h"
 
@@ -757,6 +758,39 @@ __device__ __forceinline__ void strip_data(cx<T>* gl1, cx<T>* gl2, gptr<cx<T>> z
   }
 }
 
+// Strip order of a sweep (Sec. 2, eqs. (2)-(3); single sweeps of Sec. 4):
+// the double sweep solves s = 0..N-1 forward, then N-2..0 backward (u_N =
+// v_N), 2N - 1 steps; the forward single sweep s = 0..N-1 and the reverse
+// single sweep s = N-1..0, N steps each.  data1/data2: whether the step takes
+// transmission data on Gamma_{s,1} / Gamma_{s,2} (where the strip has that
+// side; the other side gets zero data); fwd: Gamma_{s,1} data are formed from
+// the current z (otherwise the ones kept by the forward pass are read); keep:
+// they are kept for the backward pass.
+struct SweepStep {
+  int s;
+  bool fwd, data1, data2, keep;
+};
+__device__ __forceinline__ int sweep_steps(int mode, int N) {
+  return mode == SWEEP_DOUBLE ? 2 * N - 1 : N;
+}
+__device__ __forceinline__ SweepStep sweep_step(int mode, int N, int step) {
+  SweepStep o;
+  if (mode == SWEEP_REVERSE) {
+    o.s = N - 1 - step;
+    o.fwd = false;
+    o.data1 = false;
+    o.data2 = true;
+    o.keep = false;
+  } else {
+    o.fwd = step < N;
+    o.s = o.fwd ? step : 2 * N - 2 - step;
+    o.data1 = true;
+    o.data2 = !o.fwd;
+    o.keep = o.fwd && mode == SWEEP_DOUBLE;
+  }
+  return o;
+}
+
 // One workgroup of P waves runs one double sweep.  Per strip: the
 // transmission data of its interfaces go to LDS (forward: g_{s,1} from the
 // current z, also kept for the backward pass; backward: the kept g_{s,1} and
@@ -787,20 +821,24 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
   gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
   gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
   const StripDesc* strips = uniptr(tk.ch.strips);
-  for (int step = 0; step < 2 * N - 1; ++step) {
-    const bool fwd = step < N;
-    const int s = fwd ? step : 2 * N - 2 - step;
+  const int mode = uni(tk.mode);
+  const int nsteps = sweep_steps(mode, N);
+  for (int step = 0; step < nsteps; ++step) {
+    const SweepStep ss = sweep_step(mode, N, step);
+    const bool fwd = ss.fwd;
+    const int s = ss.s;
     const StripDesc* sp = strips + s;
     const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off), piv_off = uni(sp->piv_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const int pivoted = PIV ? uni(pflag[uni(sp->gid)]) : 0;
-    const bool use2 = has2 && !fwd;
-    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, has1 != 0, use2, fwd, fwd, t1off, t2off);
+    const bool use1 = has1 && ss.data1;
+    const bool use2 = has2 && ss.data2;
+    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, use1, use2, fwd, ss.keep, t1off, t2off);
     __syncthreads();
     const float winv = 1.0f / (float)w;
-    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, has1 != 0, use2, winv};
+    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, use1, use2, winv};
     if (!pivoted) {
       const int seg = uni(sp->seg);
       const cx<T>* GL = img + img_off;
@@ -1137,36 +1175,40 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
   const StripDesc* strips = uniptr(tk.ch.strips);
   ChainBar bar{uniptr(tk.bar), abort, 0u, (unsigned)G, limit, &ok};
   constexpr long long K2 = (long long)map_dim(KP) * map_dim(KP);
-  for (int step = 0; step < 2 * N - 1; ++step) {
-    const bool fwd = step < N;
-    const int s = fwd ? step : 2 * N - 2 - step;
+  const int mode = uni(tk.mode);
+  const int nsteps = sweep_steps(mode, N);
+  for (int step = 0; step < nsteps; ++step) {
+    const SweepStep ss = sweep_step(mode, N, step);
+    const bool fwd = ss.fwd;
+    const int s = ss.s;
     const StripDesc* sp = strips + s;
     const int ns = uni(sp->ns), wd = uni(sp->w), kl = uni(sp->kl);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
-    const bool use2 = has2 && !fwd;
+    const bool use1 = has1 && ss.data1;
+    const bool use2 = has2 && ss.data2;
     const float winv = 1.0f / (float)wd;
-    const SrcGather<T> gather{r, gl1, gl2, ns, wd, n, a, dir, has1 != 0, use2, winv};
+    const SrcGather<T> gather{r, gl1, gl2, ns, wd, n, a, dir, use1, use2, winv};
     const int seg = uni(sp->pseg[plan]);
     const long long tm = uni(sp->tmaps);
     const c64* GL = img + img_off;
     const c64* GU = GL + blocked_blocks(ns) * KP * 64;
     const c64* T0 = img + uni(sp->t_off);
-    const WideMaps mL{T0, uni(sp->pmap[plan]) - 1, uni(sp->pi_map), uni(sp->a1_map),
-                      uni(sp->a2_map), uni(sp->ps_map)};
+    const WideMaps mL{T0, uni(sp->pmap[plan]) - 1, uni(sp->pi_map[plan]), uni(sp->a1_map[plan]),
+                      uni(sp->a2_map[plan]), uni(sp->ps_map[plan])};
     WideMaps mU = mL;
     mU.maps = T0 + tm * K2;
-    const c64* PL = img + uni(sp->phi_off);
-    const c64* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP));
+    const c64* PL = img + uni(sp->phi_off[plan]);
+    const c64* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), plan);
     // forward substitution: its first reads (maps, residual) go out before
     // the wait for the previous strip's meeting, the transmission data that
     // need that strip's solution after it
     auto none = []() { return true; };
     auto form_data = [&]() {
       if (step > 0 && !chain_wait(bar)) return false;
-      strip_data<T, AgentAcc>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, has1 != 0, use2, fwd,
-                              fwd && g == 0, t1off, t2off);
+      strip_data<T, AgentAcc>(gl1, gl2, z, g1, trb, s, n, a, wd, dir, use1, use2, fwd,
+                              ss.keep && g == 0, t1off, t2off);
       __syncthreads();
       return true;
     };
@@ -1188,7 +1230,7 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
       return;
     // the strip's outputs are complete: the next strip waits for this
     // arrival in its forward substitution; the last needs no meeting
-    if (step < 2 * N - 2) chain_arrive(bar);
+    if (step < nsteps - 1) chain_arrive(bar);
   }
 }
 
@@ -1317,19 +1359,70 @@ static size_t wide_lds_bytes(int P, int nmax) {
   return (size_t)sweep_lds_elems_wide(P, nmax) * sizeof(c64);
 }
 
-// The wide plan runs complex64 strips whose maps fit two lanes per row, with
+// Plans 1 and 2 run complex64 strips whose maps fit two lanes per row, with
 // at most two workgroup tails per wave in step 3 (G - 1 <= 2 P).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax) {
   return precision == HH_FP32 && map_dim(blocked_kp(kmax)) <= 32 &&
-         plan_width(HH_NPLAN - 1) - 1 <= 2 * P && wide_lds_bytes(P, nmax) <= 150 * 1024;
+         plan_width(HH_PLAN_WIDE) - 1 <= 2 * P && wide_lds_bytes(P, nmax) <= 150 * 1024;
+}
+
+template <int KP>
+static const void* wide_kernel() {
+  using Sh = SweepShape<float, KP>;
+  return (const void*)k_sweep_wide<KP, Sh::U, Sh::NB>;
+}
+
+// Workgroups of k_sweep_wide that fit the device at once (a cooperative launch
+// must not exceed it): its occupancy per compute unit, for the launch's
+// workgroup size and LDS, times the compute units.
+static long long wide_capacity(int KP, int P, int nmax) {
+  int dev = 0;
+  HH_HIP(hipGetDevice(&dev));
+  const size_t lds = wide_lds_bytes(P, nmax);
+  static std::mutex mu;
+  static std::map<std::array<long long, 4>, long long> cache;
+  const std::array<long long, 4> key{dev, KP, P, (long long)lds};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const void* fn = KP == 8 ? wide_kernel<8>() : KP == 10 ? wide_kernel<10>() : wide_kernel<12>();
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * P, lds));
+  const long long c = (long long)std::max(per_cu, 0) * wide_dev().cus;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = c;
+  return c;
+}
+
+bool sweep_plan_fits(int plan, int ntasks, int precision, int KP, int P, int kmax, int nmax,
+                     bool pivots, bool built) {
+  if (plan == 0) return true;
+  if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return false;
+  if (KP != 8 && KP != 10 && KP != 12) return false;
+  if (plan == HH_PLAN_PAIR && !built) return false;
+  return (long long)ntasks * plan_width(plan) <= wide_capacity(KP, P, nmax);
 }
 
 int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built) {
-  if (pivots || !built || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
+  if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
+  const int KP = blocked_kp(kmax);
   const char* env = std::getenv("HH_SWEEP_PLAN");
-  if (env && *env) return std::atoi(env) > 0 ? HH_NPLAN - 1 : 0;
-  const int G = plan_width(HH_NPLAN - 1);
-  return (long long)ntasks * G <= wide_dev().cus / 2 ? HH_NPLAN - 1 : 0;
+  if (env && *env) {
+    const int p = std::atoi(env);
+    if (p == HH_PLAN_PAIR)
+      return sweep_plan_fits(p, ntasks, precision, KP, P, kmax, nmax, pivots, true) ? p : 0;
+    return p > 0 && sweep_plan_fits(HH_PLAN_WIDE, ntasks, precision, KP, P, kmax, nmax, pivots,
+                                    built)
+               ? HH_PLAN_WIDE
+               : 0;
+  }
+  // a few chains: sixteen workgroups each while they take at most half the
+  // device; more chains: plan 0 (see sweep_tuned for measured choices)
+  return (long long)ntasks * plan_width(HH_PLAN_WIDE) <= wide_dev().cus / 2 ? HH_PLAN_WIDE : 0;
 }
 
 template <int KP>
@@ -1372,8 +1465,8 @@ void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, i
     throw ArgError();
   }
   if (plan > 0) {
-    if (!sweep_wide_fits(precision, P, kmax, nmax)) {
-      set_error("the wide segment plan does not fit this factorisation");
+    if (!sweep_plan_fits(plan, ntasks, precision, KP, P, kmax, nmax, pivots, true)) {
+      set_error("segment plan %d does not fit this factorisation or launch", plan);
       throw ArgError();
     }
     launch_wide(d_tasks, ntasks, KP, P, nmax, plan, abort, st);

@@ -9,11 +9,12 @@
   1281^2 meshes (32 strips, 8 sources): convergence, and the FP64 residual of
   sampled right-hand sides recomputed on the CPU.
 
-Bars: FP64 kernels 1e-12 relative; complex64 strips 1e-5, or three times the
-error of the oracle's own complex64 LAPACK solve where that is larger;
-solutions 1e-6 residual (1e-6 tolerance, recomputed in FP64) and 1e-5 error
-against the direct solve; complex64 iteration counts within floor(1.1 x) of
-the plain FP64 method's.
+Bars: FP64 kernels 1e-12 relative; complex64 strips 1e-5 (2-norm and
+element-wise) where the oracle's own complex64 LAPACK emulation meets it, else
+reported as a miss and held to three times the emulation's error (see
+_parity.py); solutions 1e-6 residual (1e-6 tolerance, recomputed in FP64) and
+1e-5 error against the direct solve; complex64 iteration counts within
+floor(1.1 x) of the plain FP64 method's.
 """
 import numpy as np
 import pytest
@@ -28,6 +29,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 hh = pytest.importorskip("paper_2408_11929_amd")
+
+from _parity import check_fp32, check_fp64  # noqa: E402
 
 
 def dev(a):
@@ -65,17 +68,23 @@ def test_fullsize_strip_solves(bench_medium, prec):
             As = ost.strip_matrix(cfg.omega, cfg.c_layers, n, N, dname, s)
             rhs = rand(As.shape[0], 100 * s + d)
             x = host(pb.strip_solve(d, s, dev(rhs)))
-            xr = osw.StripSolver(As, kl).solve(rhs)
-            bar = 1e-12
+            ref = osw.StripSolver(As, kl)
+            xr = ref.solve(rhs)
             if prec == hh.HH_FP32:
                 x32 = osw.StripSolver(As, kl, np.complex64).solve(rhs)
-                bar = max(1e-5, 3 * rel(x32, xr))
-            assert rel(x, xr) < bar, (dname, s, rel(x, xr), bar)
+                check_fp32(x, xr, x32, f"strip solve {cfg.name} {dname}{s}", cond=ref.cond1())
+            else:
+                check_fp64(x, xr, f"strip solve {cfg.name} {dname}{s}")
     pb.free()
 
 
-@pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
-def test_fullsize_sweeps(bench_medium, prec):
+@pytest.mark.parametrize("plan,prec", [("", hh.HH_FP64), ("", hh.HH_FP32), ("0", hh.HH_FP32),
+                                       ("2", hh.HH_FP32)])
+def test_fullsize_sweeps(bench_medium, prec, plan, monkeypatch):
+    # the default plan (sixteen workgroups per chain for one complex64 vector)
+    # and the batch plans 0 and 2
+    if plan:
+        monkeypatch.setenv("HH_SWEEP_PLAN", plan)
     cfg, A = bench_medium
     n, N = cfg.n, cfg.nstrips
     pb = hh.Problem(cfg.omega, cfg.c_layers, n)
@@ -85,11 +94,13 @@ def test_fullsize_sweeps(bench_medium, prec):
         z = host(pb.sweep_apply(d, dev(r)))[0]
         S = osw.DoubleSweep(cfg.omega, cfg.c_layers, n, N, dname, A=A)
         zr = S.apply(r[0])
-        bar = 1e-12
         if prec == hh.HH_FP32:
             S32 = osw.DoubleSweep(cfg.omega, cfg.c_layers, n, N, dname, A=A, precision="fp32")
-            bar = max(1e-5, 3 * rel(S32.apply(r[0]), zr))
-        assert rel(z, zr) < bar, (dname, rel(z, zr), bar)
+            cond = max(sv.cond1() for sv in S.solvers)
+            check_fp32(z, zr, S32.apply(r[0]), f"sweep {cfg.name} {dname} plan={plan or 'auto'}",
+                       cond=cond)
+        else:
+            check_fp64(z, zr, f"sweep {cfg.name} {dname}")
     pb.free()
 
 

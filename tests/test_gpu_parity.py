@@ -1,13 +1,14 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Tolerances: FP64 kernels agree with the oracle to 1e-12 relative (assembly
-and SpMV to 1e-13: they differ only in summation order); complex64 strips
-agree with the FP64 oracle to 1e-5 relative (the acceptance bar for the
-complex64 sweep), or, on strips conditioned so that a complex64 LAPACK band
-solve itself misses that bar (cond_1 above ~2e3), to three times that solve's
-own error; MPGMRES runs are compared by iteration count (exact),
-solution (relative 1e-8 for FP64, both runs converged to a tighter
-tolerance) and the FP64-recomputed residual.
+Tolerances: FP64 kernels agree with the oracle to 1e-12 relative, in the
+2-norm and element-wise (assembly and SpMV to 1e-13: they differ only in
+summation order); complex64 strips agree with the FP64 oracle to 1e-5
+relative, 2-norm and element-wise, wherever the oracle's own complex64
+emulation meets 1e-5, and are otherwise reported as a miss and held to three
+times the emulation's error (see _parity.py; every complex64 case prints its
+numbers); MPGMRES runs are compared by iteration count (exact), solution
+(relative 1e-8 for FP64, both runs converged to a tighter tolerance) and the
+FP64-recomputed residual.
 """
 import numpy as np
 import pytest
@@ -23,6 +24,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 hh = pytest.importorskip("paper_2408_11929_amd")
+
+from _parity import check_fp32, check_fp64, relmax  # noqa: E402
 
 
 def dev(a):
@@ -120,8 +123,6 @@ def test_strip_solves_match_lapack(n, N, omega, c, prec, lu, monkeypatch):
         monkeypatch.setenv("HH_LU_INTERCHANGE", lu)
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
-    tol = 1e-12 if prec == hh.HH_FP64 else 1e-5
-    worst = 0.0
     for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
         for s in range(1, N + 1):
             a, w, kl = pb.strip_info(d, s)
@@ -130,36 +131,110 @@ def test_strip_solves_match_lapack(n, N, omega, c, prec, lu, monkeypatch):
             As = ost.strip_matrix(omega, c, n, N, dname, s)
             rhs = rand(As.shape[0], 10 * s + d)
             x = host(pb.strip_solve(d, s, dev(rhs)))
-            xr = osw.StripSolver(As, kl).solve(rhs)
-            bar = tol
+            ref = osw.StripSolver(As, kl)
+            xr = ref.solve(rhs)
             if prec == hh.HH_FP32:
                 x32 = osw.StripSolver(As, kl, np.complex64).solve(rhs)
-                bar = max(tol, 3 * rel(x32, xr))
-            worst = max(worst, rel(x, xr) / bar)
-    assert worst < 1, worst
+                check_fp32(x, xr, x32, f"strip solve n={n} N={N} {dname}{s} lu={lu or 'auto'}",
+                           cond=ref.cond1())
+            else:
+                check_fp64(x, xr, f"strip solve n={n} N={N} {dname}{s}")
     pb.free()
 
 
-@pytest.mark.parametrize("plan", ["0", "1"])
+@pytest.mark.parametrize("plan", ["0", "1", "2"])
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
 @pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + NARROW + PIVOTING)
 def test_sweeps_match_oracle(n, N, omega, c, prec, plan, monkeypatch):
-    # plan 0: one workgroup per chain; plan 1: eight (where the strips did not
-    # pivot and the workgroup fits the LDS, else plan 0 again)
+    # plan 0: one workgroup per chain; plan 1: sixteen, plan 2: two (complex64
+    # strips that did not pivot, where the workgroups fit; else plan 0 again)
     monkeypatch.setenv("HH_SWEEP_PLAN", plan)
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
     A = oasm.assemble(omega, c, n)
     r = rand((2, n * n), 5)
-    tol = 1e-12 if prec == hh.HH_FP64 else 1e-5
     for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
         z = host(pb.sweep_apply(d, dev(r)))
         S = osw.DoubleSweep(omega, c, n, N, dname, A=A)
         S32 = osw.DoubleSweep(omega, c, n, N, dname, A=A, precision="fp32") if prec == hh.HH_FP32 else None
+        cond = max(sv.cond1() for sv in S.solvers) if S32 is not None else None
         for v in range(2):
             zr = S.apply(r[v])
-            bar = tol if S32 is None else max(tol, 3 * rel(S32.apply(r[v]), zr))
-            assert rel(z[v], zr) < bar
+            if S32 is None:
+                check_fp64(z[v], zr, f"sweep n={n} N={N} {dname}")
+            else:
+                check_fp32(z[v], zr, S32.apply(r[v]), f"sweep n={n} N={N} {dname} v{v} plan={plan}",
+                           cond=cond)
+    pb.free()
+
+
+SINGLE = [("LR", ost.X, "forward"), ("RL", ost.X, "reverse"),
+          ("BT", ost.Y, "forward"), ("TB", ost.Y, "reverse")]
+
+
+@pytest.mark.parametrize("plan", ["0", "1", "2"])
+@pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
+@pytest.mark.parametrize("n,N,omega,c", CASES + NARROW[:1] + PIVOTING[:1])
+def test_single_sweeps_match_oracle(n, N, omega, c, prec, plan, monkeypatch):
+    # LR, RL, BT, TB of Sec. 4 (Table 1) on both plans and precisions
+    monkeypatch.setenv("HH_SWEEP_PLAN", plan)
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+    A = oasm.assemble(omega, c, n)
+    r = rand((2, n * n), 15)
+    for name, dname, order in SINGLE:
+        z = host(pb.precond_apply(name, dev(r)))
+        S = osw.SingleSweep(omega, c, n, N, dname, order=order, A=A)
+        S32 = (osw.SingleSweep(omega, c, n, N, dname, order=order, A=A, precision="fp32")
+               if prec == hh.HH_FP32 else None)
+        for v in range(2):
+            zr = S.apply(r[v])
+            if S32 is None:
+                check_fp64(z[v], zr, f"{name} n={n} N={N}")
+            else:
+                check_fp32(z[v], zr, S32.apply(r[v]), f"{name} n={n} N={N} v{v} plan={plan}")
+    # the double-sweep kinds are hh_sweep_apply
+    zd = host(pb.precond_apply(hh.HH_PRE_BTB, dev(r)))
+    assert np.array_equal(zd, host(pb.sweep_apply(hh.HH_DIR_Y, dev(r))))
+    pb.free()
+
+
+@pytest.mark.parametrize("names", [("LR", "RL"), ("LR", "BT", "RL", "TB"), ("RL",),
+                                   ("LRL", "BTB", "LR")])
+def test_mpgmres_single_sweep_combinations_match_oracle(names):
+    # Table 1's combinations: cross rule (t = 2), sum rule (t > 2), t = 1
+    n, N, omega, c = 41, 5, 25.0, [1.0, 1.7]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP64)
+    pb.set_preconditioners(list(names))
+    b = oasm.source_load(n, wl.gaussian_field(n, 0.4, 0.6, 0.05))
+    x, st, rc = pb.mpgmres(dev(b.reshape(1, -1)), tol=1e-10, maxit=150)
+    A = oasm.assemble(omega, c, n)
+    precs = [osw.preconditioner(omega, c, n, N, nm, A=A).apply for nm in names]
+    ref = omp.mpgmres(A, precs, b, tol=1e-10, maxit=150)
+    print(f"[mpgmres] {'+'.join(names)}: {st[0]['iterations']} iterations (oracle "
+          f"{ref.iterations}), res_true {st[0]['res_true']:.2e}", flush=True)
+    assert rc == hh.HH_OK and st[0]["converged"] == 1
+    assert st[0]["iterations"] == ref.iterations
+    assert rel(host(x)[0], ref.x) < 1e-8
+    assert st[0]["res_true"] < 1e-10
+    pb.free()
+
+
+def test_set_preconditioners_rejects_unfactored_direction():
+    pb = hh.Problem(10.0, [1.0], 33)
+    pb.factor_sweeps(hh.HH_DIR_X, 4, hh.HH_FP64)
+    with pytest.raises(hh.HHError):
+        pb.set_preconditioners(["LR", "BT"])       # y was not factored
+    with pytest.raises(hh.HHError):
+        pb.set_preconditioners(["LR"] * 5)         # t > 4
+    with pytest.raises(hh.HHError):
+        pb.set_preconditioners([7])                # unknown kind
+    pb.set_preconditioners(["LR", "RL"])
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, 4, hh.HH_FP64)  # resets to LRL+BTB
+    b = dev(rand((1, 33 * 33), 3))
+    x, st, rc = pb.mpgmres(b, tol=1e-8, maxit=60)
+    assert rc == hh.HH_OK
     pb.free()
 
 
@@ -180,7 +255,7 @@ def test_wide_sweep_gives_up_when_partners_are_late(monkeypatch):
     A = oasm.assemble(omega, c, n)
     zr = osw.DoubleSweep(omega, c, n, N, ost.X, A=A).apply(r[0])
     z32 = osw.DoubleSweep(omega, c, n, N, ost.X, A=A, precision="fp32").apply(r[0])
-    assert rel(z, zr) < max(1e-5, 3 * rel(z32, zr))
+    check_fp32(z, zr, z32, f"sweep after abort n={n} N={N} x")
     pb.free()
 
 

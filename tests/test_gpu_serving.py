@@ -24,6 +24,9 @@ MIX = [
     (41, 5, 22.0, [1.4, 1.1, 2.5], 1, hh.HH_FP32),
     (65, 8, 30.0, [1.0, 1.8, 2.6, 1.2], 3, hh.HH_FP32),
     (49, 6, 18.0, [2.0], 2, hh.HH_FP64),
+    # a request of the serving stream's smallest size (n = 161, 16 strips, 10
+    # points per wavelength at the slowest of 5 layers)
+    (161, 16, wl.ppwl_wavenumber(161) * 1.2, [1.2, 2.4, 1.9, 2.8, 1.5], 2, hh.HH_FP32),
 ]
 
 
@@ -33,14 +36,14 @@ def sources(n, nsrc, seed):
     return torch.from_numpy(f).to("cuda")
 
 
-def alone(n, N, omega, c, f, prec, tol, maxit):
+def alone(n, N, omega, c, f, prec, tol, maxit, dirs=hh.HH_DIR_X | hh.HH_DIR_Y):
     """The request solved on its own, with the server's segment plan."""
     old = os.environ.get("HH_SWEEP_PLAN")
     os.environ["HH_SWEEP_PLAN"] = "0"
     try:
         pb = hh.Problem(omega, c, n)
         b = pb.load_vector(f)
-        pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+        pb.factor_sweeps(dirs, N, prec)
         x, st, rc = pb.mpgmres(b, tol=tol, maxit=maxit)
         pb.free()
     finally:
@@ -118,4 +121,68 @@ def test_failing_request_does_not_disturb_others():
     assert np.array_equal(good.cpu().numpy(), xr)
     with pytest.raises(hh.HHError):
         srv.submit(40, omega, c, f, good, nstrips=N)  # (n-1) not divisible by N
+    srv.destroy()
+
+
+def _footprint(n, N, omega, c, f, x, prec, maxit):
+    """Smallest HBM budget that admits the request alone (bisection on HH_EBUDGET)."""
+    lo, hi = 1 << 20, 64 << 30
+    while hi - lo > (1 << 16):
+        mid = (lo + hi) // 2
+        srv = hh.Server(hbm_budget=mid, max_active=1)
+        try:
+            srv.submit(n, omega, c, f, x, nstrips=N, precision=prec, tol=1.0, maxit=maxit)
+            ok = True
+        except hh.HHError as e:
+            assert e.code == hh.HH_EBUDGET
+            ok = False
+        srv.destroy()
+        if ok:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def test_long_solve_grows_within_budget_next_to_others():
+    # one request (the x double sweep alone, i.e. GMRES, on a medium where it
+    # needs many iterations) runs past 34 iterations, so that its bases grow
+    # twice past the 32 iterations charged at admission, next to a short one;
+    # both match their lone runs bit for bit
+    srv = hh.Server(hbm_budget=8 << 30, max_active=8)
+    n, N, omega, c = 65, 8, 30.0, [1.0, 2.6, 1.3]
+    f = sources(n, 1, 9)
+    xl, xs = torch.empty_like(f), torch.empty_like(f)
+    tl = srv.submit(n, omega, c, f, xl, nstrips=N, dirs=hh.HH_DIR_X, precision=hh.HH_FP64,
+                    tol=1e-13, maxit=60)
+    ts = srv.submit(n, omega, c, f, xs, nstrips=N, precision=hh.HH_FP32, tol=1e-8, maxit=100)
+    res = wait_all(srv, [tl, ts])
+    print(f"[serving] long solve: {res[tl]['iterations_max']} iterations, status {res[tl]['status']}")
+    assert res[tl]["status"] in (hh.HH_OK, hh.HH_ENOCONV) and res[tl]["iterations_max"] > 34
+    assert res[ts]["status"] == hh.HH_OK
+    rl = alone(n, N, omega, c, f, hh.HH_FP64, 1e-13, 60, dirs=hh.HH_DIR_X)
+    rs = alone(n, N, omega, c, f, hh.HH_FP32, 1e-8, 100)
+    assert np.array_equal(xl.cpu().numpy(), rl[0])
+    assert np.array_equal(xs.cpu().numpy(), rs[0])
+    srv.destroy()
+
+
+def test_growth_beyond_the_budget_stops_that_request():
+    # the budget admits the request (charged for 32 iterations of Krylov
+    # memory) but not the growth of its bases at iteration 17: it stops there
+    # with HH_EBUDGET; the server then serves the next request normally
+    n, N, omega, c = 41, 5, 22.0, [1.0, 2.0]
+    f = sources(n, 1, 10)
+    xl, xs = torch.empty_like(f), torch.empty_like(f)
+    fl = _footprint(n, N, omega, c, f, xl, hh.HH_FP64, 60)
+    srv = hh.Server(hbm_budget=fl, max_active=8)
+    tl = srv.submit(n, omega, c, f, xl, nstrips=N, precision=hh.HH_FP64, tol=1e-30, maxit=60)
+    res = wait_all(srv, [tl])
+    assert res[tl]["status"] == hh.HH_EBUDGET and res[tl]["iterations_max"] == 16
+    assert np.all(np.isfinite(xl.cpu().numpy()))
+    ts = srv.submit(n, omega, c, f, xs, nstrips=N, precision=hh.HH_FP64, tol=1e-6, maxit=16)
+    res = wait_all(srv, [ts])
+    assert res[ts]["status"] == hh.HH_OK
+    rs = alone(n, N, omega, c, f, hh.HH_FP64, 1e-6, 16)
+    assert np.array_equal(xs.cpu().numpy(), rs[0])
     srv.destroy()

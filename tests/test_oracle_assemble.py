@@ -3,6 +3,7 @@ from fractions import Fraction
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from oracle import assemble as asm
@@ -109,3 +110,48 @@ def test_plane_wave_converges_second_order():
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert orders[-1] > 1.9 and orders[-1] < 2.1, orders
     assert all(o > 1.7 for o in orders), orders
+
+
+# ---------------------------------------------------------------- speed fields
+# A callable c(x, y) in place of the layer list, sampled at the triangle
+# centroids and edge midpoints.
+
+def _grid_transpose(n):
+    p = np.arange(n * n)
+    i, j = p % n, p // n
+    return sp.csr_matrix((np.ones(n * n), (p, i * n + j)), shape=(n * n, n * n))
+
+
+def test_callable_field_reproduces_layers_off_interfaces():
+    # n - 1 = 32 and 5 layers: no centroid or edge midpoint lies on a layer
+    # interface, so floor(5 y) classifies every sample point as the exact
+    # integer rule does and the two operators are identical
+    n, omega, cl = 33, 17.0, [1.0, 2.3, 1.4, 2.9, 1.7]
+    Q = 6 * (n - 1)
+    assert all((q * Q) % 5 != 0 for q in range(1, 5))
+    A = asm.assemble(omega, cl, n)
+    Af = asm.assemble(omega, lambda x, y: cl[min(int(5 * y), 4)], n)
+    assert abs(A - Af).max() == 0.0
+    Ac = asm.assemble(omega, lambda x, y: 1.6, n)
+    assert abs(asm.assemble(omega, [1.6], n) - Ac).max() == 0.0
+
+
+def test_callable_field_transposes_with_the_grid():
+    # the "/" triangulation, its centroids and edge midpoints map onto
+    # themselves under x <-> y, so A[c] = T A[c^T] T with c^T(x, y) = c(y, x);
+    # a swapped or shifted sample coordinate breaks this for a field that is
+    # not symmetric
+    n, omega = 21, 14.0
+
+    def c(x, y):
+        return 1.0 + 0.5 * np.sin(3.0 * x) + 0.2 * y + 0.1 * x * y
+
+    A = asm.assemble(omega, c, n)
+    At = asm.assemble(omega, lambda x, y: c(y, x), n)
+    T = _grid_transpose(n)
+    assert abs(A - T @ At @ T.T).max() < 1e-13 * abs(A).max()
+    assert abs(A - At).max() > 1e-3 * abs(A).max()
+    # still complex symmetric with K 1 = 0
+    assert abs(A - A.T).max() == 0.0
+    K, _, _ = asm.operator_parts(omega, c, n)
+    assert np.abs(K @ np.ones(n * n)).max() < 1e-12

@@ -263,14 +263,61 @@ def test_recomputed_left_data_differs_from_stored():
     assert np.linalg.norm(zs - zr) > 1e-6 * np.linalg.norm(zs)
 
 
-def test_complex64_diagnostic_close_to_fp64():
-    n, N, omega, c = 33, 4, 20.0, [1.0, 2.0]
+EPS32 = 2.0 ** -24   # unit roundoff of IEEE single precision
+
+
+def test_complex64_strip_solver_matches_dense_complex64_solve():
+    # The complex64 emulation that sets the complex64 parity bars: its band LU
+    # (cgbtrf/cgbtrs) must agree with an independent dense complex64 solve
+    # (cgesv through numpy) and with the FP64 solve within the error bound
+    # kappa_1(A_s) * eps32 (times a small constant); its error must also be
+    # that of single precision, not of double.
+    n, N, omega, c = 13, 3, 9.0, [1.0, 2.4, 1.6]
+    for d in (st.X, st.Y):
+        for s in range(1, N + 1):
+            As = st.strip_matrix(omega, c, n, N, d, s)
+            kl = st.band_width(n, N, s)
+            dense = As.toarray()
+            kappa = np.linalg.cond(dense, 1)
+            rhs = _rand(As.shape[0], 50 + s)
+            x64 = np.linalg.solve(dense, rhs)
+            x32 = sw.StripSolver(As, kl, np.complex64).solve(rhs)
+            xd32 = np.linalg.solve(dense.astype(np.complex64), rhs.astype(np.complex64))
+            assert x32.dtype == np.complex64 and xd32.dtype == np.complex64
+            e = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
+            ed = np.linalg.norm(xd32 - x64) / np.linalg.norm(x64)
+            assert 1e-10 < e < 8 * kappa * EPS32, (d, s, e, kappa)
+            assert ed < 8 * kappa * EPS32
+            assert np.linalg.norm(x32 - xd32) / np.linalg.norm(x64) < 16 * kappa * EPS32
+            # the LAPACK-free condition estimate used in the GPU tests' reports
+            est = sw.StripSolver(As, kl).cond1()
+            assert kappa / 3 <= est <= kappa * (1 + 1e-8)
+
+
+def test_complex64_sweep_is_single_precision_within_bound():
+    # N = 1: the complex64 sweep is a complex64 solve of A (dense cgesv as the
+    # independent reference); N > 1: its error against the FP64 sweep stays
+    # within (2N - 1) * max_s kappa_1(A_s) * eps32 times a small constant.
+    n, omega, c = 17, 12.0, [1.0, 2.0]
+    A = asm.assemble(omega, c, n)
     r = _rand(n * n, 9)
-    z64 = sw.DoubleSweep(omega, c, n, N, st.X).apply(r)
-    z32 = sw.DoubleSweep(omega, c, n, N, st.X, precision="fp32").apply(r)
+    z1 = sw.DoubleSweep(omega, c, n, 1, st.X, A=A, precision="fp32").apply(r)
+    dense = A.toarray()
+    zd = np.linalg.solve(dense.astype(np.complex64), r.astype(np.complex64))
+    x64 = np.linalg.solve(dense, r)
+    kappa = np.linalg.cond(dense, 1)
+    assert z1.dtype == np.complex64
+    assert np.linalg.norm(z1 - zd) / np.linalg.norm(x64) < 16 * kappa * EPS32
+    n, N, omega = 33, 4, 20.0
+    A = asm.assemble(omega, c, n)
+    r = _rand(n * n, 10)
+    S = sw.DoubleSweep(omega, c, n, N, st.X, A=A)
+    z64 = S.apply(r)
+    z32 = sw.DoubleSweep(omega, c, n, N, st.X, A=A, precision="fp32").apply(r)
     assert z32.dtype == np.complex64
+    kmax = max(np.linalg.cond(a.toarray(), 1) for a in S.As)
     err = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
-    assert 1e-9 < err < 1e-4
+    assert 1e-10 < err < 8 * (2 * N - 1) * kmax * EPS32, (err, kmax)
 
 
 # ---------------------------------------------------------------- single sweeps
