@@ -157,6 +157,22 @@ int hh_sweep_apply(hh_problem* pb, unsigned dir, int nvec, const hh_c128* r, hh_
  * have been factored; r, z, nvec and errors as in hh_sweep_apply. */
 int hh_precond_apply(hh_problem* pb, int kind, int nvec, const hh_c128* r, hh_c128* z);
 
+/* hh_precond_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the call's scratch (descriptors, sync
+ * words, strip buffers, complex64 staging, exchange areas) in one static
+ * device array of 64 MiB that each GPU running the library holds until the
+ * process ends.  It calls no hipMalloc/hipFree.  Calls on one GPU share that
+ * array: calls that overlap in time on the same GPU race (serialise them);
+ * the array keeps the last call's contents, and each call clears what must
+ * start at zero.  The problem's device must be current.
+ * Errors: HH_EINVAL when the call needs more than 64 MiB of scratch (about
+ * 0.93 MiB per vector at n = 321 with complex64 strips), when the problem's
+ * device is not current, or when a complex64 batch of more than eight
+ * vectors needs the one-workgroup transfer maps and no allocating
+ * application has built them yet; otherwise as hh_precond_apply. */
+int hh_precond_apply_noalloc(hh_problem* pb, int kind, int nvec, const hh_c128* r, hh_c128* z);
+
 /* Chooses the t preconditioners M_1..M_t that hh_mpgmres combines, in order
  * (Sec. 3; the combinations of Sec. 4 such as LRL+BTB, LR+RL or
  * LR+BT+RL+TB).  kinds: host pointer to t HH_PRE_* values, 1 <= t <= 4, each
@@ -220,7 +236,8 @@ int hh_free(hh_problem* pb);
  * its streams.  alloc must return device memory of the current device (NULL
  * on failure: the call that needed it returns HH_ENOMEM) and may be called
  * from the serving thread.  Only while the library holds no device memory
- * (every problem and server freed), else HH_EINVAL. */
+ * (every problem and server freed), else HH_EINVAL.  The static scratch of
+ * hh_precond_apply_noalloc is not affected. */
 int hh_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* p, void* ctx),
                      void* ctx);
 

@@ -82,6 +82,7 @@ PROTOTYPES = {
     "hh_factor_sweeps": (I, [P, U, I, I]),
     "hh_sweep_apply": (I, [P, U, I, P, P]),
     "hh_precond_apply": (I, [P, I, I, P, P]),
+    "hh_precond_apply_noalloc": (I, [P, I, I, P, P]),
     "hh_set_preconditioners": (I, [P, I, ctypes.POINTER(I)]),
     "hh_strip_solve": (I, [P, U, I, P, P]),
     "hh_strip_info": (I, [P, U, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),

@@ -555,6 +555,16 @@ int hh_precond_apply(hh_problem* pb, int kind, int nvec, const hh_c128* r, hh_c1
   });
 }
 
+int hh_precond_apply_noalloc(hh_problem* pb, int kind, int nvec, const hh_c128* r, hh_c128* z) {
+  return guard([&]() {
+    REQUIRE(pb && r && z && nvec >= 0, "invalid arguments");
+    int slot = 0, mode = 0;
+    kind_slot(pb, kind, slot, mode);
+    sweep_apply_noalloc(pb, slot, mode, nvec, (const c128*)r, (c128*)z);
+    return HH_OK;
+  });
+}
+
 int hh_set_preconditioners(hh_problem* pb, int t, const int* kinds) {
   return guard([&]() {
     REQUIRE(pb != nullptr && kinds != nullptr, "invalid arguments");

@@ -498,6 +498,9 @@ SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, 
 // unless the plan-0 transfer maps have to be built first (ensure_batch_maps).
 void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, c128* z,
                       int plan, const SweepBuffers& b);
+// The no-allocation variant (noalloc.hip): the same application on the
+// library's static device scratch.
+void sweep_apply_noalloc(hh_problem* pb, int i, int mode, int nvec, const c128* r, c128* z);
 // Zeroes bytes (a multiple of 4) with a fill kernel on st.
 void launch_zero(void* p, size_t bytes, hipStream_t st);
 
