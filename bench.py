@@ -135,8 +135,10 @@ def serve_sweep(hh, torch, count=64, max_active=16, budget_gb=96):
 
 def kernel_probe(hh, torch):
     """Short run for hardware-counter passes: one 512 MiB device copy (the
-    calibration kernel: 512 MiB read, 512 MiB written) and one complex64 solve
-    of the benchmark workload (its sweep launches are the measured kernel)."""
+    calibration kernel: 512 MiB read, 512 MiB written), one complex64 solve of
+    the benchmark workload (its sweeps run sixteen workgroups per chain: grids
+    of 32 workgroups) and the 64-source batch on the two-workgroup plan (grids
+    of 256 workgroups)."""
     import workloads as wl
     a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -148,7 +150,14 @@ def kernel_probe(hh, torch):
     f_dev = torch.from_numpy(cfg.f()).to("cuda")
     st, rc = one_solve(hh, torch, cfg, f_dev, hh.HH_FP32)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "done", "iterations": st[0]["iterations"]}))
+    bcfg = wl.layered_321_batch(64)
+    fb = torch.from_numpy(bcfg.f()).to("cuda")
+    os.environ["HH_SWEEP_PLAN"] = "2"
+    stb, rcb = one_solve(hh, torch, bcfg, fb, hh.HH_FP32)
+    del os.environ["HH_SWEEP_PLAN"]
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "iterations": st[0]["iterations"],
+                      "batch_iterations": max(s["iterations"] for s in stb)}))
 
 
 def _oracle_solves(cfg, budget_s, max_solves):
@@ -219,8 +228,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path "
-              "(requests and right-hand sides are independent; see the sharding notes "
-              "in DESIGN.md)", file=sys.stderr)
+              "(requests and right-hand sides are independent, so they would shard across "
+              "GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -239,8 +248,11 @@ def main():
     f_dev = torch.from_numpy(cfg.f()).to("cuda")
     torch.cuda.synchronize()
 
+    # the segment plan of each sweep-launch shape is measured in the warmup
+    # (autotuner) and reused by the timed steps
+    hh.hh_autotune(True)
     # warmup (also brings the library's caching allocator to steady state)
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):
         one_solve(hh, torch, cfg, f_dev, hh.HH_FP32)
         one_solve(hh, torch, cfg, f_dev, hh.HH_FP64)
 
@@ -267,6 +279,7 @@ def main():
     if not args.no_batch:
         bcfg = wl.layered_321_batch(64)
         fb = torch.from_numpy(bcfg.f()).to("cuda")
+        one_solve(hh, torch, bcfg, fb, hh.HH_FP32)  # warmup: tunes the batch's launch shape
         hh.hh_timing_enable(True)
         hh.hh_timing_reset()
         torch.cuda.synchronize()
@@ -343,6 +356,12 @@ def main():
                      "avg_launch_ms": sweep["ms"] / max(1, sweep["launches"]),
                      "algorithmic_bytes_per_launch": sweep["bytes"] / max(1, sweep["launches"])},
     }
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        tp = os.path.join(td, "tune.json")
+        hh.hh_tune_save(tp)
+        out["tuned_plans"] = json.load(open(tp))["entries"]
+    hh.hh_autotune(False)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))

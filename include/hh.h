@@ -250,6 +250,22 @@ int hh_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(vo
  * streams, and calls stay synchronous with respect to the host. */
 int hh_set_streams(void* x, void* y);
 
+/* ---- autotuning of the sweep's segment plan ----------------------------------
+ * A sweep launch runs its chains on one, two or sixteen workgroups each.  With
+ * hh_autotune(1) (or HH_AUTOTUNE=1 in the environment) hh_mpgmres times every
+ * plan that fits the first launch of each shape (precision, band, mesh, strip
+ * count, chains rounded up to a power of two), keeps the fastest and reuses
+ * it; without it, a stored choice is still used, else a fixed rule.  Off by
+ * default: the plans sum in different orders, so a timed choice would let
+ * the last bits of results vary between processes.  Choices persist in a JSON
+ * file: hh_tune_save / hh_tune_load, or automatically when HH_TUNE_CACHE names
+ * the file.  hh_tune_clear forgets them.  Errors: HH_EINVAL (unreadable or
+ * unwritable file). */
+int hh_autotune(int on);
+int hh_tune_save(const char* path);
+int hh_tune_load(const char* path);
+int hh_tune_clear(void);
+
 /* Releases the library's cached free device blocks and pooled timing events
  * (e.g. before the process exits).  Live handles are not affected. */
 int hh_release_caches(void);

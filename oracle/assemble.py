@@ -8,7 +8,7 @@ impedance condition du/dn - i k u = 0 on its boundary, and k = omega / c
 finite-difference stencil (Sec. 4); this oracle uses continuous P1 triangles
 instead, which is the discretisation this library targets.
 
-Mesh (reading c2 of the design notes): nodes (i, j) at (i h, j h),
+Mesh (the "/" diagonal in every cell): nodes (i, j) at (i h, j h),
 h = 1/(n-1), global index p = j n + i (x fastest).  Each cell
 [i, i+1] x [j, j+1] is cut by its "/" diagonal into
     T_lo = {(i,j), (i+1,j), (i+1,j+1)}   and   T_up = {(i,j), (i+1,j+1), (i,j+1)}.

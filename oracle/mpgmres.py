@@ -15,7 +15,7 @@ new basis vector that came from the *other* preconditioner; for more than
 two, each is applied to the sum of all new basis vectors of the previous
 iteration.
 
-Readings taken where the paper is silent (c10, c11 of the design notes):
+Readings taken where the paper is silent:
   * x0 = 0, no restart, default maxit = 200, relative residual tolerance
     measured in the 2-norm against ||b||.
   * The new block W = A Z_k is orthogonalised against the basis V with

@@ -221,6 +221,22 @@ def use_library_defaults(memory=True, streams=True):
         _check(lib().hh_set_streams(None, None))
 
 
+def hh_autotune(on=True):
+    _check(lib().hh_autotune(1 if on else 0))
+
+
+def hh_tune_save(path):
+    _check(lib().hh_tune_save(str(path).encode()))
+
+
+def hh_tune_load(path):
+    _check(lib().hh_tune_load(str(path).encode()))
+
+
+def hh_tune_clear():
+    _check(lib().hh_tune_clear())
+
+
 def hh_release_caches():
     _check(lib().hh_release_caches())
 

@@ -78,6 +78,10 @@ PROTOTYPES = {
     "hh_set_allocator": (I, [ALLOC_FN, FREE_FN, P]),
     "hh_set_streams": (I, [P, P]),
     "hh_release_caches": (I, []),
+    "hh_autotune": (I, [I]),
+    "hh_tune_save": (I, [ctypes.c_char_p]),
+    "hh_tune_load": (I, [ctypes.c_char_p]),
+    "hh_tune_clear": (I, []),
     "hh_load_vector": (I, [P, I, P, P]),
     "hh_factor_sweeps": (I, [P, U, I, I]),
     "hh_sweep_apply": (I, [P, U, I, P, P]),

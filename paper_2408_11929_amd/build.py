@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhh.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["assemble.hip", "factor.hip", "sweep.hip", "krylov.hip",
-           "engine.cpp", "runtime.cpp", "capi.cpp", "server.cpp", "noalloc.hip"]
+           "engine.cpp", "runtime.cpp", "capi.cpp", "server.cpp", "noalloc.hip", "tune.cpp"]
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]

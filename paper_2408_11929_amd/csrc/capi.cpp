@@ -7,6 +7,7 @@
 #include "engine.h"
 #include "hh_internal.h"
 #include "krylov.h"
+#include "tune.h"
 
 namespace hh {
 void timing_set(bool on);
@@ -235,8 +236,14 @@ void ensure_batch_maps(hh_problem* pb, hipStream_t st) {
 
 int sweep_plan_of(const hh_problem* pb, int nvec) {
   const FactorSet& fs = pb->fs;
-  return sweep_plan_for(nvec, fs.precision, fs.strips[0].segs, fs.max_kl, pb->n, fs.any_pivot,
-                        fs.strips[0].wide != 0);
+  const int KP = fs.strips[0].KP, P = fs.strips[0].segs;
+  const bool wide = fs.strips[0].wide != 0;
+  int p = 0;
+  if (!std::getenv("HH_SWEEP_PLAN") &&
+      tune_lookup(TuneKey{fs.precision, KP, P, fs.max_kl, pb->n, fs.N, tune_bucket(nvec)}, p) &&
+      sweep_plan_fits(p, nvec, fs.precision, KP, P, fs.max_kl, pb->n, fs.any_pivot, wide))
+    return p;
+  return sweep_plan_for(nvec, fs.precision, P, fs.max_kl, pb->n, fs.any_pivot, wide);
 }
 
 SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, size_t* total) {
@@ -479,6 +486,32 @@ int hh_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(vo
 
 int hh_set_streams(void* x, void* y) {
   set_caller_streams((hipStream_t)x, (hipStream_t)y);
+  return HH_OK;
+}
+
+int hh_autotune(int on) {
+  tune_set_enabled(on != 0);
+  return HH_OK;
+}
+
+int hh_tune_save(const char* path) {
+  return guard([&]() {
+    REQUIRE(path != nullptr, "path is NULL");
+    REQUIRE(tune_save(path), "cannot write %s", path);
+    return HH_OK;
+  });
+}
+
+int hh_tune_load(const char* path) {
+  return guard([&]() {
+    REQUIRE(path != nullptr, "path is NULL");
+    REQUIRE(tune_load(path), "cannot read tuning choices from %s", path);
+    return HH_OK;
+  });
+}
+
+int hh_tune_clear(void) {
+  tune_clear();
   return HH_OK;
 }
 

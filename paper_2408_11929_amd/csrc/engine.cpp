@@ -1,8 +1,10 @@
 // Batched selective MPGMRES (Sec. 3) with the Sec. 4 selection rule.
 #include "engine.h"
+#include "tune.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
@@ -372,8 +374,10 @@ void Engine::step(std::vector<Solve*>& solves) {
     int prec, KP, P, kmax, nmax;
     bool piv;
     int plan;
-    bool wide;  // the wide plan's maps were built
+    bool wide;  // the maps of plans 1 and 2 exist
     std::vector<hh_problem*> pbs;  // problems with tasks in this kind
+    bool tune = false;             // measure the plans that fit before the launch
+    TuneKey key{};
   };
   std::vector<Kind> kinds;
   for (Solve* s : live) {
@@ -414,14 +418,28 @@ void Engine::step(std::vector<Solve*>& solves) {
   {
     size_t chains = 0, xbytes = 0;
     for (Kind& k : kinds) {
-      k.plan = wide_ok_ ? sweep_plan_for((int)k.tasks.size(), k.prec, k.P, k.kmax, k.nmax, k.piv,
-                                         k.wide)
-                        : 0;
-      if (k.plan != HH_PLAN_WIDE)
+      const int nt = (int)k.tasks.size();
+      k.plan = 0;
+      k.tune = false;
+      if (wide_ok_) {
+        k.key = TuneKey{k.prec, k.KP, k.P, k.kmax, k.nmax, k.pbs[0]->fs.N, tune_bucket(nt)};
+        int p = 0;
+        if (!std::getenv("HH_SWEEP_PLAN") && tune_lookup(k.key, p) &&
+            sweep_plan_fits(p, nt, k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv, k.wide)) {
+          k.plan = p;
+        } else {
+          k.plan = sweep_plan_for(nt, k.prec, k.P, k.kmax, k.nmax, k.piv, k.wide);
+          k.tune = !std::getenv("HH_SWEEP_PLAN") && tune_enabled() && !k.piv && k.wide &&
+                   sweep_wide_fits(k.prec, k.P, k.kmax, k.nmax);
+        }
+      }
+      if (k.plan != HH_PLAN_WIDE || k.tune)
         for (hh_problem* q : k.pbs) ensure_batch_maps(q, st_);
-      if (k.plan == 0) continue;
+      if (k.plan == 0 && !k.tune) continue;
       chains += k.tasks.size();
-      xbytes += k.tasks.size() * (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);
+      // a tuned kind may run any plan: room for the widest
+      xbytes += k.tasks.size() * (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 64 *
+                esz_of(k.prec);
     }
     if (chains > 0) {
       const size_t sbytes = (chains + 1) * 128;
@@ -446,11 +464,11 @@ void Engine::step(std::vector<Solve*>& solves) {
       wide_chains = chains;
       size_t ci = 0, xo = 0;
       for (Kind& k : kinds) {
-        if (k.plan == 0) continue;
+        if (k.plan == 0 && !k.tune) continue;
         for (SweepTask& tk : k.tasks) {
           tk.bar = sync_ + 32 * (1 + ci++);
           tk.xch = (char*)xch_ + xo;
-          xo += (size_t)plan_width(k.plan) * 64 * esz_of(k.prec);
+          xo += (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 64 * esz_of(k.prec);
         }
       }
     }
@@ -618,6 +636,44 @@ void Engine::step(std::vector<Solve*>& solves) {
 
   // ---- launches
   if (dsums) launch_combine(DEV(dsums), (int)sums.size(), sumlen, HH_FP64, st_);
+  // first launch of a shape with tuning on: time every plan that fits (best of
+  // two launches each, arrival counters cleared before each), keep the
+  // fastest; the launch below then writes the outputs with it
+  for (size_t q = 0; q < kinds.size(); ++q) {
+    Kind& k = kinds[q];
+    if (!k.tune) continue;
+    const int nt = (int)k.tasks.size();
+    TuneEntry best;
+    double best_ms = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HH_HIP(hipEventCreate(&e0));
+    HH_HIP(hipEventCreate(&e1));
+    for (int p = 0; p < HH_NPLAN; ++p) {
+      if (!sweep_plan_fits(p, nt, k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv, true)) continue;
+      double ms_best = -1;
+      for (int rep = 0; rep < 2; ++rep) {
+        if (wide_chains) launch_zero(sync_ + 32, wide_chains * 128, st_);
+        HH_HIP(hipEventRecord(e0, st_));
+        launch_sweep(DEV(dsw[q]), nt, k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv, p, sync_, st_);
+        HH_HIP(hipEventRecord(e1, st_));
+        HH_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms_best < 0 || ms < ms_best) ms_best = ms;
+      }
+      best.ms[p] = ms_best;
+      if (best_ms < 0 || ms_best < best_ms) {
+        best_ms = ms_best;
+        best.plan = p;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    k.plan = best.plan;
+    tune_store(k.key, best);
+    if (wide_chains) launch_zero(sync_ + 32, wide_chains * 128, st_);
+    sync_clear_ = wide_chains;
+  }
   {
     // algorithmic bytes: each (problem, direction) factor read once per strip
     // solve of the launch, plus FP64 input and sweep-precision output per task
