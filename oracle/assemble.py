@@ -183,11 +183,54 @@ def operator_parts(omega, c_layers, n, window=None):
     return K, Mk2, Mg
 
 
-def assemble(omega, c_layers, n, window=None):
+def fd5_weights(n, window=None):
+    """Node weights of the five-point scheme on the window rectangle: 1 inside,
+    1/2 on a side, 1/4 at a corner (0 outside the window), and the indicator
+    of the window's boundary nodes."""
+    if window is None:
+        window = (0, n - 1, 0, n - 1)
+    cx0, cx1, cy0, cy1 = window
+    p = np.arange(n * n)
+    i, j = p % n, p // n
+    inside = (i >= cx0) & (i <= cx1) & (j >= cy0) & (j <= cy1)
+    wx = np.where((i == cx0) | (i == cx1), 0.5, 1.0)
+    wy = np.where((j == cy0) | (j == cy1), 0.5, 1.0)
+    side = inside & ((i == cx0) | (i == cx1) | (j == cy0) | (j == cy1))
+    return np.where(inside, wx * wy, 0.0), side.astype(np.float64)
+
+
+def node_wavenumber(omega, c_field, n):
+    """k = omega / c at the mesh nodes (five-point scheme): a layer list is read
+    at the node heights y = 6 j / (6 (n-1)), a callable c(x, y) at the nodes."""
+    p = np.arange(n * n)
+    i, j = p % n, p // n
+    if callable(c_field):
+        h = 1.0 / (n - 1)
+        c = np.array([float(c_field(a * h, b * h)) for a, b in zip(i, j)])
+        return omega / c
+    return wavenumber(omega, c_field, n, 6 * j)
+
+
+def assemble(omega, c_layers, n, window=None, scheme="p1"):
     """A = K - M_{k^2} - i M_{Gamma,k} (complex symmetric, non-Hermitian).
 
-    Weak form of eq. (1) with P1 elements; see the module docstring.
+    scheme "p1": weak form of eq. (1) with P1 elements; see the module
+    docstring.  scheme "fd5": the standard five-point finite differences of
+    Sec. 4 on the same grid, the impedance condition imposed through a ghost
+    node outside each boundary node (central difference of du/dn, the ghost
+    eliminated) and every row scaled by h^2 times its node weight (1/2 on a
+    side, 1/4 at a corner) so that the matrix is complex symmetric:
+        A = K - h^2 diag(k^2 w) - i h diag(k [node on the boundary]),
+    with K the five-point Laplacian in that scaling (which is the P1 stiffness
+    of this mesh) and k taken at the nodes.
     """
+    if scheme == "fd5":
+        h = 1.0 / (n - 1)
+        K, _, _ = operator_parts(omega, [1.0], n, window)
+        w, side = fd5_weights(n, window)
+        k = node_wavenumber(omega, c_layers, n)
+        return (K.astype(np.complex128) - sp.diags(h * h * k * k * w)
+                - 1j * sp.diags(h * k * side)).tocsr()
     K, Mk2, Mg = operator_parts(omega, c_layers, n, window)
     return (K.astype(np.complex128) - Mk2 - 1j * Mg).tocsr()
 
@@ -201,9 +244,14 @@ def mass_matrix(n):
     return _scatter(n, ids, Me)
 
 
-def source_load(n, f_nodal):
-    """Right-hand side b = -M f for the nodal source f and g = 0 (eq. (1))."""
-    return -(mass_matrix(n) @ np.asarray(f_nodal, dtype=np.complex128))
+def source_load(n, f_nodal, scheme="p1"):
+    """Right-hand side of eq. (1) for the nodal source f and g = 0: b = -M f
+    (P1), or b = -h^2 w f in the five-point scheme's row scaling."""
+    f = np.asarray(f_nodal, dtype=np.complex128)
+    if scheme == "fd5":
+        h = 1.0 / (n - 1)
+        return -(h * h) * fd5_weights(n)[0] * f
+    return -(mass_matrix(n) @ f)
 
 
 def impedance_load(n, gfun):

@@ -70,10 +70,11 @@ def strip_nodes(n, N, direction, s):
     return p.ravel()
 
 
-def strip_matrix(omega, c_layers, n, N, direction, s):
-    """A_s in local order (sparse CSR, complex128)."""
+def strip_matrix(omega, c_layers, n, N, direction, s, scheme="p1"):
+    """A_s in local order (sparse CSR, complex128): the operator of the strip's
+    rectangle with the impedance condition on all four of its sides."""
     win = strip_window(n, N, direction, s)
-    A_win = asm.assemble(omega, c_layers, n, window=win)
+    A_win = asm.assemble(omega, c_layers, n, window=win, scheme=scheme)
     idx = strip_nodes(n, N, direction, s)
     return A_win[idx][:, idx].tocsr()
 

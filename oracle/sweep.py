@@ -106,16 +106,16 @@ class DoubleSweep:
     """
 
     def __init__(self, omega, c_layers, n, N, direction, A=None, precision="fp64",
-                 backward_left="stored"):
+                 backward_left="stored", scheme="p1"):
         st.check_decomposition(n, N)
         self.n, self.N, self.direction = n, N, direction
         self.dtype = np.complex128 if precision == "fp64" else np.complex64
         self.backward_left = backward_left
-        A = asm.assemble(omega, c_layers, n) if A is None else A
+        A = asm.assemble(omega, c_layers, n, scheme=scheme) if A is None else A
         self.A = A.astype(self.dtype)
         self.idx, self.As, self.solvers, self.rows1, self.rows2 = [], [], [], [], []
         for s in range(1, N + 1):
-            A_s = st.strip_matrix(omega, c_layers, n, N, direction, s)
+            A_s = st.strip_matrix(omega, c_layers, n, N, direction, s, scheme=scheme)
             kl = st.band_width(n, N, s)
             self.idx.append(st.strip_nodes(n, N, direction, s))
             self.As.append(A_s.astype(self.dtype))
@@ -167,10 +167,11 @@ class SingleSweep(DoubleSweep):
     Same strips, strip matrices and transmission data as the double sweep."""
 
     def __init__(self, omega, c_layers, n, N, direction, order="forward", A=None,
-                 precision="fp64"):
+                 precision="fp64", scheme="p1"):
         if order not in ("forward", "reverse"):
             raise ValueError("order must be 'forward' or 'reverse'")
-        super().__init__(omega, c_layers, n, N, direction, A=A, precision=precision)
+        super().__init__(omega, c_layers, n, N, direction, A=A, precision=precision,
+                         scheme=scheme)
         self.order = order
 
     def apply(self, r):

@@ -155,3 +155,69 @@ def test_callable_field_transposes_with_the_grid():
     assert abs(A - A.T).max() == 0.0
     K, _, _ = asm.operator_parts(omega, c, n)
     assert np.abs(K @ np.ones(n * n)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- five-point scheme
+# Sec. 4's discretisation: five-point differences, the impedance condition
+# through eliminated ghost nodes, rows scaled by h^2 times the node weight.
+
+def _fd5_by_ghosts(omega, n):
+    """The five-point operator written out node by node: -(Laplacian) - k^2 on
+    each node, a ghost value u_out = u_in + 2 i k h u at each boundary side
+    (central difference of du/dn = i k u), then the row times h^2 w."""
+    h = 1.0 / (n - 1)
+    A = np.zeros((n * n, n * n), dtype=complex)
+    for j in range(n):
+        for i in range(n):
+            p = j * n + i
+            row = {p: 4.0 / h ** 2 - omega ** 2}
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                ii, jj = i + di, j + dj
+                if 0 <= ii < n and 0 <= jj < n:
+                    q = jj * n + ii
+                    row[q] = row.get(q, 0) - 1.0 / h ** 2
+                else:  # ghost: mirror neighbour plus 2 i k h u_p
+                    q = (j - dj) * n + (i - di)
+                    row[q] = row.get(q, 0) - 1.0 / h ** 2
+                    row[p] -= 2j * omega * h / h ** 2
+            w = (0.5 if i in (0, n - 1) else 1.0) * (0.5 if j in (0, n - 1) else 1.0)
+            for q, v in row.items():
+                A[p, q] = v * h * h * w
+    return A
+
+
+def test_fd5_rows_follow_from_ghost_elimination():
+    n, omega = 9, 10.0
+    A = asm.assemble(omega, [1.0], n, scheme="fd5").toarray()
+    assert np.abs(A - _fd5_by_ghosts(omega, n)).max() < 1e-13
+    assert np.abs(A - A.T).max() == 0.0                      # complex symmetric
+    assert np.abs(A - A.conj().T).max() > 0.1                # not Hermitian
+
+
+def test_fd5_is_second_order_consistent_inside():
+    # a plane wave solves the Helmholtz equation: the scaled interior rows
+    # applied to it shrink like h^4 (h^2 truncation error times the h^2 scale)
+    omega, d = 10.0, (np.cos(0.4), np.sin(0.4))
+    res = []
+    for n in (33, 65, 129):
+        h = 1.0 / (n - 1)
+        p = np.arange(n * n)
+        x, y = (p % n) * h, (p // n) * h
+        u = np.exp(1j * omega * (d[0] * x + d[1] * y))
+        A = asm.assemble(omega, [1.0], n, scheme="fd5")
+        inner = ((p % n) > 0) & ((p % n) < n - 1) & ((p // n) > 0) & ((p // n) < n - 1)
+        res.append(np.abs((A @ u)[inner]).max())
+    assert 14.0 < res[0] / res[1] < 18.0 and 14.0 < res[1] / res[2] < 18.0
+
+
+def test_fd5_sweep_one_strip_is_exact_and_load_is_weighted():
+    from oracle import strips as st
+    from oracle import sweep as sw
+    n, omega, c = 17, 12.0, [1.0, 2.0]
+    S = sw.DoubleSweep(omega, c, n, 1, st.X, scheme="fd5")
+    r = np.random.default_rng(3).standard_normal(n * n) + 0j
+    assert np.linalg.norm(S.A @ S.apply(r) - r) < 1e-12 * np.linalg.norm(r)
+    f = np.ones(n * n)
+    b = asm.source_load(n, f, scheme="fd5")
+    h = 1.0 / (n - 1)
+    assert abs(b.sum() + h * h * (n - 1) ** 2) < 1e-12      # sum of weights = area / h^2
