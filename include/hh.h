@@ -100,12 +100,25 @@ typedef struct {
   void* ctx;                /* passed to speed                                */
   int nlayers;              /* equal horizontal layers, layer 0 at the bottom */
   const double* c_layers;   /* host pointer, nlayers speeds                   */
+  int scheme;               /* HH_SCHEME_P1 or HH_SCHEME_FD5                  */
 } hh_cfield;
+
+/* Discretisations of eq. (1) on the n x n grid: continuous P1 triangles (the
+ * "/" diagonal in every cell), or the five-point finite differences of Sec. 4
+ * with the impedance condition imposed through an eliminated ghost node at
+ * each boundary side (central difference), rows scaled by h^2 times the node
+ * weight (1/2 on a side, 1/4 at a corner) so that A stays complex symmetric:
+ * A = K - h^2 diag(k^2 w) - i h diag(k on the boundary), k at the nodes, and
+ * b = -h^2 w f.  The strips of the sweeps get the same scheme on their
+ * rectangles. */
+#define HH_SCHEME_P1 0
+#define HH_SCHEME_FD5 1
 
 /* hh_assemble for a general speed field (eq. (1)): the P1 operator with the
  * wave number omega / c(centroid) on each triangle and omega / c(midpoint) on
  * each edge (boundary edges in A, interface edges in the strip operators of
- * eq. (4)).  f: NULL, or a device pointer to n*n hh_c128 nodal source values;
+ * eq. (4)), or with c->scheme == HH_SCHEME_FD5 the five-point operator with
+ * omega / c at the nodes (layers: the node's layer).  f: NULL, or a device pointer to n*n hh_c128 nodal source values;
  * then b = -M f is formed and kept with the problem, and hh_mpgmres with
  * b == NULL and nrhs == 1 solves for it.  Errors: HH_EINVAL (also for a
  * speed that is not positive and finite at a sample point), HH_ENOMEM,
@@ -113,8 +126,8 @@ typedef struct {
 int hh_assemble_field(double omega, const hh_cfield* c, int n, const hh_c128* f,
                       hh_problem** out);
 
-/* Right-hand side of eq. (1) for nodal sources: b = -M f (P1 mass matrix M),
- * impedance data g = 0.  f and b are device pointers to nvec x n*n hh_c128
+/* Right-hand side of eq. (1) for nodal sources: b = -M f (P1 mass matrix M;
+ * b = -h^2 w f for the five-point scheme), impedance data g = 0.  f and b are device pointers to nvec x n*n hh_c128
  * (vector v at offset v*n*n); f and b must not overlap. */
 int hh_load_vector(hh_problem* pb, int nvec, const hh_c128* f, hh_c128* b);
 

@@ -68,12 +68,19 @@ class Problem:
         self.c_layers = c
 
     @classmethod
-    def from_field(cls, omega, speed, n, f=None):
+    def from_field(cls, omega, speed, n, f=None, scheme="p1"):
         """hh_assemble_field: speed is a callable c(x, y) (sampled by the library at
-        the triangle centroids and edge midpoints); f an optional nodal source
-        (device tensor of n*n complex128) whose b = -M f the problem keeps."""
-        fn = _lib.SPEED_FN(lambda x, y, ctx: float(speed(x, y)))
-        field = _lib.hh_cfield(fn, None, 0, None)
+        the triangle centroids, edge midpoints and nodes) or a list of layer
+        speeds; f an optional nodal source (device tensor of n*n complex128)
+        whose right-hand side the problem keeps; scheme "p1" or "fd5"."""
+        sc = {"p1": _lib.HH_SCHEME_P1, "fd5": _lib.HH_SCHEME_FD5}[scheme]
+        if callable(speed):
+            fn = _lib.SPEED_FN(lambda x, y, ctx: float(speed(x, y)))
+            field = _lib.hh_cfield(fn, None, 0, None, sc)
+        else:
+            c = np.ascontiguousarray(np.asarray(speed, dtype=np.float64).ravel())
+            field = _lib.hh_cfield(_lib.SPEED_FN(), None, len(c),
+                                   c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sc)
         h = ctypes.c_void_p()
         fp = _dev(f, "f") if f is not None else None
         _sync()

@@ -57,7 +57,11 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 class hh_cfield(ctypes.Structure):
     _fields_ = [("speed", SPEED_FN), ("ctx", ctypes.c_void_p), ("nlayers", ctypes.c_int),
-                ("c_layers", ctypes.POINTER(ctypes.c_double))]
+                ("c_layers", ctypes.POINTER(ctypes.c_double)), ("scheme", ctypes.c_int)]
+
+
+HH_SCHEME_P1 = 0
+HH_SCHEME_FD5 = 1
 
 
 class hh_result(ctypes.Structure):

@@ -50,13 +50,61 @@ __device__ __forceinline__ double k_vedge(const Medium& m, int n, int i, int j) 
   return wave_number(6LL * j + 3, n, m.L, m.c, m.omega);
 }
 
+// The P1 stiffness part of row (i, j) over the window's cells.
+__device__ void stiffness_stencil(int i, int j, int n, int cx0, int cx1, int cy0, int cy1,
+                                  c128 out[7]) {
+  const double Ks[3][3] = {{0.5, -0.5, 0.0}, {-0.5, 1.0, -0.5}, {0.0, -0.5, 0.5}};
+  for (int cj = j - 1; cj <= j; ++cj) {
+    if (cj < cy0 || cj >= cy1) continue;
+    for (int ci = i - 1; ci <= i; ++ci) {
+      if (ci < cx0 || ci >= cx1) continue;
+      for (int t = 0; t < 2; ++t) {
+        int vx[3], vy[3];
+        vx[0] = ci; vy[0] = cj;
+        if (t == 0) { vx[1] = ci + 1; vy[1] = cj; }
+        else { vx[1] = ci; vy[1] = cj + 1; }
+        vx[2] = ci + 1; vy[2] = cj + 1;
+        int a = -1;
+        for (int v = 0; v < 3; ++v)
+          if (vx[v] == i && vy[v] == j) a = v;
+        if (a < 0) continue;
+        for (int b = 0; b < 3; ++b) out[slot_of(vx[b] - i, vy[b] - j)].re += Ks[a][b];
+      }
+    }
+  }
+}
+
+// wave number at node (i, j) (five-point scheme): the sampled field, or the
+// layer of the node's height y = 6 j / (6 (n-1))
+__device__ __forceinline__ double k_node(const Medium& m, int n, int i, int j) {
+  if (m.kn) return m.kn[(long long)j * n + i];
+  return wave_number(6LL * j, n, m.L, m.c, m.omega);
+}
+
 // 7-point stencil of row (i, j) of the operator assembled over the cells of the
 // window [cx0, cx1) x [cy0, cy1) with the impedance edge form on all four
 // window sides.  mass_only: unit-weight mass matrix (for the load vector).
+// Five-point scheme (md.fd5): the P1 stiffness of the window (on this mesh the
+// five-point Laplacian in the scaling h^2 w) minus h^2 k^2 w on the diagonal
+// and i h k on the window's boundary nodes, w = 1, 1/2 on a window side, 1/4 at
+// a window corner (mass_only: h^2 w on the diagonal).
 __device__ void node_stencil(int i, int j, int n, int cx0, int cx1, int cy0, int cy1,
                              const Medium& md, bool mass_only, c128 out[7]) {
   const double h = 1.0 / (n - 1);
   for (int d = 0; d < 7; ++d) out[d] = mk(0.0, 0.0);
+  if (md.fd5) {
+    const double wx = (i == cx0 || i == cx1) ? 0.5 : 1.0, wy = (j == cy0 || j == cy1) ? 0.5 : 1.0;
+    const double w = wx * wy;
+    if (mass_only) {
+      out[3].re = h * h * w;
+      return;
+    }
+    stiffness_stencil(i, j, n, cx0, cx1, cy0, cy1, out);
+    const double k = k_node(md, n, i, j);
+    out[3].re -= h * h * k * k * w;
+    if (i == cx0 || i == cx1 || j == cy0 || j == cy1) out[3].im -= h * k;
+    return;
+  }
   const double Ks[3][3] = {{0.5, -0.5, 0.0}, {-0.5, 1.0, -0.5}, {0.0, -0.5, 0.5}};
   const double m0 = h * h / 24.0;
   // the four cells that contain node (i, j)
@@ -119,13 +167,16 @@ __global__ void k_assemble(int n, Medium md, c128* __restrict__ A) {
   A[3 * nn + p] = st[6];
 }
 
-__global__ void k_load_vector(int n, int nvec, const c128* __restrict__ f, c128* __restrict__ b) {
+__global__ void k_load_vector(int n, int nvec, const c128* __restrict__ f, c128* __restrict__ b,
+                              int fd5) {
   long long nn = (long long)n * n;
   long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (p >= nn) return;
   int i = (int)(p % n), j = (int)(p / n);
   c128 st[7];
-  node_stencil(i, j, n, 0, n - 1, 0, n - 1, Medium{}, true, st);
+  Medium md{};
+  md.fd5 = fd5;
+  node_stencil(i, j, n, 0, n - 1, 0, n - 1, md, true, st);
   const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
   const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
   for (int v = 0; v < nvec; ++v) {
@@ -208,6 +259,8 @@ Medium medium_of(const hh_problem* pb) {
   m.kt = pb->d_kt;
   m.kv = pb->d_kv;
   m.kh = pb->d_kh;
+  m.kn = pb->d_kn;
+  m.fd5 = pb->scheme == HH_SCHEME_FD5;
   return m;
 }
 
@@ -218,11 +271,11 @@ void launch_assemble(int n, const Medium& md, c128* d_A, hipStream_t st) {
   HH_HIP(hipGetLastError());
 }
 
-void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st) {
+void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st, int fd5) {
   long long nn = (long long)n * n;
   int bs = 256;
   hipLaunchKernelGGL(k_load_vector, dim3((unsigned)((nn + bs - 1) / bs)), dim3(bs), 0, st, n,
-                     nvec, f, b);
+                     nvec, f, b, fd5);
   HH_HIP(hipGetLastError());
 }
 

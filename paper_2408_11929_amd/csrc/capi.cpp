@@ -262,7 +262,9 @@ SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, 
   b.rho = take((size_t)nvec * fs.max_ns * es);
   b.g1 = take((size_t)nvec * fs.N * pb->n * es);
   b.zs = fs.precision == HH_FP64 ? nullptr : take((size_t)nvec * len * es);
-  b.xch = plan > 0 ? take((size_t)nvec * plan_width(plan) * 64 * es) : nullptr;
+  b.xch = plan == HH_PLAN_WIDE || plan == HH_PLAN_PAIR
+              ? take((size_t)nvec * plan_width(plan) * 64 * es)
+              : nullptr;
   *total = off;
   return b;
 }
@@ -299,7 +301,17 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
     tk.bar = b.sync + 32 * (v + 1);
     tk.mode = mode;
   }
-  HH_HIP(hipMemcpyAsync(b.tasks, tasks, nvec * sizeof(SweepTask), hipMemcpyHostToDevice, st));
+  // tiles of two vectors: consecutive pairs, a last single one repeated
+  int nlaunch = nvec;
+  if (plan == HH_PLAN_TILE) {
+    nlaunch = (nvec + 1) / 2;
+    for (int q = 0; q < nlaunch; ++q) {
+      SweepTask tl = tasks[2 * q];
+      tl.ch2 = tasks[2 * q + 1 < nvec ? 2 * q + 1 : 2 * q].ch;
+      tasks[q] = tl;
+    }
+  }
+  HH_HIP(hipMemcpyAsync(b.tasks, tasks, nlaunch * sizeof(SweepTask), hipMemcpyHostToDevice, st));
   {
     double bytes = 0;
     for (int q = 0; q < fs.N; ++q) {
@@ -308,8 +320,12 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
       bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
     }
     TimedRegion tr(FAM_SWEEP, st, bytes);
-    launch_sweep(b.tasks, nvec, fs.precision, fs.strips[0].KP, fs.strips[0].segs, fs.max_kl,
-                 pb->n, fs.any_pivot, plan, b.sync, st);
+    if (plan == HH_PLAN_TILE)
+      launch_sweep_tiles(b.tasks, nlaunch, fs.precision, fs.strips[0].KP, fs.strips[0].segs,
+                         pb->n, fs.any_pivot, st);
+    else
+      launch_sweep(b.tasks, nvec, fs.precision, fs.strips[0].KP, fs.strips[0].segs, fs.max_kl,
+                   pb->n, fs.any_pivot, plan, b.sync, st);
   }
   if (fs.precision != HH_FP64) launch_widen((const c64*)zs, z, nvec * len, st);
   unsigned aborted = 0;
@@ -352,11 +368,13 @@ void problem_assemble(hh_problem* pb) {
 }  // namespace
 
 // New problem handle with the operator assembled asynchronously on its stream.
-hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n) {
+hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n, int scheme) {
+  REQUIRE(scheme == HH_SCHEME_P1 || scheme == HH_SCHEME_FD5, "unknown scheme %d", scheme);
   REQUIRE(nlayers >= 1 && c_layers != nullptr, "need at least one layer speed");
   for (int l = 0; l < nlayers; ++l)
     REQUIRE(std::isfinite(c_layers[l]) && c_layers[l] > 0, "layer speed %d is not positive", l);
   std::unique_ptr<hh_problem> pb = problem_shell(omega, n);
+  pb->scheme = scheme;
   try {
     pb->c.assign(c_layers, c_layers + nlayers);
     pb->d_c = (double*)dev_alloc(nlayers * sizeof(double));
@@ -373,13 +391,14 @@ hh_problem* problem_create(double omega, int nlayers, const double* c_layers, in
 // Wave numbers omega / c of a speed field sampled on the host at the triangle
 // centroids and the edge midpoints (the layout of hh_problem::d_kt, d_kv, d_kh).
 hh_problem* problem_create_field(double omega, double (*speed)(double, double, void*), void* ctx,
-                                 int n) {
+                                 int n, int scheme) {
   REQUIRE(speed != nullptr, "the speed field has no function");
+  REQUIRE(scheme == HH_SCHEME_P1 || scheme == HH_SCHEME_FD5, "unknown scheme %d", scheme);
   REQUIRE(std::isfinite(omega) && omega > 0, "omega must be positive and finite");
   REQUIRE(n >= 3 && n <= 8193, "n must be in [3, 8193]");
   const double h = 1.0 / (n - 1);
   const long long m = n - 1;
-  std::vector<double> kt(2 * m * m), kv((size_t)m * n), kh((size_t)m * n);
+  std::vector<double> kt(2 * m * m), kv((size_t)m * n), kh((size_t)m * n), kn((size_t)n * n);
   auto k_at = [&](double x, double y) {
     const double c = speed(x, y, ctx);
     REQUIRE(std::isfinite(c) && c > 0, "the speed field is not positive and finite at (%g, %g)", x, y);
@@ -395,9 +414,14 @@ hh_problem* problem_create_field(double omega, double (*speed)(double, double, v
     for (long long i = 0; i < n; ++i) kv[j * n + i] = k_at(i * h, (j + 0.5) * h);
   for (long long j = 0; j < n; ++j)
     for (long long i = 0; i < m; ++i) kh[j * m + i] = k_at((i + 0.5) * h, j * h);
+  for (long long j = 0; j < n; ++j)
+    for (long long i = 0; i < n; ++i) kn[j * n + i] = k_at(i * h, j * h);
   std::unique_ptr<hh_problem> pb = problem_shell(omega, n);
+  pb->scheme = scheme;
   try {
     pb->c.assign(1, 1.0);
+    pb->d_kn = (double*)dev_alloc(kn.size() * sizeof(double));
+    HH_HIP(hipMemcpyAsync(pb->d_kn, kn.data(), kn.size() * sizeof(double), hipMemcpyHostToDevice, pb->st[0]));
     pb->d_kt = (double*)dev_alloc(kt.size() * sizeof(double));
     pb->d_kv = (double*)dev_alloc(kv.size() * sizeof(double));
     pb->d_kh = (double*)dev_alloc(kh.size() * sizeof(double));
@@ -423,6 +447,7 @@ void problem_destroy(hh_problem* pb) {
   dev_free(pb->d_kt);
   dev_free(pb->d_kv);
   dev_free(pb->d_kh);
+  dev_free(pb->d_kn);
   dev_free(pb->d_b);
   if (pb->own_streams)
     for (hipStream_t s : pb->st)
@@ -457,12 +482,13 @@ int hh_assemble_field(double omega, const hh_cfield* c, int n, const hh_c128* f,
   return guard([&]() {
     REQUIRE(out != nullptr && c != nullptr, "out or c is NULL");
     *out = nullptr;
-    hh_problem* pb = c->speed ? problem_create_field(omega, c->speed, c->ctx, n)
-                              : problem_create(omega, c->nlayers, c->c_layers, n);
+    hh_problem* pb = c->speed ? problem_create_field(omega, c->speed, c->ctx, n, c->scheme)
+                              : problem_create(omega, c->nlayers, c->c_layers, n, c->scheme);
     try {
       if (f) {
         pb->d_b = (c128*)dev_alloc((size_t)n * n * sizeof(c128));
-        launch_load_vector(n, 1, (const c128*)f, pb->d_b, pb->st[0]);
+        launch_load_vector(n, 1, (const c128*)f, pb->d_b, pb->st[0],
+                           pb->scheme == HH_SCHEME_FD5);
       }
       HH_HIP(hipStreamSynchronize(pb->st[0]));
     } catch (...) {
@@ -525,7 +551,8 @@ int hh_release_caches(void) {
 int hh_load_vector(hh_problem* pb, int nvec, const hh_c128* f, hh_c128* b) {
   return guard([&]() {
     REQUIRE(pb && f && b && nvec >= 0, "invalid arguments");
-    launch_load_vector(pb->n, nvec, (const c128*)f, (c128*)b, pb->st[0]);
+    launch_load_vector(pb->n, nvec, (const c128*)f, (c128*)b, pb->st[0],
+                       pb->scheme == HH_SCHEME_FD5);
     HH_HIP(hipStreamSynchronize(pb->st[0]));
     return HH_OK;
   });

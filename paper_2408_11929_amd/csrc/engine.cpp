@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <tuple>
 #include <type_traits>
 
 namespace hh {
@@ -429,13 +430,15 @@ void Engine::step(std::vector<Solve*>& solves) {
           k.plan = p;
         } else {
           k.plan = sweep_plan_for(nt, k.prec, k.P, k.kmax, k.nmax, k.piv, k.wide);
-          k.tune = !std::getenv("HH_SWEEP_PLAN") && tune_enabled() && !k.piv && k.wide &&
-                   sweep_wide_fits(k.prec, k.P, k.kmax, k.nmax);
+          k.tune = !std::getenv("HH_SWEEP_PLAN") && tune_enabled() && !k.piv &&
+                   ((k.wide && sweep_wide_fits(k.prec, k.P, k.kmax, k.nmax)) ||
+                    sweep_plan_fits(HH_PLAN_TILE, nt, k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv,
+                                    true));
         }
       }
       if (k.plan != HH_PLAN_WIDE || k.tune)
         for (hh_problem* q : k.pbs) ensure_batch_maps(q, st_);
-      if (k.plan == 0 && !k.tune) continue;
+      if ((k.plan == 0 || k.plan == HH_PLAN_TILE) && !k.tune) continue;
       chains += k.tasks.size();
       // a tuned kind may run any plan: room for the widest
       xbytes += k.tasks.size() * (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 64 *
@@ -464,7 +467,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       wide_chains = chains;
       size_t ci = 0, xo = 0;
       for (Kind& k : kinds) {
-        if (k.plan == 0 && !k.tune) continue;
+        if ((k.plan == 0 || k.plan == HH_PLAN_TILE) && !k.tune) continue;
         for (SweepTask& tk : k.tasks) {
           tk.bar = sync_ + 32 * (1 + ci++);
           tk.xch = (char*)xch_ + xo;
@@ -473,8 +476,43 @@ void Engine::step(std::vector<Solve*>& solves) {
       }
     }
   }
-  std::vector<SweepTask*> dsw(kinds.size());
-  for (size_t q = 0; q < kinds.size(); ++q) dsw[q] = stage(kinds[q].tasks, staged_);
+  // tiles of two right-hand sides (choice HH_PLAN_TILE): tasks of the same
+  // strips, image and sweep mode in pairs, a last single one repeated
+  std::vector<std::vector<SweepTask>> tiles(kinds.size());
+  for (size_t q = 0; q < kinds.size(); ++q) {
+    Kind& k = kinds[q];
+    if (k.plan != HH_PLAN_TILE && !k.tune) continue;
+    std::vector<int> order(k.tasks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const SweepTask &x = k.tasks[a], &y = k.tasks[b];
+      return std::make_tuple((uintptr_t)x.ch.strips, x.mode) <
+             std::make_tuple((uintptr_t)y.ch.strips, y.mode);
+    });
+    for (size_t i = 0; i < order.size();) {
+      SweepTask tl = k.tasks[order[i]];
+      const bool pair = i + 1 < order.size() &&
+                        k.tasks[order[i + 1]].ch.strips == tl.ch.strips &&
+                        k.tasks[order[i + 1]].mode == tl.mode;
+      tl.ch2 = pair ? k.tasks[order[i + 1]].ch : tl.ch;
+      tiles[q].push_back(tl);
+      i += pair ? 2 : 1;
+    }
+  }
+  std::vector<SweepTask*> dsw(kinds.size()), dtl(kinds.size(), nullptr);
+  for (size_t q = 0; q < kinds.size(); ++q) {
+    dsw[q] = stage(kinds[q].tasks, staged_);
+    if (!tiles[q].empty()) dtl[q] = stage(tiles[q], staged_);
+  }
+  // one launch of kind q with choice c (a segment plan, or tiles)
+  auto launch_kind = [&](size_t q, int c) {
+    const Kind& k = kinds[q];
+    if (c == HH_PLAN_TILE)
+      launch_sweep_tiles(DEV(dtl[q]), (int)tiles[q].size(), k.prec, k.KP, k.P, k.nmax, k.piv, st_);
+    else
+      launch_sweep(DEV(dsw[q]), (int)k.tasks.size(), k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv, c,
+                   sync_, st_);
+  };
 
   // 0. t > 2 (sum rule): the sweeps' input is the sum of the previous
   // iteration's t new basis vectors (deflated ones are zero)
@@ -648,13 +686,13 @@ void Engine::step(std::vector<Solve*>& solves) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HH_HIP(hipEventCreate(&e0));
     HH_HIP(hipEventCreate(&e1));
-    for (int p = 0; p < HH_NPLAN; ++p) {
+    for (int p = 0; p < HH_NCHOICE; ++p) {
       if (!sweep_plan_fits(p, nt, k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv, true)) continue;
       double ms_best = -1;
       for (int rep = 0; rep < 2; ++rep) {
         if (wide_chains) launch_zero(sync_ + 32, wide_chains * 128, st_);
         HH_HIP(hipEventRecord(e0, st_));
-        launch_sweep(DEV(dsw[q]), nt, k.prec, k.KP, k.P, k.kmax, k.nmax, k.piv, p, sync_, st_);
+        launch_kind(q, p);
         HH_HIP(hipEventRecord(e1, st_));
         HH_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -693,10 +731,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         }
     }
     TimedRegion tr(FAM_SWEEP, st_, bytes);
-    for (size_t q = 0; q < kinds.size(); ++q)
-      launch_sweep(DEV(dsw[q]), (int)kinds[q].tasks.size(), kinds[q].prec, kinds[q].KP,
-                   kinds[q].P, kinds[q].kmax, kinds[q].nmax, kinds[q].piv, kinds[q].plan, sync_,
-                   st_);
+    for (size_t q = 0; q < kinds.size(); ++q) launch_kind(q, kinds[q].plan);
   }
   if (wide_chains > 0) {
     // zero the counters for the next launch now, behind this one on the

@@ -117,6 +117,10 @@ struct MemError {};
 constexpr int HH_NPLAN = 3;
 constexpr int HH_PLAN_WIDE = 1;
 constexpr int HH_PLAN_PAIR = 2;
+// A launch's choice is a segment plan, or HH_PLAN_TILE: plan 0's segments
+// with tiles of two right-hand sides per chain (k_sweep_n).
+constexpr int HH_PLAN_TILE = 3;
+constexpr int HH_NCHOICE = 4;
 // One strip of one sweep direction (0 = x / LRL, 1 = y / BTB).
 struct StripDesc {
   int dir;        // 0 x, 1 y
@@ -209,6 +213,8 @@ struct hh_problem {
   double* d_kt = nullptr;
   double* d_kv = nullptr;
   double* d_kh = nullptr;
+  double* d_kn = nullptr;          // ... and at the nodes (j n + i)
+  int scheme = 0;                  // HH_SCHEME_P1 or HH_SCHEME_FD5
   hh::c128* d_b = nullptr;         // right-hand side b = -M f given at assembly, or null
   hh::c128* d_A = nullptr;         // 4 * n*n upper diagonals
   hh::FactorSet fs;
@@ -251,6 +257,8 @@ struct Medium {
   const double* kt;
   const double* kv;
   const double* kh;
+  const double* kn;  // sampled field: wave numbers at the nodes (five-point scheme)
+  int fd5;           // the five-point scheme of Sec. 4 instead of P1 (see assemble.hip)
 };
 
 // ---------------------------------------------------------------- problems
@@ -259,11 +267,12 @@ struct Medium {
 void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision);
 void factor_launch(hh_problem* pb, hipStream_t st);
 int factor_finish(hh_problem* pb);
-hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n);
+hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n,
+                           int scheme = 0);
 // The same for a speed field sampled by a host callback at the triangle
-// centroids and edge midpoints.
+// centroids, edge midpoints and nodes.
 hh_problem* problem_create_field(double omega, double (*speed)(double, double, void*), void* ctx,
-                                 int n);
+                                 int n, int scheme = 0);
 void problem_destroy(hh_problem* pb);
 
 // ---------------------------------------------------------------- memory
@@ -282,7 +291,8 @@ bool caller_streams(hipStream_t& x, hipStream_t& y);
 // assemble.hip
 Medium medium_of(const hh_problem* pb);
 void launch_assemble(int n, const Medium& md, c128* d_A, hipStream_t st);
-void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st);
+// b = -M f (P1) or b = -h^2 w f (five-point scheme, fd5).
+void launch_load_vector(int n, int nvec, const c128* f, c128* b, hipStream_t st, int fd5 = 0);
 void launch_pack_strips(const hh_problem* pb, hipStream_t st);
 // Zeroes and packs again the bands of the strips whose pflag is 2 (marked by
 // the LU that assumes no interchange).
@@ -315,6 +325,7 @@ struct SweepChain {
 // One double sweep: one chain over the N strips of a direction.
 struct SweepTask {
   SweepChain ch;
+  SweepChain ch2;  // the second right-hand side of a tile (launch_sweep with nr = 2)
   const void* img;
   const int* piv;
   const int* pflag;
@@ -335,6 +346,14 @@ struct SweepTask {
 // that a workgroup raises when its partners fail to arrive in time).
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
                   int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st);
+// Tiles of two right-hand sides of the same preconditioner per chain
+// (k_sweep_n, segment plan 0): task t holds its two chains in ch and ch2.
+// They need complex64 strips none of which pivoted and a workgroup's LDS for
+// two rings per wave (sweep_tiles_fit).  The results are bitwise those of
+// launch_sweep on plan 0.
+bool sweep_tiles_fit(int precision, int KP, int P, int nmax, bool pivots);
+void launch_sweep_tiles(const SweepTask* d_tiles, int ntiles, int precision, int KP, int P,
+                        int nmax, bool pivots, hipStream_t st);
 // Whether the wide plan can run a factorisation (complex64 strips, band
 // half-width at most 31, at most two workgroup tails per wave, LDS).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
@@ -372,7 +391,9 @@ __host__ __device__ inline int segment_rows(int ns, int P) {
 // 16-row aligned segments.  Either way a segment is at least K rows long, so
 // that a segment's state (the K outputs before it) lies in the segment before
 // it, and every segment after the first starts at row K or later.
-__host__ __device__ inline int plan_width(int p) { return p == 0 ? 1 : p == HH_PLAN_WIDE ? 16 : 2; }
+__host__ __device__ inline int plan_width(int p) {
+  return p == HH_PLAN_WIDE ? 16 : p == HH_PLAN_PAIR ? 2 : 1;
+}
 __host__ __device__ inline int plan_seg(int ns, int P, int p, int K) {
   if (p == 0) return segment_rows(ns, P);
   const int S = plan_width(p) * P, per = (ns + S - 1) / S, least = (K + 15) / 16 * 16;

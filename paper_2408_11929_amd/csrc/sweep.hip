@@ -96,6 +96,13 @@ template <class T>
 __device__ __forceinline__ cx<T> sel(bool c, cx<T> a, cx<T> b) {
   return mk(c ? a.re : b.re, c ? a.im : b.im);
 }
+// a b with the rounding of each component fixed (a product, then one fused
+// multiply-add), so that every kernel forms it bit for bit alike whatever the
+// compiler would otherwise contract
+template <class T>
+__device__ __forceinline__ cx<T> cmulx(cx<T> a, cx<T> b) {
+  return mk(fmac_(a.re, b.re, -(a.im * b.im)), fmac_(a.re, b.im, a.im * b.re));
+}
 
 // Access policies for vectors that workgroups of one chain share.  Plain:
 // ordinary loads and stores (one workgroup per chain).  Agent: complex64
@@ -411,7 +418,7 @@ __device__ __forceinline__ void solve_blocked_run(BlockedPre<T, KP, U, NB, Src>&
   auto rest = [&](const cx<T>(&gb)[KP], int i0) -> cx<T> {
     const cx<T>* in = iring + ((i0 + 4 * p) & 255);
     const cx<T>* old = oring + ((i0 - K + p * KO) & 255);
-    cx<T> a0 = gb[4] * in[0], a1 = gb[5] * in[1];
+    cx<T> a0 = cmulx(gb[4], in[0]), a1 = cmulx(gb[5], in[1]);
     a0 = cfma(a0, gb[6], in[2]);
     a1 = cfma(a1, gb[7], in[3]);
 #pragma unroll
@@ -445,7 +452,7 @@ __device__ __forceinline__ void solve_blocked_run(BlockedPre<T, KP, U, NB, Src>&
       for (int u = 0; u < U; ++u) {
         const int i0 = j * R + 16 * u;
         const cx<T>* pv = oring + ((i0 - 16 + 4 * p) & 255);
-        cx<T> a0 = cfma(rst, g[h][u][0], pv[0]), a1 = g[h][u][1] * pv[1];
+        cx<T> a0 = cfma(rst, g[h][u][0], pv[0]), a1 = cmulx(g[h][u][1], pv[1]);
         a0 = cfma(a0, g[h][u][2], pv[2]);
         a1 = cfma(a1, g[h][u][3], pv[3]);
         const cx<T> part = a0 + a1;
@@ -483,7 +490,7 @@ __device__ __forceinline__ cx<T> transmission(gptr<const cx<T>> coef, gptr<cx<T>
   for (int d = 0; d < 7; ++d) {
     const int ii = i + di[d], jj = j + dj[d];
     if (ii < 0 || ii >= n || jj < 0 || jj >= n) continue;
-    g = g + ld<T>(coef, d) * A::load((gptr<const cx<T>>)z, (long long)jj * n + ii);
+    g = cfma(g, ld<T>(coef, d), A::load((gptr<const cx<T>>)z, (long long)jj * n + ii));
   }
   return g;
 }
@@ -726,6 +733,208 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
                             stt + 64 * wv, lane);
 }
 
+// ---------------------------------------------------------------- RHS tiles
+// The blocked substitution for NR right-hand sides at once (one wave, the
+// same strip): every map row the wave reads feeds all NR of them, and their
+// NR independent recurrences fill the wave's latency.  Per right-hand side
+// the operations are those of solve_blocked_run in the same order, so the
+// results are bitwise those of NR separate substitutions.  ring: NR rings of
+// 640 entries; init[v]: state of right-hand side v (LDS) or null.
+template <class T, int KP, int U, int NB, int NR, class Src>
+struct BlockedPreN {
+  typename Src::P in0[NR], in1[NR];
+  typename Src::P pend[NB][NR];
+  cx<T> g[NB][U][KP];
+  gptr<const cx<T>> gp;
+};
+
+template <class T, int KP, int U, int NB, int NR, class Src, class Dst>
+__device__ __forceinline__ void solve_blocked_n(const Src (&src)[NR], const Dst (&dst)[NR],
+                                                gptr<const cx<T>> G, int ns, int K, cx<T>* ring,
+                                                const cx<T>* const (&init)[NR], int lane) {
+  static_assert(HH_BLK == 16 && KP >= 8, "four lane groups of 16 rows, four chain terms each");
+  constexpr int R = U * 16, KO = KP - 8;
+  static_assert(R <= 64 && 64 % R == 0 && NB >= 2, "a step divides 64 rows");
+  BlockedPreN<T, KP, U, NB, NR, Src> pre;
+#pragma unroll
+  for (int v = 0; v < NR; ++v) {
+    pre.in0[v] = src[v].load(lane);
+    pre.in1[v] = src[v].load(64 + lane);
+#pragma unroll
+    for (int b = 0; b + 1 < NB; ++b) pre.pend[b][v] = src[v].load(b * R + 128 + lane);
+  }
+  pre.gp = G + lane;
+#pragma unroll
+  for (int b = 0; b + 1 < NB; ++b) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < KP; ++t) pre.g[b][u][t] = ld<T>(pre.gp, (long long)(u * KP + t) * 64);
+    pre.gp = pre.gp + (long long)U * KP * 64;
+  }
+  const cx<T> zero = mk((T)0, (T)0);
+  const int r = lane & 15, p = lane >> 4;
+  const int nst = (ns + R - 1) / R;
+  auto put = [&](cx<T>* rg, int i, cx<T> v) {
+    const int k = i & 255;
+    rg[k] = v;
+    rg[k < 64 ? k + 256 : k] = v;
+  };
+  auto put_part = [&](cx<T>* rg, int i, int part, T v) {
+    const int k = i & 255;
+    T* base = reinterpret_cast<T*>(rg) + part;
+    base[2 * k] = v;
+    base[2 * (k < 64 ? k + 256 : k)] = v;
+  };
+#pragma unroll
+  for (int v = 0; v < NR; ++v) {
+    cx<T>* oring = ring + 640 * v;
+    cx<T>* iring = oring + 320;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) oring[64 * q + lane] = zero;
+    if (init[v] && lane < K) put(oring, lane - K, init[v][lane]);
+    put(iring, lane, src[v].get(pre.in0[v]));
+    put(iring, 64 + lane, src[v].get(pre.in1[v]));
+  }
+  auto& pend = pre.pend;
+  auto& g = pre.g;
+  auto& gp = pre.gp;
+  auto rest = [&](const cx<T>(&gb)[KP], int i0, int v) -> cx<T> {
+    const cx<T>* oring = ring + 640 * v;
+    const cx<T>* in = oring + 320 + ((i0 + 4 * p) & 255);
+    const cx<T>* old = oring + ((i0 - K + p * KO) & 255);
+    cx<T> a0 = cmulx(gb[4], in[0]), a1 = cmulx(gb[5], in[1]);
+    a0 = cfma(a0, gb[6], in[2]);
+    a1 = cfma(a1, gb[7], in[3]);
+#pragma unroll
+    for (int t = 0; t < KO; t += 2) {
+      a0 = cfma(a0, gb[8 + t], old[t]);
+      if (t + 1 < KO) a1 = cfma(a1, gb[9 + t], old[t + 1]);
+    }
+    return a0 + a1;
+  };
+  cx<T> rst[NR];
+#pragma unroll
+  for (int v = 0; v < NR; ++v) rst[v] = rest(g[0][0], 0, v);
+  const int nstr = (nst + NB - 1) / NB * NB;
+  for (int j0 = 0; j0 < nstr; j0 += NB) {
+#pragma unroll
+    for (int h = 0; h < NB; ++h) {
+      const int j = j0 + h;
+      if (j >= nst) break;
+      const int hn = (h + NB - 1) % NB;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < KP; ++t) g[hn][u][t] = ld<T>(gp, (long long)(u * KP + t) * 64);
+      gp = gp + (long long)U * KP * 64;
+#pragma unroll
+      for (int v = 0; v < NR; ++v) {
+        cx<T>* iring = ring + 640 * v + 320;
+        put(iring, j * R + 128 + lane, src[v].get(pend[h][v]));
+        pend[hn][v] = src[v].load((j + NB - 1) * R + 128 + lane);
+        if (j > 0) {
+          const int q = (j - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
+          dst[v].put(qs, ring[640 * v + (qs & 255)]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i0 = j * R + 16 * u;
+#pragma unroll
+        for (int v = 0; v < NR; ++v) {
+          cx<T>* oring = ring + 640 * v;
+          const cx<T>* pv = oring + ((i0 - 16 + 4 * p) & 255);
+          cx<T> a0 = cfma(rst[v], g[h][u][0], pv[0]), a1 = cmulx(g[h][u][1], pv[1]);
+          a0 = cfma(a0, g[h][u][2], pv[2]);
+          a1 = cfma(a1, g[h][u][3], pv[3]);
+          const cx<T> part = a0 + a1;
+          const T half = sum4c(part.re, part.im);
+          if (u + 1 < U)
+            rst[v] = rest(g[h][u + 1 < U ? u + 1 : u], i0 + 16, v);
+          else
+            rst[v] = rest(g[(h + 1) % NB][0], i0 + 16, v);
+          put_part(oring, i0 + r, p & 1, half);
+        }
+      }
+    }
+  }
+  const int q = (nst - 1) * R + (lane & (R - 1)), qs = q < ns ? q : ns - 1;
+#pragma unroll
+  for (int v = 0; v < NR; ++v) dst[v].put(qs, ring[640 * v + (qs & 255)]);
+}
+
+// solve_triangle for NR right-hand sides of the same strip (segment plan 0):
+// the same three phases, each wave carrying its segment for all NR; the
+// transfer maps are staged once.  work: max(640 P NR, (P - 2) KM^2) entries;
+// yt, stt: 64 P entries per right-hand side (right-hand side v at 64 P v).
+template <class T, int KP, int U, int NB, int NR, class Src, class Dst>
+__device__ __forceinline__ void solve_triangle_n(const Src (&src)[NR], const Dst (&dst)[NR],
+                                                 const cx<T>* G, const cx<T>* Tm, int ns, int K,
+                                                 int seg, cx<T>* work, cx<T>* yt, cx<T>* stt) {
+  static_assert(NR == 2, "tiles of two right-hand sides (what the register budget allows)");
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
+  const int P = nthr >> 6;
+  const int nseg = (ns + seg - 1) / seg;
+  cx<T>* ring = work + 640 * NR * wv;
+  const int off = wv * seg, len = ns - off < seg ? ns - off : seg;
+  gptr<const cx<T>> Gw = (gptr<const cx<T>>)(G + (long long)(off / 16) * KP * 64);
+  const cx<T>* none[NR];
+#pragma unroll
+  for (int v = 0; v < NR; ++v) none[v] = nullptr;
+  if (wv == 0) {
+    SegSrc<Src> ss[NR] = {SegSrc<Src>{src[0], 0, len}, SegSrc<Src>{src[NR - 1], 0, len}};
+    SegDst<T, Dst> sd[NR] = {SegDst<T, Dst>{dst[0], 0}, SegDst<T, Dst>{dst[NR - 1], 0}};
+    solve_blocked_n<T, KP, U, NB, NR>(ss, sd, Gw, len, K, ring, none, lane);
+    if (nseg > 1 && lane < K) {
+#pragma unroll
+      for (int v = 0; v < NR; ++v) yt[64 * P * v + lane] = ring[640 * v + ((len - K + lane) & 255)];
+    }
+  } else if (wv < nseg - 1) {
+    SegSrc<Src> ss[NR] = {SegSrc<Src>{src[0], off, len}, SegSrc<Src>{src[NR - 1], off, len}};
+    DstTail<T> tl[NR] = {DstTail<T>{yt + 64 * wv, len, K}, DstTail<T>{yt + 64 * P * (NR - 1) + 64 * wv, len, K}};
+    solve_blocked_n<T, KP, U, NB, NR>(ss, tl, Gw, len, K, ring, none, lane);
+  }
+  if (nseg == 1) return;
+  __syncthreads();
+  constexpr int KM = map_dim(KP);
+  const int nT = (nseg - 2) * KM * KM;
+  gptr<const cx<T>> Tg = (gptr<const cx<T>>)Tm;
+  for (int e0 = 0; e0 < nT; e0 += 8 * nthr) {
+    cx<T> v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nthr + tid;
+      v[q] = ld<T>(Tg, e < nT ? e : nT - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nthr + tid;
+      if (e < nT) work[e] = v[q];
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {
+    for (int s = 1; s < nseg; ++s) {
+#pragma unroll
+      for (int v = 0; v < NR; ++v) {
+        cx<T>* ytv = yt + 64 * P * v;
+        cx<T>* sttv = stt + 64 * P * v;
+        const cx<T> y = lane < K ? ytv[64 * (s - 1) + lane] : mk((T)0, (T)0);
+        sttv[64 * s + lane] =
+            s >= 2 ? map_apply<T, KM>(work + (s - 2) * KM * KM, sttv + 64 * (s - 1), y, K, lane) : y;
+      }
+    }
+  }
+  __syncthreads();
+  if (wv >= 1 && wv < nseg) {
+    SegSrc<Src> ss[NR] = {SegSrc<Src>{src[0], off, len}, SegSrc<Src>{src[NR - 1], off, len}};
+    SegDst<T, Dst> sd[NR] = {SegDst<T, Dst>{dst[0], off}, SegDst<T, Dst>{dst[NR - 1], off}};
+    const cx<T>* st0[NR] = {stt + 64 * wv, stt + 64 * P * (NR - 1) + 64 * wv};
+    solve_blocked_n<T, KP, U, NB, NR>(ss, sd, Gw, len, K, ring, st0, lane);
+  }
+}
+
 // Transmission data of strip s, node lines l = 0..n-1, into LDS (all
 // threads of the workgroup): gl1 = Gamma_{s,1} data where has1 (forward:
 // formed from the current z and, if keep, stored to g1 for the backward
@@ -870,6 +1079,77 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
       const DstScatter<T> out{z, ns, w, n, a, dir, winv};
       for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(rho, q));
     }
+    __syncthreads();
+  }
+}
+
+// k_sweep for tiles of NR = 2 right-hand sides of the same preconditioner
+// (unpivoted strips, segment plan 0): task t carries its two chains in ch and
+// ch2 (the same strips and sweep mode; a tile of one repeats its chain in
+// ch2, whose identical stores are harmless).  Dynamic LDS (complex elements):
+// two node lines of transmission data per right-hand side, yt and stt (64 P
+// each per right-hand side), then the work area max(640 P NR, (P - 2) KM^2).
+template <class T, int KP, int U, int NB>
+__global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ tasks) {
+  constexpr int NR = 2;
+  extern __shared__ char smem_raw[];
+  const SweepTask& tk = tasks[blockIdx.x];
+  const int nthr = blockDim.x;
+  const int P = nthr >> 6;
+  const int n = uni(tk.n), N = uni(tk.N);
+  cx<T>* gl = reinterpret_cast<cx<T>*>(smem_raw);  // gl1, gl2 of v at gl + 2 n v
+  cx<T>* yt = gl + 2 * n * NR;
+  cx<T>* stt = yt + 64 * P * NR;
+  cx<T>* work = stt + 64 * P * NR;
+  const cx<T>* img = uniptr((const cx<T>*)tk.img);
+  const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
+  const SweepChain* chs[NR] = {&tk.ch, &tk.ch2};
+  gptr<cx<T>> z[NR], rho[NR], g1[NR];
+  gptr<const c128> r[NR];
+#pragma unroll
+  for (int v = 0; v < NR; ++v) {
+    z[v] = (gptr<cx<T>>)uniptr((cx<T>*)chs[v]->z);
+    rho[v] = (gptr<cx<T>>)uniptr((cx<T>*)chs[v]->rho);
+    g1[v] = (gptr<cx<T>>)uniptr((cx<T>*)chs[v]->g1);
+    r[v] = (gptr<const c128>)uniptr(chs[v]->r);
+  }
+  const StripDesc* strips = uniptr(tk.ch.strips);
+  const int mode = uni(tk.mode);
+  const int nsteps = sweep_steps(mode, N);
+  for (int step = 0; step < nsteps; ++step) {
+    const SweepStep ss = sweep_step(mode, N, step);
+    const bool fwd = ss.fwd;
+    const int s = ss.s;
+    const StripDesc* sp = strips + s;
+    const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
+    const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
+    const long long img_off = uni(sp->img_off);
+    const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
+    const bool use1 = has1 && ss.data1;
+    const bool use2 = has2 && ss.data2;
+#pragma unroll
+    for (int v = 0; v < NR; ++v)
+      strip_data<T>(gl + 2 * n * v, gl + 2 * n * v + n, z[v], g1[v], trb, s, n, a, w, dir, use1, use2,
+                    fwd, ss.keep, t1off, t2off);
+    __syncthreads();
+    const float winv = 1.0f / (float)w;
+    const SrcGather<T> gather[NR] = {
+        SrcGather<T>{r[0], gl, gl + n, ns, w, n, a, dir, use1, use2, winv},
+        SrcGather<T>{r[1], gl + 2 * n, gl + 3 * n, ns, w, n, a, dir, use1, use2, winv}};
+    const int seg = uni(sp->seg);
+    const cx<T>* GL = img + img_off;
+    const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
+    constexpr long long KM2 = (long long)map_dim(KP) * map_dim(KP);
+    const cx<T>* TL = img + uni(sp->t_off) + uni(sp->pmap[0]) * KM2;
+    const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
+    const DstVec<T> drho[NR] = {DstVec<T>{rho[0], ns, false}, DstVec<T>{rho[1], ns, false}};
+    solve_triangle_n<T, KP, U, NB, NR>(gather, drho, GL, TL, ns, kl, seg, work, yt, stt);
+    __syncthreads();
+    const SrcVec<T> srho[NR] = {SrcVec<T>{(gptr<const cx<T>>)rho[0], ns, true},
+                                SrcVec<T>{(gptr<const cx<T>>)rho[1], ns, true}};
+    const DstScatter<T> dz[NR] = {DstScatter<T>{z[0], ns, w, n, a, dir, winv},
+                                  DstScatter<T>{z[1], ns, w, n, a, dir, winv}};
+    solve_triangle_n<T, KP, U, NB, NR>(srho, dz, GU, TU, ns, kl, seg, work, yt, stt);
     __syncthreads();
   }
 }
@@ -1401,6 +1681,7 @@ static long long wide_capacity(int KP, int P, int nmax) {
 bool sweep_plan_fits(int plan, int ntasks, int precision, int KP, int P, int kmax, int nmax,
                      bool pivots, bool built) {
   if (plan == 0) return true;
+  if (plan == HH_PLAN_TILE) return ntasks >= 2 && sweep_tiles_fit(precision, KP, P, nmax, pivots);
   if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return false;
   if (KP != 8 && KP != 10 && KP != 12) return false;
   if (plan == HH_PLAN_PAIR && !built) return false;
@@ -1408,11 +1689,19 @@ bool sweep_plan_fits(int plan, int ntasks, int precision, int KP, int P, int kma
 }
 
 int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built) {
+  const char* tenv = std::getenv("HH_SWEEP_PLAN");
+  if (tenv && std::atoi(tenv) == HH_PLAN_TILE)
+    return sweep_plan_fits(HH_PLAN_TILE, ntasks, precision, blocked_kp(kmax), P, kmax, nmax,
+                           pivots, true)
+               ? HH_PLAN_TILE
+               : 0;
   if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
   const int KP = blocked_kp(kmax);
   const char* env = std::getenv("HH_SWEEP_PLAN");
   if (env && *env) {
     const int p = std::atoi(env);
+    if (p == HH_PLAN_TILE)
+      return sweep_plan_fits(p, ntasks, precision, KP, P, kmax, nmax, pivots, true) ? p : 0;
     if (p == HH_PLAN_PAIR)
       return sweep_plan_fits(p, ntasks, precision, KP, P, kmax, nmax, pivots, true) ? p : 0;
     return p > 0 && sweep_plan_fits(HH_PLAN_WIDE, ntasks, precision, KP, P, kmax, nmax, pivots,
@@ -1453,11 +1742,55 @@ static void launch_wide(const SweepTask* d, int ntasks, int KP, int P, int nmax,
   }
 }
 
+// Tiles of two right-hand sides (k_sweep_n): complex64 strips with the
+// one-workgroup plan's segments, when the workgroup's LDS fits.
+static size_t tile_lds_bytes(int P, int KP, int nmax) {
+  constexpr int NR = 2;
+  const long long KM = map_dim(KP);
+  const long long work = std::max(640LL * P * NR, (long long)std::max(P - 2, 0) * KM * KM);
+  return (size_t)(2LL * nmax * NR + 2LL * 64 * P * NR + work) * sizeof(c64);
+}
+
+bool sweep_tiles_fit(int precision, int KP, int P, int nmax, bool pivots) {
+  return precision == HH_FP32 && !pivots && (KP == 8 || KP == 10 || KP == 12 || KP == 16) &&
+         tile_lds_bytes(P, KP, nmax) <= 160 * 1024;
+}
+
+template <int KP>
+static void launch_tiles_kp(const SweepTask* d, int ntiles, int P, int nmax, hipStream_t st) {
+  using Sh = SweepShape<float, KP>;
+  const void* fn = (const void*)k_sweep_n<float, KP, Sh::U, 2>;
+  const size_t lds = tile_lds_bytes(P, KP, nmax);
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_sweep_n<float, KP, Sh::U, 2>), dim3(ntiles), dim3(64 * P), lds, st, d);
+}
+
+void launch_sweep_tiles(const SweepTask* d_tiles, int ntiles, int precision, int KP, int P,
+                        int nmax, bool pivots, hipStream_t st) {
+  if (ntiles <= 0) return;
+  if (!sweep_tiles_fit(precision, KP, P, nmax, pivots) || P < 1 || P > 8) {
+    set_error("right-hand-side tiles do not fit this factorisation");
+    throw ArgError();
+  }
+  switch (KP) {
+    case 8: launch_tiles_kp<8>(d_tiles, ntiles, P, nmax, st); break;
+    case 10: launch_tiles_kp<10>(d_tiles, ntiles, P, nmax, st); break;
+    case 12: launch_tiles_kp<12>(d_tiles, ntiles, P, nmax, st); break;
+    default: launch_tiles_kp<16>(d_tiles, ntiles, P, nmax, st); break;
+  }
+  HH_HIP(hipGetLastError());
+}
+
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
                   int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st) {
   if (ntasks <= 0) return;
   if (P < 1 || P > 8) {
     set_error("unsupported segment count %d", P);
+    throw ArgError();
+  }
+  if (plan == HH_PLAN_TILE) {
+    set_error("tiles of right-hand sides are launched with launch_sweep_tiles");
     throw ArgError();
   }
   if (plan < 0 || plan >= HH_NPLAN || (plan > 0 && (pivots || !abort))) {

@@ -1,7 +1,7 @@
 // Autotuner of the sweep's segment plan.
 //
 // A sweep launch can run on one, two or sixteen workgroups per chain (plans
-// 0, 2, 1).  Which is fastest depends on the strips (band half-width, rows),
+// 0, 2, 1), or on one workgroup per tile of two right-hand sides (choice 3).  Which is fastest depends on the strips (band half-width, rows),
 // the number of chains in the launch and the device, so the engine measures
 // every plan that fits a launch the first time it meets a launch of that
 // shape, keeps the fastest, and reuses it for every later launch of the same
@@ -55,10 +55,10 @@ bool load_locked(const char* path) {
     TuneEntry e{};
     const int n = std::sscanf(text.c_str() + pos,
                               "{\"precision\": %d, \"KP\": %d, \"P\": %d, \"kmax\": %d, \"n\": %d, "
-                              "\"N\": %d, \"chains\": %d, \"plan\": %d, \"ms\": [%lf, %lf, %lf]",
+                              "\"N\": %d, \"chains\": %d, \"plan\": %d, \"ms\": [%lf, %lf, %lf, %lf]",
                               &k.prec, &k.KP, &k.P, &k.kmax, &k.n, &k.N, &k.chains, &e.plan,
-                              &e.ms[0], &e.ms[1], &e.ms[2]);
-    if (n == 11 && e.plan >= 0 && e.plan < HH_NPLAN) {
+                              &e.ms[0], &e.ms[1], &e.ms[2], &e.ms[3]);
+    if (n == 12 && e.plan >= 0 && e.plan < HH_NCHOICE) {
       g_table[k] = e;
       ++loaded;
     }
@@ -77,9 +77,9 @@ bool save_locked(const char* path) {
     const TuneEntry& e = kv.second;
     std::fprintf(f,
                  "  {\"precision\": %d, \"KP\": %d, \"P\": %d, \"kmax\": %d, \"n\": %d, \"N\": %d, "
-                 "\"chains\": %d, \"plan\": %d, \"ms\": [%.6f, %.6f, %.6f]}%s\n",
+                 "\"chains\": %d, \"plan\": %d, \"ms\": [%.6f, %.6f, %.6f, %.6f]}%s\n",
                  k.prec, k.KP, k.P, k.kmax, k.n, k.N, k.chains, e.plan, e.ms[0], e.ms[1], e.ms[2],
-                 ++i < g_table.size() ? "," : "");
+                 e.ms[3], ++i < g_table.size() ? "," : "");
   }
   std::fprintf(f, "]}\n");
   return std::fclose(f) == 0;

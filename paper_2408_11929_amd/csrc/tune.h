@@ -16,11 +16,11 @@ struct TuneKey {
   }
 };
 
-// The plan chosen for a shape and the measured launch times of plans 0, 1, 2
-// (milliseconds; 0 for a plan that did not fit).
+// The choice kept for a shape (a segment plan 0, 1, 2, or HH_PLAN_TILE) and
+// the measured launch time of each choice (milliseconds; 0 where it did not fit).
 struct TuneEntry {
   int plan = 0;
-  double ms[HH_NPLAN] = {0, 0, 0};
+  double ms[HH_NCHOICE] = {0, 0, 0, 0};
 };
 
 int tune_bucket(int chains);

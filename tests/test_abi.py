@@ -59,9 +59,9 @@ def test_tune_choices_round_trip_through_json(tmp_path):
     lib = _lib.load()
     src = tmp_path / "tune_in.json"
     entries = [{"precision": 1, "KP": 10, "P": 8, "kmax": 24, "n": 321, "N": 16, "chains": 128,
-                "plan": 2, "ms": [5.4, 0.0, 3.5]},
+                "plan": 2, "ms": [5.4, 0.0, 3.5, 5.9]},
                {"precision": 1, "KP": 12, "P": 8, "kmax": 29, "n": 801, "N": 32, "chains": 16,
-                "plan": 1, "ms": [37.0, 5.1, 21.6]}]
+                "plan": 1, "ms": [37.0, 5.1, 21.6, 30.2]}]
     src.write_text(json.dumps({"entries": entries}))
     assert lib.hh_tune_clear() == 0
     assert lib.hh_tune_load(str(src).encode()) == 0

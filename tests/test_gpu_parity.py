@@ -142,12 +142,13 @@ def test_strip_solves_match_lapack(n, N, omega, c, prec, lu, monkeypatch):
     pb.free()
 
 
-@pytest.mark.parametrize("plan", ["0", "1", "2"])
+@pytest.mark.parametrize("plan", ["0", "1", "2", "3"])
 @pytest.mark.parametrize("prec", [hh.HH_FP64, hh.HH_FP32])
 @pytest.mark.parametrize("n,N,omega,c", CASES + WIDE + NARROW + PIVOTING)
 def test_sweeps_match_oracle(n, N, omega, c, prec, plan, monkeypatch):
     # plan 0: one workgroup per chain; plan 1: sixteen, plan 2: two (complex64
-    # strips that did not pivot, where the workgroups fit; else plan 0 again)
+    # strips that did not pivot, where the workgroups fit; else plan 0 again);
+    # 3: plan 0 with both vectors in one tile
     monkeypatch.setenv("HH_SWEEP_PLAN", plan)
     pb = hh.Problem(omega, c, n)
     pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
@@ -165,6 +166,40 @@ def test_sweeps_match_oracle(n, N, omega, c, prec, plan, monkeypatch):
             else:
                 check_fp32(z[v], zr, S32.apply(r[v]), f"sweep n={n} N={N} {dname} v{v} plan={plan}",
                            cond=cond)
+    pb.free()
+
+
+@pytest.mark.parametrize("nvec", [2, 3, 5])
+@pytest.mark.parametrize("n,N,omega,c", CASES + WIDE[:1] + NARROW[:1])
+def test_tiles_are_bitwise_plan0(n, N, omega, c, nvec, monkeypatch):
+    # tiles of two right-hand sides (a last single vector repeated) give
+    # exactly the one-workgroup plan's results, vector by vector
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP32)
+    r = dev(rand((nvec, n * n), 30 + nvec))
+    out = {}
+    for plan in ("0", "3"):
+        monkeypatch.setenv("HH_SWEEP_PLAN", plan)
+        out[plan] = [host(pb.precond_apply(k, r)) for k in ("LRL", "BTB", "RL")]
+    for a, b in zip(out["0"], out["3"]):
+        assert np.array_equal(a, b), np.abs(a - b).max()
+    pb.free()
+
+
+def test_mpgmres_with_tiles_is_bitwise_plan0(monkeypatch):
+    n, N, omega, c = 64, 9, 30.0, [2.2, 1.1, 1.7, 2.9, 1.3]
+    pb = hh.Problem(omega, c, n)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP32)
+    pos = wl.source_positions(21, 5)
+    b = pb.load_vector(dev(np.stack([wl.gaussian_field(n, x0, y0, 0.03) for x0, y0 in pos])))
+    res = {}
+    for plan in ("0", "3"):
+        monkeypatch.setenv("HH_SWEEP_PLAN", plan)
+        x, st, rc = pb.mpgmres(b, tol=1e-8, maxit=100)
+        assert rc == hh.HH_OK
+        res[plan] = (host(x), [s["iterations"] for s in st])
+    assert res["0"][1] == res["3"][1]
+    assert np.array_equal(res["0"][0], res["3"][0])
     pb.free()
 
 
