@@ -275,9 +275,8 @@ def main():
     lat64, st64 = timed_steps(hh, torch, cfg, f_dev, hh.HH_FP64, args.steps)
     wall64 = time.perf_counter() - t0
 
-    batched = None
-    if not args.no_batch:
-        bcfg = wl.layered_321_batch(64)
+    def batch_run(nsrc):
+        bcfg = wl.layered_321_batch(nsrc)
         fb = torch.from_numpy(bcfg.f()).to("cuda")
         one_solve(hh, torch, bcfg, fb, hh.HH_FP32)  # warmup: tunes the batch's launch shape
         hh.hh_timing_enable(True)
@@ -289,15 +288,21 @@ def main():
         tb = time.perf_counter() - tb
         kb = {k: hh.hh_timing_get(k) for k in ("sweep", "spmv", "factor", "orth")}
         hh.hh_timing_enable(False)
-        batched = {"workload": bcfg.name, "rhs": 64, "seconds": tb, "solves_per_s": 64 / tb,
-                   "iterations_max": max(s["iterations"] for s in stb),
-                   "res_true_max": max(s["res_true"] for s in stb),
-                   "all_converged": all(s["converged"] for s in stb),
-                   "kernel_ms": {k: v["ms"] for k, v in kb.items()},
-                   # algorithmic HBM rates of the batch's sweeps and sparse products (GB/s)
-                   "hbm_gbs": {k: kb[k]["bytes"] / 1e6 / kb[k]["ms"] if kb[k]["ms"] > 0 else 0.0
-                               for k in ("sweep", "spmv")}}
-        batched["hbm_frac"] = {k: v / HBM_PEAK_GBS for k, v in batched["hbm_gbs"].items()}
+        out = {"workload": bcfg.name, "rhs": nsrc, "seconds": tb, "solves_per_s": nsrc / tb,
+               "iterations_max": max(s["iterations"] for s in stb),
+               "res_true_max": max(s["res_true"] for s in stb),
+               "all_converged": all(s["converged"] for s in stb),
+               "kernel_ms": {k: v["ms"] for k, v in kb.items()},
+               # algorithmic HBM rates of the batch's sweeps and sparse products (GB/s)
+               "hbm_gbs": {k: kb[k]["bytes"] / 1e6 / kb[k]["ms"] if kb[k]["ms"] > 0 else 0.0
+                           for k in ("sweep", "spmv")}}
+        out["hbm_frac"] = {k: v / HBM_PEAK_GBS for k, v in out["hbm_gbs"].items()}
+        return out
+
+    batched = batched_256 = None
+    if not args.no_batch:
+        batched = batch_run(64)
+        batched_256 = batch_run(256)
 
     serving = None if args.no_serve else serving_run(hh, torch)
 
@@ -343,6 +348,7 @@ def main():
         "speedup_vs_plain_fp64": (args.steps / wall32) / (args.steps / wall64),
         "speedup_equal_plan": equal_plan,
         "batched": batched,
+        "batched_256": batched_256,
         "serving": serving,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in
                                (("sweep", sweep), ("spmv", spmv), ("factor", factor),

@@ -422,7 +422,12 @@ void Engine::step(std::vector<Solve*>& solves) {
       const int nt = (int)k.tasks.size();
       k.plan = 0;
       k.tune = false;
-      if (wide_ok_) {
+      if (!wide_ok_) {
+        // plan 0's results whatever the mix: plan 0, or its tiles (the same
+        // bits) when the chains outnumber the compute units
+        const int p = sweep_plan_for(nt, k.prec, k.P, k.kmax, k.nmax, k.piv, false);
+        k.plan = p == HH_PLAN_TILE ? p : 0;
+      } else {
         k.key = TuneKey{k.prec, k.KP, k.P, k.kmax, k.nmax, k.pbs[0]->fs.N, tune_bucket(nt)};
         int p = 0;
         if (!std::getenv("HH_SWEEP_PLAN") && tune_lookup(k.key, p) &&
@@ -497,6 +502,12 @@ void Engine::step(std::vector<Solve*>& solves) {
       tl.ch2 = pair ? k.tasks[order[i + 1]].ch : tl.ch;
       tiles[q].push_back(tl);
       i += pair ? 2 : 1;
+    }
+    // a rule-based choice of tiles needs pairs: with few of them the repeated
+    // singles would cost more than plan 0's second round
+    if (k.plan == HH_PLAN_TILE && !k.tune && tiles[q].size() * 4 > k.tasks.size() * 3) {
+      k.plan = 0;
+      tiles[q].clear();
     }
   }
   std::vector<SweepTask*> dsw(kinds.size()), dtl(kinds.size(), nullptr);

@@ -357,10 +357,12 @@ void launch_sweep_tiles(const SweepTask* d_tiles, int ntiles, int precision, int
 // Whether the wide plan can run a factorisation (complex64 strips, band
 // half-width at most 31, at most two workgroup tails per wave, LDS).
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
-// Plan for a launch of ntasks chains: plan 0 where some strip pivoted, the
-// wide plan's maps were not built (built = false) or it cannot run, else the
-// HH_SWEEP_PLAN environment variable (0 or 1) when set, else the wide plan
-// while ntasks times its width is at most half the compute units.
+// Choice for a launch of ntasks chains (without a tuned one): the
+// HH_SWEEP_PLAN environment variable (0-3) when set and possible; else the
+// sixteen-workgroup plan while ntasks times sixteen is at most half the
+// compute units, the two-workgroup plan while its workgroups fit the device
+// at once (built: its maps exist), tiles of two right-hand sides beyond one
+// chain per compute unit, and plan 0 otherwise (always where a strip pivoted).
 int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built);
 // Whether plan p can run a launch of ntasks chains: plan 0 always; plans 1
 // and 2 on complex64 strips none of which pivoted (sweep_wide_fits), when all

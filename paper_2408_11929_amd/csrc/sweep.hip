@@ -1695,7 +1695,12 @@ int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pi
                            pivots, true)
                ? HH_PLAN_TILE
                : 0;
-  if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return 0;
+  // more chains than compute units: plan 0 would take two rounds of
+  // workgroups, tiles of two right-hand sides take one (same results)
+  const int KPt = blocked_kp(kmax);
+  const bool many = ntasks > wide_dev().cus &&
+                    sweep_plan_fits(HH_PLAN_TILE, ntasks, precision, KPt, P, kmax, nmax, pivots, true);
+  if (pivots || !sweep_wide_fits(precision, P, kmax, nmax)) return many ? HH_PLAN_TILE : 0;
   const int KP = blocked_kp(kmax);
   const char* env = std::getenv("HH_SWEEP_PLAN");
   if (env && *env) {
@@ -1710,8 +1715,13 @@ int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pi
                : 0;
   }
   // a few chains: sixteen workgroups each while they take at most half the
-  // device; more chains: plan 0 (see sweep_tuned for measured choices)
-  return (long long)ntasks * plan_width(HH_PLAN_WIDE) <= wide_dev().cus / 2 ? HH_PLAN_WIDE : 0;
+  // device; up to one chain per two compute units: two workgroups each; more:
+  // plan 0, or its tiles beyond one chain per compute unit (the autotuner
+  // measures instead where it is on)
+  if ((long long)ntasks * plan_width(HH_PLAN_WIDE) <= wide_dev().cus / 2) return HH_PLAN_WIDE;
+  if (built && sweep_plan_fits(HH_PLAN_PAIR, ntasks, precision, KP, P, kmax, nmax, pivots, true))
+    return HH_PLAN_PAIR;
+  return many ? HH_PLAN_TILE : 0;
 }
 
 template <int KP>
