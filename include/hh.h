@@ -39,7 +39,7 @@ extern "C" {
 #define HH_PENDING 1
 #define HH_EINVAL (-1)     /* invalid argument or state                      */
 #define HH_ENOMEM (-2)     /* device memory allocation failed                */
-#define HH_ESINGULAR (-3)  /* zero pivot in a strip factorisation            */
+#define HH_ESINGULAR (-3)  /* zero or non-finite pivot in a strip factorisation */
 #define HH_ENOCONV (-4)    /* MPGMRES hit maxit before reaching the tolerance */
 #define HH_EDEVICE (-5)    /* HIP runtime error                              */
 #define HH_EBUDGET (-6)    /* request can never fit the server's HBM budget  */
@@ -140,10 +140,19 @@ int hh_load_vector(hh_problem* pb, int nvec, const hh_c128* f, hh_c128* b);
  * previous factorisation of the handle.
  *   dirs       HH_DIR_X, HH_DIR_Y or both; with both, the preconditioner order
  *              is M_1 = LRL, M_2 = BTB (the ordered combination of Sec. 4)
- *   nstrips    N >= 1 with (n-1) % N == 0 and (n-1)/N >= 2 when N > 1
+ *   nstrips    N >= 1 with (n-1) % N == 0 and (n-1)/N >= 2 when N > 1; the
+ *              band half-width of a strip, kl = (strip width in node lines)
+ *              + 1, must be at most 191.  Up to kl = 63 the strips get the
+ *              one-wave LU and the blocked substitution with its segment plans;
+ *              wider strips (e.g. N = 4 and 8 at n = 513: kl = 132 and 68) are
+ *              factored by a blocked band LU whose trailing updates run on the
+ *              matrix cores and are swept by the lane-major substitution on
+ *              one wave per chain (one workgroup per chain, no tiles; the
+ *              server refuses them).
  *   precision  HH_FP64 or HH_FP32 (factors, transmission data and sweeps)
- * Errors: HH_EINVAL, HH_ENOMEM, HH_ESINGULAR (exactly zero pivot; the message
- * names the strip), HH_EDEVICE. */
+ * Errors: HH_EINVAL, HH_ENOMEM, HH_ESINGULAR (a zero pivot, or one that is not
+ * finite in the strip precision, as when omega / c is so large that strip
+ * entries overflow complex64; the message names the strip), HH_EDEVICE. */
 int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision);
 
 /* ---- preconditioner application: eqs. (2)-(4) -------------------------------
@@ -233,9 +242,23 @@ int hh_get_operator(const hh_problem* pb, hh_c128* diag);
  *   stats      host pointer to nrhs hh_stats (may be NULL)
  * The sweeps of every RHS and direction run in one launch per iteration, one
  * chain each, on one or sixteen workgroups per chain as in hh_sweep_apply.
- * Returns HH_ENOCONV (x and stats still filled) if any RHS did not converge. */
+ * Returns HH_ENOCONV (x and stats still filled) if any RHS did not converge,
+ * HH_EINVAL if one holds a NaN or Inf (see hh_mpgmres_x0). */
 int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit,
                hh_c128* x, hh_stats* stats);
+
+/* hh_mpgmres from a starting guess x0 (Sec. 3 with a non-zero initial
+ * iterate): the Krylov space is built on r0 = b - A x0 (FP64), the result is
+ * x = x0 + Z y, and the stopping test and the reported residuals stay relative
+ * to ||b||_2, so that a solve resumed from a saved x stops where an
+ * uninterrupted one would.  x0 is a device pointer of nrhs x n*n hh_c128 or
+ * NULL (= hh_mpgmres); it may be the same array as x (resume in place) but
+ * must not overlap it otherwise.  A right-hand side with b = 0 gets x = 0;
+ * one whose b or A x0 holds a NaN or Inf is not iterated (x = x0, or 0, and
+ * res_true = NaN) and the call returns HH_EINVAL naming it, after the
+ * others are solved (hh_mpgmres does the same). */
+int hh_mpgmres_x0(hh_problem* pb, int nrhs, const hh_c128* b, const hh_c128* x0, double tol,
+                  int maxit, hh_c128* x, hh_stats* stats);
 
 /* Releases the handle and all its device memory.  NULL is accepted. */
 int hh_free(hh_problem* pb);

@@ -176,9 +176,10 @@ class Problem:
         _check(lib().hh_spmv(self.handle, nvec, _dev(x, "x"), _dev(y, "y")))
         return y
 
-    def mpgmres(self, b, tol=1e-6, maxit=200, x=None):
+    def mpgmres(self, b, tol=1e-6, maxit=200, x=None, x0=None):
         """Returns (x, stats, rc) with stats a list of dicts, rc HH_OK or HH_ENOCONV.
-        b None: the right-hand side given to from_field."""
+        b None: the right-hand side given to from_field.  x0: starting guess of
+        b's shape (hh_mpgmres_x0); it may be x itself to resume in place."""
         import torch
         nrhs = 1 if b is None else (b.shape[0] if b.dim() == 2 else 1)
         if x is None:
@@ -187,8 +188,11 @@ class Problem:
         st = (_lib.hh_stats * nrhs)()
         _sync()
         bp = None if b is None else _dev(b, "b")
-        rc = _check(lib().hh_mpgmres(self.handle, nrhs, bp, float(tol), int(maxit),
-                                     _dev(x, "x"), st), allowed=(HH_OK, HH_ENOCONV))
+        if x0 is not None and x0.numel() != nrhs * self.n * self.n:
+            raise ValueError("x0 must hold one n*n vector per right-hand side")
+        x0p = None if x0 is None else _dev(x0, "x0")
+        rc = _check(lib().hh_mpgmres_x0(self.handle, nrhs, bp, x0p, float(tol), int(maxit),
+                                        _dev(x, "x"), st), allowed=(HH_OK, HH_ENOCONV))
         stats = [{k: getattr(s, k) for k, _ in _lib.hh_stats._fields_} for s in st]
         return x, stats, rc
 

@@ -97,6 +97,7 @@ PROTOTYPES = {
     "hh_spmv": (I, [P, I, P, P]),
     "hh_get_operator": (I, [P, P]),
     "hh_mpgmres": (I, [P, I, P, D, I, P, ctypes.POINTER(hh_stats)]),
+    "hh_mpgmres_x0": (I, [P, I, P, P, D, I, P, ctypes.POINTER(hh_stats)]),
     "hh_free": (I, [P]),
     "hh_last_error": (ctypes.c_char_p, []),
     "hh_timing_enable": (I, [I]),

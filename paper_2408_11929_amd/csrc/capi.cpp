@@ -123,12 +123,15 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
     const int a = std::max(0, s * m - 1), b = std::min(n - 1, (s + 1) * m + 1);
     kl_max = std::max(kl_max, b - a + 2);
   }
-  REQUIRE(kl_max <= 63, "strip band half-width %d exceeds 63 (strips too wide)", kl_max);
-  const int S = 2 * kl_max + 1 <= 64 ? 1 : 2;
+  REQUIRE(kl_max <= HH_KL_MAX, "strip band half-width %d exceeds %d (strips too wide)", kl_max,
+          HH_KL_MAX);
+  const bool lane_major = kl_max > HH_KL_WINDOW;  // blocked MFMA LU, lane-major substitution
+  const int SL = lane_major ? lane_slots(kl_max) : 1;
+  const int S = lane_major ? 2 * SL : 2 * kl_max + 1 <= 64 ? 1 : 2;
   const int P = sweep_segments(map_dim(blocked_kp(kl_max)), n,
                                precision == HH_FP64 ? sizeof(c128) : sizeof(c64));
   // the wide segment plan's maps are built only where that plan can run
-  const bool wide = sweep_wide_fits(precision, P, kl_max, n);
+  const bool wide = !lane_major && sweep_wide_fits(precision, P, kl_max, n);
   for (int i = 0; i < fs.nd; ++i) {
     for (int s = 0; s < N; ++s) {
       StripDesc sd{};
@@ -143,6 +146,7 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       sd.has1 = s > 0;
       sd.has2 = s < N - 1;
       sd.S = S;
+      sd.SL = SL;
       sd.KP = blocked_kp(kl_max);
       sd.gid = (int)fs.strips.size();
       const long long NP = sd.ns + HH_PAD;
@@ -151,7 +155,7 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       sd.segs = P;
       sd.wide = wide;
       plan_layout(sd);
-      for (int p = 0; p < HH_NPLAN; ++p)
+      for (int p = 0; p < HH_NPLAN && !lane_major; ++p)
         REQUIRE(sd.pseg[p] >= sd.kl, "segment of %d rows is shorter than the band half-width %d",
                 sd.pseg[p], sd.kl);
       sd.img_off = img;
@@ -217,7 +221,8 @@ int factor_finish(hh_problem* pb) {
   fs.any_pivot = std::any_of(fs.h_pflag.begin(), fs.h_pflag.end(), [](int f) { return f != 0; });
   if (fs.h_err[0]) {
     const StripDesc& sd = fs.strips[fs.h_err[0] - 1];
-    set_error("zero pivot in the LU of strip %d of direction %c", sd.s + 1, sd.dir == 0 ? 'x' : 'y');
+    set_error("zero or non-finite pivot in the LU of strip %d of direction %c (in complex%d)", sd.s + 1,
+              sd.dir == 0 ? 'x' : 'y', fs.precision == HH_FP64 ? 128 : 64);
     return HH_ESINGULAR;
   }
   return HH_OK;
@@ -676,6 +681,11 @@ int hh_get_operator(const hh_problem* pb, hh_c128* diag) {
 
 int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit, hh_c128* x,
                hh_stats* stats) {
+  return hh_mpgmres_x0(pb, nrhs, b, nullptr, tol, maxit, x, stats);
+}
+
+int hh_mpgmres_x0(hh_problem* pb, int nrhs, const hh_c128* b, const hh_c128* x0, double tol,
+                  int maxit, hh_c128* x, hh_stats* stats) {
   return guard([&]() {
     REQUIRE(pb && x && nrhs >= 0, "invalid arguments");
     if (!b) {
@@ -695,6 +705,7 @@ int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit
       s.pb = pb;
       s.b = (const c128*)b + r * len;
       s.x = (c128*)x + r * len;
+      s.x0 = x0 ? (const c128*)x0 + r * len : nullptr;
       s.len = len;
       s.tol = tol;
       s.maxit = maxit;
@@ -715,9 +726,11 @@ int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit
       for (Solve* s : ptr) Engine::release(s);
       throw;
     }
+    int bad = -1;
     for (int r = 0; r < nrhs; ++r) {
       Solve& s = solves[r];
-      if (!s.converged) rc = HH_ENOCONV;
+      if (s.fail == HH_EINVAL && bad < 0) bad = r;
+      if (!s.converged && rc == HH_OK) rc = HH_ENOCONV;
       if (stats) {
         stats[r].iterations = s.k;
         stats[r].converged = s.converged ? 1 : 0;
@@ -727,6 +740,10 @@ int hh_mpgmres(hh_problem* pb, int nrhs, const hh_c128* b, double tol, int maxit
         stats[r].deflated = s.deflated;
       }
       Engine::release(&s);
+    }
+    if (bad >= 0) {
+      set_error("right-hand side %d (or b - A x0) is not finite: no iteration was run for it", bad);
+      return HH_EINVAL;
     }
     if (rc == HH_ENOCONV) set_error("MPGMRES did not reach the tolerance within maxit for some RHS");
     return rc;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <tuple>
 #include <type_traits>
 
@@ -296,17 +297,58 @@ void Engine::begin(std::vector<Solve*>& solves) {
     if (!s->rho) s->rho = dev_alloc((size_t)s->t * fs.max_ns * es + 256);
     if (!s->g1) s->g1 = dev_alloc((size_t)s->t * fs.N * s->pb->n * es + 256);
     if (s->t > 2 && !s->sumv) s->sumv = (c128*)dev_alloc((size_t)s->len * sizeof(c128));
-    HH_HIP(hipMemcpyAsync(s->V, s->b, (size_t)s->len * sizeof(c128), hipMemcpyDeviceToDevice, st_));
+    if (!s->x0)
+      HH_HIP(hipMemcpyAsync(s->V, s->b, (size_t)s->len * sizeof(c128), hipMemcpyDeviceToDevice, st_));
     live.push_back(s);
   }
   if (live.empty()) return;
   if (sync_) HH_HIP(hipMemsetAsync(sync_, 0, sizeof(unsigned), st_));  // clear a past abort
-  // beta^2 = b^H b into NR slot 0, then v1 = b / beta
   staged_ = 256;  // offset 0 is reserved so that no staged array aliases nullptr
-  std::vector<GramTask> gt;
-  std::vector<NormTask> nt;
   long long maxlen = 0;
   int maxblk = 1;
+  // with a starting guess: v1 = b - A x0 and ||b||^2 into the (still unused) G1 slot
+  std::vector<SpmvTask> sp0;
+  std::vector<ResTask> rt0;
+  std::vector<GramTask> gb;
+  for (Solve* s : live) {
+    maxlen = std::max(maxlen, s->len);
+    if (!s->x0) continue;
+    SpmvTask tk{};
+    tk.A = s->pb->d_A;
+    tk.x = s->x0;
+    tk.y = s->V;
+    tk.n = s->pb->n;
+    tk.nvec = 1;
+    sp0.push_back(tk);
+    rt0.push_back(ResTask{s->b, s->V, s->len});
+    HdLayout L(s->hcap, s->t);
+    GramTask g{};
+    g.X = s->b;
+    g.Y = s->b;
+    g.out = s->Hd + L.g1;
+    g.part = s->part;
+    g.len = s->len;
+    g.ldx = g.ldy = s->len;
+    g.ldo = 1;
+    g.px = 1;
+    g.ty = 1;
+    g.nblk = nblk_for(s->len, live.size());
+    maxblk = std::max(maxblk, g.nblk);
+    gb.push_back(g);
+  }
+  if (!sp0.empty()) {
+    SpmvTask* dsp = stage(sp0, staged_);
+    ResTask* drt = stage(rt0, staged_);
+    GramTask* dgb = stage(gb, staged_);
+    upload();
+    launch_spmv(DEV(dsp), (int)sp0.size(), maxlen, HH_FP64, st_);
+    launch_residual(DEV(drt), (int)rt0.size(), maxlen, st_);
+    launch_gram(DEV(dgb), (int)gb.size(), maxblk, 1, 1, st_);
+    staged_ = 256;
+  }
+  // beta^2 = v1^H v1 into NR slot 0, then v1 = v1 / beta
+  std::vector<GramTask> gt;
+  std::vector<NormTask> nt;
   for (Solve* s : live) {
     HdLayout L(s->hcap, s->t);
     GramTask g{};
@@ -342,18 +384,34 @@ void Engine::begin(std::vector<Solve*>& solves) {
   for (Solve* s : live) {
     HdLayout L(s->hcap, s->t);
     zd v;
+    zd bb(0.0, 0.0), v2(0.0, 0.0);
     HH_HIP(hipMemcpyAsync(&v, s->Hd + L.rd, sizeof(zd), hipMemcpyDeviceToHost, st_));
+    HH_HIP(hipMemcpyAsync(&v2, s->Hd + L.nr, sizeof(zd), hipMemcpyDeviceToHost, st_));
+    if (s->x0) HH_HIP(hipMemcpyAsync(&bb, s->Hd + L.g1, sizeof(zd), hipMemcpyDeviceToHost, st_));
     HH_HIP(hipStreamSynchronize(st_));
-    s->beta = v.real();
+    // the normalisation deflates a NaN norm to zero: the raw square tells
+    s->beta = std::isfinite(v2.real()) ? v.real() : v2.real();
+    s->bnorm = s->x0 ? (std::isfinite(bb.real()) ? std::sqrt(std::max(0.0, bb.real())) : bb.real())
+                     : s->beta;
   }
   for (Solve* s : live) {
     s->ls.init(s->beta);
     for (int i = 0; i < s->t; ++i) s->inputs[i] = 0;
     s->res_est = 1.0;
-    if (s->beta == 0.0) {
+    if (!std::isfinite(s->beta) || !std::isfinite(s->bnorm)) {
+      // a NaN or Inf in b (or in A x0): no iteration; x = 0 or x0
       s->done = true;
+      s->fail = HH_EINVAL;
+      s->res_est = std::numeric_limits<double>::quiet_NaN();
+    } else if (s->bnorm == 0.0) {
+      s->done = true;  // b = 0: x = 0 whatever x0
       s->converged = true;
       s->res_est = 0.0;
+      s->x0 = nullptr;
+    } else if (s->beta <= s->tol * s->bnorm) {
+      s->done = true;  // x0 (or x = 0 when tol >= 1) already meets the tolerance
+      s->converged = true;
+      s->res_est = s->beta / s->bnorm;
     }
   }
 }
@@ -838,7 +896,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     }
     s->k += 1;
     s->m += t;
-    s->res_est = s->ls.residual() / s->beta;
+    s->res_est = s->ls.residual() / s->bnorm;
     s->sum_input = false;
     if (s->res_est <= s->tol) {
       s->done = true;
@@ -881,6 +939,7 @@ void Engine::finish(std::vector<Solve*>& solves) {
     CombTask c{};
     c.Z = s->Z;
     c.y = s->ydev;
+    c.x0 = s->x0;
     c.x = s->x;
     c.len = s->len;
     c.ncols = nc;
@@ -935,7 +994,8 @@ void Engine::finish(std::vector<Solve*>& solves) {
   HH_HIP(hipStreamSynchronize(st_));
   for (size_t q = 0; q < fin.size(); ++q) {
     Solve* s = fin[q];
-    s->res_true = s->beta > 0 ? std::sqrt(std::max(0.0, nr[q].real())) / s->beta : 0.0;
+    s->res_true = s->bnorm > 0 ? std::sqrt(std::max(0.0, nr[q].real())) / s->bnorm : 0.0;
+    if (s->fail == HH_EINVAL) s->res_true = std::numeric_limits<double>::quiet_NaN();
     s->finalized = true;
   }
 }

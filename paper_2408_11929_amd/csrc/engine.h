@@ -50,13 +50,15 @@ struct Solve {
   hh_problem* pb = nullptr;
   const c128* b = nullptr;  // device
   c128* x = nullptr;        // device
+  const c128* x0 = nullptr; // device starting guess (nullptr: x0 = 0); may equal x
   long long len = 0;
   int t = 0;
   int prec = HH_FP64;
   double tol = 1e-6;
   int maxit = 200;
   // state
-  double beta = 0;
+  double beta = 0;   // ||b - A x0||_2, the Krylov space's starting norm
+  double bnorm = 0;  // ||b||_2: tolerances and reported residuals are relative to it
   int k = 0;        // completed iterations
   int m = 0;        // basis columns in use (1 + k t)
   int vcap = 0, zcap = 0;
@@ -75,7 +77,8 @@ struct Solve {
   bool sum_input = false; // the next sweeps read sumv (formed at the next step)
   LeastSquares ls;
   bool done = false, converged = false, breakdown = false, finalized = false;
-  int fail = 0;           // stopped early: HH_EBUDGET (growth refused) or HH_ENOMEM
+  int fail = 0;           // stopped early: HH_EBUDGET (growth refused), HH_ENOMEM, or
+                          // HH_EINVAL (b or b - A x0 not finite)
   void* owner = nullptr;  // the caller's tag (the server's request)
   int charged_its = 0;    // iterations of Krylov memory charged to the owner's budget
   int deflated = 0;

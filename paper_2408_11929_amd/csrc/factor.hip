@@ -15,7 +15,8 @@
 // After the elimination a second pass writes the "solve image" the sweep
 // kernels stream through, one 64-lane row per substitution step so that a step
 // is one coalesced load (NP = ns + HH_PAD steps, zero rows past the end):
-//   Lm[j][l]       multiplier L(j+c, j), c = (l - j) mod 64, if 1 <= c <= kl
+//   Lm[j][k][l]    multiplier L(j+c, j), c = 64 k + ((l - j) mod 64), if
+//                  1 <= c <= kl   (k < SL: one slot unless kl >= 64)
 //   Um[J][k][l]    U(j-c, j) / U(j, j) for column j = ns-1-J,
 //                  c = 64 k + ((l - J) mod 64), if 1 <= c <= 2 kl   (k < S)
 //   rd[J]          1 / U(j, j)
@@ -33,6 +34,13 @@ constexpr int LU_WAVES = 4;
 constexpr int LU_THREADS = 64 * LU_WAVES;
 constexpr int LU_ROWS = (63 + LU_WAVES - 1) / LU_WAVES;  // rows of the window per wave (kl <= 63)
 constexpr int LU_CH = 16;  // column steps per staged chunk of entering rows
+
+// A pivot the elimination cannot divide by: zero, not finite, or so large
+// that its squared modulus overflows the strip precision.
+template <class T>
+__device__ __forceinline__ bool bad_pivot(T pd) {
+  return !(pd > (T)0) || __builtin_isinf(pd);
+}
 
 template <class T>
 __device__ __forceinline__ void wave_argmax(T& v, int& idx) {
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(const StripDesc* __restr
       const int prp = prow(rp);
       const cx<T> pv = rdlc(val, rp);
       const T pd = pv.re * pv.re + pv.im * pv.im;
-      const bool singular = pd == (T)0;
+      const bool singular = bad_pivot(pd);
       const T ipd = singular ? (T)0 : (T)1 / pd;
       const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
       // multiplier of (new) row r, which is the old row 0 if r == rp
@@ -351,7 +359,7 @@ __global__ __launch_bounds__(64) void k_band_lu_w(const StripDesc* __restrict__ 
       }
       const cx<T> pv = rdlc(val, rp);
       const T pd = pv.re * pv.re + pv.im * pv.im;
-      const bool singular = pd == (T)0;
+      const bool singular = bad_pivot(pd);
       const T ipd = singular ? (T)0 : (T)1 / pd;
       const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
       const cx<T> v0 = rdlc(val, 0);
@@ -554,7 +562,7 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
 #pragma unroll
       for (int k = 0; k < R; ++k) lr[k] = colb[h * R + k];
       const T pd = pv.re * pv.re + pv.im * pv.im;
-      const T ipd = pd == (T)0 ? (T)0 : recip(pd);
+      const T ipd = bad_pivot(pd) ? (T)0 : recip(pd);
       const cx<T> ipv = mk(pv.re * ipd, -pv.im * ipd);
       // row k of the half loses L(k) u0 = col(k) (u0 / pivot): the pivot
       // column is zero in the rows that have not entered and past the matrix
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
       const T av = lane <= rmax ? cabs1(val) : (T)-1;
       // a running maximum, which the compiler keeps as one accumulator (an
       // OR of the steps' comparisons it would keep alive to the chunk end)
-      const T d = pd == (T)0 && j < ns ? (T)1 : av - cabs1(pv);
+      const T d = bad_pivot(pd) && j < ns ? (T)1 : av - cabs1(pv);
       badm = fmax(badm, d);
       if (lane >= 1 && lane <= rmax) ab[(long long)j * ldab + kv + lane] = val * ipv;
       if (h == 0 && act && col < ns && j < ns) ab[uoff + j] = a0;
@@ -602,6 +610,246 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
   }
 }
 
+// ---- wide bands (kl >= 64): blocked elimination with MFMA trailing updates
+//
+// Beyond the one-wave window of the kernels above, a strip is factored by a
+// blocked right-looking band LU (the same pivot rule and the same storage;
+// the multipliers of a column stay in the row order of its own step, so the
+// lane-major substitution applies the interchanges as it goes).  One
+// workgroup of four waves per strip:
+//   1. the panel of LU_NB columns j0.. and the rows j0 .. j0+LU_NB-1+kl that
+//      they reach are loaded to LDS and eliminated column by column
+//      (pivot search, interchange within the panel, multipliers, rank-1
+//      update of the panel's remaining columns);
+//   2. L11^{-1} (unit lower, LU_NB x LU_NB) is formed in LDS;
+//   3. the trailing columns j0+LU_NB .. j0+LU_NB-1+2kl (where U's fill can
+//      reach) go through LDS LU_NB at a time: the panel's interchanges in
+//      order, U12 = L11^{-1} A12 and A22 -= L21 U12, both products of 16 x 16
+//      complex tiles on the matrix cores (four real f64 16x16x4 MFMAs per
+//      complex step).
+// The elimination runs in FP64 for either storage precision: a complex64
+// strip is widened on load and its factors rounded once on store, so that
+// the explicit L11^{-1} and the blocked updates do not lose accuracy against
+// the column-by-column elimination (their complex64 rounding, step by step,
+// gave three times the solve error of LAPACK's on a kl = 131 strip).
+// Entries outside the band are zero in exact arithmetic (U's rows reach 2kl
+// columns past the diagonal, L's columns kl rows below it), so the loads
+// fill them with zeros and the stores skip them.
+constexpr int LU_NB = 16;
+
+template <class T>
+struct MfmaT;
+// Both take A as lane l = row l mod 16, k = l / 16 of a 4-wide k slice and B
+// as lane l = k l / 16, column l mod 16; the accumulator's entry i of lane l
+// is column l mod 16 and row row(l, i): 4 (l / 16) + i for f32, l / 16 + 4 i
+// for f64 (rows interleaved), as measured on gfx950.
+template <>
+struct MfmaT<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+template <>
+struct MfmaT<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+
+// C += sg A B for 16 x 16 complex tiles in LDS (row-major, strides lda, ldb),
+// C held as two accumulators (real and imaginary parts) in the layout above.
+template <class T>
+__device__ __forceinline__ void ctile_mma(typename MfmaT<T>::v4& cre, typename MfmaT<T>::v4& cim,
+                                          const cx<T>* A, int lda, const cx<T>* B, int ldb,
+                                          int lane, T sg) {
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const cx<T> a = A[(lane & 15) * lda + k0 + (lane >> 4)];
+    const cx<T> b = B[(k0 + (lane >> 4)) * ldb + (lane & 15)];
+    const T are = sg * a.re, aim = sg * a.im;
+    cre = MfmaT<T>::op(are, b.re, cre);
+    cre = MfmaT<T>::op(-aim, b.im, cre);
+    cim = MfmaT<T>::op(are, b.im, cim);
+    cim = MfmaT<T>::op(aim, b.re, cim);
+  }
+}
+
+// Rows of the LDS panel and chunk: LU_NB + kl rounded up to whole tiles.
+__host__ __device__ inline int lu_blk_rows(int kl) { return (LU_NB + kl + 15) / 16 * 16; }
+__host__ inline size_t lu_blk_lds(int kl) {
+  return (size_t)(2 * lu_blk_rows(kl) * LU_NB + LU_NB * LU_NB) * sizeof(c128) + 4 * sizeof(double) +
+         (4 + LU_NB) * sizeof(int);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_band_lu_blk(const StripDesc* __restrict__ strips,
+                                                     cx<T>* __restrict__ band,
+                                                     int* __restrict__ piv, int* __restrict__ err,
+                                                     int* __restrict__ pflag) {
+  using W = double;  // the elimination runs in FP64 whatever the storage
+  using V4 = typename MfmaT<W>::v4;
+  extern __shared__ unsigned char smem_raw[];
+  const StripDesc sd = strips[blockIdx.x];
+  const int ns = sd.ns, kl = sd.kl, kv = 2 * kl, ldab = sd.ldab;
+  const int RM = lu_blk_rows(kl);
+  cx<T>* ab = band + sd.band_off;
+  int* pv = piv + sd.piv_off;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  cx<W>* Pn = reinterpret_cast<cx<W>*>(smem_raw);  // RM x LU_NB, row-major
+  cx<W>* Ch = Pn + RM * LU_NB;                      // RM x LU_NB, row-major
+  cx<W>* Li = Ch + RM * LU_NB;                      // LU_NB x LU_NB, row-major
+  W* redv = reinterpret_cast<W*>(Li + LU_NB * LU_NB);
+  int* redi = reinterpret_cast<int*>(redv + 4);
+  int* pl = redi + 4;  // the panel's pivot rows, relative to j0
+  const cx<W> zero = mk(0.0, 0.0);
+  auto at = [&](int i, int j) { return (long long)j * ldab + kv + i - j; };
+  if (tid == 0) pflag[blockIdx.x] = 1;  // every strip takes the lane-major substitution
+  for (int j0 = 0; j0 < ns; j0 += LU_NB) {
+    const int nb = min(LU_NB, ns - j0);
+    const int R = min(nb + kl, ns - j0);
+    // ---- 1. the panel (consecutive threads read consecutive rows of a column)
+    for (int e = tid; e < RM * LU_NB; e += 256) {
+      const int c = e / RM, r = e - c * RM, i = j0 + r, j = j0 + c;
+      const bool in = r < R && c < nb && i - j <= kl && j - i <= kv;
+      Pn[r * LU_NB + c] = in ? ccast<W>(ab[at(i, j)]) : zero;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nb; ++jj) {
+      const int j = j0 + jj, km = min(kl, ns - 1 - j);
+      W v = -1.0;
+      int idx = 1 << 20;
+      if (tid <= km) {
+        v = cabs1(Pn[(jj + tid) * LU_NB + jj]);
+        idx = tid;
+      }
+      wave_argmax(v, idx);
+      if (lane == 0) {
+        redv[wv] = v;
+        redi[wv] = idx;
+      }
+      __syncthreads();
+      // largest |Re| + |Im|, first index on ties (wave 0 always holds row jj)
+      W bv = redv[0];
+      int p = redi[0];
+      for (int w = 1; w < 4; ++w)
+        if (redv[w] > bv || (redv[w] == bv && redi[w] < p)) {
+          bv = redv[w];
+          p = redi[w];
+        }
+      const cx<W> pvv = Pn[(jj + p) * LU_NB + jj];
+      const W pd = pvv.re * pvv.re + pvv.im * pvv.im;
+      // the stored pivot must be usable in the strip precision too
+      const cx<T> pvs = ccast<T>(pvv);
+      const T pds = pvs.re * pvs.re + pvs.im * pvs.im;
+      if (tid == 0) {
+        pv[j] = j + p;
+        pl[jj] = jj + p;
+        if (bad_pivot(pd) || bad_pivot(pds)) atomicCAS(err, 0, (int)blockIdx.x + 1);
+      }
+      if (p != 0 && tid < nb) {  // whole rows: L11 and L21 in the final row order
+        const cx<W> t0 = Pn[jj * LU_NB + tid];
+        Pn[jj * LU_NB + tid] = Pn[(jj + p) * LU_NB + tid];
+        Pn[(jj + p) * LU_NB + tid] = t0;
+      }
+      __syncthreads();
+      const W ipd = bad_pivot(pd) ? 0.0 : 1.0 / pd;
+      const cx<W> ipv = mk(pvv.re * ipd, -pvv.im * ipd);
+      if (tid >= 1 && tid <= km) {
+        const int r = jj + tid;
+        const cx<W> m = Pn[r * LU_NB + jj] * ipv;
+        Pn[r * LU_NB + jj] = m;
+        for (int c = jj + 1; c < nb; ++c)
+          Pn[r * LU_NB + c] = cfms(Pn[r * LU_NB + c], m, Pn[jj * LU_NB + c]);
+      }
+      __syncthreads();
+    }
+    const int j1 = j0 + nb, jmax = min(j0 + nb - 1 + kv, ns - 1);
+    // ---- 2. L11^{-1}, column tid (a full panel: nb == LU_NB wherever j1 <= jmax)
+    if (j1 <= jmax && tid < LU_NB) {
+      cx<W> xc[LU_NB];
+#pragma unroll
+      for (int r = 0; r < LU_NB; ++r) xc[r] = r == tid ? mk(1.0, 0.0) : zero;
+#pragma unroll
+      for (int c = 0; c < LU_NB; ++c)
+#pragma unroll
+        for (int r = c + 1; r < LU_NB; ++r) xc[r] = cfms(xc[r], Pn[r * LU_NB + c], xc[c]);
+#pragma unroll
+      for (int r = 0; r < LU_NB; ++r) Li[r * LU_NB + tid] = xc[r];
+    }
+    __syncthreads();
+    // ---- 3. trailing columns, LU_NB at a time
+    const int ntile = (R - nb + 15) / 16;
+    for (int c0 = j1; c0 <= jmax; c0 += LU_NB) {
+      const int cw = min(LU_NB, jmax - c0 + 1);
+      for (int e = tid; e < RM * LU_NB; e += 256) {
+        const int c = e / RM, r = e - c * RM, i = j0 + r, j = c0 + c;
+        const bool in = r < R && c < cw && i - j <= kl && j - i <= kv;
+        Ch[r * LU_NB + c] = in ? ccast<W>(ab[at(i, j)]) : zero;
+      }
+      __syncthreads();
+      if (tid < cw) {
+        for (int jj = 0; jj < nb; ++jj) {
+          const int p = pl[jj];
+          if (p != jj) {
+            const cx<W> t0 = Ch[jj * LU_NB + tid];
+            Ch[jj * LU_NB + tid] = Ch[p * LU_NB + tid];
+            Ch[p * LU_NB + tid] = t0;
+          }
+        }
+      }
+      __syncthreads();
+      if (wv == 0) {  // U12 = L11^{-1} A12 (the wave reads all of A12 before it writes)
+        V4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+        ctile_mma<W>(cre, cim, Li, LU_NB, Ch, LU_NB, lane, 1.0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          Ch[MfmaT<W>::row(lane, i) * LU_NB + (lane & 15)] = mk(cre[i], cim[i]);
+      }
+      __syncthreads();
+      for (int t = wv; t < ntile; t += 4) {  // A22 -= L21 U12, one 16-row tile per wave
+        const int r0 = nb + 16 * t;
+        V4 cre, cim;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const cx<W> c = Ch[(r0 + MfmaT<W>::row(lane, i)) * LU_NB + (lane & 15)];
+          cre[i] = c.re;
+          cim[i] = c.im;
+        }
+        ctile_mma<W>(cre, cim, Pn + r0 * LU_NB, LU_NB, Ch, LU_NB, lane, -1.0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          Ch[(r0 + MfmaT<W>::row(lane, i)) * LU_NB + (lane & 15)] = mk(cre[i], cim[i]);
+      }
+      __syncthreads();
+      for (int e = tid; e < RM * LU_NB; e += 256) {
+        const int c = e / RM, r = e - c * RM, i = j0 + r, j = c0 + c;
+        if (r < R && c < cw && i - j <= kl && j - i <= kv) ab[at(i, j)] = ccast<T>(Ch[r * LU_NB + c]);
+      }
+      __syncthreads();
+    }
+    // ---- 4. the panel back to the band, each column's multipliers in the
+    // row order of its own step (later interchanges undone on the L part)
+    for (int jj = nb - 1; jj >= 1; --jj) {
+      const int p = pl[jj];
+      if (p != jj && tid < jj) {
+        const cx<W> t0 = Pn[jj * LU_NB + tid];
+        Pn[jj * LU_NB + tid] = Pn[p * LU_NB + tid];
+        Pn[p * LU_NB + tid] = t0;
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < RM * LU_NB; e += 256) {
+      const int c = e / RM, r = e - c * RM, i = j0 + r, j = j0 + c;
+      if (r < R && c < nb && i - j <= kl && j - i <= kv) ab[at(i, j)] = ccast<T>(Pn[r * LU_NB + c]);
+    }
+    __syncthreads();
+  }
+}
+
 // Solve image of every strip (layout above).  grid = (NP*64 / 256, strips).
 template <class T>
 __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>* __restrict__ band,
@@ -609,18 +857,22 @@ __global__ void k_build_image(const StripDesc* __restrict__ strips, const cx<T>*
                               const int* __restrict__ pflag) {
   if (!pflag[blockIdx.y]) return;  // unpivoted strips use the blocked image
   const StripDesc sd = strips[blockIdx.y];
-  const int ns = sd.ns, NP = ns + HH_PAD, kl = sd.kl, kv = 2 * kl, S = sd.S, ldab = sd.ldab;
+  const int ns = sd.ns, NP = ns + HH_PAD, kl = sd.kl, kv = 2 * kl, S = sd.S, SL = sd.SL;
+  const int ldab = sd.ldab;
   const long long e = blockIdx.x * 256LL + threadIdx.x;
   if (e >= (long long)NP * 64) return;
   const int j = (int)(e >> 6), l = (int)(e & 63);
   const cx<T> zero = mk((T)0, (T)0);
   const cx<T>* ab = band + sd.band_off;
   cx<T>* Lm = img + sd.img_off;
-  cx<T>* Um = Lm + (long long)NP * 64;
+  cx<T>* Um = Lm + (long long)NP * 64 * SL;
   cx<T>* rdg = Um + (long long)NP * 64 * S;
-  int c = (l - (j & 63)) & 63;
-  const bool inl = j < ns && c >= 1 && c <= kl && j + c < ns;
-  Lm[e] = csel(inl, ab[inl ? (long long)j * ldab + kv + c : 0], zero);
+  int c;
+  for (int k = 0; k < SL; ++k) {
+    c = 64 * k + ((l - (j & 63)) & 63);
+    const bool inl = j < ns && c >= 1 && c <= kl && j + c < ns;
+    Lm[((long long)j * SL + k) * 64 + l] = csel(inl, ab[inl ? (long long)j * ldab + kv + c : 0], zero);
+  }
   const int col = ns - 1 - j;  // step J = j of the back substitution
   cx<T> rd = zero;
   if (j < ns) {
@@ -1127,6 +1379,14 @@ template <class T>
 static void launch_lu(const hh_problem* pb, size_t lds, hipStream_t st) {
   const FactorSet& fs = pb->fs;
   const int nstr = (int)fs.strips.size();
+  if (fs.max_kl > HH_KL_WINDOW) {
+    const size_t bl = lu_blk_lds(fs.max_kl);
+    HH_HIP(hipFuncSetAttribute((const void*)k_band_lu_blk<T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bl));
+    hipLaunchKernelGGL(k_band_lu_blk<T>, dim3(nstr), dim3(256), bl, st, fs.d_strips,
+                       (cx<T>*)fs.band, fs.piv, fs.d_err, fs.d_pflag);
+    return;
+  }
   if (fs.max_kl < 32) {
     if (lu_interchanging_only()) return launch_lu_w_any<T>(fs, st, 0);
     launch_lu_h_any<T>(fs, st);
@@ -1178,20 +1438,24 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
     hipLaunchKernelGGL(k_build_image<double>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c128*)fs.band, (c128*)fs.img, fs.piv,
                        fs.d_pflag);
-    hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
-                       (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
-    launch_transfer(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
-    launch_products(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+    if (fs.max_kl <= HH_KL_WINDOW) {  // wide bands take the lane-major substitution only
+      hipLaunchKernelGGL(k_build_blocked<double>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
+                         (const c128*)fs.band, (c128*)fs.img, fs.d_pflag);
+      launch_transfer(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+      launch_products(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+    }
   } else {
     launch_lu<float>(pb, lds, st);
     HH_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_build_image<float>, dim3((unsigned)(((long long)(fs.max_ns + HH_PAD) * 64 + 255) / 256), nstr),
                        dim3(256), 0, st, fs.d_strips, (const c64*)fs.band, (c64*)fs.img, fs.piv,
                        fs.d_pflag);
-    hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
-                       (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
-    launch_transfer(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
-    launch_products(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+    if (fs.max_kl <= HH_KL_WINDOW) {  // wide bands take the lane-major substitution only
+      hipLaunchKernelGGL(k_build_blocked<float>, blocked_grid(fs), dim3(64), 0, st, fs.d_strips,
+                         (const c64*)fs.band, (c64*)fs.img, fs.d_pflag);
+      launch_transfer(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+      launch_products(fs, HH_EAGER_PLANS | (fs.batch_maps ? HH_BATCH_PLANS : 0), st);
+    }
   }
   HH_HIP(hipGetLastError());
 }

@@ -133,6 +133,7 @@ struct StripDesc {
   int has1;       // interface Gamma_{s,1} (short index 0) present
   int has2;       // interface Gamma_{s,2} (short index w-1) present
   int S;          // lane slots of the back-substitution window (2 kl + 1 <= 64 S)
+  int SL;         // lane slots of the forward-substitution window (kl + 1 <= 64 SL)
   int KP;         // terms per lane of the blocked substitution (see factor.hip)
   int gid;        // index of this strip in FactorSet::strips
   long long band_off;  // complex elements into the LU work buffer (factorisation only)
@@ -153,6 +154,14 @@ struct StripDesc {
   long long phi_off[HH_NPLAN];  // plans p >= 1: complex elements into the solve image of the
                                 // segment responses (L, then U; see plan_phi_elems)
 };
+
+// Band half-widths: the one-wave LU window, the blocked substitution and the
+// segment plans take kl <= HH_KL_WINDOW; wider strips (up to HH_KL_MAX) are
+// factored by the blocked MFMA LU and solved by the lane-major substitution
+// alone, with SL = ceil((kl + 1) / 64) and S = 2 SL window slots.
+constexpr int HH_KL_WINDOW = 63;
+constexpr int HH_KL_MAX = 191;
+inline int lane_slots(int kl) { return (kl + 64) / 64; }
 
 // Zero steps appended to every strip's solve image and pivot list, so that the
 // substitution loops may run and prefetch past the end without bounds checks.
@@ -488,6 +497,7 @@ inline int sweep_segments(int KM, int n, size_t esz) {
 // built is decided by the LU.
 inline long long strip_image_elems(long long ns, int S, int KP, int K, int P, bool wide) {
   const long long lane_major = (ns + HH_PAD) * (64LL * (1 + S) + 1);
+  if (K > HH_KL_WINDOW) return (ns + HH_PAD) * (64LL * 3 * lane_slots(K) + 1);
   StripDesc sd{};
   sd.ns = (int)ns;
   sd.kl = K;

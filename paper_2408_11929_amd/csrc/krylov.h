@@ -56,6 +56,7 @@ struct NormTask {
 struct CombTask {
   const void* Z;
   const c128* y;
+  const c128* x0;  // added to Z y when not null (may equal x)
   c128* x;
   long long len;
   int ncols;

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_combine(const CombTask* __restrict__ ta
   if (p >= tk.len) return;
   c128 acc = mk(0.0, 0.0);
   for (int j = 0; j < tk.ncols; ++j) acc = acc + ld_c128<T>(tk.Z, j * (long long)tk.len + p) * tk.y[j];
-  tk.x[p] = acc;
+  tk.x[p] = tk.x0 ? tk.x0[p] + acc : acc;
 }
 
 // r = b - Ab (elementwise), in place on ab.

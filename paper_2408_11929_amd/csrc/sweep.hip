@@ -207,6 +207,78 @@ __device__ __forceinline__ void solve_lower(gptr<cx<T>> (&x)[C], gptr<const cx<T
   }
 }
 
+// solve_lower for one chain with a window of SL 64-element slots, for band
+// half-widths up to 64 SL - 1: slot k of lane l holds the element 64 k past
+// that of its slot 0, and the pivot row of a step may sit in any slot.  The
+// coefficient row of step j is SL x 64 wide (Lm[j][k][l], c = 64 k + ((l -
+// j) mod 64)).  The update is applied before the finished lane moves on, so
+// that each slot meets the coefficient of the element it holds.
+template <class T, int D, int SL>
+__device__ __forceinline__ void solve_lower_w(gptr<cx<T>> x, gptr<const cx<T>> Lm,
+                                              gptr<const int> piv, int ns, int lane) {
+  const cx<T> zero = mk((T)0, (T)0);
+  cx<T> b[SL], cc[SL][D], cn[SL][D];
+#pragma unroll
+  for (int k = 0; k < SL; ++k) {
+    const int e = 64 * k + lane;
+    b[k] = csel(e < ns, ld<T>(x, e < ns ? e : 0), zero);
+  }
+  const int e0 = 64 * SL + lane;
+  cx<T> nxtA = csel(e0 < ns, ld<T>(x, e0 < ns ? e0 : 0), zero), nxt = zero, yout = zero;
+  int pc = lane < D ? piv[lane] : 0, pn = 0;
+#pragma unroll
+  for (int u = 0; u < D; ++u)
+#pragma unroll
+    for (int k = 0; k < SL; ++k) cc[k][u] = ld<T>(Lm, ((long long)u * SL + k) * 64 + lane);
+  for (int j0 = 0; j0 < ns; j0 += D) {
+    if ((j0 & 63) == 0) {
+      nxt = nxtA;
+      const int e = j0 + 64 * SL + 64 + lane;
+      nxtA = csel(e < ns, ld<T>(x, e < ns ? e : 0), zero);
+    }
+    gptr<const cx<T>> row = Lm + (long long)(j0 + D) * SL * 64 + lane;
+#pragma unroll
+    for (int u = 0; u < D; ++u)
+#pragma unroll
+      for (int k = 0; k < SL; ++k) cn[k][u] = ld<T>(row, ((long long)u * SL + k) * 64);
+    pn = lane < D ? piv[j0 + D + lane] : 0;
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int j = j0 + u, lj = j & 63;
+      const int p = __builtin_amdgcn_readlane(pc, u), lp = p & 63;
+      const int kp = (p - j - ((lp - lj) & 63)) >> 6;  // slot of element p in lane lp
+      const cx<T> bj0 = rlc(b[0], lj);                  // element j
+      cx<T> bj = zero;                                  // element p: y_j
+#pragma unroll
+      for (int k = 0; k < SL; ++k)
+        if (k == kp) bj = rlc(b[k], lp);
+#pragma unroll
+      for (int k = 0; k < SL; ++k)
+        if (k == kp) b[k] = wlc(bj0, lp, b[k]);  // interchange: element p takes element j
+      yout = wlc(bj, lj, yout);
+#pragma unroll
+      for (int k = 0; k < SL; ++k) b[k] = cfms(b[k], cc[k][u], bj);
+#pragma unroll
+      for (int k = 0; k + 1 < SL; ++k) b[k] = sel(lane == lj, b[k + 1], b[k]);
+      b[SL - 1] = sel(lane == lj, nxt, b[SL - 1]);
+    }
+    if (((j0 + D) & 63) == 0) {
+      const int e = j0 + D - 64 + lane;
+      if (e < ns) st<T>(x, e, yout);
+    }
+#pragma unroll
+    for (int u = 0; u < D; ++u)
+#pragma unroll
+      for (int k = 0; k < SL; ++k) cc[k][u] = cn[k][u];
+    pc = pn;
+  }
+  const int jend = (ns + D - 1) / D * D;
+  if (jend & 63) {
+    const int e = (jend & ~63) + lane;
+    if (e < ns) st<T>(x, e, yout);
+  }
+}
+
 // Back substitution with the solve image for C chains: on entry x holds y,
 // on exit U^{-1} y.  Reversed indices E = ns-1-e; S lane slots.
 template <class T, int C, int D, int S>
@@ -1083,6 +1155,62 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
   }
 }
 
+// k_sweep for factorisations of wide strips (kl > HH_KL_WINDOW): one wave per
+// chain, every strip through the lane-major substitution (solve_lower_w with
+// SL slots, solve_upper with S = 2 SL).  Dynamic LDS: two node lines of
+// transmission data.
+template <class T, int D, int SL>
+__global__ __launch_bounds__(64) void k_sweep_lm(const SweepTask* __restrict__ tasks) {
+  constexpr int S = 2 * SL;
+  extern __shared__ char smem_raw[];
+  const SweepTask& tk = tasks[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int n = uni(tk.n), N = uni(tk.N);
+  cx<T>* gl1 = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* gl2 = gl1 + n;
+  const cx<T>* img = uniptr((const cx<T>*)tk.img);
+  const int* pivb = uniptr(tk.piv);
+  const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
+  gptr<cx<T>> z = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.z);
+  gptr<cx<T>> rho = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.rho);
+  gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
+  gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
+  const StripDesc* strips = uniptr(tk.ch.strips);
+  const int mode = uni(tk.mode);
+  const int nsteps = sweep_steps(mode, N);
+  for (int step = 0; step < nsteps; ++step) {
+    const SweepStep ss = sweep_step(mode, N, step);
+    const int s = ss.s;
+    const StripDesc* sp = strips + s;
+    const int ns = uni(sp->ns), w = uni(sp->w);
+    const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
+    const long long img_off = uni(sp->img_off), piv_off = uni(sp->piv_off);
+    const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
+    const bool use1 = has1 && ss.data1;
+    const bool use2 = has2 && ss.data2;
+    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, use1, use2, ss.fwd, ss.keep, t1off, t2off);
+    __syncthreads();
+    const float winv = 1.0f / (float)w;
+    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, use1, use2, winv};
+    // a single wave: its memory accesses are performed in order, the fences
+    // only keep the compiler from reordering them
+    for (int q = lane; q < ns; q += 64) st<T>(rho, q, gather.get(gather.load(q)));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const long long NP = ns + HH_PAD;
+    solve_lower_w<T, D, SL>(rho, (gptr<const cx<T>>)(img + img_off),
+                            (gptr<const int>)(pivb + piv_off), ns, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    gptr<cx<T>> x[1] = {rho};
+    gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64 * SL)};
+    gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64 * (SL + S))};
+    solve_upper<T, 1, D, S>(x, Um, rdg, ns, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const DstScatter<T> out{z, ns, w, n, a, dir, winv};
+    for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(rho, q));
+    __syncthreads();
+  }
+}
+
 // k_sweep for tiles of NR = 2 right-hand sides of the same preconditioner
 // (unpivoted strips, segment plan 0): task t carries its two chains in ch and
 // ch2 (the same strips and sweep mode; a tile of one repeats its chain in
@@ -1568,6 +1696,38 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
   }
 }
 
+// Strip solve of a wide strip (test hook): lane-major substitutions on one wave.
+template <class T, int D, int SL>
+__global__ __launch_bounds__(64) void k_strip_solve_lm(const StripDesc* __restrict__ strips, int si,
+                                                       const void* __restrict__ img,
+                                                       const int* __restrict__ pivb,
+                                                       const c128* __restrict__ rhs,
+                                                       c128* __restrict__ x,
+                                                       cx<T>* __restrict__ work) {
+  constexpr int S = 2 * SL;
+  const int lane = threadIdx.x;
+  const StripDesc* sp = strips + si;
+  const int ns = uni(sp->ns);
+  const long long ioff = uni(sp->img_off), poff = uni(sp->piv_off), NP = ns + HH_PAD;
+  const cx<T>* im = (const cx<T>*)img;
+  gptr<cx<T>> wk = (gptr<cx<T>>)work;
+  const SrcC128<T> in{(gptr<const c128>)rhs, ns};
+  for (int q = lane; q < ns; q += 64) st<T>(wk, q, in.get(in.load(q)));
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  solve_lower_w<T, D, SL>(wk, (gptr<const cx<T>>)(im + ioff), (gptr<const int>)(pivb + poff), ns,
+                          lane);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  gptr<cx<T>> xs[1] = {wk};
+  gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64 * SL)};
+  gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64 * (SL + S))};
+  solve_upper<T, 1, D, S>(xs, Um, rdg, ns, lane);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int q = lane; q < ns; q += 64) {
+    const cx<T> v = ld<T>(wk, q);
+    x[q] = mk((double)v.re, (double)v.im);
+  }
+}
+
 }  // namespace
 
 // Template choice.  D: coefficient prefetch depth of the pivoted path (deep
@@ -1792,9 +1952,49 @@ void launch_sweep_tiles(const SweepTask* d_tiles, int ntiles, int precision, int
   HH_HIP(hipGetLastError());
 }
 
+// Wide strips: prefetch depth D of the lane-major rows (registers: 2 S D
+// complex coefficients per lane, S = 2 SL).
+template <class T>
+struct LaneMajorShape {
+  static constexpr int D = sizeof(T) == 8 ? 2 : 4;
+};
+template <class T, int SL>
+static void launch_sweep_lm_t(const SweepTask* d, int ntasks, int nmax, hipStream_t st) {
+  const size_t lds = (size_t)2 * nmax * sizeof(cx<T>);
+  const void* fn = (const void*)k_sweep_lm<T, LaneMajorShape<T>::D, SL>;
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_sweep_lm<T, LaneMajorShape<T>::D, SL>), dim3(ntasks), dim3(64), lds, st,
+                     d);
+}
+static void launch_sweep_lm(const SweepTask* d, int ntasks, int precision, int kmax, int nmax,
+                            hipStream_t st) {
+  const int SL = lane_slots(kmax);
+  if (kmax > HH_KL_MAX || SL < 2 || SL > 3) {
+    set_error("no lane-major sweep for band half-width %d", kmax);
+    throw ArgError();
+  }
+  if (precision == HH_FP64) {
+    if (SL == 2) launch_sweep_lm_t<double, 2>(d, ntasks, nmax, st);
+    else launch_sweep_lm_t<double, 3>(d, ntasks, nmax, st);
+  } else {
+    if (SL == 2) launch_sweep_lm_t<float, 2>(d, ntasks, nmax, st);
+    else launch_sweep_lm_t<float, 3>(d, ntasks, nmax, st);
+  }
+  HH_HIP(hipGetLastError());
+}
+
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
                   int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st) {
   if (ntasks <= 0) return;
+  if (kmax > HH_KL_WINDOW) {
+    if (plan != 0) {
+      set_error("strips of band half-width %d run on segment plan 0 only", kmax);
+      throw ArgError();
+    }
+    launch_sweep_lm(d_tasks, ntasks, precision, kmax, nmax, st);
+    return;
+  }
   if (P < 1 || P > 8) {
     set_error("unsupported segment count %d", P);
     throw ArgError();
@@ -1850,6 +2050,26 @@ static void launch_strip_t(const hh_problem* pb, int si, const c128* rhs, c128* 
 
 void launch_strip_solve(const hh_problem* pb, int si, const c128* rhs, c128* x, void* scratch,
                         hipStream_t st) {
+  const FactorSet& fs = pb->fs;
+  if (fs.max_kl > HH_KL_WINDOW) {
+    const int SL = fs.strips[si].SL;
+    const bool dbl = fs.precision == HH_FP64;
+    const void* img = fs.img;
+    if (dbl && SL == 2)
+      hipLaunchKernelGGL((k_strip_solve_lm<double, LaneMajorShape<double>::D, 2>), dim3(1), dim3(64), 0,
+                         st, fs.d_strips, si, img, fs.piv, rhs, x, (c128*)scratch);
+    else if (dbl)
+      hipLaunchKernelGGL((k_strip_solve_lm<double, LaneMajorShape<double>::D, 3>), dim3(1), dim3(64), 0,
+                         st, fs.d_strips, si, img, fs.piv, rhs, x, (c128*)scratch);
+    else if (SL == 2)
+      hipLaunchKernelGGL((k_strip_solve_lm<float, LaneMajorShape<float>::D, 2>), dim3(1), dim3(64), 0,
+                         st, fs.d_strips, si, img, fs.piv, rhs, x, (c64*)scratch);
+    else
+      hipLaunchKernelGGL((k_strip_solve_lm<float, LaneMajorShape<float>::D, 3>), dim3(1), dim3(64), 0,
+                         st, fs.d_strips, si, img, fs.piv, rhs, x, (c64*)scratch);
+    HH_HIP(hipGetLastError());
+    return;
+  }
   if (pb->fs.precision == HH_FP64)
     launch_strip_t<double>(pb, si, rhs, x, scratch, st);
   else

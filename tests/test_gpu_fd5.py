@@ -70,17 +70,21 @@ def test_table5_paper_shaped_runs():
     n = 513
     out = []
     for k, N, lrl_p, both_p in rows:
-        if N < 16:
-            continue
+        # N = 4 and 8 (band half-widths 132 and 68) take the blocked MFMA LU
+        # and the lane-major sweep, whose iterations cost about 0.35 s here:
+        # LRL alone, which does not converge in this construction (see the
+        # Table 4 check in test_golden.py), is run on N >= 16 only
         f = torch.from_numpy(paper_source(n, float(k))).to("cuda")
         pb = hh.Problem.from_field(float(k), [1.0], n, f=f, scheme="fd5")
         pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP64)
         x, st, rc = pb.mpgmres(None, tol=1e-6, maxit=200)
         both = st[0]["iterations"]
         assert rc == hh.HH_OK and st[0]["res_true"] <= 1e-6
-        pb.set_preconditioners(["LRL"])
-        x, st1, rc1 = pb.mpgmres(None, tol=1e-6, maxit=200)
-        one = st1[0]["iterations"]
+        one = None
+        if N >= 16:
+            pb.set_preconditioners(["LRL"])
+            x, st1, rc1 = pb.mpgmres(None, tol=1e-6, maxit=200)
+            one = st1[0]["iterations"]
         pb.free()
         out.append((k, N, one, lrl_p, both, both_p))
         print(f"[table5] k={k} N={N}: LRL {one} (paper {lrl_p}), LRL+BTB {both} (paper {both_p})",
