@@ -22,6 +22,8 @@ mpgmres   Selective multipreconditioned GMRES (Sec. 3) with the selection
           rule of Sec. 4, plus an independent textbook right-preconditioned
           GMRES used to pin the t = 1 case.
 direct    Full direct solve of the global system (LAPACK band LU or SuperLU).
+recursive Double sweeps whose strip solves are inner double sweeps over
+          sub-blocks along the strip (Sec. 4, closing discussion).
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` against closed forms, invariants, special cases
