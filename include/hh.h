@@ -155,6 +155,23 @@ int hh_load_vector(hh_problem* pb, int nvec, const hh_c128* f, hh_c128* b);
  * entries overflow complex64; the message names the strip), HH_EDEVICE. */
 int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision);
 
+/* Recursive strip solves (Sec. 4, closing discussion: the strip problems
+ * decomposed again in the perpendicular direction and solved approximately):
+ * as hh_factor_sweeps, but every strip is cut along its length into nsub
+ * sub-blocks by the same rule as the strips ((n-1) % nsub == 0, (n-1)/nsub
+ * >= 2, one extra mesh line past each internal boundary), only the
+ * sub-blocks are factored, and each strip solve of a sweep becomes one inner
+ * double sweep over them, with the strip operator A_s in the role of A: the
+ * sub-block operators carry the impedance condition on all four sides and
+ * their transmission data are A_{s,t} R_t u - R_t A_s u on their interface
+ * lines.  A sub-block is ordered by its narrower side, so wide strips get
+ * narrow bands (at most 191).  nsub = 1 is hh_factor_sweeps with the strip
+ * solves done this way (the exact strip solve).  The preconditioner, sweep
+ * and MPGMRES entry points then apply these inexact sweeps (one wave per
+ * chain, lane-major substitutions); hh_strip_solve is refused.
+ * Errors: as hh_factor_sweeps. */
+int hh_factor_sweeps_inner(hh_problem* pb, unsigned dirs, int nstrips, int nsub, int precision);
+
 /* ---- preconditioner application: eqs. (2)-(4) -------------------------------
  * z = M_dir^{-1} r for nvec vectors: forward sweep over strips 1..N, backward
  * sweep over N-1..1, 2N-1 strip solves, overlap values from the most recent

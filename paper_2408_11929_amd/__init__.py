@@ -125,8 +125,14 @@ class Problem:
         return out
 
     # -- strips
-    def factor_sweeps(self, dirs=HH_DIR_X | HH_DIR_Y, nstrips=4, precision=HH_FP64):
-        _check(lib().hh_factor_sweeps(self.handle, int(dirs), int(nstrips), int(precision)))
+    def factor_sweeps(self, dirs=HH_DIR_X | HH_DIR_Y, nstrips=4, precision=HH_FP64, nsub=None):
+        """hh_factor_sweeps, or with nsub hh_factor_sweeps_inner (every strip solve
+        an inner double sweep over nsub sub-blocks along the strip)."""
+        if nsub is None:
+            _check(lib().hh_factor_sweeps(self.handle, int(dirs), int(nstrips), int(precision)))
+        else:
+            _check(lib().hh_factor_sweeps_inner(self.handle, int(dirs), int(nstrips), int(nsub),
+                                                int(precision)))
         self.dirs, self.nstrips, self.precision = int(dirs), int(nstrips), int(precision)
 
     def strip_info(self, direction, s):

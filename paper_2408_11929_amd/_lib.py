@@ -88,6 +88,7 @@ PROTOTYPES = {
     "hh_tune_clear": (I, []),
     "hh_load_vector": (I, [P, I, P, P]),
     "hh_factor_sweeps": (I, [P, U, I, I]),
+    "hh_factor_sweeps_inner": (I, [P, U, I, I, I]),
     "hh_sweep_apply": (I, [P, U, I, P, P]),
     "hh_precond_apply": (I, [P, I, I, P, P]),
     "hh_precond_apply_noalloc": (I, [P, I, I, P, P]),

@@ -12,6 +12,8 @@
 // (offsets 0, +-1, +-n, +-(n+1)).
 #include <cstdlib>
 
+#include <algorithm>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -221,7 +223,7 @@ __global__ void k_pack_strips(int n, Medium md,
   const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
   const int kv = 2 * sd.kl;
   cx<T>* ab = band + sd.band_off;
-  for (int d = 0; d < 7; ++d) {
+  for (int d = 0; d < 7 && band; ++d) {  // band == nullptr: the transmission data only
     if (st[d].re == 0.0 && st[d].im == 0.0) continue;
     int ii = i + di[d], jj = j + dj[d];
     int qq = sd.dir == 0 ? jj * sd.w + (ii - sd.a) : ii * sd.w + (jj - sd.a);
@@ -232,6 +234,63 @@ __global__ void k_pack_strips(int n, Medium md,
     c128 g[7];
     node_stencil(i, j, n, 0, n - 1, 0, n - 1, md, false, g);
     cx<T>* out = tr + (side1 ? sd.tr1_off : sd.tr2_off) + 7LL * l;
+    for (int d = 0; d < 7; ++d) out[d] = mk((T)(st[d].re - g[d].re), (T)(st[d].im - g[d].im));
+  }
+}
+
+// Sub-blocks of the strips (recursive strip solves): the operator of the
+// sub-block's rectangle with the impedance condition on all four sides, in
+// the sub-block's order (orient 0: q' = L w + T, orient 1: q' = T len + L,
+// L = line along the strip - c0, T = across), band-packed like a strip; and
+// on its interface lines the transmission coefficients (A_{s,t} - A_s) of
+// the seven stencil neighbours, node T at tr + tr{1,2}_off + 7 T.
+// grid = (ns blocks, sub-blocks).
+template <class T>
+__global__ void k_pack_sub(int n, Medium md, const StripDesc* __restrict__ subs,
+                           cx<T>* __restrict__ band, cx<T>* __restrict__ tr) {
+  const StripDesc sd = subs[blockIdx.y];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= sd.ns) return;
+  const int w = sd.w, len = sd.len;
+  int L, Tt;
+  if (sd.orient == 0) {
+    L = q / w;
+    Tt = q - L * w;
+  } else {
+    Tt = q / len;
+    L = q - Tt * len;
+  }
+  const int l = sd.c0 + L;
+  int i, j, cx0, cx1, cy0, cy1;
+  if (sd.dir == 0) {
+    i = sd.a + Tt; j = l;
+    cx0 = sd.a; cx1 = sd.a + w - 1; cy0 = sd.c0; cy1 = sd.c0 + len - 1;
+  } else {
+    i = l; j = sd.a + Tt;
+    cx0 = sd.c0; cx1 = sd.c0 + len - 1; cy0 = sd.a; cy1 = sd.a + w - 1;
+  }
+  c128 st[7];
+  node_stencil(i, j, n, cx0, cx1, cy0, cy1, md, false, st);
+  const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
+  const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
+  const int kv = 2 * sd.kl;
+  cx<T>* ab = band + sd.band_off;
+  for (int d = 0; d < 7; ++d) {
+    if (st[d].re == 0.0 && st[d].im == 0.0) continue;
+    const int ii = i + di[d], jj = j + dj[d];
+    const int T2 = sd.dir == 0 ? ii - sd.a : jj - sd.a;
+    const int L2 = (sd.dir == 0 ? jj : ii) - sd.c0;
+    const int qq = sd.orient == 0 ? L2 * w + T2 : T2 * len + L2;
+    ab[(long long)qq * sd.ldab + kv + q - qq] = mk((T)st[d].re, (T)st[d].im);
+  }
+  const bool side1 = L == 0 && sd.has1, side2 = L == len - 1 && sd.has2;
+  if (side1 || side2) {
+    c128 g[7];
+    if (sd.dir == 0)
+      node_stencil(i, j, n, sd.a, sd.a + w - 1, 0, n - 1, md, false, g);
+    else
+      node_stencil(i, j, n, 0, n - 1, sd.a, sd.a + w - 1, md, false, g);
+    cx<T>* out = tr + (side1 ? sd.tr1_off : sd.tr2_off) + 7LL * Tt;
     for (int d = 0; d < 7; ++d) out[d] = mk((T)(st[d].re - g[d].re), (T)(st[d].im - g[d].im));
   }
 }
@@ -285,6 +344,27 @@ void launch_pack_strips(const hh_problem* pb, hipStream_t st) {
   HH_HIP(hipMemsetAsync(fs.band, 0, fs.band_elems * esz, st));
   HH_HIP(hipMemsetAsync(fs.tr, 0, fs.tr_elems * esz, st));
   int bs = 256;
+  if (fs.nsub > 1) {
+    // recursive strip solves: the outer strips give their transmission data
+    // only, the sub-blocks their matrices and inner transmission data
+    const dim3 go((unsigned)((fs.max_ns + bs - 1) / bs), (unsigned)fs.first_sub);
+    int ns_sub = 0;
+    for (size_t u = fs.first_sub; u < fs.strips.size(); ++u) ns_sub = std::max(ns_sub, fs.strips[u].ns);
+    const dim3 gs((unsigned)((ns_sub + bs - 1) / bs), (unsigned)(fs.strips.size() - fs.first_sub));
+    if (fs.precision == HH_FP64) {
+      hipLaunchKernelGGL(k_pack_strips<double>, go, dim3(bs), 0, st, pb->n, medium_of(pb),
+                         fs.d_strips, (c128*)nullptr, (c128*)fs.tr, (const int*)nullptr);
+      hipLaunchKernelGGL(k_pack_sub<double>, gs, dim3(bs), 0, st, pb->n, medium_of(pb),
+                         fs.d_strips + fs.first_sub, (c128*)fs.band, (c128*)fs.tr);
+    } else {
+      hipLaunchKernelGGL(k_pack_strips<float>, go, dim3(bs), 0, st, pb->n, medium_of(pb),
+                         fs.d_strips, (c64*)nullptr, (c64*)fs.tr, (const int*)nullptr);
+      hipLaunchKernelGGL(k_pack_sub<float>, gs, dim3(bs), 0, st, pb->n, medium_of(pb),
+                         fs.d_strips + fs.first_sub, (c64*)fs.band, (c64*)fs.tr);
+    }
+    HH_HIP(hipGetLastError());
+    return;
+  }
   dim3 grid((unsigned)((fs.max_ns + bs - 1) / bs), (unsigned)fs.strips.size());
   if (fs.precision == HH_FP64)
     hipLaunchKernelGGL(k_pack_strips<double>, grid, dim3(bs), 0, st, pb->n, medium_of(pb),

@@ -98,7 +98,86 @@ void sweep_apply(hh_problem* pb, int i, int mode, int nvec, const c128* r, c128*
 
 namespace hh {
 
-void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
+// Sub-blocks of every strip for recursive strip solves: nsub per strip along
+// its length, the outer strips' rule (one extra line past each internal
+// boundary), each ordered by its narrower side; lane-major factors only.
+static void sub_block_setup(FactorSet& fs, int n, int nsub, long long& band, long long& img,
+                            long long& piv, long long& tr) {
+  const int m2 = (n - 1) / nsub;
+  const int nouter = (int)fs.strips.size();
+  fs.first_sub = nouter;
+  int kl_max = 0, ns_sub = 0, w_max = 0;
+  // one window slot count for all sub-blocks (the sweep kernel's template)
+  for (int o = 0; o < nouter; ++o)
+    for (int t = 0; t < nsub; ++t) {
+      const int len = std::min(n - 1, (t + 1) * m2 + 1) - std::max(0, t * m2 - 1) + 1;
+      kl_max = std::max(kl_max, std::min(fs.strips[o].w, len) + 1);
+    }
+  REQUIRE(kl_max <= HH_KL_MAX, "sub-block band half-width %d exceeds %d", kl_max, HH_KL_MAX);
+  const int SL = lane_slots(kl_max);
+  fs.strips.reserve((size_t)nouter * (1 + nsub));
+  for (int o = 0; o < nouter; ++o) {
+    // a copy: the push_backs below may move the vector's storage
+    fs.strips[o].sub = (int)fs.strips.size() - o;  // relative to the strip's own descriptor
+    fs.strips[o].nsub = nsub;
+    const StripDesc sd = fs.strips[o];
+    w_max = std::max(w_max, sd.w);
+    for (int t = 0; t < nsub; ++t) {
+      StripDesc u{};
+      u.dir = sd.dir;
+      u.s = sd.s;
+      u.a = sd.a;
+      u.w = sd.w;
+      u.c0 = std::max(0, t * m2 - 1);
+      u.len = std::min(n - 1, (t + 1) * m2 + 1) - u.c0 + 1;
+      u.orient = sd.w <= u.len ? 0 : 1;
+      u.ns = sd.w * u.len;
+      u.kl = (u.orient == 0 ? sd.w : u.len) + 1;
+      u.ldab = 3 * u.kl + 1;
+      u.has1 = t > 0;
+      u.has2 = t < nsub - 1;
+      u.SL = SL;
+      u.S = 2 * SL;
+      u.KP = sd.KP;
+      u.segs = sd.segs;
+      u.gid = (int)fs.strips.size();
+      u.sub = -1;
+      u.band_off = band;
+      band += (long long)u.ns * u.ldab;
+      u.img_off = img;
+      img += (long long)(u.ns + HH_PAD) * (64LL * 3 * u.SL + 1);
+      u.piv_off = piv;
+      piv += u.ns + HH_PAD;
+      u.tr1_off = u.has1 ? tr : -1;
+      if (u.has1) tr += 7LL * sd.w;
+      u.tr2_off = u.has2 ? tr : -1;
+      if (u.has2) tr += 7LL * sd.w;
+      ns_sub = std::max(ns_sub, u.ns);
+      fs.strips.push_back(u);
+    }
+  }
+  // every sub-block inside its strip, with the geometry the kernels index by
+  for (int o = 0; o < nouter; ++o) {
+    const StripDesc& sd = fs.strips[o];
+    REQUIRE(sd.sub == (int)fs.strips.size() - nouter * nsub + o * (nsub - 1) && sd.nsub == nsub,
+            "sub-block layout of strip %d", o);
+    for (int t = 0; t < nsub; ++t) {
+      const StripDesc& u = fs.strips[o + sd.sub + t];
+      REQUIRE(u.w == sd.w && u.a == sd.a && u.dir == sd.dir && u.c0 >= 0 && u.len >= 3 &&
+                  u.c0 + u.len <= n && u.ns == u.w * u.len && u.ns <= sd.ns &&
+                  u.kl == (u.orient ? u.len : u.w) + 1 && u.kl <= kl_max && u.SL == SL &&
+                  u.band_off >= 0 && u.img_off >= 0 && u.piv_off >= 0,
+              "sub-block %d of strip %d is inconsistent", t, o);
+    }
+  }
+  fs.max_kl = kl_max;
+  // per chain: the strip right-hand side, the inner solution and the
+  // sub-block work vector (ns of the strip each), the inner Gamma_1 data
+  // (nsub x w)
+  fs.rho_elems = 3LL * fs.max_ns + (long long)nsub * w_max + 64;
+}
+
+void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision, int nsub) {
   REQUIRE(dirs >= 1 && dirs <= 3, "dirs must be HH_DIR_X, HH_DIR_Y or both");
   REQUIRE(precision == HH_FP64 || precision == HH_FP32, "precision must be HH_FP64 or HH_FP32");
   const int n = pb->n, N = nstrips;
@@ -123,15 +202,21 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
     const int a = std::max(0, s * m - 1), b = std::min(n - 1, (s + 1) * m + 1);
     kl_max = std::max(kl_max, b - a + 2);
   }
-  REQUIRE(kl_max <= HH_KL_MAX, "strip band half-width %d exceeds %d (strips too wide)", kl_max,
-          HH_KL_MAX);
-  const bool lane_major = kl_max > HH_KL_WINDOW;  // blocked MFMA LU, lane-major substitution
+  const bool rec = nsub > 1;
+  if (rec) {
+    REQUIRE((n - 1) % nsub == 0, "(n-1) = %d is not divisible by nsub = %d", n - 1, nsub);
+    REQUIRE((n - 1) / nsub >= 2, "each sub-block needs at least 2 intervals (nsub <= (n-1)/2)");
+  } else {
+    REQUIRE(kl_max <= HH_KL_MAX, "strip band half-width %d exceeds %d (strips too wide)", kl_max,
+            HH_KL_MAX);
+  }
+  const bool lane_major = !rec && kl_max > HH_KL_WINDOW;  // blocked MFMA LU, lane-major substitution
   const int SL = lane_major ? lane_slots(kl_max) : 1;
   const int S = lane_major ? 2 * SL : 2 * kl_max + 1 <= 64 ? 1 : 2;
   const int P = sweep_segments(map_dim(blocked_kp(kl_max)), n,
                                precision == HH_FP64 ? sizeof(c128) : sizeof(c64));
   // the wide segment plan's maps are built only where that plan can run
-  const bool wide = !lane_major && sweep_wide_fits(precision, P, kl_max, n);
+  const bool wide = !rec && !lane_major && sweep_wide_fits(precision, P, kl_max, n);
   for (int i = 0; i < fs.nd; ++i) {
     for (int s = 0; s < N; ++s) {
       StripDesc sd{};
@@ -149,9 +234,11 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       sd.SL = SL;
       sd.KP = blocked_kp(kl_max);
       sd.gid = (int)fs.strips.size();
+      sd.sub = -1;
+      sd.nsub = 1;
       const long long NP = sd.ns + HH_PAD;
       sd.band_off = band;
-      band += (long long)sd.ns * sd.ldab;
+      if (!rec) band += (long long)sd.ns * sd.ldab;  // recursive: the sub-blocks hold the factors
       sd.segs = P;
       sd.wide = wide;
       plan_layout(sd);
@@ -166,9 +253,9 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
         sd.phi_off[p] = po;
         if (wide) po += 2 * plan_phi_elems(sd.ns, P, sd.kl, map_dim(sd.KP), p);
       }
-      img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P, wide);
+      if (!rec) img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P, wide);
       sd.piv_off = piv;
-      piv += NP;
+      if (!rec) piv += NP;
       sd.tr1_off = sd.has1 ? tr : -1;
       if (sd.has1) tr += 7LL * n;
       sd.tr2_off = sd.has2 ? tr : -1;
@@ -178,6 +265,10 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision) {
       fs.strips.push_back(sd);
     }
   }
+  fs.nsub = rec ? nsub : 1;
+  fs.first_sub = (int)fs.strips.size();
+  fs.rho_elems = fs.max_ns;
+  if (rec) sub_block_setup(fs, n, nsub, band, img, piv, tr);
   const size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
   fs.band_elems = band;
   fs.img_elems = img;
@@ -220,7 +311,9 @@ int factor_finish(hh_problem* pb) {
   }
   fs.any_pivot = std::any_of(fs.h_pflag.begin(), fs.h_pflag.end(), [](int f) { return f != 0; });
   if (fs.h_err[0]) {
-    const StripDesc& sd = fs.strips[fs.h_err[0] - 1];
+    // the LU launch of recursive solves covers the sub-blocks only
+    const int e = fs.h_err[0] - 1 + (fs.nsub > 1 ? fs.first_sub : 0);
+    const StripDesc& sd = fs.strips[e];
     set_error("zero or non-finite pivot in the LU of strip %d of direction %c (in complex%d)", sd.s + 1,
               sd.dir == 0 ? 'x' : 'y', fs.precision == HH_FP64 ? 128 : 64);
     return HH_ESINGULAR;
@@ -241,6 +334,7 @@ void ensure_batch_maps(hh_problem* pb, hipStream_t st) {
 
 int sweep_plan_of(const hh_problem* pb, int nvec) {
   const FactorSet& fs = pb->fs;
+  if (fs.nsub > 1) return HH_PLAN_REC;
   const int KP = fs.strips[0].KP, P = fs.strips[0].segs;
   const bool wide = fs.strips[0].wide != 0;
   int p = 0;
@@ -264,7 +358,7 @@ SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, 
   SweepBuffers b{};
   b.tasks = (SweepTask*)take((size_t)nvec * sizeof(SweepTask));
   b.sync = (unsigned*)take((size_t)(nvec + 1) * 128);  // [0] abort, then a line per chain
-  b.rho = take((size_t)nvec * fs.max_ns * es);
+  b.rho = take((size_t)nvec * fs.rho_elems * es);
   b.g1 = take((size_t)nvec * fs.N * pb->n * es);
   b.zs = fs.precision == HH_FP64 ? nullptr : take((size_t)nvec * len * es);
   b.xch = plan == HH_PLAN_WIDE || plan == HH_PLAN_PAIR
@@ -294,7 +388,7 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
     tk.ch.strips = fs.d_strips + (size_t)i * fs.N;
     tk.ch.r = r + v * len;
     tk.ch.z = (char*)zs + v * len * es;
-    tk.ch.rho = (char*)b.rho + (size_t)v * fs.max_ns * es;
+    tk.ch.rho = (char*)b.rho + (size_t)v * fs.rho_elems * es;
     tk.ch.g1 = (char*)b.g1 + (size_t)v * fs.N * pb->n * es;
     tk.img = fs.img;
     tk.piv = fs.piv;
@@ -573,6 +667,17 @@ int hh_factor_sweeps(hh_problem* pb, unsigned dirs, int nstrips, int precision) 
   });
 }
 
+int hh_factor_sweeps_inner(hh_problem* pb, unsigned dirs, int nstrips, int nsub, int precision) {
+  return guard([&]() {
+    REQUIRE(pb != nullptr, "problem is NULL");
+    REQUIRE(nsub >= 1, "nsub must be >= 1");
+    factor_setup(pb, dirs, nstrips, precision, nsub);
+    factor_launch(pb, pb->st[0]);
+    HH_HIP(hipStreamSynchronize(pb->st[0]));
+    return factor_finish(pb);
+  });
+}
+
 int hh_strip_info(const hh_problem* pb, unsigned dir, int s, int* a, int* w, int* kl) {
   return guard([&]() {
     REQUIRE(pb != nullptr, "problem is NULL");
@@ -591,6 +696,7 @@ int hh_strip_solve(hh_problem* pb, unsigned dir, int s, const hh_c128* rhs, hh_c
     REQUIRE(pb && rhs && x, "invalid arguments");
     const int i = dir_slot(pb, dir);
     REQUIRE(s >= 1 && s <= pb->fs.N, "strip index out of range");
+    REQUIRE(pb->fs.nsub <= 1, "the strips of this factorisation are solved by inner sweeps");
     const int si = i * pb->fs.N + s - 1;
     const size_t es = pb->fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
     ensure_batch_maps(pb, pb->st[0]);  // the strip solve runs segment plan 0

@@ -174,7 +174,7 @@ size_t Engine::footprint(const hh_problem* pb, int t, int prec, int maxit) {
   HdLayout L(cols, t);
   b += L.total * sizeof(c128);
   b += (size_t)nblk_for(len) * (cols + t) * t * sizeof(c128);    // partial sums
-  b += (size_t)t * (pb->fs.max_ns + (size_t)pb->fs.N * pb->n) * esz_of(prec);
+  b += (size_t)t * (pb->fs.rho_elems + (size_t)pb->fs.N * pb->n) * esz_of(prec);
   b += (size_t)cols * t * sizeof(c128);
   if (t > 2) b += (size_t)len * sizeof(c128);                    // summed sweep input
   return b;
@@ -294,7 +294,7 @@ void Engine::begin(std::vector<Solve*>& solves) {
     const size_t es = esz_of(s->prec);
     ensure_capacity(s);  // the first bases fit the iterations charged at admission
     if (!s->flags) s->flags = (int*)dev_alloc(4 * sizeof(int));
-    if (!s->rho) s->rho = dev_alloc((size_t)s->t * fs.max_ns * es + 256);
+    if (!s->rho) s->rho = dev_alloc((size_t)s->t * fs.rho_elems * es + 256);
     if (!s->g1) s->g1 = dev_alloc((size_t)s->t * fs.N * s->pb->n * es + 256);
     if (s->t > 2 && !s->sumv) s->sumv = (c128*)dev_alloc((size_t)s->len * sizeof(c128));
     if (!s->x0)
@@ -434,6 +434,7 @@ void Engine::step(std::vector<Solve*>& solves) {
     bool piv;
     int plan;
     bool wide;  // the maps of plans 1 and 2 exist
+    bool rec = false;              // recursive strip solves (k_sweep_rec)
     std::vector<hh_problem*> pbs;  // problems with tasks in this kind
     bool tune = false;             // measure the plans that fit before the launch
     TuneKey key{};
@@ -445,12 +446,13 @@ void Engine::step(std::vector<Solve*>& solves) {
     const size_t es = esz_of(fs.precision);
     const int KP = fs.strips[0].KP, P = fs.strips[0].segs;
     const bool wide = fs.strips[0].wide != 0;
+    const bool rec = fs.nsub > 1;
     auto it = std::find_if(kinds.begin(), kinds.end(), [&](const Kind& k) {
       return k.prec == fs.precision && k.KP == KP && k.P == P && k.piv == fs.any_pivot &&
-             k.wide == wide;
+             k.wide == wide && k.rec == rec;
     });
     if (it == kinds.end()) {
-      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0, wide, {}});
+      kinds.push_back({{}, fs.precision, KP, P, 0, 0, fs.any_pivot, 0, wide, rec, {}});
       it = kinds.end() - 1;
     }
     if (std::find(it->pbs.begin(), it->pbs.end(), s->pb) == it->pbs.end()) it->pbs.push_back(s->pb);
@@ -462,7 +464,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       tk.mode = fs.pre_mode[i];
       tk.ch.r = s->sum_input ? s->sumv : s->V + (size_t)s->inputs[i] * s->len;
       tk.ch.z = (char*)s->Z + ((size_t)s->k * s->t + i) * s->len * es;
-      tk.ch.rho = (char*)s->rho + (size_t)i * fs.max_ns * es;
+      tk.ch.rho = (char*)s->rho + (size_t)i * fs.rho_elems * es;
       tk.ch.g1 = (char*)s->g1 + (size_t)i * fs.N * pb->n * es;
       tk.img = fs.img;
       tk.piv = fs.piv;
@@ -480,6 +482,10 @@ void Engine::step(std::vector<Solve*>& solves) {
       const int nt = (int)k.tasks.size();
       k.plan = 0;
       k.tune = false;
+      if (k.rec) {
+        k.plan = HH_PLAN_REC;
+        continue;
+      }
       if (!wide_ok_) {
         // plan 0's results whatever the mix: plan 0, or its tiles (the same
         // bits) when the chains outnumber the compute units
@@ -530,7 +536,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       wide_chains = chains;
       size_t ci = 0, xo = 0;
       for (Kind& k : kinds) {
-        if ((k.plan == 0 || k.plan == HH_PLAN_TILE) && !k.tune) continue;
+        if ((k.plan == 0 || k.plan == HH_PLAN_TILE || k.plan == HH_PLAN_REC) && !k.tune) continue;
         for (SweepTask& tk : k.tasks) {
           tk.bar = sync_ + 32 * (1 + ci++);
           tk.xch = (char*)xch_ + xo;

@@ -1430,8 +1430,37 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
   size_t esz = fs.precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
   size_t lds = (size_t)(fs.max_kl + 1 + LU_CH) * (2 * fs.max_kl + 1) * esz;
   double bytes = 0;
-  for (auto& s : fs.strips) bytes += 2.0 * (double)s.ns * s.ldab * esz;
+  for (size_t u = fs.nsub > 1 ? fs.first_sub : 0; u < fs.strips.size(); ++u)
+    bytes += 2.0 * (double)fs.strips[u].ns * fs.strips[u].ldab * esz;
   TimedRegion tr(FAM_FACTOR, st, bytes);
+  if (fs.nsub > 1) {
+    // recursive strip solves: the sub-blocks, by the blocked LU (any band
+    // half-width) and the lane-major image
+    const int nsubs = (int)fs.strips.size() - fs.first_sub;
+    int ns_sub = 0;
+    for (size_t u = fs.first_sub; u < fs.strips.size(); ++u) ns_sub = std::max(ns_sub, fs.strips[u].ns);
+    const StripDesc* ds = fs.d_strips + fs.first_sub;
+    int* pf = fs.d_pflag + fs.first_sub;
+    const size_t bl = lu_blk_lds(fs.max_kl);
+    const dim3 gi((unsigned)(((long long)(ns_sub + HH_PAD) * 64 + 255) / 256), (unsigned)nsubs);
+    if (fs.precision == HH_FP64) {
+      HH_HIP(hipFuncSetAttribute((const void*)k_band_lu_blk<double>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bl));
+      hipLaunchKernelGGL(k_band_lu_blk<double>, dim3(nsubs), dim3(256), bl, st, ds, (c128*)fs.band,
+                         fs.piv, fs.d_err, pf);
+      hipLaunchKernelGGL(k_build_image<double>, gi, dim3(256), 0, st, ds, (const c128*)fs.band,
+                         (c128*)fs.img, fs.piv, pf);
+    } else {
+      HH_HIP(hipFuncSetAttribute((const void*)k_band_lu_blk<float>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bl));
+      hipLaunchKernelGGL(k_band_lu_blk<float>, dim3(nsubs), dim3(256), bl, st, ds, (c64*)fs.band,
+                         fs.piv, fs.d_err, pf);
+      hipLaunchKernelGGL(k_build_image<float>, gi, dim3(256), 0, st, ds, (const c64*)fs.band,
+                         (c64*)fs.img, fs.piv, pf);
+    }
+    HH_HIP(hipGetLastError());
+    return;
+  }
   if (fs.precision == HH_FP64) {
     launch_lu<double>(pb, lds, st);
     HH_HIP(hipGetLastError());

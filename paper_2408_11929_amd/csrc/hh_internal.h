@@ -121,6 +121,9 @@ constexpr int HH_PLAN_PAIR = 2;
 // with tiles of two right-hand sides per chain (k_sweep_n).
 constexpr int HH_PLAN_TILE = 3;
 constexpr int HH_NCHOICE = 4;
+// The launch of a factorisation with recursive strip solves (k_sweep_rec);
+// not a choice the tuner makes.
+constexpr int HH_PLAN_REC = 4;
 // One strip of one sweep direction (0 = x / LRL, 1 = y / BTB).
 struct StripDesc {
   int dir;        // 0 x, 1 y
@@ -153,6 +156,15 @@ struct StripDesc {
   long long t_off;     // complex elements into the solve image: transfer maps (L, then U)
   long long phi_off[HH_NPLAN];  // plans p >= 1: complex elements into the solve image of the
                                 // segment responses (L, then U; see plan_phi_elems)
+  // Recursive strip solves (hh_factor_sweeps_inner): an outer strip names its
+  // nsub sub-blocks (the descriptors this + sub .. this + sub + nsub - 1) and carries no
+  // factors; a sub-block of the strip of width w (its a, w, dir are the
+  // strip's) covers the strip's lines c0 .. c0+len-1 along its length, in the
+  // order q' = (l - c0) w + t (orient 0) or q' = t len + (l - c0) (orient 1),
+  // with has1/has2 and tr1_off/tr2_off for its own interfaces (w nodes each).
+  int sub;
+  int nsub;
+  int c0, len, orient;
 };
 
 // Band half-widths: the one-wave LU window, the blocked substitution and the
@@ -205,6 +217,9 @@ struct FactorSet {
   bool batch_maps = true;             // the maps of plans 0 and 2 are built or queued
   size_t band_elems = 0, img_elems = 0, piv_elems = 0, tr_elems = 0;
   int max_ns = 0, max_kl = 0;
+  int nsub = 1;       // sub-blocks per strip (> 1: recursive strip solves)
+  int first_sub = 0;  // index of the first sub-block in strips
+  long long rho_elems = 0;  // per-chain strip scratch of a sweep (elements)
   size_t bytes() const;
 };
 
@@ -273,7 +288,7 @@ struct Medium {
 // ---------------------------------------------------------------- problems
 // Internal halves of hh_assemble / hh_factor_sweeps / hh_free (capi.cpp),
 // also driven asynchronously by the serving loop.
-void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision);
+void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision, int nsub = 1);
 void factor_launch(hh_problem* pb, hipStream_t st);
 int factor_finish(hh_problem* pb);
 hh_problem* problem_create(double omega, int nlayers, const double* c_layers, int n,

@@ -1211,6 +1211,134 @@ __global__ __launch_bounds__(64) void k_sweep_lm(const SweepTask* __restrict__ t
   }
 }
 
+// Inner transmission data of a sub-block interface node (strip-local line l,
+// position t across the strip): g = sum_d coef_d U[neighbour d] over the
+// seven stencil neighbours in the strip's local order q = l w + t (x strips:
+// t along x, l along y; y strips: l along x, t along y).  Neighbours outside
+// the strip have zero coefficients and are skipped.
+template <class T>
+__device__ __forceinline__ cx<T> inner_transmission(gptr<const cx<T>> coef, gptr<cx<T>> U, int l,
+                                                    int t, int w, int n, int dir) {
+  const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
+  const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
+  cx<T> g = mk((T)0, (T)0);
+#pragma unroll
+  for (int d = 0; d < 7; ++d) {
+    const int ll = l + (dir == 0 ? dj[d] : di[d]), tt = t + (dir == 0 ? di[d] : dj[d]);
+    if (ll < 0 || ll >= n || tt < 0 || tt >= w) continue;
+    g = cfma(g, ld<T>(coef, d), ld<T>(U, (long long)ll * w + tt));
+  }
+  return g;
+}
+
+// Double sweeps whose strip solves are inner double sweeps (recursive strip
+// solves, Sec. 4 closing discussion): one wave per chain.  Per outer step the
+// strip right-hand side R_s r + g (outer transmission data as in k_sweep) goes
+// to scratch A, the inner solution U starts from zero, and sub-blocks t = 1..N2
+// then N2-1..1 are solved with the lane-major substitution: right-hand side
+// A restricted to the sub-block plus its inner transmission data (formed from
+// U, the Gamma_1 data kept for the backward pass), solution written over U.
+// U then goes over z.  Scratch per chain (rho): A, U and the sub-block vector
+// (ns of the strip each), then the inner Gamma_1 data (N2 x w).  Dynamic LDS:
+// the outer data (2n) and the inner data (2n).
+template <class T, int D, int SL>
+__global__ __launch_bounds__(64) void k_sweep_rec(const SweepTask* __restrict__ tasks) {
+  constexpr int S = 2 * SL;
+  extern __shared__ char smem_raw[];
+  const SweepTask& tk = tasks[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int n = uni(tk.n), N = uni(tk.N);
+  cx<T>* gl1 = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* gl2 = gl1 + n;
+  cx<T>* gi1 = gl2 + n;
+  cx<T>* gi2 = gi1 + n;
+  const cx<T>* img = uniptr((const cx<T>*)tk.img);
+  const int* pivb = uniptr(tk.piv);
+  const cx<T>* trb = uniptr((const cx<T>*)tk.tr);
+  const cx<T> zero = mk((T)0, (T)0);
+  gptr<cx<T>> z = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.z);
+  gptr<cx<T>> rho = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.rho);
+  gptr<cx<T>> g1 = (gptr<cx<T>>)uniptr((cx<T>*)tk.ch.g1);
+  gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
+  const StripDesc* strips = uniptr(tk.ch.strips);
+  const int mode = uni(tk.mode);
+  const int nsteps = sweep_steps(mode, N);
+  for (int step = 0; step < nsteps; ++step) {
+    const SweepStep ss = sweep_step(mode, N, step);
+    const int s = ss.s;
+    const StripDesc* sp = strips + s;
+    const int ns = uni(sp->ns), w = uni(sp->w);
+    const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
+    const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
+    const bool use1 = has1 && ss.data1;
+    const bool use2 = has2 && ss.data2;
+    strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, use1, use2, ss.fwd, ss.keep, t1off, t2off);
+    __syncthreads();
+    gptr<cx<T>> A = rho, U = rho + ns, C = rho + 2LL * ns, G1 = rho + 3LL * ns;
+    const float winv = 1.0f / (float)w;
+    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, use1, use2, winv};
+    // a single wave: its memory accesses are performed in order, the fences
+    // only keep the compiler from reordering them
+    for (int q = lane; q < ns; q += 64) {
+      st<T>(A, q, gather.get(gather.load(q)));
+      st<T>(U, q, zero);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    const StripDesc* subs = sp + uni(sp->sub);
+    const int N2 = uni(sp->nsub);
+    for (int it = 0; it < 2 * N2 - 1; ++it) {
+      const SweepStep is = sweep_step(SWEEP_DOUBLE, N2, it);
+      const StripDesc* up = subs + is.s;
+      const int c0 = uni(up->c0), len = uni(up->len), orient = uni(up->orient), nsu = uni(up->ns);
+      const bool u1 = uni(up->has1) && is.data1, u2 = uni(up->has2) && is.data2;
+      const long long i1 = uni(up->tr1_off), i2 = uni(up->tr2_off);
+      for (int t = lane; t < w; t += 64) {
+        cx<T> e1 = zero, e2 = zero;
+        if (u1) {
+          if (is.fwd) {
+            e1 = inner_transmission<T>((gptr<const cx<T>>)(trb + i1 + 7LL * t), U, c0, t, w, n, dir);
+            if (is.keep) st<T>(G1, (long long)is.s * w + t, e1);
+          } else {
+            e1 = ld<T>(G1, (long long)is.s * w + t);
+          }
+        }
+        if (u2)
+          e2 = inner_transmission<T>((gptr<const cx<T>>)(trb + i2 + 7LL * t), U, c0 + len - 1, t, w,
+                                     n, dir);
+        gi1[t] = e1;
+        gi2[t] = e2;
+      }
+      __syncthreads();
+      for (int q = lane; q < nsu; q += 64) {
+        const int L = orient == 0 ? q / w : q % len, Tt = orient == 0 ? q % w : q / len;
+        cx<T> v = ld<T>(A, (long long)(c0 + L) * w + Tt);
+        if (u1 && L == 0) v = v + gi1[Tt];
+        if (u2 && L == len - 1) v = v + gi2[Tt];
+        st<T>(C, q, v);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      const long long ioff = uni(up->img_off), NP = nsu + HH_PAD;
+      solve_lower_w<T, D, SL>(C, (gptr<const cx<T>>)(img + ioff),
+                              (gptr<const int>)(pivb + uni(up->piv_off)), nsu, lane);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      gptr<cx<T>> x[1] = {C};
+      gptr<const cx<T>> Um[1] = {(gptr<const cx<T>>)(img + ioff + NP * 64 * SL)};
+      gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(img + ioff + NP * 64 * (SL + S))};
+      solve_upper<T, 1, D, S>(x, Um, rdg, nsu, lane);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      for (int q = lane; q < nsu; q += 64) {
+        const int L = orient == 0 ? q / w : q % len, Tt = orient == 0 ? q % w : q / len;
+        st<T>(U, (long long)(c0 + L) * w + Tt, ld<T>(C, q));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __syncthreads();
+    }
+    const DstScatter<T> out{z, ns, w, n, a, dir, winv};
+    for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(U, q));
+    __syncthreads();
+  }
+}
+
 // k_sweep for tiles of NR = 2 right-hand sides of the same preconditioner
 // (unpivoted strips, segment plan 0): task t carries its two chains in ch and
 // ch2 (the same strips and sweep mode; a tile of one repeats its chain in
@@ -1967,6 +2095,33 @@ static void launch_sweep_lm_t(const SweepTask* d, int ntasks, int nmax, hipStrea
   hipLaunchKernelGGL((k_sweep_lm<T, LaneMajorShape<T>::D, SL>), dim3(ntasks), dim3(64), lds, st,
                      d);
 }
+template <class T, int SL>
+static void launch_sweep_rec_t(const SweepTask* d, int ntasks, int nmax, hipStream_t st) {
+  const size_t lds = (size_t)4 * nmax * sizeof(cx<T>);
+  const void* fn = (const void*)k_sweep_rec<T, LaneMajorShape<T>::D, SL>;
+  if (lds > 64 * 1024)
+    HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_sweep_rec<T, LaneMajorShape<T>::D, SL>), dim3(ntasks), dim3(64), lds, st,
+                     d);
+}
+static void launch_sweep_rec(const SweepTask* d, int ntasks, int precision, int kmax, int nmax,
+                             hipStream_t st) {
+  const int SL = lane_slots(kmax);
+  if (kmax > HH_KL_MAX || SL < 1 || SL > 3) {
+    set_error("no recursive sweep for sub-block band half-width %d", kmax);
+    throw ArgError();
+  }
+  if (precision == HH_FP64) {
+    if (SL == 1) launch_sweep_rec_t<double, 1>(d, ntasks, nmax, st);
+    else if (SL == 2) launch_sweep_rec_t<double, 2>(d, ntasks, nmax, st);
+    else launch_sweep_rec_t<double, 3>(d, ntasks, nmax, st);
+  } else {
+    if (SL == 1) launch_sweep_rec_t<float, 1>(d, ntasks, nmax, st);
+    else if (SL == 2) launch_sweep_rec_t<float, 2>(d, ntasks, nmax, st);
+    else launch_sweep_rec_t<float, 3>(d, ntasks, nmax, st);
+  }
+  HH_HIP(hipGetLastError());
+}
 static void launch_sweep_lm(const SweepTask* d, int ntasks, int precision, int kmax, int nmax,
                             hipStream_t st) {
   const int SL = lane_slots(kmax);
@@ -1987,6 +2142,10 @@ static void launch_sweep_lm(const SweepTask* d, int ntasks, int precision, int k
 void launch_sweep(const SweepTask* d_tasks, int ntasks, int precision, int KP, int P, int kmax,
                   int nmax, bool pivots, int plan, unsigned* abort, hipStream_t st) {
   if (ntasks <= 0) return;
+  if (plan == HH_PLAN_REC) {
+    launch_sweep_rec(d_tasks, ntasks, precision, kmax, nmax, st);
+    return;
+  }
   if (kmax > HH_KL_WINDOW) {
     if (plan != 0) {
       set_error("strips of band half-width %d run on segment plan 0 only", kmax);
