@@ -123,12 +123,15 @@ def serve_sweep(hh, torch, count=64, max_active=16, budget_gb=96):
     closed = serving_run(hh, torch, count=count, rate=1e9, max_active=max_active,
                          budget_gb=budget_gb)
     cap = closed["requests_per_s"]
+    print(f"[serve] closed loop: {cap:.2f} requests/s", file=sys.stderr, flush=True)
     runs = []
     for frac in (0.25, 0.5, 0.75, 1.0):
         r = serving_run(hh, torch, count=count, rate=frac * cap, max_active=max_active,
                         budget_gb=budget_gb)
         r["load"] = frac
         runs.append(r)
+        print(f"[serve] load {frac}: p50 {r['latency_ms']['p50']:.0f} ms, "
+              f"p99 {r['latency_ms']['p99']:.0f} ms", file=sys.stderr, flush=True)
     return {"serve_sweep": True, "requests_per_run": count, "closed_loop": closed,
             "capacity_requests_per_s": cap, "runs": runs}
 
@@ -223,6 +226,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only the serving stream at 0.25-1.0 x its measured capacity")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests per run of --serve-sweep")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only the short run used for hardware-counter passes")
     args = ap.parse_args()
@@ -241,7 +246,7 @@ def main():
         kernel_probe(hh, torch)
         return
     if args.serve_sweep:
-        print(json.dumps(serve_sweep(hh, torch)))
+        print(json.dumps(serve_sweep(hh, torch, count=args.serve_requests)))
         return
 
     cfg = wl.layered_321()
