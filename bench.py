@@ -163,6 +163,67 @@ def kernel_probe(hh, torch):
                       "batch_iterations": max(s["iterations"] for s in stb)}))
 
 
+def wide_probe(hh, torch):
+    """Sec. 4's set-up with the widest strips of Table 5: n = 513 (h = 2^-9),
+    five-point scheme, k = 50, the paper's point source, N = 4 strips per
+    direction (band half-width 132: the blocked MFMA LU and the lane-major
+    sweep).  Factors in complex64 and complex128 and solves once with LRL+BTB
+    in FP64; the run the wide-band LU's counters are taken on."""
+    import workloads as wl
+    n, k, N = 513, 50.0, 4
+    f = torch.from_numpy(wl.paper_point_source(n, k)).to("cuda")
+    out = {"probe": "wide", "n": n, "k": k, "N": N}
+    for prec, name in ((hh.HH_FP32, "c64"), (hh.HH_FP64, "c128")):
+        pb = hh.Problem.from_field(k, [1.0], n, f=f, scheme="fd5")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec)
+        torch.cuda.synchronize()
+        out[f"factor_s_{name}"] = time.perf_counter() - t0
+        if prec == hh.HH_FP64:
+            t0 = time.perf_counter()
+            x, st, rc = pb.mpgmres(None, tol=1e-6, maxit=60)
+            torch.cuda.synchronize()
+            out.update(solve_s=time.perf_counter() - t0, iterations=st[0]["iterations"],
+                       res_true=st[0]["res_true"], rc=rc)
+        pb.free()
+        print(f"[wide] {name} done", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
+def large_run(hh, torch):
+    """The k_max = 800 layered medium on the 801 x 801 (about 6 points per
+    wavelength) and 1281 x 1281 (about 10) meshes, 32 strips per direction,
+    8 sources per batch: one warm-up batch, then one timed batch with complex64
+    strips and one with complex128 strips (the plain method)."""
+    import workloads as wl
+    out = {"large": True, "runs": []}
+    hh.hh_autotune(True)  # the warm-up measures the segment plans of each launch shape
+    for n in (801, 1281):
+        cfg = wl.large_layered(n)
+        fb = torch.from_numpy(cfg.f()).to("cuda")
+        one_solve(hh, torch, cfg, fb, hh.HH_FP32)
+        one_solve(hh, torch, cfg, fb, hh.HH_FP64)
+        for prec, name in ((hh.HH_FP32, "complex64 strips"), (hh.HH_FP64, "complex128 strips")):
+            hh.hh_timing_enable(True)
+            hh.hh_timing_reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, rc = one_solve(hh, torch, cfg, fb, prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            kb = {k: hh.hh_timing_get(k)["ms"] for k in ("sweep", "spmv", "factor", "orth")}
+            hh.hh_timing_enable(False)
+            out["runs"].append({"workload": cfg.name, "strips": name, "rhs": cfg.nsrc, "seconds": dt,
+                                "solves_per_s": cfg.nsrc / dt,
+                                "iterations_max": max(s["iterations"] for s in st),
+                                "res_true_max": max(s["res_true"] for s in st),
+                                "all_converged": all(s["converged"] for s in st),
+                                "kernel_ms": kb})
+            print(f"[large] n={n} {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def _oracle_solves(cfg, budget_s, max_solves):
     from oracle import assemble as oasm
     from oracle import mpgmres as omp
@@ -228,6 +289,10 @@ def main():
                     help="only the serving stream at 0.25-1.0 x its measured capacity")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests per run of --serve-sweep")
+    ap.add_argument("--wide-probe", action="store_true",
+                    help="factor and solve the Table 5 N = 4 set-up once (wide-strip path)")
+    ap.add_argument("--large", action="store_true",
+                    help="time the k_max = 800 media on 801^2 and 1281^2 meshes (8 sources)")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only the short run used for hardware-counter passes")
     args = ap.parse_args()
@@ -244,6 +309,12 @@ def main():
 
     if args.kernel_probe:
         kernel_probe(hh, torch)
+        return
+    if args.wide_probe:
+        wide_probe(hh, torch)
+        return
+    if args.large:
+        large_run(hh, torch)
         return
     if args.serve_sweep:
         print(json.dumps(serve_sweep(hh, torch, count=args.serve_requests)))

@@ -383,8 +383,8 @@ void launch_sweep_tiles(const SweepTask* d_tiles, int ntiles, int precision, int
 bool sweep_wide_fits(int precision, int P, int kmax, int nmax);
 // Choice for a launch of ntasks chains (without a tuned one): the
 // HH_SWEEP_PLAN environment variable (0-3) when set and possible; else the
-// sixteen-workgroup plan while ntasks times sixteen is at most half the
-// compute units, the two-workgroup plan while its workgroups fit the device
+// sixteen-workgroup plan while ntasks times sixteen workgroups fit the
+// device at once, the two-workgroup plan while its workgroups fit the device
 // at once (built: its maps exist), tiles of two right-hand sides beyond one
 // chain per compute unit, and plan 0 otherwise (always where a strip pivoted).
 int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pivots, bool built);

@@ -2002,11 +2002,14 @@ int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pi
                ? HH_PLAN_WIDE
                : 0;
   }
-  // a few chains: sixteen workgroups each while they take at most half the
-  // device; up to one chain per two compute units: two workgroups each; more:
-  // plan 0, or its tiles beyond one chain per compute unit (the autotuner
-  // measures instead where it is on)
-  if ((long long)ntasks * plan_width(HH_PLAN_WIDE) <= wide_dev().cus / 2) return HH_PLAN_WIDE;
+  // a few chains: sixteen workgroups each while they all fit the device at
+  // once (16 chains of the 801 x 801 medium: 66.6 ms of sweeps per batch
+  // against 243 ms on two workgroups each); up to one chain per two compute
+  // units: two workgroups each; more: plan 0, or its tiles beyond one chain
+  // per compute unit (the autotuner measures instead where it is on)
+  if ((long long)ntasks * plan_width(HH_PLAN_WIDE) <= wide_dev().cus &&
+      sweep_plan_fits(HH_PLAN_WIDE, ntasks, precision, KP, P, kmax, nmax, pivots, built))
+    return HH_PLAN_WIDE;
   if (built && sweep_plan_fits(HH_PLAN_PAIR, ntasks, precision, KP, P, kmax, nmax, pivots, true))
     return HH_PLAN_PAIR;
   return many ? HH_PLAN_TILE : 0;
@@ -2080,11 +2083,13 @@ void launch_sweep_tiles(const SweepTask* d_tiles, int ntiles, int precision, int
   HH_HIP(hipGetLastError());
 }
 
-// Wide strips: prefetch depth D of the lane-major rows (registers: 2 S D
-// complex coefficients per lane, S = 2 SL).
+// Wide strips: prefetch depth D of the lane-major rows (registers: 2 (SL + S) D
+// complex coefficients per lane, S = 2 SL; D divides 64).  Four rows ahead in
+// FP64 and eight in FP32 fit without scratch (a few values go to the
+// accumulation registers at SL = 3).
 template <class T>
 struct LaneMajorShape {
-  static constexpr int D = sizeof(T) == 8 ? 2 : 4;
+  static constexpr int D = sizeof(T) == 8 ? 4 : 8;
 };
 template <class T, int SL>
 static void launch_sweep_lm_t(const SweepTask* d, int ntasks, int nmax, hipStream_t st) {

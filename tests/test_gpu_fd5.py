@@ -8,6 +8,8 @@ against a loose band around the printed values."""
 import os
 
 import numpy as np
+
+import workloads as wl
 import pytest
 
 from oracle import assemble as oasm
@@ -25,10 +27,7 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def paper_source(n, k):
-    h = 1.0 / (n - 1)
-    x = np.arange(n) * h
-    X, Y = np.meshgrid(x, x, indexing="xy")
-    return (3e4 * np.exp(-200.0 * k * ((X - 0.5) ** 2 + (Y - 0.5) ** 2))).ravel().astype(complex)
+    return wl.paper_point_source(n, k)
 
 
 def upper_diagonals(A, n):

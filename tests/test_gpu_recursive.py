@@ -123,3 +123,17 @@ def test_recursive_factorisation_refusals():
     with pytest.raises(hh.HHError, match="inner sweeps"):
         pb.strip_solve(hh.HH_DIR_X, 1, torch.zeros(33 * 11, dtype=torch.complex128, device="cuda"))
     pb.free()
+
+
+def test_recursive_five_point_sweeps_match_oracle():
+    n, N, N2, omega = 65, 2, 8, 30.0
+    f = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+    pb = hh.Problem.from_field(omega, [1.0], n, f=f, scheme="fd5")
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP64, nsub=N2)
+    A = oasm.assemble(omega, [1.0], n, scheme="fd5")
+    r = rand((1, n * n), 13)
+    for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
+        z = host(pb.sweep_apply(d, dev(r)))
+        ref = orc.RecursiveSweep(omega, [1.0], n, N, dname, N2, A=A, scheme="fd5").apply(r[0])
+        check_fp64(z[0], ref, f"recursive five-point sweep {dname}")
+    pb.free()

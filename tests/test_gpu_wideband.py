@@ -121,3 +121,19 @@ def test_bands_beyond_the_lane_major_window_are_refused():
     with pytest.raises(hh.HHError, match="band half-width"):
         pb.factor_sweeps(hh.HH_DIR_X, 2, hh.HH_FP32)
     pb.free()
+
+
+def test_wide_five_point_sweeps_match_oracle():
+    # the strips of Table 5's N = 4 column at a smaller size: five-point
+    # scheme, kl = 67, against the oracle's five-point sweep
+    n, N, omega = 129, 2, 60.0
+    f = torch.zeros(n * n, dtype=torch.complex128, device="cuda")
+    pb = hh.Problem.from_field(omega, [1.0], n, f=f, scheme="fd5")
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, hh.HH_FP64)
+    A = oasm.assemble(omega, [1.0], n, scheme="fd5")
+    r = rand((1, n * n), 12)
+    for d, dname in ((hh.HH_DIR_X, ost.X), (hh.HH_DIR_Y, ost.Y)):
+        z = host(pb.sweep_apply(d, dev(r)))
+        ref = osw.DoubleSweep(omega, [1.0], n, N, dname, A=A, scheme="fd5").apply(r[0])
+        check_fp64(z[0], ref, f"wide five-point sweep {dname}")
+    pb.free()

@@ -48,6 +48,23 @@ def test_noalloc_matches_allocating_entry_point(prec):
         pb.free()
 
 
+def test_noalloc_on_wide_and_recursive_factorisations():
+    # strips beyond the one-wave window (kl = 67, lane-major sweep), then a
+    # factorisation with recursive strip solves, two calls in a row on the
+    # shared scratch
+    calls = [((129, 2, 60.0, [1.0, 1.5]), None, 2, hh.HH_PRE_LRL, hh.HH_FP32),
+             ((33, 4, 18.0, [1.0, 2.0, 1.5]), 4, 1, hh.HH_PRE_BT, hh.HH_FP64)]
+    for (n, N, omega, c), nsub, nvec, kind, prec in calls:
+        pb = hh.Problem(omega, c, n)
+        pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, N, prec, nsub=nsub)
+        r = torch.from_numpy(rand((nvec, n * n), n + 1)).to("cuda")
+        z_ref = apply(pb, kind, r, noalloc=False)
+        z_na = apply(pb, kind, r, noalloc=True)
+        assert np.all(np.isfinite(z_na))
+        assert np.array_equal(z_na, z_ref), np.abs(z_na - z_ref).max()
+        pb.free()
+
+
 def test_noalloc_rejects_oversized_calls():
     n, N = 321, 16
     pb = hh.Problem(200.0, [1.0], n)

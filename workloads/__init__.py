@@ -88,6 +88,15 @@ class Problem:
                 "nsrc": self.nsrc, "sigma": self.sigma, "tol": self.tol}
 
 
+def paper_point_source(n, k):
+    """The source of Sec. 4's experiments: f = 3e4 exp(-200 k r^2) about the
+    centre of the unit square, nodal values (complex) on the n x n grid."""
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    return (3e4 * np.exp(-200.0 * k * ((X - 0.5) ** 2 + (Y - 0.5) ** 2))).ravel().astype(complex)
+
+
 def homogeneous_small():
     """Constant c = 1, k = 20, 101 x 101 nodes, centre Gaussian (sigma 0.02),
     4 strips per direction: the small case the oracle finishes in seconds."""
