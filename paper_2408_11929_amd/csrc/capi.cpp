@@ -247,11 +247,10 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision, int
                 sd.pseg[p], sd.kl);
       sd.img_off = img;
       sd.t_off = img + 2 * blocked_blocks(sd.ns) * sd.KP * 64;
-      sd.phi_off[0] = 0;
       long long po = sd.t_off + 2LL * sd.tmaps * map_dim(sd.KP) * map_dim(sd.KP);
-      for (int p = 1; p < HH_NPLAN; ++p) {
+      for (int p = 0; p < HH_NPLAN; ++p) {
         sd.phi_off[p] = po;
-        if (wide) po += 2 * plan_phi_elems(sd.ns, P, sd.kl, map_dim(sd.KP), p);
+        if (p == 0 || wide) po += 2 * plan_phi_elems(sd.ns, P, sd.kl, map_dim(sd.KP), p);
       }
       if (!rec) img += strip_image_elems(sd.ns, S, sd.KP, sd.kl, P, wide);
       sd.piv_off = piv;
@@ -267,7 +266,7 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision, int
   }
   fs.nsub = rec ? nsub : 1;
   fs.first_sub = (int)fs.strips.size();
-  fs.rho_elems = fs.max_ns;
+  fs.rho_elems = 2LL * fs.max_ns;  // the strip vector and the back substitution's scratch
   if (rec) sub_block_setup(fs, n, nsub, band, img, piv, tr);
   const size_t es = precision == HH_FP64 ? sizeof(c128) : sizeof(c64);
   fs.band_elems = band;

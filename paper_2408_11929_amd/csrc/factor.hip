@@ -993,8 +993,8 @@ __host__ __device__ inline int transfer_ring(int kl) { return kl < 32 ? 32 : 64;
 // (1..nseg-2), and for plans 1 and 2 also the last one (its response only).
 __host__ __device__ inline int transfer_jobs(const StripDesc& sd, int p) {
   const int nseg = plan_nseg(sd.ns, sd.pseg[p]);
-  if (p >= 1) return sd.wide && nseg > 1 ? nseg - 1 : 0;
-  return plan_seg_maps(sd.ns, sd.pseg[p]);
+  if (p >= 1 && !sd.wide) return 0;
+  return nseg > 1 ? nseg - 1 : 0;  // segments 1 .. nseg-1: responses, maps for all but the last
 }
 
 // Segment transfer maps of an unpivoted strip.  The substitutions split a
@@ -1041,16 +1041,15 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
   const int lane = threadIdx.x;
   const bool upper = blockIdx.y == 1;
   const cx<T>* ab = band + sd.band_off;
-  // the tail map T_s exists for s <= nseg-2; the wide plan also keeps every
-  // row of the segment (its response Phi_s), the last segment included
+  // the tail map T_s exists for s <= nseg-2; every row of the segment (its
+  // response Phi_s) is kept too, the last segment included
   const bool tmap = s <= nseg - 2;
   const int KM = map_dim(sd.KP);
   cx<T>* Tm = img + sd.t_off +
               ((upper ? (long long)sd.tmaps : 0LL) + pmap + m) * KM * KM;
-  cx<T>* Ph = plan >= 1 ? img + strips[blockIdx.x].phi_off[plan] +
-                             (upper ? plan_phi_elems(ns, sd.segs, K, KM, plan) : 0LL) +
-                             (long long)(s - 1) * seg * KM
-                       : nullptr;
+  cx<T>* Ph = img + strips[blockIdx.x].phi_off[plan] +
+              (upper ? plan_phi_elems(ns, sd.segs, K, KM, plan) : 0LL) +
+              (long long)(s - 1) * seg * KM;
   const int s0 = s * seg, s1 = s0 + seg < ns ? s0 + seg : ns;
   // lane c < K fetches T(i, c + 1)
   auto coef = [&](int i) -> c128 {

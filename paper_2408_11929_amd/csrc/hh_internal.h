@@ -154,8 +154,8 @@ struct StripDesc {
   int pi_map[HH_NPLAN], a1_map[HH_NPLAN], a2_map[HH_NPLAN], ps_map[HH_NPLAN];
   int wide;            // the maps and responses of plans 1 and 2 exist (sweep_wide_fits)
   long long t_off;     // complex elements into the solve image: transfer maps (L, then U)
-  long long phi_off[HH_NPLAN];  // plans p >= 1: complex elements into the solve image of the
-                                // segment responses (L, then U; see plan_phi_elems)
+  long long phi_off[HH_NPLAN];  // complex elements into the solve image of the segment
+                                // responses of plan p (L, then U; see plan_phi_elems)
   // Recursive strip solves (hh_factor_sweeps_inner): an outer strip names its
   // nsub sub-blocks (the descriptors this + sub .. this + sub + nsub - 1) and carries no
   // factors; a sub-block of the strip of width w (its a, w, dir are the
@@ -343,7 +343,7 @@ struct SweepChain {
   const StripDesc* strips;  // N descriptors of the direction (device)
   const c128* r;            // FP64 input, n*n
   void* z;                  // output in sweep precision, n*n
-  void* rho;                // scratch, >= max ns elements of sweep precision
+  void* rho;                // scratch, >= 2 max ns elements of sweep precision (FactorSet::rho_elems)
   void* g1;                 // scratch, N*n elements of sweep precision
 };
 // One double sweep: one chain over the N strips of a direction.
@@ -447,7 +447,7 @@ __host__ __device__ inline int plan_wg_maps(int ns, int seg, int P, int G) {
 __host__ __device__ constexpr int map_dim(int KP) {
   return KP <= 8 ? 16 : KP <= 10 ? 24 : KP <= 12 ? 32 : KP <= 16 ? 48 : 64;
 }
-// Segment responses of plan p >= 1 (one triangle): for segments c = 1 ..
+// Segment responses of plan p (one triangle): for segments c = 1 ..
 // nseg-1, the outputs of the segment's rows started from the unit state e_k
 // with zero inputs, Phi_c[k][i] at ((c - 1) KM + k) seg + i (zero for k >= K).
 __host__ __device__ inline long long plan_phi_elems(int ns, int P, int K, int KM, int p) {
@@ -520,7 +520,8 @@ inline long long strip_image_elems(long long ns, int S, int KP, int K, int P, bo
   sd.wide = wide;
   const int KM = map_dim(KP);
   long long phi = 0;
-  for (int p = 1; wide && p < HH_NPLAN; ++p) phi += 2 * plan_phi_elems((int)ns, P, K, KM, p);
+  for (int p = 0; p < HH_NPLAN; ++p)
+    if (p == 0 || wide) phi += 2 * plan_phi_elems((int)ns, P, K, KM, p);
   const long long blocked = 2 * blocked_blocks(ns) * KP * 64 + 2LL * plan_layout(sd) * KM * KM + phi;
   return lane_major > blocked ? lane_major : blocked;
 }

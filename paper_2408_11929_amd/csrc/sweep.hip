@@ -661,6 +661,10 @@ struct DstC128 {  // strip-local FP64 output, reversed order
     x[q].re = (double)v.re;
     x[q].im = (double)v.im;
   }
+  __device__ cx<T> get(int i) const {  // exact: the value put was of this precision
+    const int q = ns - 1 - i;
+    return mk((T)x[q].re, (T)x[q].im);
+  }
 };
 // Scatter of the strip solution over the global vector, reversed order (the
 // back substitution produces the last local row first).
@@ -744,22 +748,136 @@ __device__ __forceinline__ cx<T> map_apply(const cx<T>* M, const cx<T>* x, cx<T>
   return csel(lane < K, v + y, zero);
 }
 
-// One triangular substitution of a strip by all P waves of the workgroup
-// (the recurrence is linear, so it splits exactly over segments of seg rows):
-//  1. every segment but the last runs from a zero state; segment 0 is then
-//     final and written out, the others keep only their last K outputs;
+// outputs += Phi_c s_c over the rows 0..len-1 of a segment (lane = row), RB
+// blocks of 64 rows at a time with all their response loads issued together
+// (the correction is bound by those loads' latency), each row's KM terms
+// into four partial sums in a fixed order, so that the tiles of k_sweep_n and
+// plan 0 agree bit for bit.  Phi_c[k][i] at k seg + i, zero-padded to KM rows
+// (the padding adds exact zeros); sc: the state (LDS, zero beyond K).  The
+// zero-start outputs come from in (the destination itself where that is a
+// contiguous vector, else a contiguous scratch, so that a scattered
+// destination is written once).
+// KC terms of RB row blocks in flight, sized to what the kernels' register
+// files leave (KC a multiple of four dividing KM: the order of a row's terms
+// is the same whatever the shape, so plan 0 and the tiles still agree).  The
+// loop over chunks stays rolled: unrolled, the scheduler hoists every chunk's
+// loads to the top and the kernels spill.
+template <class T, int KM, int NR>
+struct ResponseShape {
+  static constexpr bool dbl = sizeof(T) == 8;
+  static constexpr int KC = dbl ? (KM == 24 ? 8 : 16)
+                                : NR == 1 ? (KM == 48 ? 16 : KM == 64 ? 32 : KM)
+                                          : (KM <= 24 ? KM : 16);
+  static constexpr int RB = dbl ? (KM == 24 ? 2 : 1)
+                                : NR == 1 ? (KM == 16 ? 4 : KM == 24 || KM == 48 ? 2 : 1)
+                                          : (KM == 16 ? 2 : 1);
+  static_assert(KC % 4 == 0 && KM % KC == 0, "whole chunks of four terms");
+};
+template <class T, int KM, class Out, class In>
+__device__ __forceinline__ void add_response(const Out& out, const In& in, int len, int seg,
+                                             gptr<const cx<T>> Ph, const cx<T>* sc, int lane) {
+  constexpr int KC = ResponseShape<T, KM, 1>::KC, RB = ResponseShape<T, KM, 1>::RB;
+  const cx<T> zero = mk((T)0, (T)0);
+  for (int i0 = 0; i0 < len; i0 += 64 * RB) {
+    int ic[RB];
+    cx<T> a[RB][4];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = i0 + 64 * b + lane;
+      ic[b] = i < len ? i : len - 1;
+      a[b][0] = in.get(ic[b]);
+      a[b][1] = a[b][2] = a[b][3] = zero;
+    }
+#pragma unroll 1
+    for (int k0 = 0; k0 < KM; k0 += KC) {
+      cx<T> pv[RB][KC];
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int q = 0; q < KC; ++q) pv[b][q] = ld<T>(Ph, (long long)(k0 + q) * seg + ic[b]);
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int q = 0; q < KC; ++q) a[b][q & 3] = cfma(a[b][q & 3], pv[b][q], sc[k0 + q]);
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = i0 + 64 * b + lane;
+      if (i < len) out.put(i, (a[b][0] + a[b][1]) + (a[b][2] + a[b][3]));
+    }
+  }
+}
+
+// add_response for the NR right-hand sides of a tile: per right-hand side the
+// same operations in the same order, the responses read once for all, and
+// every zero-start output read before any corrected one is written (a tile
+// of one repeats its chain: both then read the same value and write the same
+// result).
+template <class T, int KM, int NR, class Out, class In>
+__device__ __forceinline__ void add_response_n(const Out (&out)[NR], const In (&in)[NR], int len,
+                                               int seg, gptr<const cx<T>> Ph,
+                                               const cx<T>* const (&sc)[NR], int lane) {
+  constexpr int KC = ResponseShape<T, KM, NR>::KC, RB = ResponseShape<T, KM, NR>::RB;
+  const cx<T> zero = mk((T)0, (T)0);
+  for (int i0 = 0; i0 < len; i0 += 64 * RB) {
+    int ic[RB];
+    cx<T> a[RB][NR][4];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = i0 + 64 * b + lane;
+      ic[b] = i < len ? i : len - 1;
+#pragma unroll
+      for (int v = 0; v < NR; ++v) {
+        a[b][v][0] = in[v].get(ic[b]);
+        a[b][v][1] = a[b][v][2] = a[b][v][3] = zero;
+      }
+    }
+#pragma unroll 1
+    for (int k0 = 0; k0 < KM; k0 += KC) {
+      cx<T> pv[RB][KC];
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int q = 0; q < KC; ++q) pv[b][q] = ld<T>(Ph, (long long)(k0 + q) * seg + ic[b]);
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int v = 0; v < NR; ++v)
+#pragma unroll
+          for (int q = 0; q < KC; ++q)
+            a[b][v][q & 3] = cfma(a[b][v][q & 3], pv[b][q], sc[v][k0 + q]);
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int i = i0 + 64 * b + lane;
+      if (i < len) {
+#pragma unroll
+        for (int v = 0; v < NR; ++v)
+          out[v].put(i, (a[b][v][0] + a[b][v][1]) + (a[b][v][2] + a[b][v][3]));
+      }
+    }
+  }
+}
+
+// One triangular substitution of a strip by all P waves of the workgroup,
+// segment plan 0 (the recurrence is linear, so it splits exactly over
+// segments of seg rows):
+//  1. every segment runs from a zero state and writes its outputs (segment
+//     0's state is the true one, so its outputs are final); the tails (last
+//     K outputs) of all but the last go to yt;
 //  2. wave 0 propagates the true states, state_{s+1} = tail_s + T_s state_s,
 //     with the transfer maps T_s staged into LDS;
-//  3. segments 1.. run again from their true state and are written out.
-// Phase 1 of a segment and phase 3 of the next one together cost two blocked
-// substitutions of seg rows, so the chain of one strip shortens from ns to
-// about 2 ns / P rows.  work: the LDS shared by the rings (phases 1 and 3,
-// 640 entries per wave) and the staged maps (phase 2, KM x KM each); yt,
-// stt: 64 entries per segment.
-template <class T, int KP, int U, int NB, class Src, class Dst>
-__device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, const cx<T>* G,
-                                               const cx<T>* Tm, int ns, int K, int seg,
-                                               cx<T>* work, cx<T>* yt, cx<T>* stt) {
+//  3. segments 1.. add their response Phi_s times their state (the outputs of
+//     the segment started from the unit states with zero inputs).
+// The chain of one strip is one blocked substitution of seg rows, about ns / P
+// (a second substitution in place of phase 3 would double it).  work: the
+// LDS shared by the rings (phase 1, 640 entries per wave) and the staged maps
+// (phase 2, KM x KM each); yt, stt: 64 entries per segment.
+template <class T, int KP, int U, int NB, class Src, class Dst, class Tmp>
+__device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, const Tmp& tmp,
+                                               const cx<T>* G, const cx<T>* Tm, const cx<T>* Ph,
+                                               int ns, int K, int seg, cx<T>* work, cx<T>* yt,
+                                               cx<T>* stt) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
   const int nseg = (ns + seg - 1) / seg;
   cx<T>* ring = work + 640 * wv;
@@ -768,11 +886,11 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
   if (wv == 0) {
     solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, 0, len}, SegDst<T, Dst>{dst, 0}, Gw, len, K, ring,
                             (const cx<T>*)nullptr, lane);
-    if (nseg > 1 && lane < K) yt[lane] = ring[(len - K + lane) & 255];
-  } else if (wv < nseg - 1) {
-    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, DstTail<T>{yt + 64 * wv, len, K}, Gw, len,
-                            K, ring, (const cx<T>*)nullptr, lane);
+  } else if (wv < nseg) {
+    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, SegDst<T, Tmp>{tmp, off}, Gw, len, K,
+                            ring, (const cx<T>*)nullptr, lane);
   }
+  if (wv < nseg - 1 && lane < K) yt[64 * wv + lane] = ring[(len - K + lane) & 255];
   if (nseg == 1) return;
   __syncthreads();
   constexpr int KM = map_dim(KP);
@@ -800,9 +918,12 @@ __device__ __forceinline__ void solve_triangle(const Src& src, const Dst& dst, c
     }
   }
   __syncthreads();
+  // the rings were overwritten by the staged maps: the zero-start outputs
+  // come back from tmp
   if (wv >= 1 && wv < nseg)
-    solve_blocked<T, KP, U, NB>(SegSrc<Src>{src, off, len}, SegDst<T, Dst>{dst, off}, Gw, len, K, ring,
-                            stt + 64 * wv, lane);
+    add_response<T, KM>(SegDst<T, Dst>{dst, off}, SegDst<T, Tmp>{tmp, off}, len, seg,
+                        (gptr<const cx<T>>)(Ph + (long long)(wv - 1) * seg * KM), stt + 64 * wv,
+                        lane);
 }
 
 // ---------------------------------------------------------------- RHS tiles
@@ -938,11 +1059,13 @@ __device__ __forceinline__ void solve_blocked_n(const Src (&src)[NR], const Dst 
 
 // solve_triangle for NR right-hand sides of the same strip (segment plan 0):
 // the same three phases, each wave carrying its segment for all NR; the
-// transfer maps are staged once.  work: max(640 P NR, (P - 2) KM^2) entries;
-// yt, stt: 64 P entries per right-hand side (right-hand side v at 64 P v).
-template <class T, int KP, int U, int NB, int NR, class Src, class Dst>
+// transfer maps are staged once, the responses read once per 64 rows for
+// both.  work: max(640 P NR, (P - 2) KM^2) entries; yt, stt: 64 P entries per
+// right-hand side (right-hand side v at 64 P v).
+template <class T, int KP, int U, int NB, int NR, class Src, class Dst, class Tmp>
 __device__ __forceinline__ void solve_triangle_n(const Src (&src)[NR], const Dst (&dst)[NR],
-                                                 const cx<T>* G, const cx<T>* Tm, int ns, int K,
+                                                 const Tmp (&tmp)[NR], const cx<T>* G,
+                                                 const cx<T>* Tm, const cx<T>* Ph, int ns, int K,
                                                  int seg, cx<T>* work, cx<T>* yt, cx<T>* stt) {
   static_assert(NR == 2, "tiles of two right-hand sides (what the register budget allows)");
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nthr = blockDim.x;
@@ -958,14 +1081,15 @@ __device__ __forceinline__ void solve_triangle_n(const Src (&src)[NR], const Dst
     SegSrc<Src> ss[NR] = {SegSrc<Src>{src[0], 0, len}, SegSrc<Src>{src[NR - 1], 0, len}};
     SegDst<T, Dst> sd[NR] = {SegDst<T, Dst>{dst[0], 0}, SegDst<T, Dst>{dst[NR - 1], 0}};
     solve_blocked_n<T, KP, U, NB, NR>(ss, sd, Gw, len, K, ring, none, lane);
-    if (nseg > 1 && lane < K) {
-#pragma unroll
-      for (int v = 0; v < NR; ++v) yt[64 * P * v + lane] = ring[640 * v + ((len - K + lane) & 255)];
-    }
-  } else if (wv < nseg - 1) {
+  } else if (wv < nseg) {
     SegSrc<Src> ss[NR] = {SegSrc<Src>{src[0], off, len}, SegSrc<Src>{src[NR - 1], off, len}};
-    DstTail<T> tl[NR] = {DstTail<T>{yt + 64 * wv, len, K}, DstTail<T>{yt + 64 * P * (NR - 1) + 64 * wv, len, K}};
-    solve_blocked_n<T, KP, U, NB, NR>(ss, tl, Gw, len, K, ring, none, lane);
+    SegDst<T, Tmp> sd[NR] = {SegDst<T, Tmp>{tmp[0], off}, SegDst<T, Tmp>{tmp[NR - 1], off}};
+    solve_blocked_n<T, KP, U, NB, NR>(ss, sd, Gw, len, K, ring, none, lane);
+  }
+  if (wv < nseg - 1 && lane < K) {
+#pragma unroll
+    for (int v = 0; v < NR; ++v)
+      yt[64 * P * v + 64 * wv + lane] = ring[640 * v + ((len - K + lane) & 255)];
   }
   if (nseg == 1) return;
   __syncthreads();
@@ -1000,10 +1124,11 @@ __device__ __forceinline__ void solve_triangle_n(const Src (&src)[NR], const Dst
   }
   __syncthreads();
   if (wv >= 1 && wv < nseg) {
-    SegSrc<Src> ss[NR] = {SegSrc<Src>{src[0], off, len}, SegSrc<Src>{src[NR - 1], off, len}};
-    SegDst<T, Dst> sd[NR] = {SegDst<T, Dst>{dst[0], off}, SegDst<T, Dst>{dst[NR - 1], off}};
-    const cx<T>* st0[NR] = {stt + 64 * wv, stt + 64 * P * (NR - 1) + 64 * wv};
-    solve_blocked_n<T, KP, U, NB, NR>(ss, sd, Gw, len, K, ring, st0, lane);
+    const SegDst<T, Dst> sd[NR] = {SegDst<T, Dst>{dst[0], off}, SegDst<T, Dst>{dst[NR - 1], off}};
+    const SegDst<T, Tmp> st[NR] = {SegDst<T, Tmp>{tmp[0], off}, SegDst<T, Tmp>{tmp[NR - 1], off}};
+    const cx<T>* const sc[NR] = {stt + 64 * wv, stt + 64 * P * (NR - 1) + 64 * wv};
+    add_response_n<T, KM, NR>(sd, st, len, seg,
+                              (gptr<const cx<T>>)(Ph + (long long)(wv - 1) * seg * KM), sc, lane);
   }
 }
 
@@ -1127,11 +1252,17 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
       constexpr long long KM2 = (long long)map_dim(KP) * map_dim(KP);
       const cx<T>* TL = img + uni(sp->t_off) + uni(sp->pmap[0]) * KM2;
       const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
-      solve_triangle<T, KP, U, NB>(gather, DstVec<T>{rho, ns, false}, GL, TL, ns, kl, seg, work, yt,
-                               stt);
+      const cx<T>* PL = img + uni(sp->phi_off[0]);
+      const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
+      // the back substitution's later segments keep their zero-start
+      // outputs in the second half of the chain's scratch, so that z (a
+      // scatter) is written once
+      const DstVec<T> drho{rho, ns, false};
+      solve_triangle<T, KP, U, NB>(gather, drho, drho, GL, TL, PL, ns, kl, seg, work, yt, stt);
       __syncthreads();
       solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
-                               DstScatter<T>{z, ns, w, n, a, dir, winv}, GU, TU, ns, kl, seg, work, yt,
+                               DstScatter<T>{z, ns, w, n, a, dir, winv},
+                               DstVec<T>{rho + ns, ns, false}, GU, TU, PU, ns, kl, seg, work, yt,
                                stt);
     } else if (PIV && wv == 0) {
       // single wave: its memory accesses are performed in order, the fences
@@ -1398,14 +1529,17 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
     constexpr long long KM2 = (long long)map_dim(KP) * map_dim(KP);
     const cx<T>* TL = img + uni(sp->t_off) + uni(sp->pmap[0]) * KM2;
     const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
+    const cx<T>* PL = img + uni(sp->phi_off[0]);
+    const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
     const DstVec<T> drho[NR] = {DstVec<T>{rho[0], ns, false}, DstVec<T>{rho[1], ns, false}};
-    solve_triangle_n<T, KP, U, NB, NR>(gather, drho, GL, TL, ns, kl, seg, work, yt, stt);
+    solve_triangle_n<T, KP, U, NB, NR>(gather, drho, drho, GL, TL, PL, ns, kl, seg, work, yt, stt);
     __syncthreads();
     const SrcVec<T> srho[NR] = {SrcVec<T>{(gptr<const cx<T>>)rho[0], ns, true},
                                 SrcVec<T>{(gptr<const cx<T>>)rho[1], ns, true}};
     const DstScatter<T> dz[NR] = {DstScatter<T>{z[0], ns, w, n, a, dir, winv},
                                   DstScatter<T>{z[1], ns, w, n, a, dir, winv}};
-    solve_triangle_n<T, KP, U, NB, NR>(srho, dz, GU, TU, ns, kl, seg, work, yt, stt);
+    const DstVec<T> dtmp[NR] = {DstVec<T>{rho[0] + ns, ns, false}, DstVec<T>{rho[1] + ns, ns, false}};
+    solve_triangle_n<T, KP, U, NB, NR>(srho, dz, dtmp, GU, TU, PU, ns, kl, seg, work, yt, stt);
     __syncthreads();
   }
 }
@@ -1800,10 +1934,14 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
     constexpr long long KM2 = (long long)map_dim(KP) * map_dim(KP);
     const cx<T>* TL = im + uni(sp->t_off) + uni(sp->pmap[0]) * KM2;
     const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
-    solve_triangle<T, KP, U, NB>(in, DstVec<T>{wk, ns, false}, GL, TL, ns, kl, seg, lds, yt, stt);
+    const cx<T>* PL = im + uni(sp->phi_off[0]);
+    const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
+    const DstVec<T> dwk{wk, ns, false};
+    const DstC128<T> dx{(gptr<c128>)x, ns};
+    solve_triangle<T, KP, U, NB>(in, dwk, dwk, GL, TL, PL, ns, kl, seg, lds, yt, stt);
     __syncthreads();
-    solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true},
-                             DstC128<T>{(gptr<c128>)x, ns}, GU, TU, ns, kl, seg, lds, yt, stt);
+    solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true}, dx, dx, GU, TU, PU, ns,
+                             kl, seg, lds, yt, stt);
   } else if (wv == 0) {
     for (int q = lane; q < ns; q += 64) st<T>(wk, q, in.get(in.load(q)));
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
