@@ -140,6 +140,7 @@ Engine::~Engine() {
   if (sync_) dev_free(sync_);
   if (xch_) dev_free(xch_);
   if (ones_) dev_free(ones_);
+  if (dl_dev_) dev_free(dl_dev_);
 }
 
 template <class TT>
@@ -152,8 +153,9 @@ TT* Engine::stage(const std::vector<TT>& v, size_t& off) {
   return d;
 }
 
-// Copies the staged host descriptors to the device in one transfer.
-void Engine::upload() {
+// Makes the device area hold the staged bytes (its address is final from
+// here until the next stage() beyond it).
+void Engine::reserve_dev() {
   task_host_.reserve(staged_, true);
   if (staged_ > task_cap_) {
     HH_HIP(hipStreamSynchronize(st_));
@@ -161,7 +163,26 @@ void Engine::upload() {
     task_cap_ = staged_ * 2;
     task_dev_ = dev_alloc(task_cap_);
   }
+}
+
+// Copies the staged host descriptors to the device in one transfer.
+void Engine::upload() {
+  reserve_dev();
   if (staged_) HH_HIP(hipMemcpyAsync(task_dev_, task_host_.p, staged_, hipMemcpyHostToDevice, st_));
+}
+
+// Makes the device area hold dl bytes of gathered results (and the pinned
+// host area as many).
+void Engine::reserve_dl(size_t dl) {
+  if (dl > dl_dev_cap_) {
+    HH_HIP(hipStreamSynchronize(st_));
+    if (dl_dev_) dev_free(dl_dev_);
+    dl_dev_ = nullptr;
+    dl_dev_cap_ = 0;
+    dl_dev_ = static_cast<unsigned char*>(dev_alloc(dl * 2));
+    dl_dev_cap_ = dl * 2;
+  }
+  dl_host_.reserve(dl, false);
 }
 
 #define DEV(ptr) reinterpret_cast<std::remove_reference_t<decltype(ptr)>>((char*)task_dev_ + (size_t)(ptr))
@@ -175,7 +196,6 @@ size_t Engine::footprint(const hh_problem* pb, int t, int prec, int maxit) {
   b += L.total * sizeof(c128);
   b += (size_t)nblk_for(len) * (cols + t) * t * sizeof(c128);    // partial sums
   b += (size_t)t * (pb->fs.rho_elems + (size_t)pb->fs.N * pb->n) * esz_of(prec);
-  b += (size_t)cols * t * sizeof(c128);
   if (t > 2) b += (size_t)len * sizeof(c128);                    // summed sweep input
   return b;
 }
@@ -188,7 +208,6 @@ void Engine::release(Solve* s) {
   dev_free(s->flags);
   dev_free(s->rho);
   dev_free(s->g1);
-  dev_free(s->ydev);
   dev_free(s->sumv);
   s->sumv = nullptr;
   s->V = nullptr;
@@ -197,7 +216,6 @@ void Engine::release(Solve* s) {
   s->part = nullptr;
   s->flags = nullptr;
   s->rho = s->g1 = nullptr;
-  s->ydev = nullptr;
 }
 
 size_t Engine::iteration_bytes(const Solve* s) {
@@ -252,13 +270,11 @@ void Engine::ensure_capacity(Solve* s) {
   if (s->m + t > s->hcap || !s->Hd) {
     if (s->Hd) dev_free(s->Hd);
     if (s->part) dev_free(s->part);
-    if (s->ydev) dev_free(s->ydev);
     s->hcap = s->vcap;
     HdLayout L(s->hcap, t);
     s->Hd = (c128*)dev_alloc(L.total * sizeof(c128));
     s->part_elems = (size_t)nblk_for(s->len) * (s->hcap + t) * t;
     s->part = (c128*)dev_alloc(s->part_elems * sizeof(c128));
-    s->ydev = (c128*)dev_alloc((size_t)s->zcap * sizeof(c128) + 256);
   }
 }
 
@@ -297,8 +313,6 @@ void Engine::begin(std::vector<Solve*>& solves) {
     if (!s->rho) s->rho = dev_alloc((size_t)s->t * fs.rho_elems * es + 256);
     if (!s->g1) s->g1 = dev_alloc((size_t)s->t * fs.N * s->pb->n * es + 256);
     if (s->t > 2 && !s->sumv) s->sumv = (c128*)dev_alloc((size_t)s->len * sizeof(c128));
-    if (!s->x0)
-      HH_HIP(hipMemcpyAsync(s->V, s->b, (size_t)s->len * sizeof(c128), hipMemcpyDeviceToDevice, st_));
     live.push_back(s);
   }
   if (live.empty()) return;
@@ -346,14 +360,16 @@ void Engine::begin(std::vector<Solve*>& solves) {
     launch_gram(DEV(dgb), (int)gb.size(), maxblk, 1, 1, st_);
     staged_ = 256;
   }
-  // beta^2 = v1^H v1 into NR slot 0, then v1 = v1 / beta
+  // beta^2 = r0^H r0 into NR slot 0, then v1 = r0 / beta, with r0 = b (read
+  // in place) or b - A x0 (formed in v1's column above)
   std::vector<GramTask> gt;
   std::vector<NormTask> nt;
   for (Solve* s : live) {
     HdLayout L(s->hcap, s->t);
+    const c128* r0 = s->x0 ? s->V : s->b;
     GramTask g{};
-    g.X = s->V;
-    g.Y = s->V;
+    g.X = r0;
+    g.Y = r0;
     g.out = s->Hd + L.nr;
     g.part = s->part;
     g.len = s->len;
@@ -366,6 +382,7 @@ void Engine::begin(std::vector<Solve*>& solves) {
     gt.push_back(g);
     NormTask q{};
     q.y = s->V;
+    q.x = r0;
     q.nrm2 = s->Hd + L.nr;
     q.ref2 = s->Hd + L.nr;
     q.rdiag = s->Hd + L.rd;
@@ -378,21 +395,34 @@ void Engine::begin(std::vector<Solve*>& solves) {
   }
   GramTask* dg = stage(gt, staged_);
   NormTask* dn = stage(nt, staged_);
+  // per solve beta, its square and ||b||^2 to the host in one transfer
+  std::vector<CopyTask> dlt;
+  constexpr long long zw = sizeof(zd) / 4;
+  for (size_t q = 0; q < live.size(); ++q) {
+    const Solve* s = live[q];
+    HdLayout L(s->hcap, s->t);
+    const long long o = (long long)(q * 3 * sizeof(zd));
+    dlt.push_back({s->Hd + L.rd, o, zw});
+    dlt.push_back({s->Hd + L.nr, o + (long long)sizeof(zd), zw});
+    if (s->x0) dlt.push_back({s->Hd + L.g1, o + 2 * (long long)sizeof(zd), zw});
+  }
+  CopyTask* ddl = stage(dlt, staged_);
+  const size_t dl = live.size() * 3 * sizeof(zd);
+  reserve_dl(dl);
   upload();
   launch_gram(DEV(dg), (int)gt.size(), maxblk, 1, 1, st_);
   launch_normalize(DEV(dn), (int)nt.size(), maxlen, st_);
-  for (Solve* s : live) {
-    HdLayout L(s->hcap, s->t);
-    zd v;
-    zd bb(0.0, 0.0), v2(0.0, 0.0);
-    HH_HIP(hipMemcpyAsync(&v, s->Hd + L.rd, sizeof(zd), hipMemcpyDeviceToHost, st_));
-    HH_HIP(hipMemcpyAsync(&v2, s->Hd + L.nr, sizeof(zd), hipMemcpyDeviceToHost, st_));
-    if (s->x0) HH_HIP(hipMemcpyAsync(&bb, s->Hd + L.g1, sizeof(zd), hipMemcpyDeviceToHost, st_));
-    HH_HIP(hipStreamSynchronize(st_));
+  launch_gather(DEV(ddl), (int)dlt.size(), dl_dev_, st_);
+  HH_HIP(hipMemcpyAsync(dl_host_.p, dl_dev_, dl, hipMemcpyDeviceToHost, st_));
+  HH_HIP(hipStreamSynchronize(st_));
+  for (size_t q = 0; q < live.size(); ++q) {
+    Solve* s = live[q];
+    zd r[3];
+    std::memcpy(r, dl_host_.p + q * 3 * sizeof(zd), sizeof(r));
+    const double v = r[0].real(), v2 = r[1].real(), bb = s->x0 ? r[2].real() : 0.0;
     // the normalisation deflates a NaN norm to zero: the raw square tells
-    s->beta = std::isfinite(v2.real()) ? v.real() : v2.real();
-    s->bnorm = s->x0 ? (std::isfinite(bb.real()) ? std::sqrt(std::max(0.0, bb.real())) : bb.real())
-                     : s->beta;
+    s->beta = std::isfinite(v2) ? v : v2;
+    s->bnorm = s->x0 ? (std::isfinite(bb) ? std::sqrt(std::max(0.0, bb)) : bb) : s->beta;
   }
   for (Solve* s : live) {
     s->ls.init(s->beta);
@@ -745,6 +775,27 @@ void Engine::step(std::vector<Solve*>& solves) {
     if (!mu[i].empty()) dmu[i] = stage(mu[i], staged_);
   for (size_t i = 0; i < mn.size(); ++i)
     if (!mn[i].empty()) dmn[i] = stage(mn[i], staged_);
+  // the iteration's results for the host, gathered into one device area and
+  // sent in one transfer: per solve its coefficients and flags, then the
+  // abort word
+  std::vector<size_t> hoff(live.size()), foff(live.size());
+  std::vector<CopyTask> dlt;
+  size_t dl = 0;
+  for (size_t q = 0; q < live.size(); ++q) {
+    Solve* s = live[q];
+    const size_t hb = HdLayout(s->hcap, s->t).total * sizeof(c128);
+    hoff[q] = dl;
+    dlt.push_back({s->Hd, (long long)dl, (long long)(hb / 4)});
+    dl += hb;
+    foff[q] = dl;
+    dlt.push_back({s->flags, (long long)dl, (long long)s->t});
+    dl += (s->t * sizeof(int) + 15) & ~size_t(15);
+  }
+  const size_t aoff = dl;
+  if (sync_) dlt.push_back({sync_, (long long)aoff, 1});
+  dl += sizeof(unsigned);
+  CopyTask* ddl = stage(dlt, staged_);
+  reserve_dl(dl);
   upload();
 
   // ---- launches
@@ -845,27 +896,8 @@ void Engine::step(std::vector<Solve*>& solves) {
   }
 
   // ---- coefficients to the host, least squares, selection
-  // one pinned area: per solve its coefficients and flags, then the abort word
-  std::vector<size_t> hoff(live.size()), foff(live.size());
-  size_t dl = 0;
-  for (size_t q = 0; q < live.size(); ++q) {
-    hoff[q] = dl;
-    dl += HdLayout(live[q]->hcap, live[q]->t).total * sizeof(c128);
-    foff[q] = dl;
-    dl += (live[q]->t * sizeof(int) + 15) & ~size_t(15);
-  }
-  const size_t aoff = dl;
-  dl_host_.reserve(dl + sizeof(unsigned), false);
-  for (size_t q = 0; q < live.size(); ++q) {
-    Solve* s = live[q];
-    HdLayout L(s->hcap, s->t);
-    HH_HIP(hipMemcpyAsync(dl_host_.p + hoff[q], s->Hd, L.total * sizeof(c128),
-                          hipMemcpyDeviceToHost, st_));
-    HH_HIP(hipMemcpyAsync(dl_host_.p + foff[q], s->flags, s->t * sizeof(int),
-                          hipMemcpyDeviceToHost, st_));
-  }
-  if (sync_)
-    HH_HIP(hipMemcpyAsync(dl_host_.p + aoff, sync_, sizeof(unsigned), hipMemcpyDeviceToHost, st_));
+  launch_gather(DEV(ddl), (int)dlt.size(), dl_dev_, st_);
+  HH_HIP(hipMemcpyAsync(dl_host_.p, dl_dev_, dl, hipMemcpyDeviceToHost, st_));
   HH_HIP(hipStreamSynchronize(st_));
   std::vector<std::vector<int>> flags(live.size());
   for (size_t q = 0; q < live.size(); ++q) {
@@ -936,15 +968,14 @@ void Engine::finish(std::vector<Solve*>& solves) {
   std::vector<GramTask> gt;
   long long maxlen = 0;
   int maxblk = 1;
+  // the coefficients y travel with the descriptors: c.y holds the staged
+  // offset until the device area's address is known
   for (Solve* s : fin) {
-    std::vector<zd> y = s->ls.solve();
+    const std::vector<zd> y = s->ls.solve();
     const int nc = (int)y.size();
-    if (nc > 0)
-      HH_HIP(hipMemcpyAsync(s->ydev, y.data(), nc * sizeof(zd), hipMemcpyHostToDevice, st_));
-    HH_HIP(hipStreamSynchronize(st_));
     CombTask c{};
     c.Z = s->Z;
-    c.y = s->ydev;
+    c.y = nc > 0 ? reinterpret_cast<c128*>(stage(y, staged_)) : nullptr;
     c.x0 = s->x0;
     c.x = s->x;
     c.len = s->len;
@@ -985,22 +1016,36 @@ void Engine::finish(std::vector<Solve*>& solves) {
   SpmvTask* dsp = stage(sp, staged_);
   ResTask* drt = stage(rt, staged_);
   GramTask* dgt = stage(gt, staged_);
+  std::vector<CopyTask> dlt;
+  for (size_t q = 0; q < fin.size(); ++q) {
+    const Solve* s = fin[q];
+    HdLayout L(s->hcap, s->t);
+    dlt.push_back({s->Hd + L.nr, (long long)(q * sizeof(zd)), (long long)(sizeof(zd) / 4)});
+  }
+  CopyTask* ddl = stage(dlt, staged_);
+  const size_t dl = fin.size() * sizeof(zd);
+  reserve_dl(dl);
+  reserve_dev();
+  for (int a = 0; a < 2; ++a) {
+    if (!dct[a]) continue;
+    CombTask* hc = reinterpret_cast<CombTask*>(task_host_.p + reinterpret_cast<size_t>(dct[a]));
+    for (size_t i = 0; i < ct[a].size(); ++i)
+      if (hc[i].y) hc[i].y = DEV(hc[i].y);
+  }
   upload();
   for (int a = 0; a < 2; ++a)
     if (dct[a]) launch_combine(DEV(dct[a]), (int)ct[a].size(), maxlen, a == 0 ? HH_FP64 : HH_FP32, st_);
   launch_spmv(DEV(dsp), (int)sp.size(), maxlen, HH_FP64, st_);
   launch_residual(DEV(drt), (int)rt.size(), maxlen, st_);
   launch_gram(DEV(dgt), (int)gt.size(), maxblk, 1, 1, st_);
-  std::vector<zd> nr(fin.size());
-  for (size_t q = 0; q < fin.size(); ++q) {
-    Solve* s = fin[q];
-    HdLayout L(s->hcap, s->t);
-    HH_HIP(hipMemcpyAsync(&nr[q], s->Hd + L.nr, sizeof(zd), hipMemcpyDeviceToHost, st_));
-  }
+  launch_gather(DEV(ddl), (int)dlt.size(), dl_dev_, st_);
+  HH_HIP(hipMemcpyAsync(dl_host_.p, dl_dev_, dl, hipMemcpyDeviceToHost, st_));
   HH_HIP(hipStreamSynchronize(st_));
   for (size_t q = 0; q < fin.size(); ++q) {
     Solve* s = fin[q];
-    s->res_true = s->bnorm > 0 ? std::sqrt(std::max(0.0, nr[q].real())) / s->bnorm : 0.0;
+    zd nr;
+    std::memcpy(&nr, dl_host_.p + q * sizeof(zd), sizeof(zd));
+    s->res_true = s->bnorm > 0 ? std::sqrt(std::max(0.0, nr.real())) / s->bnorm : 0.0;
     if (s->fail == HH_EINVAL) s->res_true = std::numeric_limits<double>::quiet_NaN();
     s->finalized = true;
   }

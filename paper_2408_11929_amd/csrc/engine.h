@@ -71,7 +71,6 @@ struct Solve {
   int* flags = nullptr;   // t deflation flags
   void* rho = nullptr;    // sweep scratch, t chains
   void* g1 = nullptr;
-  c128* ydev = nullptr;
   c128* sumv = nullptr;   // t > 2: the sum of the new basis vectors (sweep input)
   int inputs[4] = {0, 0, 0, 0};
   bool sum_input = false; // the next sweeps read sumv (formed at the next step)
@@ -139,9 +138,13 @@ class Engine {
   size_t task_cap_ = 0;
   PinnedBuf task_host_;  // staged descriptors
   PinnedBuf dl_host_;    // one iteration's coefficients, flags and abort word
+  unsigned char* dl_dev_ = nullptr;  // the same gathered on the device, one transfer
+  size_t dl_dev_cap_ = 0;
   template <class TT>
   TT* stage(const std::vector<TT>& v, size_t& off);
   void upload();
+  void reserve_dev();
+  void reserve_dl(size_t dl);
   void ensure_capacity(Solve* s);
   // ensure_capacity for every solve, stopping (fail) the ones whose growth
   // is refused or cannot be allocated, without touching the others.

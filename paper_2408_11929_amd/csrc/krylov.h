@@ -44,6 +44,7 @@ struct UpdTask {
 // y /= ||y|| unless ||y|| <= tol * ref (then y = 0 and *flag = 1).
 struct NormTask {
   c128* y;
+  const c128* x;     // the vector normalised into y (null: y itself)
   const c128* nrm2;  // .re = ||y||^2
   const c128* ref2;  // .re = reference norm squared
   c128* rdiag;       // receives ||y|| (0 if deflated)
@@ -69,6 +70,14 @@ struct ResTask {
   long long len;
 };
 
+// One region of a gather into a contiguous buffer: `words` 4-byte words from
+// src to byte offset dst (a multiple of 4) of the destination.
+struct CopyTask {
+  const void* src;
+  long long dst;
+  long long words;
+};
+
 void launch_spmv(const SpmvTask* d_tasks, int ntasks, long long max_rows, int xprec,
                  hipStream_t st);
 void launch_gram(const GramTask* d_tasks, int ntasks, int max_nblk, int max_px, int max_ty,
@@ -79,6 +88,9 @@ void launch_normalize(const NormTask* d_tasks, int ntasks, long long max_len, hi
 void launch_combine(const CombTask* d_tasks, int ntasks, long long max_len, int zprec,
                     hipStream_t st);
 void launch_residual(const ResTask* d_tasks, int ntasks, long long max_len, hipStream_t st);
+// The regions of ntasks copy tasks into dst, one workgroup per task (so that
+// an iteration's small results leave the device in one transfer).
+void launch_gather(const CopyTask* d_tasks, int ntasks, unsigned char* dst, hipStream_t st);
 
 }  // namespace hh
 

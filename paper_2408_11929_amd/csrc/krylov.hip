@@ -149,8 +149,9 @@ __global__ __launch_bounds__(256) void k_block_update(const UpdTask* __restrict_
     if (c < tk.ty) tk.Y[c * (long long)tk.ldy + p] = y[c];
 }
 
-// Normalise y by the norm whose square is nrm2->re; deflate (zero y, flag) when
-// the norm is at most tol times sqrt(ref2->re).  grid = (row blocks, tasks).
+// y = x / the norm whose square is nrm2->re (x = y when not given); deflate
+// (zero y, flag) when the norm is at most tol times sqrt(ref2->re).
+// grid = (row blocks, tasks).
 __global__ __launch_bounds__(256) void k_normalize(const NormTask* __restrict__ tasks) {
   const NormTask tk = tasks[blockIdx.y];
   const double nrm = sqrt(fmax(tk.nrm2->re, 0.0));
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void k_normalize(const NormTask* __restrict__ 
     *tk.rdiag = mk(defl ? 0.0 : nrm, 0.0);
     *tk.flag = defl ? 1 : 0;
   }
-  if (p < tk.len) tk.y[p] = cscale(tk.y[p], s);
+  if (p < tk.len) tk.y[p] = cscale(tk.x ? tk.x[p] : tk.y[p], s);
 }
 
 // x = Z y (plus x0 if add); Z columns contiguous with stride len.
@@ -265,6 +266,14 @@ __global__ void k_widen(const c64* __restrict__ a, c128* __restrict__ b, long lo
   long long p = blockIdx.x * 256LL + threadIdx.x;
   if (p < n) b[p] = mk((double)a[p].re, (double)a[p].im);
 }
+
+__global__ __launch_bounds__(256) void k_gather(const CopyTask* __restrict__ tasks,
+                                                unsigned char* __restrict__ dst) {
+  const CopyTask t = tasks[blockIdx.x];
+  const unsigned* __restrict__ src = static_cast<const unsigned*>(t.src);
+  unsigned* __restrict__ out = reinterpret_cast<unsigned*>(dst + t.dst);
+  for (long long i = threadIdx.x; i < t.words; i += blockDim.x) out[i] = src[i];
+}
 }  // namespace
 
 __global__ __launch_bounds__(256) void k_zero(unsigned* __restrict__ p, long long n) {
@@ -276,6 +285,12 @@ void launch_zero(void* p, size_t bytes, hipStream_t st) {
   const long long n = (long long)(bytes / 4);
   if (n <= 0) return;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (unsigned*)p, n);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_gather(const CopyTask* d_tasks, int ntasks, unsigned char* dst, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)ntasks), dim3(256), 0, st, d_tasks, dst);
   HH_HIP(hipGetLastError());
 }
 
