@@ -208,6 +208,12 @@ __global__ void k_pack_strips(int n, Medium md,
   const StripDesc sd = strips[blockIdx.y];
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= sd.ns) return;
+  const int kv = 2 * sd.kl;
+  cx<T>* ab = band + sd.band_off;
+  if (q >= sd.nr) {  // identity rows past the strip's unknowns
+    if (band) ab[(long long)q * sd.ldab + kv] = mk((T)1, (T)0);
+    return;
+  }
   int l = q / sd.w, t = q - l * sd.w;
   int i, j, cx0, cx1, cy0, cy1;
   if (sd.dir == 0) {
@@ -221,8 +227,6 @@ __global__ void k_pack_strips(int n, Medium md,
   node_stencil(i, j, n, cx0, cx1, cy0, cy1, md, false, st);
   const int di[7] = {-1, 0, -1, 0, 1, 0, 1};
   const int dj[7] = {-1, -1, 0, 0, 0, 1, 1};
-  const int kv = 2 * sd.kl;
-  cx<T>* ab = band + sd.band_off;
   for (int d = 0; d < 7 && band; ++d) {  // band == nullptr: the transmission data only
     if (st[d].re == 0.0 && st[d].im == 0.0) continue;
     int ii = i + di[d], jj = j + dj[d];

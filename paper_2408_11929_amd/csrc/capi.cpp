@@ -132,6 +132,7 @@ static void sub_block_setup(FactorSet& fs, int n, int nsub, long long& band, lon
       u.len = std::min(n - 1, (t + 1) * m2 + 1) - u.c0 + 1;
       u.orient = sd.w <= u.len ? 0 : 1;
       u.ns = sd.w * u.len;
+      u.nr = u.ns;
       u.kl = (u.orient == 0 ? sd.w : u.len) + 1;
       u.ldab = 3 * u.kl + 1;
       u.has1 = t > 0;
@@ -225,7 +226,16 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision, int
       sd.a = std::max(0, s * m - 1);
       const int b = std::min(n - 1, (s + 1) * m + 1);
       sd.w = b - sd.a + 1;
-      sd.ns = n * sd.w;
+      sd.nr = n * sd.w;
+      // strips whose sweeps may take the wide plan get identity rows up to a
+      // whole number of its segment groups, so that a workgroup's rows of
+      // the back substitution are its own of the forward one (mirror); not
+      // where plan 0 is the one taken (eager_batch_maps: the server)
+      sd.ns = sd.nr;
+      if (wide && !fs.eager_batch_maps) {
+        const long long grp = (long long)P * plan_seg(sd.nr, P, HH_PLAN_WIDE, sd.w + 1);
+        sd.ns = (int)((sd.nr + grp - 1) / grp * grp);
+      }
       sd.kl = sd.w + 1;
       sd.ldab = 3 * sd.kl + 1;
       sd.has1 = s > 0;
@@ -242,6 +252,11 @@ void factor_setup(hh_problem* pb, unsigned dirs, int nstrips, int precision, int
       sd.segs = P;
       sd.wide = wide;
       plan_layout(sd);
+      sd.mirror = 0;
+      for (int p = 1; p < HH_NPLAN && wide; ++p)
+        if (plan_width(p) > 1 && sd.ns % ((long long)P * sd.pseg[p]) == 0) sd.mirror |= 1 << p;
+      REQUIRE(!wide || fs.eager_batch_maps || (sd.mirror >> HH_PLAN_WIDE & 1),
+              "strip %d: %d rows are not whole segment groups of the wide plan", s, sd.ns);
       for (int p = 0; p < HH_NPLAN && !lane_major; ++p)
         REQUIRE(sd.pseg[p] >= sd.kl, "segment of %d rows is shorter than the band half-width %d",
                 sd.pseg[p], sd.kl);
@@ -360,8 +375,10 @@ SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, 
   b.rho = take((size_t)nvec * fs.rho_elems * es);
   b.g1 = take((size_t)nvec * fs.N * pb->n * es);
   b.zs = fs.precision == HH_FP64 ? nullptr : take((size_t)nvec * len * es);
+  // the exchange areas of the forward and the back substitution (64 entries
+  // per workgroup each)
   b.xch = plan == HH_PLAN_WIDE || plan == HH_PLAN_PAIR
-              ? take((size_t)nvec * plan_width(plan) * 64 * es)
+              ? take((size_t)nvec * 2 * plan_width(plan) * 64 * es)
               : nullptr;
   *total = off;
   return b;
@@ -395,7 +412,7 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
     tk.tr = fs.tr;
     tk.n = pb->n;
     tk.N = fs.N;
-    tk.xch = b.xch ? (char*)b.xch + (size_t)v * G * 64 * es : nullptr;
+    tk.xch = b.xch ? (char*)b.xch + (size_t)v * G * 128 * es : nullptr;
     tk.bar = b.sync + 32 * (v + 1);
     tk.mode = mode;
   }
@@ -415,7 +432,7 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
     for (int q = 0; q < fs.N; ++q) {
       const StripDesc& sd = fs.strips[(size_t)i * fs.N + q];
       const double solves = mode != SWEEP_DOUBLE ? 1.0 : q == fs.N - 1 ? 1.0 : 2.0;
-      bytes += solves * ((double)sd.ns * sd.ldab * es + nvec * (double)sd.ns * (sizeof(c128) + es));
+      bytes += solves * ((double)sd.nr * sd.ldab * es + nvec * (double)sd.nr * (sizeof(c128) + es));
     }
     TimedRegion tr(FAM_SWEEP, st, bytes);
     if (plan == HH_PLAN_TILE)

@@ -539,8 +539,9 @@ void Engine::step(std::vector<Solve*>& solves) {
         for (hh_problem* q : k.pbs) ensure_batch_maps(q, st_);
       if ((k.plan == 0 || k.plan == HH_PLAN_TILE) && !k.tune) continue;
       chains += k.tasks.size();
-      // a tuned kind may run any plan: room for the widest
-      xbytes += k.tasks.size() * (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 64 *
+      // a tuned kind may run any plan: room for the widest (the exchange
+      // areas of both substitutions, 64 entries per workgroup each)
+      xbytes += k.tasks.size() * (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 128 *
                 esz_of(k.prec);
     }
     if (chains > 0) {
@@ -570,7 +571,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         for (SweepTask& tk : k.tasks) {
           tk.bar = sync_ + 32 * (1 + ci++);
           tk.xch = (char*)xch_ + xo;
-          xo += (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 64 * esz_of(k.prec);
+          xo += (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 128 * esz_of(k.prec);
         }
       }
     }
@@ -852,8 +853,8 @@ void Engine::step(std::vector<Solve*>& solves) {
         for (int q = 0; q < fs.N; ++q) {
           const StripDesc& sd = fs.strips[(size_t)fs.pre_slot[i] * fs.N + q];
           const double solves = fs.pre_mode[i] != SWEEP_DOUBLE ? 1.0 : q == fs.N - 1 ? 1.0 : 2.0;
-          if (first) bytes += solves * (double)sd.ns * sd.ldab * es;
-          bytes += solves * (double)sd.ns * (sizeof(c128) + es);
+          if (first) bytes += solves * (double)sd.nr * sd.ldab * es;
+          bytes += solves * (double)sd.nr * (sizeof(c128) + es);
         }
     }
     TimedRegion tr(FAM_SWEEP, st_, bytes);

@@ -1430,7 +1430,7 @@ void launch_band_lu(const hh_problem* pb, hipStream_t st) {
   size_t lds = (size_t)(fs.max_kl + 1 + LU_CH) * (2 * fs.max_kl + 1) * esz;
   double bytes = 0;
   for (size_t u = fs.nsub > 1 ? fs.first_sub : 0; u < fs.strips.size(); ++u)
-    bytes += 2.0 * (double)fs.strips[u].ns * fs.strips[u].ldab * esz;
+    bytes += 2.0 * (double)fs.strips[u].nr * fs.strips[u].ldab * esz;
   TimedRegion tr(FAM_FACTOR, st, bytes);
   if (fs.nsub > 1) {
     // recursive strip solves: the sub-blocks, by the blocked LU (any band

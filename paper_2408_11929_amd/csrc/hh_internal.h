@@ -130,7 +130,8 @@ struct StripDesc {
   int s;          // 0-based position in the sweep
   int a;          // first node line across the strip
   int w;          // width in node lines
-  int ns;         // unknowns n*w, local order q = long*w + short
+  int ns;         // rows of the factored system: the nr unknowns, then ns - nr identity rows
+  int nr;         // unknowns n*w, local order q = long*w + short
   int kl;         // band half-width w + 1 (ku = kl)
   int ldab;       // band column stride 3*kl + 1
   int has1;       // interface Gamma_{s,1} (short index 0) present
@@ -153,6 +154,10 @@ struct StripDesc {
   // plans p >= 1: slots of the products of maps (see plan_layout; index 0 unused)
   int pi_map[HH_NPLAN], a1_map[HH_NPLAN], a2_map[HH_NPLAN], ps_map[HH_NPLAN];
   int wide;            // the maps and responses of plans 1 and 2 exist (sweep_wide_fits)
+  // bit p: ns is a whole number of plan p's segment groups (P pseg[p] rows),
+  // so that workgroup g's rows of the forward substitution are those of the
+  // back substitution's workgroup gu - 1 - g (gu: workgroups holding segments)
+  int mirror;
   long long t_off;     // complex elements into the solve image: transfer maps (L, then U)
   long long phi_off[HH_NPLAN];  // complex elements into the solve image of the segment
                                 // responses of plan p (L, then U; see plan_phi_elems)
@@ -356,7 +361,8 @@ struct SweepTask {
   const void* tr;
   int n;
   int N;
-  void* xch;      // wide plan: G * 64 elements of sweep precision (workgroup tails)
+  void* xch;      // wide plan: 2 G * 64 elements of sweep precision (workgroup tails of the
+                  // forward substitution, then of the back substitution)
   unsigned* bar;  // wide plan: arrival counter of the chain's workgroups, zero at launch
   int mode;       // SweepMode: double sweep, forward or reverse single sweep
 };

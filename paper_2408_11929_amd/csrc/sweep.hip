@@ -597,26 +597,28 @@ struct SrcVec {  // x[i] (rev: x[ns-1-i]) in the working precision
   __device__ cx<T> get(const P& v) const { return v; }
 };
 template <class T>
-struct SrcC128 {  // strip-local FP64 right-hand side, forward order
+struct SrcC128 {  // strip-local FP64 right-hand side (nr rows), forward order
   gptr<const c128> b;
-  int ns;
+  int nr;
   using P = c128;
-  __device__ P load(int i) const {
-    const int q = i < ns ? i : ns - 1;
-    return mk(b[q].re, b[q].im);
+  __device__ P load(int i) const {  // zero on the identity rows past nr
+    const int q = i < nr ? i : nr - 1;
+    const c128 v = mk(b[q].re, b[q].im);
+    return i < nr ? v : mk(0.0, 0.0);
   }
   __device__ cx<T> get(const P& v) const { return mk((T)v.re, (T)v.im); }
 };
 // Strip right-hand side R_s r + g, forward order: local row q = l w + t is the
 // global node (a + t, l) of an x strip or (l, a + t) of a y strip; the
 // transmission data of node line l sit in LDS (e1 on t = 0 where the strip has
-// a Gamma_{s,1} side, e2 on t = w - 1 where Gamma_{s,2} data apply).
+// a Gamma_{s,1} side, e2 on t = w - 1 where Gamma_{s,2} data apply).  Rows
+// past the nr unknowns (identity rows) read zero.
 template <class T>
 struct SrcGather {
   gptr<const c128> r;
   const cx<T>* gl1;
   const cx<T>* gl2;
-  int ns, w, n, a, dir;
+  int nr, w, n, a, dir;
   bool use1, use2;
   struct P {
     c128 v;
@@ -627,15 +629,17 @@ struct SrcGather {
   // the global read is issued at load, the transmission data (LDS) are read
   // at get, so that loads may run ahead of the transmission data
   __device__ P load(int i) const {
-    const int q = i < ns ? i : ns - 1;
+    const bool in = i < nr;
+    const int q = in ? i : nr - 1;
     int l, t;
     line_of(q, w, winv, l, t);
     const long long p = dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
+    const c128 v = mk(r[p].re, r[p].im);
     P o;
-    o.v = mk(r[p].re, r[p].im);
+    o.v = in ? v : mk(0.0, 0.0);
     o.l = l;
-    o.f1 = use1 && t == 0;
-    o.f2 = use2 && t == w - 1;
+    o.f1 = in && use1 && t == 0;
+    o.f2 = in && use2 && t == w - 1;
     return o;
   }
   __device__ cx<T> get(const P& o) const {
@@ -653,34 +657,62 @@ struct DstVec {  // x[i] (rev: x[ns-1-i])
   __device__ cx<T> get(int i) const { return A::load((gptr<const cx<T>>)x, rev ? ns - 1 - i : i); }
 };
 template <class T>
-struct DstC128 {  // strip-local FP64 output, reversed order
+struct DstC128 {  // strip-local FP64 output (nr rows), reversed order over ns rows
   gptr<c128> x;
-  int ns;
-  __device__ void put(int i, cx<T> v) const {
+  int ns, nr;
+  __device__ void put(int i, cx<T> v) const {  // identity rows (q >= nr) are dropped
     const int q = ns - 1 - i;
+    if (q >= nr) return;
     x[q].re = (double)v.re;
     x[q].im = (double)v.im;
   }
   __device__ cx<T> get(int i) const {  // exact: the value put was of this precision
     const int q = ns - 1 - i;
+    if (q >= nr) return mk((T)0, (T)0);
     return mk((T)x[q].re, (T)x[q].im);
   }
 };
 // Scatter of the strip solution over the global vector, reversed order (the
-// back substitution produces the last local row first).
+// back substitution produces the last local row first); the identity rows
+// (q >= nr, which come first) are dropped and read back as zero, their value.
 template <class T, class A = PlainAcc>
 struct DstScatter {
   gptr<cx<T>> z;
-  int ns, w, n, a, dir;
+  int ns, nr, w, n, a, dir;
   float winv;  // 1 / w
-  __device__ long long pos(int i) const {
-    const int q = ns - 1 - i;
+  __device__ long long pos(int q) const {
     int l, t;
     line_of(q, w, winv, l, t);
     return dir == 0 ? (long long)l * n + a + t : (long long)(a + t) * n + l;
   }
-  __device__ void put(int i, cx<T> v) const { A::store(z, pos(i), v); }
-  __device__ cx<T> get(int i) const { return A::load((gptr<const cx<T>>)z, pos(i)); }
+  __device__ void put(int i, cx<T> v) const {
+    const int q = ns - 1 - i;
+    if (q < nr) A::store(z, pos(q), v);
+  }
+  __device__ cx<T> get(int i) const {
+    const int q = ns - 1 - i;
+    const cx<T> v = A::load((gptr<const cx<T>>)z, pos(q < nr ? q : 0));
+    return q < nr ? v : mk((T)0, (T)0);
+  }
+};
+
+// Rows base .. base + cnt - 1 of a strip vector held in LDS (the wide plan's
+// forward outputs of one workgroup): DstLds in forward order, SrcLdsRev as
+// the back substitution reads them (x[ns - 1 - i]).
+template <class T>
+struct DstLds {
+  cx<T>* v;
+  int base;
+  __device__ void put(int i, cx<T> x) const { v[i - base] = x; }
+  __device__ cx<T> get(int i) const { return v[i - base]; }
+};
+template <class T>
+struct SrcLdsRev {
+  const cx<T>* v;
+  int ns, base;
+  using P = cx<T>;
+  __device__ P load(int i) const { return v[ns - 1 - i - base]; }
+  __device__ cx<T> get(const P& x) const { return x; }
 };
 
 // Segment views for the parallel substitution: rows off..off+len-1 of a
@@ -1234,7 +1266,7 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
     const bool fwd = ss.fwd;
     const int s = ss.s;
     const StripDesc* sp = strips + s;
-    const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
+    const int ns = uni(sp->ns), nr = uni(sp->nr), w = uni(sp->w), kl = uni(sp->kl);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off), piv_off = uni(sp->piv_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
@@ -1244,7 +1276,7 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
     strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, use1, use2, fwd, ss.keep, t1off, t2off);
     __syncthreads();
     const float winv = 1.0f / (float)w;
-    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, use1, use2, winv};
+    const SrcGather<T> gather{r, gl1, gl2, nr, w, n, a, dir, use1, use2, winv};
     if (!pivoted) {
       const int seg = uni(sp->seg);
       const cx<T>* GL = img + img_off;
@@ -1261,7 +1293,7 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
       solve_triangle<T, KP, U, NB>(gather, drho, drho, GL, TL, PL, ns, kl, seg, work, yt, stt);
       __syncthreads();
       solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
-                               DstScatter<T>{z, ns, w, n, a, dir, winv},
+                               DstScatter<T>{z, ns, nr, w, n, a, dir, winv},
                                DstVec<T>{rho + ns, ns, false}, GU, TU, PU, ns, kl, seg, work, yt,
                                stt);
     } else if (PIV && wv == 0) {
@@ -1279,7 +1311,7 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
       gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64 * (1 + S))};
       solve_upper<T, 1, D, S>(x, Um, rdg, ns, lane);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      const DstScatter<T> out{z, ns, w, n, a, dir, winv};
+      const DstScatter<T> out{z, ns, nr, w, n, a, dir, winv};
       for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(rho, q));
     }
     __syncthreads();
@@ -1313,7 +1345,7 @@ __global__ __launch_bounds__(64) void k_sweep_lm(const SweepTask* __restrict__ t
     const SweepStep ss = sweep_step(mode, N, step);
     const int s = ss.s;
     const StripDesc* sp = strips + s;
-    const int ns = uni(sp->ns), w = uni(sp->w);
+    const int ns = uni(sp->ns), nr = uni(sp->nr), w = uni(sp->w);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off), piv_off = uni(sp->piv_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
@@ -1322,7 +1354,7 @@ __global__ __launch_bounds__(64) void k_sweep_lm(const SweepTask* __restrict__ t
     strip_data<T>(gl1, gl2, z, g1, trb, s, n, a, w, dir, use1, use2, ss.fwd, ss.keep, t1off, t2off);
     __syncthreads();
     const float winv = 1.0f / (float)w;
-    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, use1, use2, winv};
+    const SrcGather<T> gather{r, gl1, gl2, nr, w, n, a, dir, use1, use2, winv};
     // a single wave: its memory accesses are performed in order, the fences
     // only keep the compiler from reordering them
     for (int q = lane; q < ns; q += 64) st<T>(rho, q, gather.get(gather.load(q)));
@@ -1336,7 +1368,7 @@ __global__ __launch_bounds__(64) void k_sweep_lm(const SweepTask* __restrict__ t
     gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(img + img_off + NP * 64 * (SL + S))};
     solve_upper<T, 1, D, S>(x, Um, rdg, ns, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    const DstScatter<T> out{z, ns, w, n, a, dir, winv};
+    const DstScatter<T> out{z, ns, nr, w, n, a, dir, winv};
     for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(rho, q));
     __syncthreads();
   }
@@ -1398,7 +1430,7 @@ __global__ __launch_bounds__(64) void k_sweep_rec(const SweepTask* __restrict__ 
     const SweepStep ss = sweep_step(mode, N, step);
     const int s = ss.s;
     const StripDesc* sp = strips + s;
-    const int ns = uni(sp->ns), w = uni(sp->w);
+    const int ns = uni(sp->ns), nr = uni(sp->nr), w = uni(sp->w);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const bool use1 = has1 && ss.data1;
@@ -1407,7 +1439,7 @@ __global__ __launch_bounds__(64) void k_sweep_rec(const SweepTask* __restrict__ 
     __syncthreads();
     gptr<cx<T>> A = rho, U = rho + ns, C = rho + 2LL * ns, G1 = rho + 3LL * ns;
     const float winv = 1.0f / (float)w;
-    const SrcGather<T> gather{r, gl1, gl2, ns, w, n, a, dir, use1, use2, winv};
+    const SrcGather<T> gather{r, gl1, gl2, nr, w, n, a, dir, use1, use2, winv};
     // a single wave: its memory accesses are performed in order, the fences
     // only keep the compiler from reordering them
     for (int q = lane; q < ns; q += 64) {
@@ -1464,7 +1496,7 @@ __global__ __launch_bounds__(64) void k_sweep_rec(const SweepTask* __restrict__ 
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       __syncthreads();
     }
-    const DstScatter<T> out{z, ns, w, n, a, dir, winv};
+    const DstScatter<T> out{z, ns, nr, w, n, a, dir, winv};
     for (int q = lane; q < ns; q += 64) out.put(ns - 1 - q, ld<T>(U, q));
     __syncthreads();
   }
@@ -1508,7 +1540,7 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
     const bool fwd = ss.fwd;
     const int s = ss.s;
     const StripDesc* sp = strips + s;
-    const int ns = uni(sp->ns), w = uni(sp->w), kl = uni(sp->kl);
+    const int ns = uni(sp->ns), nr = uni(sp->nr), w = uni(sp->w), kl = uni(sp->kl);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
@@ -1521,8 +1553,8 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
     __syncthreads();
     const float winv = 1.0f / (float)w;
     const SrcGather<T> gather[NR] = {
-        SrcGather<T>{r[0], gl, gl + n, ns, w, n, a, dir, use1, use2, winv},
-        SrcGather<T>{r[1], gl + 2 * n, gl + 3 * n, ns, w, n, a, dir, use1, use2, winv}};
+        SrcGather<T>{r[0], gl, gl + n, nr, w, n, a, dir, use1, use2, winv},
+        SrcGather<T>{r[1], gl + 2 * n, gl + 3 * n, nr, w, n, a, dir, use1, use2, winv}};
     const int seg = uni(sp->seg);
     const cx<T>* GL = img + img_off;
     const cx<T>* GU = GL + blocked_blocks(ns) * KP * 64;
@@ -1536,8 +1568,8 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
     __syncthreads();
     const SrcVec<T> srho[NR] = {SrcVec<T>{(gptr<const cx<T>>)rho[0], ns, true},
                                 SrcVec<T>{(gptr<const cx<T>>)rho[1], ns, true}};
-    const DstScatter<T> dz[NR] = {DstScatter<T>{z[0], ns, w, n, a, dir, winv},
-                                  DstScatter<T>{z[1], ns, w, n, a, dir, winv}};
+    const DstScatter<T> dz[NR] = {DstScatter<T>{z[0], ns, nr, w, n, a, dir, winv},
+                                  DstScatter<T>{z[1], ns, nr, w, n, a, dir, winv}};
     const DstVec<T> dtmp[NR] = {DstVec<T>{rho[0] + ns, ns, false}, DstVec<T>{rho[1] + ns, ns, false}};
     solve_triangle_n<T, KP, U, NB, NR>(srho, dz, dtmp, GU, TU, PU, ns, kl, seg, work, yt, stt);
     __syncthreads();
@@ -1820,7 +1852,8 @@ __device__ __forceinline__ bool solve_triangle_wide(
 // (640 P).
 template <int KP, int U, int NB>
 __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict__ tasks, int plan,
-                                                    unsigned* abort, long long limit) {
+                                                    unsigned* abort, long long limit,
+                                                    int lo_cap) {
   using T = float;
   extern __shared__ char smem_raw[];
   __shared__ int ok;
@@ -1835,6 +1868,7 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
   c64* kb = yt + 64 * P;
   c64* pw = kb + 64 * P;
   c64* ring = pw + 64 * P + 640 * w;
+  c64* lo = pw + 64 * P + 640 * P;  // lo_cap entries: a workgroup's forward outputs
   const c64* img = uniptr((const c64*)tk.img);
   const c64* trb = uniptr((const c64*)tk.tr);
   gptr<c64> z = (gptr<c64>)uniptr((c64*)tk.ch.z);
@@ -1852,15 +1886,24 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     const bool fwd = ss.fwd;
     const int s = ss.s;
     const StripDesc* sp = strips + s;
-    const int ns = uni(sp->ns), wd = uni(sp->w), kl = uni(sp->kl);
+    const int ns = uni(sp->ns), nr = uni(sp->nr), wd = uni(sp->w), kl = uni(sp->kl);
     const int dir = uni(sp->dir), a = uni(sp->a), has1 = uni(sp->has1), has2 = uni(sp->has2);
     const long long img_off = uni(sp->img_off);
     const long long t1off = uni(sp->tr1_off), t2off = uni(sp->tr2_off);
     const bool use1 = has1 && ss.data1;
     const bool use2 = has2 && ss.data2;
     const float winv = 1.0f / (float)wd;
-    const SrcGather<T> gather{r, gl1, gl2, ns, wd, n, a, dir, use1, use2, winv};
+    const SrcGather<T> gather{r, gl1, gl2, nr, wd, n, a, dir, use1, use2, winv};
     const int seg = uni(sp->pseg[plan]);
+    // local: the strip is whole segment groups (mirror), so this workgroup's
+    // rows of the back substitution (role gu - 1 - g) are its own rows of the
+    // forward one; where they fit the LDS its forward outputs stay there, and
+    // the back substitution reads them after a workgroup barrier instead of a
+    // meeting of the chain
+    const int gu = (plan_nseg(ns, seg) + P - 1) / P;
+    const bool local = (uni(sp->mirror) >> plan & 1) != 0 && P * seg <= lo_cap;
+    const int gb = local && g < gu ? gu - 1 - g : g;
+    const int base = g * P * seg;
     const long long tm = uni(sp->tmaps);
     const c64* GL = img + img_off;
     const c64* GU = GL + blocked_blocks(ns) * KP * 64;
@@ -1882,22 +1925,41 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
       __syncthreads();
       return true;
     };
-    if (!solve_triangle_wide<KP, U, NB, true>(gather, DstVec<T, AgentAcc>{rho, ns, false}, GL,
-                                              none, form_data, mL, PL, ns, kl, seg, g, G, ring,
-                                              yt, kb, pw, xch, bar))
+    if (local) {
+      if (!solve_triangle_wide<KP, U, NB, true>(gather, DstLds<T>{lo, base}, GL, none, form_data, mL,
+                                                PL, ns, kl, seg, g, G, ring, yt, kb, pw, xch, bar))
+        return;
+    } else if (!solve_triangle_wide<KP, U, NB, true>(gather, DstVec<T, AgentAcc>{rho, ns, false}, GL,
+                                                     none, form_data, mL, PL, ns, kl, seg, g, G,
+                                                     ring, yt, kb, pw, xch, bar)) {
       return;
-    // back substitution: its inputs were written by every workgroup, so they
-    // are read after the meeting; its maps between the arrival and the wait
-    auto arrive = [&]() {
-      chain_arrive(bar);
-      return true;
-    };
-    auto wait = [&]() { return chain_wait(bar); };
-    if (!solve_triangle_wide<KP, U, NB, false>(SrcVec<T, AgentAcc>{(gptr<const c64>)rho, ns, true},
-                                               DstScatter<T, AgentAcc>{z, ns, wd, n, a, dir, winv},
-                                               GU, arrive, wait, mU, PU, ns, kl, seg, g, G, ring,
-                                               yt, kb, pw, xch, bar))
-      return;
+    }
+    // back substitution, with the second exchange area (a workgroup may start
+    // it while another still reads the forward one's tails): its inputs come
+    // from the LDS after a workgroup barrier (local) or from every
+    // workgroup's stores after a meeting; its maps go out before either
+    const SrcVec<T, AgentAcc> bin{(gptr<const c64>)rho, ns, true};
+    const DstScatter<T, AgentAcc> bout{z, ns, nr, wd, n, a, dir, winv};
+    const gptr<c64> xchb = xch + (long long)G * 64;
+    if (local) {
+      auto sync = []() {
+        __syncthreads();
+        return true;
+      };
+      if (!solve_triangle_wide<KP, U, NB, false>(SrcLdsRev<T>{lo, ns, base}, bout, GU, none, sync,
+                                                 mU, PU, ns, kl, seg, gb, G, ring, yt, kb, pw, xchb,
+                                                 bar))
+        return;
+    } else {
+      auto arrive = [&]() {
+        chain_arrive(bar);
+        return true;
+      };
+      auto wait = [&]() { return chain_wait(bar); };
+      if (!solve_triangle_wide<KP, U, NB, false>(bin, bout, GU, arrive, wait, mU, PU, ns, kl, seg,
+                                                 gb, G, ring, yt, kb, pw, xchb, bar))
+        return;
+    }
     // the strip's outputs are complete: the next strip waits for this
     // arrival in its forward substitution; the last needs no meeting
     if (step < nsteps - 1) chain_arrive(bar);
@@ -1921,12 +1983,12 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
   cx<T>* stt = yt + 64 * P;
   cx<T>* lds = stt + 64 * P;
   const StripDesc* sp = strips + si;
-  const int ns = uni(sp->ns), kl = uni(sp->kl);
+  const int ns = uni(sp->ns), nr = uni(sp->nr), kl = uni(sp->kl);
   const long long ioff = uni(sp->img_off), poff = uni(sp->piv_off);
   const int pivoted = uni(pflag[si]);
   const cx<T>* im = (const cx<T>*)img;
   gptr<cx<T>> wk = (gptr<cx<T>>)work;
-  const SrcC128<T> in{(gptr<const c128>)rhs, ns};
+  const SrcC128<T> in{(gptr<const c128>)rhs, nr};
   if (!pivoted) {
     const int seg = uni(sp->seg);
     const cx<T>* GL = im + ioff;
@@ -1937,7 +1999,7 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
     const cx<T>* PL = im + uni(sp->phi_off[0]);
     const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
     const DstVec<T> dwk{wk, ns, false};
-    const DstC128<T> dx{(gptr<c128>)x, ns};
+    const DstC128<T> dx{(gptr<c128>)x, ns, nr};
     solve_triangle<T, KP, U, NB>(in, dwk, dwk, GL, TL, PL, ns, kl, seg, lds, yt, stt);
     __syncthreads();
     solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true}, dx, dx, GU, TU, PU, ns,
@@ -1955,7 +2017,7 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
     gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64 * (1 + S))};
     solve_upper<T, 1, D, S>(xs, Um, rdg, ns, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (int q = lane; q < ns; q += 64) {
+    for (int q = lane; q < nr; q += 64) {
       const cx<T> v = ld<T>(wk, q);
       x[q] = mk((double)v.re, (double)v.im);
     }
@@ -1973,11 +2035,11 @@ __global__ __launch_bounds__(64) void k_strip_solve_lm(const StripDesc* __restri
   constexpr int S = 2 * SL;
   const int lane = threadIdx.x;
   const StripDesc* sp = strips + si;
-  const int ns = uni(sp->ns);
+  const int ns = uni(sp->ns), nr = uni(sp->nr);
   const long long ioff = uni(sp->img_off), poff = uni(sp->piv_off), NP = ns + HH_PAD;
   const cx<T>* im = (const cx<T>*)img;
   gptr<cx<T>> wk = (gptr<cx<T>>)work;
-  const SrcC128<T> in{(gptr<const c128>)rhs, ns};
+  const SrcC128<T> in{(gptr<const c128>)rhs, nr};
   for (int q = lane; q < ns; q += 64) st<T>(wk, q, in.get(in.load(q)));
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   solve_lower_w<T, D, SL>(wk, (gptr<const cx<T>>)(im + ioff), (gptr<const int>)(pivb + poff), ns,
@@ -1988,7 +2050,7 @@ __global__ __launch_bounds__(64) void k_strip_solve_lm(const StripDesc* __restri
   gptr<const cx<T>> rdg[1] = {(gptr<const cx<T>>)(im + ioff + NP * 64 * (SL + S))};
   solve_upper<T, 1, D, S>(xs, Um, rdg, ns, lane);
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  for (int q = lane; q < ns; q += 64) {
+  for (int q = lane; q < nr; q += 64) {
     const cx<T> v = ld<T>(wk, q);
     x[q] = mk((double)v.re, (double)v.im);
   }
@@ -2061,8 +2123,17 @@ static WideDev wide_dev() {
   return d;
 }
 
+// Entries of LDS for a workgroup's forward outputs (plans whose strips are
+// whole segment groups): as many as fit beside the rest under 150 KB, at most
+// 4096 (P pseg of the 321 x 321 benchmark: 512 on sixteen workgroups, 3840 on
+// two).
+static int wide_lo_cap(int P, int nmax) {
+  const long long room = 150LL * 1024 / (long long)sizeof(c64) - sweep_lds_elems_wide(P, nmax);
+  return (int)std::max(0LL, std::min(4096LL, room));
+}
+
 static size_t wide_lds_bytes(int P, int nmax) {
-  return (size_t)sweep_lds_elems_wide(P, nmax) * sizeof(c64);
+  return (size_t)(sweep_lds_elems_wide(P, nmax) + wide_lo_cap(P, nmax)) * sizeof(c64);
 }
 
 // Plans 1 and 2 run complex64 strips whose maps fit two lanes per row, with
@@ -2166,7 +2237,8 @@ static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int nmax, int 
   const char* env = std::getenv("HH_SWEEP_WAIT_US");
   const long long us = env && *env ? std::atoll(env) : 250000LL;
   long long limit = (long long)wide_dev().khz * us / 1000;
-  void* args[] = {(void*)&d, (void*)&plan, (void*)&abort, (void*)&limit};
+  int lo_cap = wide_lo_cap(P, nmax);
+  void* args[] = {(void*)&d, (void*)&plan, (void*)&abort, (void*)&limit, (void*)&lo_cap};
   HH_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)(ntasks * G)), dim3(64 * P), args,
                                     (unsigned)lds, st));
 }
