@@ -1286,11 +1286,13 @@ __global__ __launch_bounds__(512) void k_sweep(const SweepTask* __restrict__ tas
       const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
       const cx<T>* PL = img + uni(sp->phi_off[0]);
       const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
-      // the back substitution's later segments keep their zero-start
-      // outputs in the second half of the chain's scratch, so that z (a
-      // scatter) is written once
+      // the forward substitution ends at the last unknown (the identity rows
+      // past it feed nothing) and the back substitution reads those rows as
+      // zero; its later segments keep their zero-start outputs in the second
+      // half of the chain's scratch, so that z (a scatter) is written once
+      for (int q = nr + tid; q < ns; q += nthr) st<T>(rho, q, mk((T)0, (T)0));
       const DstVec<T> drho{rho, ns, false};
-      solve_triangle<T, KP, U, NB>(gather, drho, drho, GL, TL, PL, ns, kl, seg, work, yt, stt);
+      solve_triangle<T, KP, U, NB>(gather, drho, drho, GL, TL, PL, nr, kl, seg, work, yt, stt);
       __syncthreads();
       solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)rho, ns, true},
                                DstScatter<T>{z, ns, nr, w, n, a, dir, winv},
@@ -1563,8 +1565,13 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
     const cx<T>* TU = TL + uni(sp->tmaps) * KM2;
     const cx<T>* PL = img + uni(sp->phi_off[0]);
     const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
+    // the forward substitution ends at the last unknown; the back
+    // substitution reads the identity rows past it as zero
+#pragma unroll
+    for (int v = 0; v < NR; ++v)
+      for (int q = nr + (int)threadIdx.x; q < ns; q += nthr) st<T>(rho[v], q, mk((T)0, (T)0));
     const DstVec<T> drho[NR] = {DstVec<T>{rho[0], ns, false}, DstVec<T>{rho[1], ns, false}};
-    solve_triangle_n<T, KP, U, NB, NR>(gather, drho, drho, GL, TL, PL, ns, kl, seg, work, yt, stt);
+    solve_triangle_n<T, KP, U, NB, NR>(gather, drho, drho, GL, TL, PL, nr, kl, seg, work, yt, stt);
     __syncthreads();
     const SrcVec<T> srho[NR] = {SrcVec<T>{(gptr<const cx<T>>)rho[0], ns, true},
                                 SrcVec<T>{(gptr<const cx<T>>)rho[1], ns, true}};
@@ -2000,7 +2007,8 @@ __global__ __launch_bounds__(512) void k_strip_solve(const StripDesc* __restrict
     const cx<T>* PU = PL + plan_phi_elems(ns, uni(sp->segs), kl, map_dim(KP), 0);
     const DstVec<T> dwk{wk, ns, false};
     const DstC128<T> dx{(gptr<c128>)x, ns, nr};
-    solve_triangle<T, KP, U, NB>(in, dwk, dwk, GL, TL, PL, ns, kl, seg, lds, yt, stt);
+    for (int q = nr + (int)threadIdx.x; q < ns; q += (int)blockDim.x) st<T>(wk, q, mk((T)0, (T)0));
+    solve_triangle<T, KP, U, NB>(in, dwk, dwk, GL, TL, PL, nr, kl, seg, lds, yt, stt);
     __syncthreads();
     solve_triangle<T, KP, U, NB>(SrcVec<T>{(gptr<const cx<T>>)wk, ns, true}, dx, dx, GU, TU, PU, ns,
                              kl, seg, lds, yt, stt);
