@@ -58,6 +58,27 @@ def timed_steps(hh, torch, cfg, f_dev, precision, steps):
     return lat, stats
 
 
+def solve_phase(hh, torch, cfg, f_dev, precision, steps):
+    """Solve phase only: the problem assembled and its strips factored once
+    (the factors resident in HBM), one warm-up solve, then `steps` timed
+    MPGMRES solves of its right-hand side."""
+    pb = hh.Problem(cfg.omega, cfg.c_layers, cfg.n)
+    b = pb.load_vector(f_dev)
+    pb.factor_sweeps(hh.HH_DIR_X | hh.HH_DIR_Y, cfg.nstrips, precision)
+    pb.mpgmres(b, tol=cfg.tol, maxit=cfg.maxit)
+    lat, st = [], None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, rc = pb.mpgmres(b, tol=cfg.tol, maxit=cfg.maxit)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        if rc != hh.HH_OK:
+            raise RuntimeError(f"solve did not converge: {st}")
+    pb.free()
+    return lat, st
+
+
 def traffic_record(kernel_src):
     """HBM traffic per sweep launch from the committed rocprofv3 counter summary,
     valid only while the sweep kernel source is unchanged."""
@@ -225,23 +246,45 @@ def large_run(hh, torch):
 
 
 def _oracle_solves(cfg, budget_s, max_solves):
+    """Whole oracle solves until budget_s has been spent (at most max_solves),
+    with the time of each phase: assembly, strip factorisation (the LAPACK
+    band LU of every strip of both directions) and MPGMRES."""
     from oracle import assemble as oasm
     from oracle import mpgmres as omp
     from oracle import strips as ost
     from oracle import sweep as osw
-    times, res = [], None
+    times, res, phases = [], None, {"assemble_s": 0.0, "factor_s": 0.0, "mpgmres_s": 0.0}
     t_start = time.perf_counter()
     while True:
         t0 = time.perf_counter()
         A = oasm.assemble(cfg.omega, cfg.c_layers, cfg.n)
         b = oasm.source_load(cfg.n, cfg.f(0))
+        t1 = time.perf_counter()
         SX = osw.DoubleSweep(cfg.omega, cfg.c_layers, cfg.n, cfg.nstrips, ost.X, A=A)
         SY = osw.DoubleSweep(cfg.omega, cfg.c_layers, cfg.n, cfg.nstrips, ost.Y, A=A)
+        t2 = time.perf_counter()
         res = omp.mpgmres(A, [SX.apply, SY.apply], b, tol=cfg.tol, maxit=cfg.maxit)
-        times.append(time.perf_counter() - t0)
+        t3 = time.perf_counter()
+        times.append(t3 - t0)
+        phases["assemble_s"] += t1 - t0
+        phases["factor_s"] += t2 - t1
+        phases["mpgmres_s"] += t3 - t2
         if time.perf_counter() - t_start > budget_s or len(times) >= max_solves:
             break
-    return times, res
+    phases = {k: v / len(times) for k, v in phases.items()}
+    return times, res, phases
+
+
+def _oracle_direct(cfg):
+    """Seconds of the oracle's full direct solve of the workload's system
+    (SuperLU at this size, the band LU's fill being 1.6 GB)."""
+    from oracle import assemble as oasm
+    from oracle import direct as odir
+    A = oasm.assemble(cfg.omega, cfg.c_layers, cfg.n)
+    b = oasm.source_load(cfg.n, cfg.f(0))
+    t0 = time.perf_counter()
+    odir.direct_solve(A, b)
+    return time.perf_counter() - t0
 
 
 def cpu_baseline(cfg, budget_s=15.0):
@@ -254,10 +297,13 @@ def cpu_baseline(cfg, budget_s=15.0):
         from threadpoolctl import threadpool_limits
     except Exception:
         threadpool_limits = None
-    out = {}
+    out, phases, direct_s = {}, None, None
     for label, ncore in (("all", cores), ("one", 1)):
         limiter = threadpool_limits(limits=ncore) if threadpool_limits else None
-        times, res = _oracle_solves(cfg, budget_s, 5)
+        times, res, ph = _oracle_solves(cfg, budget_s, 5)
+        if label == "all":
+            phases = ph
+            direct_s = _oracle_direct(cfg)
         if limiter is not None:
             limiter.unregister()
         out[label] = (len(times) / sum(times), len(times), res.iterations)
@@ -274,6 +320,8 @@ def cpu_baseline(cfg, budget_s=15.0):
             "sample": f"{k} whole solves (assembly, strip LU, MPGMRES) of the benchmark workload, "
                       f"FP64 NumPy/SciPy with BLAS/LAPACK threads = {cores}, {its} iterations each",
             "one_core": {"value": out["one"][0], "solves": out["one"][1]},
+            "phases_s": dict(phases, direct_s=direct_s,
+                             direct="SuperLU (scipy.sparse.linalg.splu), factor and solve"),
             "cpu_model": cpu, "iterations": its}
 
 
@@ -351,6 +399,18 @@ def main():
     lat64, st64 = timed_steps(hh, torch, cfg, f_dev, hh.HH_FP64, args.steps)
     wall64 = time.perf_counter() - t0
 
+    # the same two with the factors resident (solve phase only)
+    lat32s, _ = solve_phase(hh, torch, cfg, f_dev, hh.HH_FP32, args.steps)
+    lat64s, _ = solve_phase(hh, torch, cfg, f_dev, hh.HH_FP64, args.steps)
+
+    def phase(lat):
+        return {"solves_per_s": len(lat) / sum(lat), "latency_ms": {
+            "p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)}}
+
+    solve_only = {"factors": "resident (assembled and factored once, outside the timed solves)",
+                  "complex64": phase(lat32s), "complex128": phase(lat64s),
+                  "ratio": sum(lat64s) / sum(lat32s)}
+
     def batch_run(nsrc):
         bcfg = wl.layered_321_batch(nsrc)
         fb = torch.from_numpy(bcfg.f()).to("cuda")
@@ -423,6 +483,7 @@ def main():
                        "iterations": st64[0]["iterations"], "res_true": st64[0]["res_true"]},
         "speedup_vs_plain_fp64": (args.steps / wall32) / (args.steps / wall64),
         "speedup_equal_plan": equal_plan,
+        "solve_phase_only": solve_only,
         "batched": batched,
         "batched_256": batched_256,
         "serving": serving,
