@@ -539,7 +539,11 @@ __global__ __launch_bounds__(64) void k_band_lu_h(const StripDesc* __restrict__ 
 #pragma unroll
     for (int k = 0; k < R; ++k) colb[h * R + k] = a[k];
   }
-  const int nsteps = (ns + CH - 1) / CH * CH;  // steps past ns change nothing
+  // steps past ns change nothing; nor do those past the unknowns (sd.nr): the
+  // identity rows after them are packed as their own factors, and no
+  // earlier step reaches their columns
+  const int nsteps = (sd.nr + CH - 1) / CH * CH;
+  for (int j = nsteps + lane; j < ns; j += 64) piv[j] = j;
   for (int jc = 0; jc < nsteps; jc += CH) {
     wave_lds_sync();
 #pragma unroll
