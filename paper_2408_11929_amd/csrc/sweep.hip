@@ -1855,8 +1855,9 @@ __device__ __forceinline__ bool solve_triangle_wide(
 // unpivoted strips): workgroup g = blockIdx.x % G of chain blockIdx.x / G.
 // Every workgroup forms the transmission data of all node lines itself
 // (workgroup 0 keeps the forward ones for the backward pass).  Dynamic LDS
-// (complex elements): two node lines, yt, kb, pw (64 P each), then the rings
-// (640 P).
+// (complex elements): two node lines, yt, kb, pw (64 P each), the rings
+// (640 P), then lo_cap entries for the workgroup's forward outputs where a
+// strip is whole segment groups of the plan and they fit.
 template <int KP, int U, int NB>
 __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict__ tasks, int plan,
                                                     unsigned* abort, long long limit,
