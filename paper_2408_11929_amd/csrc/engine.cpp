@@ -710,72 +710,79 @@ void Engine::step(std::vector<Solve*>& solves) {
   GramTask* dg2 = stage(g2, staged_);
   UpdTask* du2 = stage(u2, staged_);
 
-  // 7. modified Gram-Schmidt inside the block, two passes, then normalisation
-  std::vector<std::vector<GramTask>> mg(4 * 3);
-  std::vector<std::vector<UpdTask>> mu(4 * 2);
-  std::vector<std::vector<NormTask>> mn(4);
+  // 7. QR of the new block: modified Gram-Schmidt with two passes per column,
+  // then normalisation, in fused steps (k_qr_step; bitwise the separate
+  // kernels): the first column's norm; per column c the step that normalises
+  // it and forms the first pass's products of column c + 1, then that pass's
+  // update with the second pass's products, then the second update with the
+  // norm of c + 1.  A solve of t columns takes 3t - 1 steps; step k of every
+  // solve is one launch.  Consecutive steps use two halves of the partial
+  // sums' scratch, since a step reads its predecessor's while writing its own.
+  std::vector<std::vector<QrTask>> qs(3 * HH_MAXPRE - 1);
+  int maxqblk = 1;
   for (Solve* s : live) {
     HdLayout L(s->hcap, s->t);
-    const int m = s->m, t = s->t;
+    const int m = s->m, t = s->t, nb = nblk_for(s->len, live.size());
+    maxqblk = std::max(maxqblk, nb);
     c128* W = s->V + (size_t)m * s->len;
+    auto col = [&](int c) { return W + (size_t)c * s->len; };
+    auto step = [&]() {
+      QrTask q{};
+      q.len = s->len;
+      q.ld = s->len;
+      q.nblk = nb;
+      q.cnblk = nb;
+      q.xg_is_y = -1;
+      q.tol = 1e-12;
+      return q;
+    };
+    std::vector<QrTask> chain;
+    QrTask q = step();
+    q.Xg = col(0);
+    q.gy = col(0);
+    q.gpx = 1;
+    chain.push_back(q);
     for (int c = 0; c < t; ++c) {
-      c128* wc = W + (size_t)c * s->len;
-      for (int pass = 0; pass < 2 && c > 0; ++pass) {
-        GramTask g{};
-        g.X = W;
-        g.Y = wc;
-        g.out = s->Hd + (pass == 0 ? L.r1 : L.r2) + (size_t)c * t;
-        g.part = s->part;
-        g.len = s->len;
-        g.ldx = g.ldy = s->len;
-        g.ldo = t;
-        g.px = c;
-        g.ty = 1;
-        g.nblk = nblk_for(s->len, live.size());
-        mg[c * 3 + pass].push_back(g);
-        UpdTask u{};
-        u.X = W;
-        u.Y = wc;
-        u.C = g.out;
-        u.len = s->len;
-        u.ldx = u.ldy = s->len;
-        u.ldc = t;
-        u.px = c;
-        u.ty = 1;
-        mu[c * 2 + pass].push_back(u);
-      }
-      GramTask g{};
-      g.X = wc;
-      g.Y = wc;
-      g.out = s->Hd + L.nr + c;
-      g.part = s->part;
-      g.len = s->len;
-      g.ldx = g.ldy = s->len;
-      g.ldo = 1;
-      g.px = 1;
-      g.ty = 1;
-      g.nblk = nblk_for(s->len, live.size());
-      mg[c * 3 + 2].push_back(g);
-      NormTask q{};
-      q.y = wc;
-      q.nrm2 = s->Hd + L.nr + c;
+      q = step();  // normalise c; the first pass's products of c + 1
+      q.cpx = 1;
+      q.cout = s->Hd + L.nr + c;
+      q.op = 2;
+      q.y = col(c);
       q.ref2 = s->Hd + L.g1 + (size_t)(m + c) + (size_t)c * (m + t);  // ||A z_c||^2
       q.rdiag = s->Hd + L.rd + c;
       q.flag = s->flags + c;
-      q.len = s->len;
-      q.tol = 1e-12;
-      mn[c].push_back(q);
+      if (c + 1 < t) {
+        q.Xg = W;
+        q.gy = col(c + 1);
+        q.gpx = c + 1;
+        q.xg_is_y = c;
+      }
+      chain.push_back(q);
+      if (c + 1 == t) break;
+      for (int pass = 0; pass < 2; ++pass) {
+        q = step();  // the pass's update of c + 1; the next pass's products or its norm
+        q.cpx = c + 1;
+        q.cout = s->Hd + (pass == 0 ? L.r1 : L.r2) + (size_t)(c + 1) * t;
+        q.op = 1;
+        q.y = col(c + 1);
+        q.Xop = W;
+        q.Xg = pass == 0 ? W : col(c + 1);
+        q.gy = col(c + 1);
+        q.gpx = pass == 0 ? c + 1 : 1;
+        q.xg_is_y = pass == 0 ? -1 : 0;
+        q.gy_is_y = 1;
+        chain.push_back(q);
+      }
+    }
+    for (size_t k = 0; k < chain.size(); ++k) {
+      chain[k].gpart = s->part + (k % 2) * (size_t)nb * 4;
+      chain[k].cpart = s->part + ((k + 1) % 2) * (size_t)nb * 4;
+      qs[k].push_back(chain[k]);
     }
   }
-  std::vector<GramTask*> dmg(mg.size(), nullptr);
-  std::vector<UpdTask*> dmu(mu.size(), nullptr);
-  std::vector<NormTask*> dmn(mn.size(), nullptr);
-  for (size_t i = 0; i < mg.size(); ++i)
-    if (!mg[i].empty()) dmg[i] = stage(mg[i], staged_);
-  for (size_t i = 0; i < mu.size(); ++i)
-    if (!mu[i].empty()) dmu[i] = stage(mu[i], staged_);
-  for (size_t i = 0; i < mn.size(); ++i)
-    if (!mn[i].empty()) dmn[i] = stage(mn[i], staged_);
+  std::vector<QrTask*> dqs(qs.size(), nullptr);
+  for (size_t k = 0; k < qs.size(); ++k)
+    if (!qs[k].empty()) dqs[k] = stage(qs[k], staged_);
   // the iteration's results for the host, gathered into one device area and
   // sent in one transfer: per solve its coefficients and flags, then the
   // abort word
@@ -882,18 +889,8 @@ void Engine::step(std::vector<Solve*>& solves) {
     launch_block_update(DEV(du1), n, maxlen, maxt, st_);
     launch_gram(DEV(dg2), n, maxblk, maxpx, maxt, st_);
     launch_block_update(DEV(du2), n, maxlen, maxt, st_);
-    for (int c = 0; c < 4; ++c) {
-      for (int pass = 0; pass < 2; ++pass) {
-        if (dmg[c * 3 + pass]) {
-          launch_gram(DEV(dmg[c * 3 + pass]), (int)mg[c * 3 + pass].size(), maxblk, c, 1, st_);
-          launch_block_update(DEV(dmu[c * 2 + pass]), (int)mu[c * 2 + pass].size(), maxlen, 1, st_);
-        }
-      }
-      if (dmg[c * 3 + 2]) {
-        launch_gram(DEV(dmg[c * 3 + 2]), (int)mg[c * 3 + 2].size(), maxblk, 1, 1, st_);
-        launch_normalize(DEV(dmn[c]), (int)mn[c].size(), maxlen, st_);
-      }
-    }
+    for (size_t k = 0; k < qs.size(); ++k)
+      if (dqs[k]) launch_qr_step(DEV(dqs[k]), (int)qs[k].size(), maxqblk, st_);
   }
 
   // ---- coefficients to the host, least squares, selection

@@ -53,6 +53,35 @@ struct NormTask {
   double tol;
 };
 
+// One step of the QR of a solve's new block (modified Gram-Schmidt, two
+// passes per column, then normalisation), fused: the previous step's Gram
+// partial sums (cpx entries over cnblk row blocks) are reduced into cout, the
+// column op is applied to y (1: y -= Xop[:, 0..cpx) cout; 2: y /= ||y|| with
+// ||y||^2 = cout[0], deflated as NormTask), then the next step's Gram partial
+// sums Xg[:, 0..gpx)^H gy go to gpart (gpx = 0: none).  Every value is formed
+// as by k_gram_reduce, k_block_update, k_normalize and k_gram_partial in
+// turn, so the results are bitwise theirs.
+struct QrTask {
+  const c128* cpart;
+  c128* cout;
+  int cpx, cnblk;
+  int op;
+  c128* y;
+  const c128* Xop;
+  const c128* ref2;
+  c128* rdiag;
+  int* flag;
+  double tol;
+  const c128* Xg;
+  const c128* gy;
+  c128* gpart;
+  int gpx;
+  int xg_is_y;  // column of Xg that is y (-1: none)
+  int gy_is_y;  // gy is y
+  int nblk;     // row blocks of the Gram (the op covers the same rows)
+  long long len, ld;
+};
+
 // x = Z y.
 struct CombTask {
   const void* Z;
@@ -88,6 +117,8 @@ void launch_normalize(const NormTask* d_tasks, int ntasks, long long max_len, hi
 void launch_combine(const CombTask* d_tasks, int ntasks, long long max_len, int zprec,
                     hipStream_t st);
 void launch_residual(const ResTask* d_tasks, int ntasks, long long max_len, hipStream_t st);
+// One fused QR step for ntasks solves (grid: max_nblk row blocks x tasks).
+void launch_qr_step(const QrTask* d_tasks, int ntasks, int max_nblk, hipStream_t st);
 // The regions of ntasks copy tasks into dst, one workgroup per task (so that
 // an iteration's small results leave the device in one transfer).
 void launch_gather(const CopyTask* d_tasks, int ntasks, unsigned char* dst, hipStream_t st);

@@ -166,6 +166,94 @@ __global__ __launch_bounds__(256) void k_normalize(const NormTask* __restrict__ 
   if (p < tk.len) tk.y[p] = cscale(tk.x ? tk.x[p] : tk.y[p], s);
 }
 
+// One fused step of the block's QR (QrTask).  Rows as k_gram_partial's: row
+// block blk of the task, thread tid taking rows r0 + tid, r0 + tid + 256, ...
+// in order; every row of y lies in exactly one block, so the op is applied
+// once per row.  Reductions in the orders of k_gram_reduce (one wave per
+// entry) and k_gram_partial (wave sums, then the four waves in turn).
+__global__ __launch_bounds__(256) void k_qr_step(const QrTask* __restrict__ tasks) {
+  constexpr int CX = 4;
+  const QrTask tk = tasks[blockIdx.y];
+  const int blk = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  if (blk >= tk.nblk) return;
+  __shared__ c128 coef[CX];
+  __shared__ double red[4][CX * 2];
+  // 1. the previous Gram's coefficients
+  if (wv < tk.cpx) {
+    double sr = 0.0, si = 0.0;
+    for (int b = ln; b < tk.cnblk; b += 64) {
+      const c128 v = tk.cpart[(long long)b * tk.cpx + wv];
+      sr += v.re;
+      si += v.im;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (ln == 0) {
+      coef[wv] = mk(sr, si);
+      if (blk == 0) tk.cout[wv] = mk(sr, si);
+    }
+  }
+  __syncthreads();
+  double scale = 1.0;
+  if (tk.op == 2) {
+    const double nrm = sqrt(fmax(coef[0].re, 0.0));
+    const double ref = sqrt(fmax(tk.ref2->re, 0.0));
+    const bool defl = !(nrm > tk.tol * ref) || nrm == 0.0;
+    scale = defl ? 0.0 : 1.0 / nrm;
+    if (blk == 0 && tid == 0) {
+      *tk.rdiag = mk(defl ? 0.0 : nrm, 0.0);
+      *tk.flag = defl ? 1 : 0;
+    }
+  }
+  // 2. the op and the next Gram's partial sums, row by row
+  const long long rows_per = (tk.len + tk.nblk - 1) / tk.nblk;
+  const long long r0 = blk * rows_per;
+  const long long r1 = min(tk.len, r0 + rows_per);
+  double acc_re[CX], acc_im[CX];
+#pragma unroll
+  for (int a = 0; a < CX; ++a) acc_re[a] = acc_im[a] = 0.0;
+  for (long long p = r0 + tid; p < r1; p += 256) {
+    c128 v = mk(0.0, 0.0);
+    if (tk.op == 1) {
+      v = tk.y[p];
+      for (int i = 0; i < tk.cpx; ++i) v = cfms(v, tk.Xop[i * tk.ld + p], coef[i]);
+      tk.y[p] = v;
+    } else if (tk.op == 2) {
+      v = cscale(tk.y[p], scale);
+      tk.y[p] = v;
+    }
+    if (tk.gpx > 0) {
+      const c128 y = tk.gy_is_y ? v : tk.gy[p];
+#pragma unroll
+      for (int a = 0; a < CX; ++a) {
+        if (a < tk.gpx) {
+          const c128 x = a == tk.xg_is_y ? v : tk.Xg[a * tk.ld + p];
+          const c128 d = cdotc(x, y);
+          acc_re[a] += d.re;
+          acc_im[a] += d.im;
+        }
+      }
+    }
+  }
+  if (tk.gpx <= 0) return;
+#pragma unroll
+  for (int a = 0; a < CX; ++a) {
+    const double sr = wave_sum(acc_re[a]);
+    const double si = wave_sum(acc_im[a]);
+    if (ln == 0) {
+      red[wv][a * 2] = sr;
+      red[wv][a * 2 + 1] = si;
+    }
+  }
+  __syncthreads();
+  if (tid < tk.gpx) {
+    const int k = tid * 2;
+    const double sr = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    const double si = red[0][k + 1] + red[1][k + 1] + red[2][k + 1] + red[3][k + 1];
+    tk.gpart[(long long)blk * tk.gpx + tid] = mk(sr, si);
+  }
+}
+
 // x = Z y (plus x0 if add); Z columns contiguous with stride len.
 template <class T>
 __global__ __launch_bounds__(256) void k_combine(const CombTask* __restrict__ tasks) {
@@ -217,6 +305,13 @@ void launch_gram(const GramTask* d_tasks, int ntasks, int max_nblk, int max_px, 
   HH_HIP(hipGetLastError());
   dim3 g2((unsigned)((max_px * max_ty + 3) / 4), (unsigned)ntasks);
   hipLaunchKernelGGL(k_gram_reduce, g2, dim3(256), 0, st, d_tasks);
+  HH_HIP(hipGetLastError());
+}
+
+void launch_qr_step(const QrTask* d_tasks, int ntasks, int max_nblk, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_qr_step, dim3((unsigned)max_nblk, (unsigned)ntasks), dim3(256), 0, st,
+                     d_tasks);
   HH_HIP(hipGetLastError());
 }
 
