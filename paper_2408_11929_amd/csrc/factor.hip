@@ -1001,6 +1001,22 @@ __host__ __device__ inline int transfer_jobs(const StripDesc& sd, int p) {
   return nseg > 1 ? nseg - 1 : 0;  // segments 1 .. nseg-1: responses, maps for all but the last
 }
 
+// Both halves of the wave get v(l mod 32) + v(l mod 32 + 32), summed in that
+// order.
+__device__ __forceinline__ c128 halves_sum(c128 v) {
+  const unsigned long long r = __double_as_longlong(v.re), m = __double_as_longlong(v.im);
+  const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)r, (unsigned)r, false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)(r >> 32), (unsigned)(r >> 32), false,
+                                                   false);
+  const auto ml = __builtin_amdgcn_permlane32_swap((unsigned)m, (unsigned)m, false, false);
+  const auto mh = __builtin_amdgcn_permlane32_swap((unsigned)(m >> 32), (unsigned)(m >> 32), false,
+                                                   false);
+  auto d = [](unsigned lo, unsigned hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  };
+  return mk(d(rl[0], rh[0]) + d(rl[1], rh[1]), d(ml[0], mh[0]) + d(ml[1], mh[1]));
+}
+
 // Segment transfer maps of an unpivoted strip.  The substitutions split a
 // strip's rows into segments (one cut per segment plan) that are solved in
 // parallel from a zero state; the true state of segment s+1 (the K outputs
@@ -1117,6 +1133,38 @@ __global__ __launch_bounds__(64) void k_build_transfer(const StripDesc* __restri
     fetch(i0 + CR);
     wave_lds_sync();
     const int un = s1 - i0 < CR ? s1 - i0 : CR;
+    if (K <= 32) {
+      // two lanes per column: lane c + 32 h sums the terms of its half (h = 0:
+      // rows 1 .. H back, h = 1: H + 1 .. K back), one swap of the halves
+      // gives both lanes the same total, and both write it to the window, so
+      // that each lane reads back only rows it wrote itself
+      const int col = lane & 31, h = lane >> 5, H = (K + 1) >> 1;
+      const int cb0 = h ? H + 1 : 1, ce = h ? K : H;
+      if (col < K) {
+        for (int u = 0; u < un; ++u) {
+          const int i = i0 + u;
+          const c128* cf = cb + u * W;
+          c128 a[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+          int c = cb0;
+          for (; c + 3 <= ce; c += 4) {
+            c128 wv[4], fv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              wv[q] = win[((i - c - q) & rm) * W + col];
+              fv[q] = cf[c - 1 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = cfms(a[q], fv[q], wv[q]);
+          }
+          for (; c <= ce; ++c) a[0] = cfms(a[0], cf[c - 1], win[((i - c) & rm) * W + col]);
+          const c128 acc = halves_sum((a[0] + a[1]) + (a[2] + a[3])) * cf[K];
+          win[(i & rm) * W + col] = acc;
+          if (h == 0 && tmap && i >= s1 - K)
+            Tm[(long long)col * KM + (i - (s1 - K))] = mk((T)acc.re, (T)acc.im);
+        }
+      }
+      continue;
+    }
     // lanes past K have no column: they stay out of the rows, which keeps the
     // LDS reads to the K live lanes
     if (lane < K) {
