@@ -1605,9 +1605,11 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
 //  4. every segment but segment 0 adds Phi_c s_c to its outputs.
 // The maps of steps 2 and 3 are read into registers (one row per lane), those
 // of step 3 and the first rows of Phi_c while the workgroup waits to meet.
-// The workgroups meet again when a triangle's output is complete (the back
-// substitution reads rows that other workgroups wrote, the next strip's
-// transmission data read the solution), so a strip solve is four meetings.
+// The workgroups meet again when the strip's solution is complete (the next
+// strip's transmission data read it), and, unless the strip is whole segment
+// groups of the plan (then each workgroup's back substitution takes its own
+// forward rows, from its LDS), when the forward output is complete: a strip
+// solve is three meetings, or four.
 
 // Meeting of the G workgroups of one chain, in two halves so that work can
 // go between them.  Everything the workgroups exchange goes through AgentAcc
