@@ -746,7 +746,7 @@ void Engine::step(std::vector<Solve*>& solves) {
       q = step();  // normalise c; the first pass's products of c + 1
       q.cpx = 1;
       q.cout = s->Hd + L.nr + c;
-      q.op = 2;
+      q.op = QR_NORMALIZE;
       q.y = col(c);
       q.ref2 = s->Hd + L.g1 + (size_t)(m + c) + (size_t)c * (m + t);  // ||A z_c||^2
       q.rdiag = s->Hd + L.rd + c;
@@ -763,7 +763,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         q = step();  // the pass's update of c + 1; the next pass's products or its norm
         q.cpx = c + 1;
         q.cout = s->Hd + (pass == 0 ? L.r1 : L.r2) + (size_t)(c + 1) * t;
-        q.op = 1;
+        q.op = QR_UPDATE;
         q.y = col(c + 1);
         q.Xop = W;
         q.Xg = pass == 0 ? W : col(c + 1);

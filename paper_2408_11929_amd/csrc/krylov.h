@@ -56,11 +56,13 @@ struct NormTask {
 // One step of the QR of a solve's new block (modified Gram-Schmidt, two
 // passes per column, then normalisation), fused: the previous step's Gram
 // partial sums (cpx entries over cnblk row blocks) are reduced into cout, the
-// column op is applied to y (1: y -= Xop[:, 0..cpx) cout; 2: y /= ||y|| with
-// ||y||^2 = cout[0], deflated as NormTask), then the next step's Gram partial
-// sums Xg[:, 0..gpx)^H gy go to gpart (gpx = 0: none).  Every value is formed
+// column op is applied to y (QR_UPDATE: y -= Xop[:, 0..cpx) cout;
+// QR_NORMALIZE: y /= ||y|| with ||y||^2 = cout[0], deflated as NormTask),
+// then the next step's Gram partial sums Xg[:, 0..gpx)^H gy go to gpart
+// (gpx = 0: none).  Every value is formed
 // as by k_gram_reduce, k_block_update, k_normalize and k_gram_partial in
 // turn, so the results are bitwise theirs.
+enum QrOp { QR_NONE = 0, QR_UPDATE = 1, QR_NORMALIZE = 2 };
 struct QrTask {
   const c128* cpart;
   c128* cout;

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_qr_step(const QrTask* __restrict__ task
   }
   __syncthreads();
   double scale = 1.0;
-  if (tk.op == 2) {
+  if (tk.op == QR_NORMALIZE) {
     const double nrm = sqrt(fmax(coef[0].re, 0.0));
     const double ref = sqrt(fmax(tk.ref2->re, 0.0));
     const bool defl = !(nrm > tk.tol * ref) || nrm == 0.0;
@@ -214,11 +214,11 @@ __global__ __launch_bounds__(256) void k_qr_step(const QrTask* __restrict__ task
   for (int a = 0; a < CX; ++a) acc_re[a] = acc_im[a] = 0.0;
   for (long long p = r0 + tid; p < r1; p += 256) {
     c128 v = mk(0.0, 0.0);
-    if (tk.op == 1) {
+    if (tk.op == QR_UPDATE) {
       v = tk.y[p];
       for (int i = 0; i < tk.cpx; ++i) v = cfms(v, tk.Xop[i * tk.ld + p], coef[i]);
       tk.y[p] = v;
-    } else if (tk.op == 2) {
+    } else if (tk.op == QR_NORMALIZE) {
       v = cscale(tk.y[p], scale);
       tk.y[p] = v;
     }
