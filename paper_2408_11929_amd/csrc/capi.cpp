@@ -375,11 +375,11 @@ SweepBuffers sweep_layout(const hh_problem* pb, int nvec, int plan, char* base, 
   b.rho = take((size_t)nvec * fs.rho_elems * es);
   b.g1 = take((size_t)nvec * fs.N * pb->n * es);
   b.zs = fs.precision == HH_FP64 ? nullptr : take((size_t)nvec * len * es);
-  // the exchange areas of the forward and the back substitution (64 entries
-  // per workgroup each)
+  // the exchange areas of the forward and the back substitution
   b.xch = plan == HH_PLAN_WIDE || plan == HH_PLAN_PAIR
-              ? take((size_t)nvec * 2 * plan_width(plan) * 64 * es)
+              ? take((size_t)nvec * plan_width(plan) * HH_XCH_BYTES_PER_WG)
               : nullptr;
+  b.xch_bytes = b.xch ? (size_t)nvec * plan_width(plan) * HH_XCH_BYTES_PER_WG : 0;
   *total = off;
   return b;
 }
@@ -394,6 +394,7 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
   hipStream_t st = pb->st[0];
   if (plan != HH_PLAN_WIDE) ensure_batch_maps(pb, st);
   launch_zero(b.sync, (size_t)(nvec + 1) * 128, st);
+  if (b.xch) launch_zero(b.xch, b.xch_bytes, st);  // no tail stamp is zero
   // descriptors staged on the stack for up to 64 chains (no host allocation)
   SweepTask few[64];
   std::vector<SweepTask> many(nvec > 64 ? nvec : 0);
@@ -412,7 +413,7 @@ void sweep_apply_core(hh_problem* pb, int i, int mode, int nvec, const c128* r, 
     tk.tr = fs.tr;
     tk.n = pb->n;
     tk.N = fs.N;
-    tk.xch = b.xch ? (char*)b.xch + (size_t)v * G * 128 * es : nullptr;
+    tk.xch = b.xch ? (char*)b.xch + (size_t)v * G * HH_XCH_BYTES_PER_WG : nullptr;
     tk.bar = b.sync + 32 * (v + 1);
     tk.mode = mode;
   }

@@ -539,10 +539,9 @@ void Engine::step(std::vector<Solve*>& solves) {
         for (hh_problem* q : k.pbs) ensure_batch_maps(q, st_);
       if ((k.plan == 0 || k.plan == HH_PLAN_TILE) && !k.tune) continue;
       chains += k.tasks.size();
-      // a tuned kind may run any plan: room for the widest (the exchange
-      // areas of both substitutions, 64 entries per workgroup each)
-      xbytes += k.tasks.size() * (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 128 *
-                esz_of(k.prec);
+      // a tuned kind may run any plan: room for the widest
+      xbytes += k.tasks.size() * (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) *
+                HH_XCH_BYTES_PER_WG;
     }
     if (chains > 0) {
       const size_t sbytes = (chains + 1) * 128;
@@ -559,6 +558,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         if (xch_) dev_free(xch_);
         xch_cap_ = xbytes * 2;
         xch_ = dev_alloc(xch_cap_);
+        launch_zero(xch_, xch_cap_, st_);  // no tail stamp is zero
       }
       // arrival counters start from zero in every launch; normally the
       // previous launch's lines were cleared behind it (below)
@@ -571,7 +571,7 @@ void Engine::step(std::vector<Solve*>& solves) {
         for (SweepTask& tk : k.tasks) {
           tk.bar = sync_ + 32 * (1 + ci++);
           tk.xch = (char*)xch_ + xo;
-          xo += (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * 128 * esz_of(k.prec);
+          xo += (size_t)plan_width(k.tune ? HH_PLAN_WIDE : k.plan) * HH_XCH_BYTES_PER_WG;
         }
       }
     }

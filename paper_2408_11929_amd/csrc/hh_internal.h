@@ -361,8 +361,8 @@ struct SweepTask {
   const void* tr;
   int n;
   int N;
-  void* xch;      // wide plan: 2 G * 64 elements of sweep precision (workgroup tails of the
-                  // forward substitution, then of the back substitution)
+  void* xch;      // wide plan: HH_XCH_BYTES_PER_WG bytes per workgroup (G * 64 stamped
+                  // tail entries of the forward substitution, then as many of the back one)
   unsigned* bar;  // wide plan: arrival counter of the chain's workgroups, zero at launch
   int mode;       // SweepMode: double sweep, forward or reverse single sweep
 };
@@ -423,6 +423,9 @@ __host__ __device__ inline int segment_rows(int ns, int P) {
 // 16-row aligned segments.  Either way a segment is at least K rows long, so
 // that a segment's state (the K outputs before it) lies in the segment before
 // it, and every segment after the first starts at row K or later.
+// Exchange area of a wide-plan chain, per workgroup: 64 tail entries for each
+// of the two substitutions, each entry two 64-bit words (value half, stamp).
+constexpr size_t HH_XCH_BYTES_PER_WG = 2 * 64 * 16;
 __host__ __device__ inline int plan_width(int p) {
   return p == HH_PLAN_WIDE ? 16 : p == HH_PLAN_PAIR ? 2 : 1;
 }
@@ -542,6 +545,7 @@ struct SweepBuffers {
   void* g1;
   void* zs;
   void* xch;
+  size_t xch_bytes;
 };
 // Segment plan of an application to nvec vectors.
 int sweep_plan_of(const hh_problem* pb, int nvec);

@@ -27,6 +27,7 @@
 // complex multiply-subtract per lane with that lane's coefficient, which the
 // solve image provides as one coalesced 64-lane row per step.  Coefficient
 // rows are prefetched D steps ahead, window elements one 64-block ahead.
+#include <atomic>
 #include <cstdlib>
 #include <map>
 
@@ -1596,20 +1597,24 @@ __global__ __launch_bounds__(512) void k_sweep_n(const SweepTask* __restrict__ t
 //  2. the zero-start states after each segment of a workgroup follow from an
 //     inclusive scan over its P segments (steps of distance 1, 2, 4 with the
 //     maps T_c, T_c T_{c-1} and T_c ... T_{c-3}, all waves at once); the last
-//     one, the workgroup's tail, goes to the chain's exchange area;
-//  3. the G workgroups meet (chain_wait); workgroup g forms its true start
+//     one, the workgroup's tail, goes to the chain's exchange area, stamped
+//     (tail_put);
+//  3. workgroup g waits for the stamped tails of workgroups j < g (tail_get:
+//     no meeting of the chain) and forms its true start
 //     state S_g = sum_{j<g} Psi_{j,g} tail_j (Psi_{j,g} = W_{g-1} ... W_{j+1},
 //     W the workgroup maps, Psi_{g-1,g} = I; one product per wave), and the
 //     true states s_c = z_c + Pi_c S_g (z_c the zero-start state, Pi_c the
 //     product of the workgroup's maps before segment c);
 //  4. every segment but segment 0 adds Phi_c s_c to its outputs.
 // The maps of steps 2 and 3 are read into registers (one row per lane), those
-// of step 3 and the first rows of Phi_c while the workgroup waits to meet.
-// The workgroups meet again when the strip's solution is complete (the next
-// strip's transmission data read it), and, unless the strip is whole segment
-// groups of the plan (then each workgroup's back substitution takes its own
-// forward rows, from its LDS), when the forward output is complete: a strip
-// solve is three meetings, or four.
+// of step 3 and the first rows of Phi_c before the tails.  The workgroups
+// meet when the strip's solution is complete (the next strip's transmission
+// data read it), and, unless the strip is whole segment groups of the plan
+// (then each workgroup's back substitution takes its own forward rows, from
+// its LDS), when the forward output is complete: a strip solve is one
+// meeting, or two.  A workgroup rewrites its tail in an exchange area only
+// in the next strip, after a meeting that every reader of the old tail
+// reaches only once it has read it.
 
 // Meeting of the G workgroups of one chain, in two halves so that work can
 // go between them.  Everything the workgroups exchange goes through AgentAcc
@@ -1626,7 +1631,8 @@ struct ChainBar {
   unsigned need;    // arrivals that complete the current meeting
   unsigned G;
   long long limit;
-  int* ok;  // LDS word
+  int* ok;       // LDS word (1 until the chain gives up)
+  unsigned tag;  // stamp of the current triangle's tails (tail_put / tail_get)
 };
 
 __device__ __forceinline__ void chain_arrive(ChainBar& b) {
@@ -1663,6 +1669,49 @@ __device__ __forceinline__ bool chain_wait(ChainBar& b) {
 __device__ __forceinline__ bool chain_meet(ChainBar& b) {
   chain_arrive(b);
   return chain_wait(b);
+}
+
+// The workgroup tails of a triangle travel without a meeting: entry i of the
+// exchange area is two agent-scope 64-bit words, the real and the imaginary
+// part each in the low half of its word beside the triangle's stamp in the
+// high half.  A word is written whole (single-copy atomic), so a reader that
+// finds the stamp in both words holds the value; a stale entry carries
+// another stamp (a stamp names the launch and the triangle).
+__device__ __forceinline__ void tail_put(gptr<c64> x, long long i, c64 v, unsigned tag) {
+  const AgentAcc::u64g p = (AgentAcc::u64g)x + 2 * i;
+  const unsigned long long t = (unsigned long long)tag << 32;
+  __hip_atomic_store(p, t | __float_as_uint(v.re), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, t | __float_as_uint(v.im), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Entry i as soon as it carries the stamp (lanes with need false read
+// nothing and get zero).  The wait is bounded as chain_wait's: past the
+// limit, or once another workgroup has given up, the wave raises the abort
+// word and returns false (the same answer in every lane).
+__device__ __forceinline__ bool tail_get(gptr<const c64> x, long long i, bool need, c64& v,
+                                         const ChainBar& b) {
+  const AgentAcc::cu64g p = (AgentAcc::cu64g)x + 2 * (need ? i : 0);
+  unsigned long long re = 0, im = 0;
+  bool have = !need;
+  long long t0 = 0;
+  for (unsigned it = 0;; ++it) {
+    if (!have) {
+      re = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      im = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      have = (unsigned)(re >> 32) == b.tag && (unsigned)(im >> 32) == b.tag;
+    }
+    if (__all(have)) break;
+    if (it == 0) t0 = wall_clock64();
+    if ((it & 7) == 7 &&
+        __any(__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+              wall_clock64() - t0 > b.limit)) {
+      __hip_atomic_store(b.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  v = need ? mk(__uint_as_float((unsigned)re), __uint_as_float((unsigned)im)) : mk(0.0f, 0.0f);
+  return true;
 }
 
 // One row of a KM x KM map (KM <= 32, column-major, zero beyond K) held in
@@ -1713,7 +1762,7 @@ struct WideMaps {
 // One triangular substitution of a strip by workgroup g of the chain's G
 // (steps 1-4 above), after before() and after() (see step 1).  Phi: the segment
 // responses (plan_phi_elems layout),
-// xch: exchange area (64 entries per workgroup).  LDS: the wave's ring (640
+// xch: exchange area (64 stamped entries per workgroup).  LDS: the wave's ring (640
 // entries from ring), yt, kb, pw (64 entries per wave each: tails and
 // states, scan exchange, partial sums).  Returns false when the chain was
 // aborted.
@@ -1749,7 +1798,7 @@ __device__ __forceinline__ bool solve_triangle_wide(
     if (!EARLY_INPUTS) blocked_fetch_inputs(pre, ssrc, lane);
     // a segment that step 4 corrects from its ring keeps its zero-start
     // outputs there only: their stores would be overwritten unread, and the
-    // meeting's arrival would wait for them
+    // next meeting's arrival would wait for them
     const SegDstIf<T, Dst> zout{dst, off, c == 0 || len > 256};
     solve_blocked_run(pre, ssrc, zout, len, K, ring, (const c64*)nullptr, lane);
     if (c < nseg - 1 && lane < K) yt[64 * w + lane] = ring[(len - K + lane) & 255];
@@ -1773,10 +1822,11 @@ __device__ __forceinline__ bool solve_triangle_wide(
     __syncthreads();
   }
   kb[64 * w + lane] = b;  // zero-start state after segment c
-  if (w == P - 1 && g < gu - 1 && lane < K) AgentAcc::store(xch, (long long)g * 64 + lane, b);
-  chain_arrive(bar);
-  // maps of step 3 and the first rows of the correction, read while waiting
-  // wave w takes the tails of workgroups w and w + P (G - 1 <= 2 P)
+  if (w == P - 1 && g < gu - 1 && lane < K) tail_put(xch, (long long)g * 64 + lane, b, bar.tag);
+  __syncthreads();  // the states in kb
+  // maps of step 3 and the first rows of the correction, read before the
+  // other workgroups' tails; wave w takes the tails of workgroups w and w + P
+  // (G - 1 <= 2 P)
   MapRow<T, KM> PI, PS0, PS1;
   if (g >= 1 && w >= 1 && c <= nseg - 1) map_row_load(PI, mslot(mp.pi + c - 1), lane);
   if (g >= 2 && w <= g - 2) map_row_load(PS0, mslot(mp.ps + g * Gw + w), lane);
@@ -1789,21 +1839,21 @@ __device__ __forceinline__ bool solve_triangle_wide(
 #pragma unroll
     for (int k = 0; k < KM; ++k) ph0[k] = corr ? ld<T>(Ph, (long long)k * seg + ic) : zero;
   }
-  if (!chain_wait(bar)) return false;
   // 3. true states
   c64 s = zero;
   if (g == 0) {
     if (w >= 1 && c < nseg) s = kb[64 * (w - 1) + lane];
   } else if (g < gu) {
     if (w < g) {
-      c64 t[2];
+      c64 t[2] = {zero, zero};
+      bool got = true;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const int j = w + P * k;
-        t[k] = csel(lane < K && j < g,
-                    AgentAcc::load((gptr<const c64>)xch, (long long)(j < g ? j : 0) * 64 + lane),
-                    zero);
+        got = got && tail_get((gptr<const c64>)xch, (long long)j * 64 + lane, lane < K && j < g,
+                              t[k], bar);
       }
+      if (!got) *bar.ok = 0;
       c64 v = zero;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
@@ -1820,6 +1870,7 @@ __device__ __forceinline__ bool solve_triangle_wide(
       pw[64 * w + lane] = v;
     }
     __syncthreads();
+    if (*bar.ok == 0) return false;
     c64 S = zero;
     for (int j = 0; j < (g < P ? g : P); ++j) S = S + pw[64 * j + lane];
     if (w == 0) {
@@ -1863,10 +1914,11 @@ __device__ __forceinline__ bool solve_triangle_wide(
 template <int KP, int U, int NB>
 __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict__ tasks, int plan,
                                                     unsigned* abort, long long limit,
-                                                    int lo_cap) {
+                                                    int lo_cap, unsigned epoch) {
   using T = float;
   extern __shared__ char smem_raw[];
   __shared__ int ok;
+  if (threadIdx.x == 0) ok = 1;  // read after the first strip's barriers
   const int G = plan_width(plan);
   const SweepTask& tk = tasks[blockIdx.x / G];
   const int g = uni((int)(blockIdx.x % G));
@@ -1887,7 +1939,7 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
   gptr<c64> xch = (gptr<c64>)uniptr((c64*)tk.xch);
   gptr<const c128> r = (gptr<const c128>)uniptr(tk.ch.r);
   const StripDesc* strips = uniptr(tk.ch.strips);
-  ChainBar bar{uniptr(tk.bar), abort, 0u, (unsigned)G, limit, &ok};
+  ChainBar bar{uniptr(tk.bar), abort, 0u, (unsigned)G, limit, &ok, 0u};
   constexpr long long K2 = (long long)map_dim(KP) * map_dim(KP);
   const int mode = uni(tk.mode);
   const int nsteps = sweep_steps(mode, N);
@@ -1935,6 +1987,7 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
       __syncthreads();
       return true;
     };
+    bar.tag = epoch << 16 | (unsigned)(2 * step);  // stamps of this launch: (epoch, triangle)
     if (local) {
       if (!solve_triangle_wide<KP, U, NB, true>(gather, DstLds<T>{lo, base}, GL, none, form_data, mL,
                                                 PL, ns, kl, seg, g, G, ring, yt, kb, pw, xch, bar))
@@ -1950,7 +2003,8 @@ __global__ __launch_bounds__(512) void k_sweep_wide(const SweepTask* __restrict_
     // workgroup's stores after a meeting; its maps go out before either
     const SrcVec<T, AgentAcc> bin{(gptr<const c64>)rho, ns, true};
     const DstScatter<T, AgentAcc> bout{z, ns, nr, wd, n, a, dir, winv};
-    const gptr<c64> xchb = xch + (long long)G * 64;
+    const gptr<c64> xchb = xch + (long long)G * 128;  // 64 two-word entries per workgroup
+    bar.tag = epoch << 16 | (unsigned)(2 * step + 1);
     if (local) {
       auto sync = []() {
         __syncthreads();
@@ -2249,7 +2303,14 @@ static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int nmax, int 
   const long long us = env && *env ? std::atoll(env) : 250000LL;
   long long limit = (long long)wide_dev().khz * us / 1000;
   int lo_cap = wide_lo_cap(P, nmax);
-  void* args[] = {(void*)&d, (void*)&plan, (void*)&abort, (void*)&limit, (void*)&lo_cap};
+  // the launch's part of its tails' stamps: 16 bits, never 0, so that the
+  // zeros of a fresh exchange area match no stamp and a stamp comes back
+  // only after 65535 launches
+  static std::atomic<unsigned> launches{0};
+  unsigned epoch = 0;
+  while (epoch == 0) epoch = ++launches & 0xffffu;
+  void* args[] = {(void*)&d,     (void*)&plan,   (void*)&abort,
+                  (void*)&limit, (void*)&lo_cap, (void*)&epoch};
   HH_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)(ntasks * G)), dim3(64 * P), args,
                                     (unsigned)lds, st));
 }
