@@ -2289,6 +2289,17 @@ int sweep_plan_for(int ntasks, int precision, int P, int kmax, int nmax, bool pi
   return many ? HH_PLAN_TILE : 0;
 }
 
+// The launch's part of its tails' stamps, one count over every wide launch
+// of the process (every instantiation, every exchange area): 16 bits, never
+// 0, so that the zeros of a fresh exchange area match no stamp and a stamp
+// comes back only after 65535 launches.
+static std::atomic<unsigned> g_wide_launches{0};
+static unsigned next_wide_epoch() {
+  unsigned e = 0;
+  while (e == 0) e = ++g_wide_launches & 0xffffu;
+  return e;
+}
+
 template <int KP>
 static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int nmax, int plan,
                            unsigned* abort, hipStream_t st) {
@@ -2303,12 +2314,7 @@ static void launch_wide_kp(const SweepTask* d, int ntasks, int P, int nmax, int 
   const long long us = env && *env ? std::atoll(env) : 250000LL;
   long long limit = (long long)wide_dev().khz * us / 1000;
   int lo_cap = wide_lo_cap(P, nmax);
-  // the launch's part of its tails' stamps: 16 bits, never 0, so that the
-  // zeros of a fresh exchange area match no stamp and a stamp comes back
-  // only after 65535 launches
-  static std::atomic<unsigned> launches{0};
-  unsigned epoch = 0;
-  while (epoch == 0) epoch = ++launches & 0xffffu;
+  unsigned epoch = next_wide_epoch();
   void* args[] = {(void*)&d,     (void*)&plan,   (void*)&abort,
                   (void*)&limit, (void*)&lo_cap, (void*)&epoch};
   HH_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)(ntasks * G)), dim3(64 * P), args,
